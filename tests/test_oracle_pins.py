@@ -1,0 +1,272 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+* hand-worked golden cases (constraint inequalities of Sec. II-C, Alg. 1);
+* brute force on tiny random streams: every occurrence enumerated from the
+  inequalities, then an exhaustive and a dynamic-programming maximum
+  non-overlapped subset (neither is the greedy);
+* special cases that reduce to library routines (1-node = numpy.unique;
+  2-node = an independent bisect-based greedy);
+* invariants of the frequency measure (anti-monotonicity of Sec. II-C and
+  others), and planted-cascade recovery;
+* the two oracle formulations (decomposition of Sec. IV-A + Alg. 1, and the
+  serial state machine of Sec. III-A) agree.
+"""
+import bisect
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import spikegen as sg
+from oracle import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+
+
+def stream_from_events(events, K=3):
+    ev = sorted(events, key=lambda e: e[1])  # stable: keeps the listed order of equal times
+    return dict(types=np.array([e[0] for e in ev], np.int32),
+                times=np.array([e[1] for e in ev], np.int64), K=K, ts_kind=1)
+
+
+def one_candidate(ep, lo, hi):
+    return sg.candidates_from_list([(list(ep), list(lo), list(hi))])
+
+
+def golden_cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", golden_cases(), ids=lambda c: c["name"].split()[0])
+@pytest.mark.parametrize("method", ["decomp", "fsm"])
+def test_golden_worked_examples(case, method):
+    # keep the listed event order (W3 lists (B,5) before (A,5))
+    s = dict(types=np.array([e[0] for e in case["events"]], np.int32),
+             times=np.array([e[1] for e in case["events"]], np.int64), K=3, ts_kind=1)
+    assert np.all(np.diff(s["times"]) >= 0)
+    c = one_candidate(case["episode"], case["lo"], case["hi"])
+    assert oracle.count(s, c, method)[0] == case["count"]
+    occ = brute.occurrences(s["types"], s["times"], case["episode"], case["lo"], case["hi"])
+    assert sorted(occ) == sorted(tuple(o) for o in case["occurrences"])
+    assert brute.max_nonoverlapped_exhaustive(occ) == case["count"]
+    assert brute.max_nonoverlapped_dp(occ) == case["count"]
+
+
+def test_paper_literal_initialisation_would_lose_time_zero():
+    """Alg. 1 as printed starts the previous end at 0; a start at time 0 is then
+    never strictly after it.  The oracle starts at minus infinity instead."""
+    s = stream_from_events([(0, 0), (1, 6)])
+    assert oracle.count(s, one_candidate([0, 1], [5], [10]))[0] == 1
+    spans = [(0, 6)]
+    prev_e, literal = 0, 0
+    for st, en in spans:
+        if prev_e < st:
+            prev_e, literal = en, literal + 1
+    assert literal == 0
+
+
+def _tiny_cases(seed, ncase, n, K, tmax, nmax, gap):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for _ in range(ncase):
+        s = sg.tiny_stream(rng, int(rng.integers(1, n + 1)), K, tmax)
+        c = sg.tiny_candidates(rng, 6, K, nmax, gap)
+        yield s, c
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bruteforce_tiny_streams(seed):
+    """P1: definition by enumeration == both oracle formulations, on tiny
+    streams with many equal timestamps."""
+    for s, c in _tiny_cases(100 + seed, 40, 24, 4, 30, 4, 12):
+        got_d = oracle.count(s, c, "decomp")
+        got_f = oracle.count(s, c, "fsm")
+        for i in range(c["N"].size):
+            N = int(c["N"][i])
+            ep = list(c["types"][i, :N])
+            lo = list(c["lo"][i, : N - 1])
+            hi = list(c["hi"][i, : N - 1])
+            spans = brute.occurrences(s["types"], s["times"], ep, lo, hi)
+            want = brute.max_nonoverlapped_dp(spans)
+            if len(set(spans)) <= 14:
+                assert brute.max_nonoverlapped_exhaustive(spans) == want
+            assert got_d[i] == want, (ep, lo, hi)
+            assert got_f[i] == want, (ep, lo, hi)
+
+
+def test_bruteforce_dense_ties():
+    """Streams where most events share timestamps (times in 0..6)."""
+    for s, c in _tiny_cases(7, 200, 16, 3, 6, 3, 4):
+        got = oracle.count(s, c, "fsm")
+        for i in range(c["N"].size):
+            N = int(c["N"][i])
+            spans = brute.occurrences(s["types"], s["times"], list(c["types"][i, :N]),
+                                      list(c["lo"][i, : N - 1]), list(c["hi"][i, : N - 1]))
+            assert got[i] == brute.max_nonoverlapped_dp(spans)
+
+
+def _medium_stream(seed, K=6, rate=40.0, dur=20.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return sg.poisson_stream(rng, K=K, rate_hz=rate, dur_s=dur, ts_kind=1, unit_per_ms=1)
+
+
+def _medium_cands(seed, K=6, m=300, nmin=1, nmax=5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return sg.random_candidates(rng, m, K, nmin, nmax, 1, low_ms=(0, 1, 3, 8), width_ms=(1, 4, 10, 30))
+
+
+def test_one_node_equals_unique():
+    """P5: a 1-node episode counts the distinct timestamps of its type."""
+    s = _medium_stream(1)
+    c = sg.candidates_from_list([([k], [], []) for k in range(s["K"])])
+    got = oracle.count(s, c, "decomp")
+    got_f = oracle.count(s, c, "fsm")
+    for k in range(s["K"]):
+        want = np.unique(s["times"][s["types"] == k]).size
+        assert got[k] == want and got_f[k] == want
+
+
+def _two_node_greedy(times_a, times_b, lo, hi):
+    """Independent 2-node greedy: walk B in time order; take the latest A
+    with t_a < t_b - lo (bisect); accept if it is >= t_b - hi and starts
+    after the previously accepted end."""
+    count, prev_e = 0, None
+    for tb in times_b:
+        k = bisect.bisect_left(times_a, tb - lo) - 1
+        if k < 0:
+            continue
+        ta = times_a[k]
+        if ta < tb - hi:
+            continue
+        if prev_e is None or ta > prev_e:
+            count += 1
+            prev_e = tb
+    return count
+
+
+def test_two_node_equals_bisect_greedy():
+    s = _medium_stream(2)
+    rng = np.random.Generator(np.random.PCG64(3))
+    eps = []
+    for _ in range(120):
+        a, b = rng.permutation(s["K"])[:2]
+        lo = int(rng.integers(0, 20))
+        hi = lo + int(rng.integers(1, 40))
+        eps.append(([a, b], [lo], [hi]))
+    c = sg.candidates_from_list(eps)
+    got = oracle.count(s, c)
+    for i, (ep, lo, hi) in enumerate(eps):
+        ta = list(s["times"][s["types"] == ep[0]])
+        tb = list(s["times"][s["types"] == ep[1]])
+        assert got[i] == _two_node_greedy(ta, tb, lo[0], hi[0])
+
+
+def test_formulations_agree_medium():
+    """P6: decomposition (latest start per end + Alg. 1) == state machine."""
+    for seed in range(3):
+        s = _medium_stream(10 + seed, rate=60.0)
+        c = _medium_cands(20 + seed, m=400, nmax=8)
+        np.testing.assert_array_equal(oracle.count(s, c, "decomp"), oracle.count(s, c, "fsm"))
+
+
+def _sub(c, i, a, b):
+    """Sub-episode of candidate i made of nodes a..b-1."""
+    ep = list(c["types"][i, a:b])
+    return (ep, list(c["lo"][i, a:b - 1]), list(c["hi"][i, a:b - 1]))
+
+
+def test_invariant_prefix_suffix_and_rarest():
+    """Anti-monotonicity (Sec. II-C): a count never exceeds that of its prefix
+    or suffix sub-episode, nor the distinct timestamps of its rarest type."""
+    s = _medium_stream(4, rate=60.0)
+    c = _medium_cands(5, m=300, nmin=2, nmax=6)
+    full = oracle.count(s, c)
+    pre, suf = [], []
+    for i in range(c["N"].size):
+        N = int(c["N"][i])
+        pre.append(_sub(c, i, 0, N - 1))
+        suf.append(_sub(c, i, 1, N))
+    cp = oracle.count(s, sg.candidates_from_list(pre))
+    cs = oracle.count(s, sg.candidates_from_list(suf))
+    assert np.all(full <= cp) and np.all(full <= cs)
+    for i in range(c["N"].size):
+        N = int(c["N"][i])
+        for k in c["types"][i, :N]:
+            assert full[i] <= np.unique(s["times"][s["types"] == k]).size
+    assert full.max() > 0  # not vacuous
+
+
+def test_invariant_widening_never_decreases():
+    s = _medium_stream(6, rate=60.0)
+    c = _medium_cands(7, m=300, nmin=2, nmax=5)
+    base = oracle.count(s, c)
+    w = {k: v.copy() for k, v in c.items()}
+    live = np.arange(7)[None, :] < (c["N"][:, None].astype(int) - 1)
+    w["lo"] = np.where(live, np.maximum(c["lo"] - 1, 0), 0)
+    w["hi"] = np.where(live, c["hi"] + 2, 0)
+    assert np.all(oracle.count(s, w) >= base)
+
+
+def test_invariant_time_shift_units_and_relabel():
+    s = _medium_stream(8, rate=50.0)
+    c = _medium_cands(9, m=250, nmax=6)
+    base = oracle.count(s, c)
+    shifted = dict(s, times=s["times"] + 123456789)
+    np.testing.assert_array_equal(oracle.count(shifted, c), base)
+    scaled = dict(s, times=s["times"] * 1000)
+    cs = dict(c, lo=c["lo"] * 1000, hi=c["hi"] * 1000)
+    np.testing.assert_array_equal(oracle.count(scaled, cs), base)
+    perm = np.random.Generator(np.random.PCG64(1)).permutation(s["K"]).astype(np.int32)
+    rel = dict(s, types=perm[s["types"]])
+    cr = dict(c, types=np.where(c["types"] >= 0, perm[np.maximum(c["types"], 0)], -1))
+    np.testing.assert_array_equal(oracle.count(rel, cr), base)
+
+
+def test_invariant_equal_time_permutation():
+    """The count does not depend on the order of events with equal times."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    for _ in range(5):
+        s = sg.tiny_stream(rng, 400, 4, 120)  # about 3 events per timestamp
+        c = sg.tiny_candidates(rng, 80, 4, 4, 10)
+        base = oracle.count(s, c, "fsm")
+        key = rng.random(s["times"].size)
+        order = np.lexsort((key, s["times"]))
+        ps = dict(s, types=s["types"][order], times=s["times"][order])
+        np.testing.assert_array_equal(oracle.count(ps, c, "fsm"), base)
+        np.testing.assert_array_equal(oracle.count(ps, c, "decomp"), base)
+
+
+def test_invariant_concatenation_adds():
+    """Two streams separated by a gap larger than every episode span: counts add."""
+    a = _medium_stream(12, dur=5.0)
+    b = _medium_stream(13, dur=5.0)
+    c = _medium_cands(14, m=200, nmax=6)
+    gap = int(a["times"].max()) + 7 * 40 + 1
+    cat = dict(types=np.concatenate([a["types"], b["types"]]),
+               times=np.concatenate([a["times"], b["times"] + gap]), K=a["K"], ts_kind=1)
+    np.testing.assert_array_equal(oracle.count(cat, c), oracle.count(a, c) + oracle.count(b, c))
+
+
+def test_planted_cascade_recovery():
+    """P4: each planted instance is a valid occurrence by construction, so the
+    count of the planted episode is at least the largest non-overlapped subset
+    of the planted instances."""
+    s = sg.config_stream(1)
+    for p in s["planted"]:
+        inst = p["instances"]
+        spans = [(int(r[0]), int(r[-1])) for r in inst]
+        c = one_candidate(p["types"], p["lo"], p["hi"])
+        assert oracle.count(s, c)[0] >= brute.max_nonoverlapped_dp(spans) > 100
+    s2 = sg.config_stream(2, scale=0.2)
+    for p in s2["planted"]:
+        spans = [(int(r[0]), int(r[-1])) for r in p["instances"]]
+        c = one_candidate(p["types"], p["lo"], p["hi"])
+        assert oracle.count(s2, c)[0] >= brute.max_nonoverlapped_dp(spans) > 0
+
+
+def test_oracle_rejects_bad_input():
+    s = stream_from_events([(0, 1), (5, 2)], K=3)
+    with pytest.raises(ValueError):
+        oracle.count(s, one_candidate([0, 1], [0], [5]))
