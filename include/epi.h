@@ -1,0 +1,188 @@
+/*
+ * epi.h -- C ABI of the MI355X (gfx950) serial-episode counting engine.
+ *
+ * The engine counts, exactly, the non-overlapped occurrences of serial
+ * episodes with inter-event constraints in a long event stream:
+ *   - event stream (E_i, t_i), i = 0..n-1, integer times, t_i <= t_{i+1},
+ *     E_i in 0..K-1                                          (paper, Def. 1)
+ *   - serial episode alpha = (A_1 .. A_N), distinct types, 1 <= N <= 8
+ *                                                            (paper, Def. 2)
+ *   - constraint j (j = 1..N-1):  lo_j < t(A_{j+1}) - t(A_j) <= hi_j,
+ *     0 <= lo_j < hi_j                                 (paper, Sec. II-C)
+ *   - frequency = size of the largest set of occurrences no two of which
+ *     overlap in time; occurrences sharing a timestamp overlap
+ *                                      (paper, Sec. II-C, Sec. IV-A, Alg. 1)
+ *
+ * Conventions for every entry point:
+ *   - the return value is a status: EPI_OK (0) or a negative error code;
+ *     nothing aborts or throws across the ABI, and the message of the last
+ *     error of a context is available from epi_last_error();
+ *   - HIP runtime failures map to EPI_EDEVICE (message = hipError string);
+ *   - a context is not thread-safe: use one per host thread;
+ *   - host inputs are copied before the call returns; "_device" inputs are
+ *     borrowed until epi_sync() returns;
+ *   - outputs go to caller-owned buffers; device memory made by the library
+ *     is owned by the context and freed by epi_release_* and epi_destroy;
+ *   - there is no CPU fallback: every count is computed by HIP kernels.
+ *
+ * Timestamps are unit-agnostic integers, int32 (EPI_TS_I32) or int64
+ * (EPI_TS_I64); by convention microseconds and nanoseconds.  Candidate
+ * interval bounds are always passed as int64 and must fit the stream's
+ * timestamp type together with the stream's times (see EPI_EOVERFLOW).
+ */
+#ifndef EPI_H
+#define EPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct epi_ctx epi_ctx;
+typedef int32_t epi_status;
+
+enum {
+    EPI_OK = 0,
+    EPI_EINVAL = -1,    /* null pointer, bad enum, bad size argument            */
+    EPI_EUNSORTED = -2, /* stream times decrease somewhere                       */
+    EPI_ETYPE = -3,     /* event or episode type outside [0, K)                  */
+    EPI_EINTERVAL = -4, /* an interval violates 0 <= lo < hi                     */
+    EPI_ESIZE = -5,     /* episode size outside 1..8, or n / K / m out of range  */
+    EPI_EREPEAT = -6,   /* a type occurs twice in one episode                    */
+    EPI_EOVERFLOW = -7, /* times +- the episode span leave the timestamp type    */
+    EPI_ENOMEM = -8,    /* device or host allocation failed                      */
+    EPI_EDEVICE = -9,   /* HIP runtime error or a device-side check failed       */
+    EPI_ESTATE = -10    /* unknown id, or counts read before a count was issued  */
+};
+
+enum { EPI_TS_I32 = 0, EPI_TS_I64 = 1 };
+enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1 };
+enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1 };
+
+#define EPI_MAX_N 8 /* largest episode size */
+
+/* ------------------------------------------------------------------------
+ * Contexts
+ * ---------------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device` (0-based).  *out receives the
+ * context.  EPI_EDEVICE if the device cannot be selected. */
+epi_status epi_create(int device, epi_ctx **out);
+
+/* Free every device buffer of the context and the context itself.  Waits
+ * for outstanding work.  Null is accepted. */
+void epi_destroy(epi_ctx *ctx);
+
+/* Message of the context's last error ("" if none).  Valid until the next
+ * call on the context.  Null ctx: the message of the last failed
+ * epi_create on this thread. */
+const char *epi_last_error(const epi_ctx *ctx);
+
+/* Static name of a status code. */
+const char *epi_status_string(epi_status s);
+
+/* ------------------------------------------------------------------------
+ * Host-only validators (no GPU touched; also used internally)
+ * ---------------------------------------------------------------------- */
+
+/* Check a host stream: n >= 0 (n < 2^31), 1 <= K <= 65536, every type in
+ * [0, K), times non-decreasing (Def. 1), and every time strictly inside the
+ * timestamp type's range (its minimum and maximum are reserved).
+ * `times` is int32_t[n] or int64_t[n] according to ts_kind. */
+epi_status epi_validate_stream(const int32_t *types, const void *times, int64_t n, int ts_kind,
+                               int32_t K);
+
+/* Check m candidate episodes (Def. 2, Sec. II-C):
+ *   N[c] in 1..8; types[c*8 + j] in [0, K) and distinct for j < N[c];
+ *   0 <= lo[c*7 + j] < hi[c*7 + j] for j < N[c]-1; the span sum_j hi
+ *   fits the timestamp type.  Slots beyond N[c] are ignored. */
+epi_status epi_validate_candidates(int64_t m, const uint8_t *N, const int32_t *types,
+                                   const int64_t *lo, const int64_t *hi, int32_t K,
+                                   int ts_kind);
+
+/* ------------------------------------------------------------------------
+ * Streams (Def. 1) and the per-type index (pre-processing of Sec. IV-A)
+ * ---------------------------------------------------------------------- */
+
+/* Copy a host stream to the device, validate it, and build its per-type
+ * index (events grouped by type, each group in time order).  *stream_id
+ * receives a handle.  Errors: the validator's codes, EPI_ENOMEM, EPI_EDEVICE. */
+epi_status epi_load_stream(epi_ctx *ctx, const int32_t *types, const void *times, int64_t n,
+                           int ts_kind, int32_t K, int32_t *stream_id);
+
+/* Same, from device buffers (int32 types, int32/int64 times) enqueued on
+ * `hip_stream` (hipStream_t; null = the context's stream).  The inputs are
+ * validated on the device; a violation is reported as EPI_EUNSORTED or
+ * EPI_ETYPE by this call (it synchronises once to read the verdict). */
+epi_status epi_load_stream_device(epi_ctx *ctx, const int32_t *d_types, const void *d_times,
+                                  int64_t n, int ts_kind, int32_t K, void *hip_stream,
+                                  int32_t *stream_id);
+
+/* Number of events, K and timestamp kind of a loaded stream. */
+epi_status epi_stream_info(epi_ctx *ctx, int32_t stream_id, int64_t *n, int32_t *K,
+                           int *ts_kind);
+
+/* Copy the per-type index back: off[K+1] (int32) and the timestamps grouped
+ * by type (ts_kind width, n entries).  For inspection and tests. */
+epi_status epi_read_type_index(epi_ctx *ctx, int32_t stream_id, int32_t *off, void *ts_by_type);
+
+epi_status epi_release_stream(epi_ctx *ctx, int32_t stream_id);
+
+/* ------------------------------------------------------------------------
+ * Candidate sets
+ * ---------------------------------------------------------------------- */
+
+/* Validate m host candidates against the stream (see epi_validate_candidates
+ * and EPI_EOVERFLOW: min time - span and max time + span must stay inside the
+ * timestamp type) and copy them to the device.  m may be 0.
+ * Layout: N[m] (uint8), types[m*8] (int32), lo[m*7], hi[m*7] (int64). */
+epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, const uint8_t *N,
+                                 const int32_t *types, const int64_t *lo, const int64_t *hi,
+                                 int32_t *set_id);
+
+epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
+
+/* ------------------------------------------------------------------------
+ * Counting
+ * ---------------------------------------------------------------------- */
+
+/* Enqueue the count of k candidate sets on `hip_stream` (null = the
+ * context's stream).  Asynchronous.  mode: EPI_MODE_PLAIN (one launch per
+ * set and episode-size class) or EPI_MODE_BATCHED (one persistent launch over
+ * all sets); sched: EPI_SCHED_RR or EPI_SCHED_LEARNED (batched mode only).
+ * The counts never depend on mode or sched. */
+epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched,
+                     void *hip_stream);
+
+/* Engine options (per context), used by tests and by tuning:
+ *   EPI_OPT_SEGMENTS      0 = automatic (default); k >= 1 = cut the stream
+ *                         into k time segments counted in parallel and
+ *                         reconciled exactly (1 = no segmentation)
+ *   EPI_OPT_LANES         0 = automatic (default); else the largest number
+ *                         of episodes per workgroup (64, 128 or 256); the
+ *                         engine uses the widest one whose state fits LDS
+ *   EPI_OPT_TARGET_LANES  automatic segmentation aims at this many
+ *                         (episode, segment) work lanes (default 262144)
+ * EPI_EINVAL for an unknown option or value.  Counts never depend on them. */
+enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3 };
+epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
+
+/* Wait for all work of the context and report device-side check failures. */
+epi_status epi_sync(epi_ctx *ctx);
+
+/* Blocking copy of a set's counts (int32, candidate order of submission) to
+ * host memory counts[m]; m must equal the set's size.  EPI_ESTATE if the set
+ * was never counted. */
+epi_status epi_read_counts(epi_ctx *ctx, int32_t set_id, int32_t *counts, int64_t m);
+
+/* Device pointer to a set's counts (int32[m], submission order), valid until
+ * the set is released; contents are defined once the count's stream work is
+ * complete. */
+epi_status epi_counts_device(epi_ctx *ctx, int32_t set_id, const int32_t **d_counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPI_H */

@@ -1,0 +1,532 @@
+// C ABI of the episode-counting engine: contexts, validation, stream and
+// candidate ingest, counting and readback.  Kernels live in epi_index.hip
+// (per-type index) and epi_tiled.hip (counting and reconciliation).
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "epi_internal.h"
+
+using namespace epi;
+
+struct epi_ctx {
+    Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+epi_status fail(epi_ctx *ctx, epi_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->c.err = buf;
+    return code;
+}
+
+epi_status hipfail(epi_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(ctx, EPI_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(ctx, EPI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPTRY(ctx, expr, what)                          \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hipfail(ctx, e_, what); \
+    } while (0)
+
+template <typename T>
+epi_status check_stream_t(const int32_t *types, const T *times, int64_t n, int32_t K, std::string *msg) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (types[i] < 0 || types[i] >= K) {
+            if (msg) *msg = "event " + std::to_string(i) + " has type " + std::to_string(types[i]) + " outside [0, K)";
+            return EPI_ETYPE;
+        }
+        if (times[i] == TsLimits<T>::lo() || times[i] == TsLimits<T>::hi()) {
+            if (msg) *msg = "event " + std::to_string(i) + " uses a reserved timestamp (type minimum or maximum)";
+            return EPI_EOVERFLOW;
+        }
+        if (i > 0 && times[i] < times[i - 1]) {
+            if (msg) *msg = "times decrease at event " + std::to_string(i);
+            return EPI_EUNSORTED;
+        }
+    }
+    return EPI_OK;
+}
+
+epi_status check_stream(const int32_t *types, const void *times, int64_t n, int ts_kind, int32_t K,
+                        std::string *msg) {
+    if (ts_kind != EPI_TS_I32 && ts_kind != EPI_TS_I64) {
+        if (msg) *msg = "ts_kind must be EPI_TS_I32 or EPI_TS_I64";
+        return EPI_EINVAL;
+    }
+    if (n < 0 || n >= (int64_t(1) << 31)) {
+        if (msg) *msg = "n must be in [0, 2^31)";
+        return EPI_ESIZE;
+    }
+    if (K < 1 || K > kMaxK) {
+        if (msg) *msg = "K must be in [1, " + std::to_string(kMaxK) + "]";
+        return EPI_ESIZE;
+    }
+    if (n > 0 && (!types || !times)) {
+        if (msg) *msg = "null stream pointer";
+        return EPI_EINVAL;
+    }
+    if (ts_kind == EPI_TS_I64) return check_stream_t(types, (const int64_t *)times, n, K, msg);
+    return check_stream_t(types, (const int32_t *)times, n, K, msg);
+}
+
+// Sum of the upper bounds of candidate c (its longest possible span), or -1
+// on overflow.
+int64_t span_of(int N, const int64_t *hi) {
+    int64_t s = 0;
+    for (int j = 0; j + 1 < N; ++j) {
+        if (hi[j] > INT64_MAX - s) return -1;
+        s += hi[j];
+    }
+    return s;
+}
+
+epi_status check_candidates(int64_t m, const uint8_t *N, const int32_t *types, const int64_t *lo,
+                            const int64_t *hi, int32_t K, int ts_kind, std::string *msg) {
+    if (ts_kind != EPI_TS_I32 && ts_kind != EPI_TS_I64) {
+        if (msg) *msg = "ts_kind must be EPI_TS_I32 or EPI_TS_I64";
+        return EPI_EINVAL;
+    }
+    if (m < 0 || m >= (int64_t(1) << 31)) {
+        if (msg) *msg = "m must be in [0, 2^31)";
+        return EPI_ESIZE;
+    }
+    if (m > 0 && (!N || !types || !lo || !hi)) {
+        if (msg) *msg = "null candidate pointer";
+        return EPI_EINVAL;
+    }
+    const int64_t tmax = ts_kind == EPI_TS_I64 ? INT64_MAX : INT32_MAX;
+    for (int64_t c = 0; c < m; ++c) {
+        const int n = N[c];
+        auto say = [&](const std::string &s) {
+            if (msg) *msg = "candidate " + std::to_string(c) + ": " + s;
+        };
+        if (n < 1 || n > kMaxN) {
+            say("size must be in 1..8");
+            return EPI_ESIZE;
+        }
+        const int32_t *ty = types + c * kMaxN;
+        for (int j = 0; j < n; ++j) {
+            if (ty[j] < 0 || ty[j] >= K) {
+                say("type outside [0, K)");
+                return EPI_ETYPE;
+            }
+            for (int k = 0; k < j; ++k)
+                if (ty[k] == ty[j]) {
+                    say("repeated event type");
+                    return EPI_EREPEAT;
+                }
+        }
+        const int64_t *l = lo + c * (kMaxN - 1), *h = hi + c * (kMaxN - 1);
+        for (int j = 0; j + 1 < n; ++j) {
+            if (!(0 <= l[j] && l[j] < h[j])) {
+                say("interval must satisfy 0 <= lo < hi");
+                return EPI_EINTERVAL;
+            }
+            if (queue_bound(l[j], h[j]) > kMaxQueue) {
+                say("interval (lo, hi] too narrow for its offset: 1 + hi/(hi-lo+1) exceeds the supported queue depth " +
+                    std::to_string(kMaxQueue));
+                return EPI_EINTERVAL;
+            }
+        }
+        const int64_t sp = span_of(n, h);
+        if (sp < 0 || sp >= tmax) {
+            say("episode span overflows the timestamp type");
+            return EPI_EOVERFLOW;
+        }
+    }
+    return EPI_OK;
+}
+
+int queue_class(int64_t b) {
+    int q = 1;
+    while (q < b) q <<= 1;
+    return q;
+}
+
+template <typename T>
+hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int32_t *types, const int64_t *lo,
+                             const int64_t *hi, hipStream_t st) {
+    // launch class of each candidate: (N, queue capacity)
+    std::vector<int> key(m);
+    for (int64_t c = 0; c < m; ++c) {
+        int Q = 1;
+        for (int j = 0; j + 1 < N[c]; ++j)
+            Q = std::max<int>(Q, queue_class(queue_bound(lo[c * 7 + j], hi[c * 7 + j])));
+        key[c] = N[c] * 64 + Q;
+    }
+    std::vector<int32_t> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    std::vector<int32_t> h_types((size_t)kMaxN * m, 0);
+    std::vector<T> h_lo((size_t)(kMaxN - 1) * m, 0), h_hi((size_t)(kMaxN - 1) * m, 0);
+    cs.groups.clear();
+    for (int64_t s = 0; s < m; ++s) {
+        const int32_t c = order[s];
+        for (int j = 0; j < kMaxN; ++j) h_types[(size_t)j * m + s] = j < N[c] ? types[(int64_t)c * 8 + j] : 0;
+        for (int j = 0; j + 1 < kMaxN; ++j) {
+            h_lo[(size_t)j * m + s] = j + 1 < N[c] ? (T)lo[(int64_t)c * 7 + j] : T(0);
+            h_hi[(size_t)j * m + s] = j + 1 < N[c] ? (T)hi[(int64_t)c * 7 + j] : T(0);
+        }
+        if (cs.groups.empty() || key[c] != cs.groups.back().N * 64 + cs.groups.back().Q) {
+            Group g;
+            g.N = N[c];
+            g.Q = key[c] % 64;
+            g.begin = s;
+            g.end = s;
+            cs.groups.push_back(g);
+        }
+        cs.groups.back().end = s + 1;
+    }
+    hipError_t e;
+    if ((e = cs.types.alloc(sizeof(int32_t) * h_types.size())) != hipSuccess) return e;
+    if ((e = cs.lo.alloc(sizeof(T) * h_lo.size())) != hipSuccess) return e;
+    if ((e = cs.hi.alloc(sizeof(T) * h_hi.size())) != hipSuccess) return e;
+    if ((e = cs.orig.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    if ((e = cs.counts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    if (m > 0) {
+        if ((e = hipMemcpyAsync(cs.types.p, h_types.data(), sizeof(int32_t) * h_types.size(), hipMemcpyHostToDevice,
+                                st)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(cs.lo.p, h_lo.data(), sizeof(T) * h_lo.size(), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(cs.hi.p, h_hi.data(), sizeof(T) * h_hi.size(), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(cs.orig.p, order.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return e;
+    }
+    // host staging vectors die here: wait for the copies
+    return hipStreamSynchronize(st);
+}
+
+epi_status check_flags(epi_ctx *ctx) {
+    int32_t f[kNumFlags];
+    HIPTRY(ctx, hipMemcpy(f, ctx->c.flags.p, sizeof(f), hipMemcpyDeviceToHost), "reading device flags");
+    if (f[kFlagQueueOverflow] | f[kFlagUnsorted] | f[kFlagBadType] | f[kFlagBadTime]) {
+        HIPTRY(ctx, hipMemset(ctx->c.flags.p, 0, sizeof(f)), "clearing device flags");
+        if (f[kFlagUnsorted]) return fail(ctx, EPI_EUNSORTED, "device check: stream times decrease");
+        if (f[kFlagBadType]) return fail(ctx, EPI_ETYPE, "device check: event type outside [0, K)");
+        if (f[kFlagBadTime]) return fail(ctx, EPI_EOVERFLOW, "device check: reserved timestamp value in stream");
+        return fail(ctx, EPI_EDEVICE, "device check: interval queue overflow (%d)", f[kFlagQueueOverflow]);
+    }
+    return EPI_OK;
+}
+
+Stream *find_stream(epi_ctx *ctx, int32_t id) {
+    auto it = ctx->c.streams.find(id);
+    return it == ctx->c.streams.end() ? nullptr : it->second.get();
+}
+
+CandSet *find_set(epi_ctx *ctx, int32_t id) {
+    auto it = ctx->c.sets.find(id);
+    return it == ctx->c.sets.end() ? nullptr : it->second.get();
+}
+
+hipStream_t pick_stream(epi_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->c.stream; }
+
+}  // namespace
+
+extern "C" {
+
+epi_status epi_create(int device, epi_ctx **out) {
+    if (!out) return EPI_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || device < 0 || device >= ndev) {
+        g_create_err = std::string("no HIP device ") + std::to_string(device) + ": " +
+                       (e != hipSuccess ? hipGetErrorString(e) : "index out of range");
+        return EPI_EDEVICE;
+    }
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        g_create_err = hipGetErrorString(e);
+        return EPI_EDEVICE;
+    }
+    epi_ctx *ctx = new (std::nothrow) epi_ctx();
+    if (!ctx) return EPI_ENOMEM;
+    ctx->c.device = device;
+    if ((e = hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = ctx->c.flags.alloc(sizeof(int32_t) * kNumFlags)) != hipSuccess ||
+        (e = hipMemset(ctx->c.flags.p, 0, sizeof(int32_t) * kNumFlags)) != hipSuccess) {
+        g_create_err = hipGetErrorString(e);
+        delete ctx;
+        return EPI_EDEVICE;
+    }
+    *out = ctx;
+    return EPI_OK;
+}
+
+void epi_destroy(epi_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipDeviceSynchronize();
+    ctx->c.sets.clear();
+    ctx->c.streams.clear();
+    ctx->c.flags.reset();
+    if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
+    delete ctx;
+}
+
+const char *epi_last_error(const epi_ctx *ctx) { return ctx ? ctx->c.err.c_str() : g_create_err.c_str(); }
+
+const char *epi_status_string(epi_status s) {
+    switch (s) {
+        case EPI_OK: return "EPI_OK";
+        case EPI_EINVAL: return "EPI_EINVAL";
+        case EPI_EUNSORTED: return "EPI_EUNSORTED";
+        case EPI_ETYPE: return "EPI_ETYPE";
+        case EPI_EINTERVAL: return "EPI_EINTERVAL";
+        case EPI_ESIZE: return "EPI_ESIZE";
+        case EPI_EREPEAT: return "EPI_EREPEAT";
+        case EPI_EOVERFLOW: return "EPI_EOVERFLOW";
+        case EPI_ENOMEM: return "EPI_ENOMEM";
+        case EPI_EDEVICE: return "EPI_EDEVICE";
+        case EPI_ESTATE: return "EPI_ESTATE";
+        default: return "EPI_UNKNOWN";
+    }
+}
+
+epi_status epi_validate_stream(const int32_t *types, const void *times, int64_t n, int ts_kind, int32_t K) {
+    return check_stream(types, times, n, ts_kind, K, nullptr);
+}
+
+epi_status epi_validate_candidates(int64_t m, const uint8_t *N, const int32_t *types, const int64_t *lo,
+                                   const int64_t *hi, int32_t K, int ts_kind) {
+    return check_candidates(m, N, types, lo, hi, K, ts_kind, nullptr);
+}
+
+epi_status epi_load_stream(epi_ctx *ctx, const int32_t *types, const void *times, int64_t n, int ts_kind,
+                           int32_t K, int32_t *stream_id) {
+    if (!ctx || !stream_id) return fail(ctx, EPI_EINVAL, "null argument");
+    std::string msg;
+    epi_status v = check_stream(types, times, n, ts_kind, K, &msg);
+    if (v != EPI_OK) return fail(ctx, v, "%s", msg.c_str());
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    auto s = std::make_unique<Stream>();
+    s->n = n;
+    s->K = K;
+    s->ts_kind = ts_kind;
+    if (n > 0) {
+        s->tmin = ts_kind == EPI_TS_I64 ? ((const int64_t *)times)[0] : ((const int32_t *)times)[0];
+        s->tmax = ts_kind == EPI_TS_I64 ? ((const int64_t *)times)[n - 1] : ((const int32_t *)times)[n - 1];
+    }
+    HIPTRY(ctx, s->types.alloc(sizeof(int32_t) * n), "allocating stream types");
+    HIPTRY(ctx, s->times.alloc(s->ts_bytes() * n), "allocating stream times");
+    if (n > 0) {
+        HIPTRY(ctx, hipMemcpy(s->types.p, types, sizeof(int32_t) * n, hipMemcpyHostToDevice), "copying types");
+        HIPTRY(ctx, hipMemcpy(s->times.p, times, s->ts_bytes() * n, hipMemcpyHostToDevice), "copying times");
+    }
+    HIPTRY(ctx, build_type_index(*s, ctx->c.stream), "building the per-type index");
+    const int32_t id = ctx->c.next_id++;
+    ctx->c.streams[id] = std::move(s);
+    *stream_id = id;
+    return EPI_OK;
+}
+
+epi_status epi_load_stream_device(epi_ctx *ctx, const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
+                                  int32_t K, void *hip_stream, int32_t *stream_id) {
+    if (!ctx || !stream_id) return fail(ctx, EPI_EINVAL, "null argument");
+    std::string msg;
+    // shape checks only; the element checks run on the device
+    epi_status v = check_stream(nullptr, nullptr, 0, ts_kind, K, &msg);
+    if (v != EPI_OK) return fail(ctx, v, "%s", msg.c_str());
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(ctx, EPI_ESIZE, "n must be in [0, 2^31)");
+    if (n > 0 && (!d_types || !d_times)) return fail(ctx, EPI_EINVAL, "null stream pointer");
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    auto s = std::make_unique<Stream>();
+    s->n = n;
+    s->K = K;
+    s->ts_kind = ts_kind;
+    HIPTRY(ctx, s->types.alloc(sizeof(int32_t) * n), "allocating stream types");
+    HIPTRY(ctx, s->times.alloc(s->ts_bytes() * n), "allocating stream times");
+    if (n > 0) {
+        HIPTRY(ctx, hipMemcpyAsync(s->types.p, d_types, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st),
+               "copying types");
+        HIPTRY(ctx, hipMemcpyAsync(s->times.p, d_times, s->ts_bytes() * n, hipMemcpyDeviceToDevice, st),
+               "copying times");
+        HIPTRY(ctx, validate_stream_device(s->types.as<int32_t>(), s->times.p, n, ts_kind, K,
+                                           ctx->c.flags.as<int32_t>(), st),
+               "validating the stream");
+        HIPTRY(ctx, hipStreamSynchronize(st), "validating the stream");
+        epi_status f = check_flags(ctx);
+        if (f != EPI_OK) return f;
+        int64_t ends[2] = {0, 0};
+        if (ts_kind == EPI_TS_I64) {
+            HIPTRY(ctx, hipMemcpy(&ends[0], s->times.as<int64_t>(), 8, hipMemcpyDeviceToHost), "reading times");
+            HIPTRY(ctx, hipMemcpy(&ends[1], s->times.as<int64_t>() + (n - 1), 8, hipMemcpyDeviceToHost),
+                   "reading times");
+        } else {
+            int32_t a = 0, b = 0;
+            HIPTRY(ctx, hipMemcpy(&a, s->times.as<int32_t>(), 4, hipMemcpyDeviceToHost), "reading times");
+            HIPTRY(ctx, hipMemcpy(&b, s->times.as<int32_t>() + (n - 1), 4, hipMemcpyDeviceToHost), "reading times");
+            ends[0] = a;
+            ends[1] = b;
+        }
+        s->tmin = ends[0];
+        s->tmax = ends[1];
+    }
+    HIPTRY(ctx, build_type_index(*s, st), "building the per-type index");
+    const int32_t id = ctx->c.next_id++;
+    ctx->c.streams[id] = std::move(s);
+    *stream_id = id;
+    return EPI_OK;
+}
+
+epi_status epi_stream_info(epi_ctx *ctx, int32_t stream_id, int64_t *n, int32_t *K, int *ts_kind) {
+    if (!ctx) return EPI_EINVAL;
+    Stream *s = find_stream(ctx, stream_id);
+    if (!s) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
+    if (n) *n = s->n;
+    if (K) *K = s->K;
+    if (ts_kind) *ts_kind = s->ts_kind;
+    return EPI_OK;
+}
+
+epi_status epi_read_type_index(epi_ctx *ctx, int32_t stream_id, int32_t *off, void *ts_by_type) {
+    if (!ctx || !off || !ts_by_type) return fail(ctx, EPI_EINVAL, "null argument");
+    Stream *s = find_stream(ctx, stream_id);
+    if (!s) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
+    HIPTRY(ctx, hipStreamSynchronize(ctx->c.stream), "sync");
+    HIPTRY(ctx, hipMemcpy(off, s->type_off.p, sizeof(int32_t) * (s->K + 1), hipMemcpyDeviceToHost), "copy");
+    if (s->n > 0)
+        HIPTRY(ctx, hipMemcpy(ts_by_type, s->ts_by_type.p, s->ts_bytes() * s->n, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_release_stream(epi_ctx *ctx, int32_t stream_id) {
+    if (!ctx) return EPI_EINVAL;
+    if (!find_stream(ctx, stream_id)) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
+    for (auto &kv : ctx->c.sets)
+        if (kv.second->stream_id == stream_id)
+            return fail(ctx, EPI_ESTATE, "stream %d still has candidate set %d", stream_id, kv.first);
+    (void)hipDeviceSynchronize();
+    ctx->c.streams.erase(stream_id);
+    return EPI_OK;
+}
+
+epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, const uint8_t *N, const int32_t *types,
+                                 const int64_t *lo, const int64_t *hi, int32_t *set_id) {
+    if (!ctx || !set_id) return fail(ctx, EPI_EINVAL, "null argument");
+    Stream *s = find_stream(ctx, stream_id);
+    if (!s) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
+    std::string msg;
+    epi_status v = check_candidates(m, N, types, lo, hi, s->K, s->ts_kind, &msg);
+    if (v != EPI_OK) return fail(ctx, v, "%s", msg.c_str());
+    // times +- span must stay strictly inside the timestamp type
+    const int64_t tlo = s->ts_kind == EPI_TS_I64 ? INT64_MIN : INT32_MIN;
+    const int64_t thi = s->ts_kind == EPI_TS_I64 ? INT64_MAX : INT32_MAX;
+    if (s->n > 0) {
+        for (int64_t c = 0; c < m; ++c) {
+            const int64_t sp = span_of(N[c], hi + c * 7);
+            if (s->tmax > thi - 1 - sp || s->tmin < tlo + 1 + sp)
+                return fail(ctx, EPI_EOVERFLOW, "candidate %lld: stream times +- its span leave the timestamp type",
+                            (long long)c);
+        }
+    }
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    auto cs = std::make_unique<CandSet>();
+    cs->stream_id = stream_id;
+    cs->m = m;
+    hipError_t e = s->ts_kind == EPI_TS_I64 ? upload_candidates<int64_t>(*cs, m, N, types, lo, hi, ctx->c.stream)
+                                            : upload_candidates<int32_t>(*cs, m, N, types, lo, hi, ctx->c.stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "uploading candidates");
+    const int32_t id = ctx->c.next_id++;
+    ctx->c.sets[id] = std::move(cs);
+    *set_id = id;
+    return EPI_OK;
+}
+
+epi_status epi_release_set(epi_ctx *ctx, int32_t set_id) {
+    if (!ctx) return EPI_EINVAL;
+    if (!find_set(ctx, set_id)) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    (void)hipDeviceSynchronize();
+    ctx->c.sets.erase(set_id);
+    return EPI_OK;
+}
+
+epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched, void *hip_stream) {
+    if (!ctx) return EPI_EINVAL;
+    if (k < 0 || (k > 0 && !set_ids)) return fail(ctx, EPI_EINVAL, "bad set list");
+    if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED) return fail(ctx, EPI_EINVAL, "unknown mode %d", mode);
+    if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED) return fail(ctx, EPI_EINVAL, "unknown sched %d", sched);
+    if (mode == EPI_MODE_BATCHED) return fail(ctx, EPI_EINVAL, "batched mode is not available in this build");
+    for (int32_t i = 0; i < k; ++i)
+        if (!find_set(ctx, set_ids[i])) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    for (int32_t i = 0; i < k; ++i) {
+        CandSet *cs = find_set(ctx, set_ids[i]);
+        Stream *s = find_stream(ctx, cs->stream_id);
+        HIPTRY(ctx, launch_count(*s, *cs, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "launching the count");
+        cs->counted = true;
+    }
+    return EPI_OK;
+}
+
+epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
+    if (!ctx) return EPI_EINVAL;
+    switch (option) {
+        case EPI_OPT_SEGMENTS:
+            if (value < 0) return fail(ctx, EPI_EINVAL, "segments must be >= 0");
+            ctx->c.opt.segments = value;
+            return EPI_OK;
+        case EPI_OPT_LANES:
+            if (value != 0 && value != 64 && value != 128 && value != 256)
+                return fail(ctx, EPI_EINVAL, "lanes must be 0, 64, 128 or 256");
+            ctx->c.opt.lanes = (int)value;
+            return EPI_OK;
+        case EPI_OPT_TARGET_LANES:
+            if (value < 1) return fail(ctx, EPI_EINVAL, "target lanes must be >= 1");
+            ctx->c.opt.target_lanes = value;
+            return EPI_OK;
+        default:
+            return fail(ctx, EPI_EINVAL, "unknown option %d", option);
+    }
+}
+
+epi_status epi_sync(epi_ctx *ctx) {
+    if (!ctx) return EPI_EINVAL;
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    HIPTRY(ctx, hipDeviceSynchronize(), "synchronising");
+    return check_flags(ctx);
+}
+
+epi_status epi_read_counts(epi_ctx *ctx, int32_t set_id, int32_t *counts, int64_t m) {
+    if (!ctx) return EPI_EINVAL;
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (!cs->counted) return fail(ctx, EPI_ESTATE, "set %d has not been counted", set_id);
+    if (m != cs->m) return fail(ctx, EPI_EINVAL, "set %d holds %lld candidates, not %lld", set_id,
+                                (long long)cs->m, (long long)m);
+    if (m > 0 && !counts) return fail(ctx, EPI_EINVAL, "null counts");
+    epi_status f = epi_sync(ctx);
+    if (f != EPI_OK) return f;
+    if (m > 0) HIPTRY(ctx, hipMemcpy(counts, cs->counts.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_counts_device(epi_ctx *ctx, int32_t set_id, const int32_t **d_counts) {
+    if (!ctx || !d_counts) return fail(ctx, EPI_EINVAL, "null argument");
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    *d_counts = cs->counts.as<int32_t>();
+    return EPI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Internal declarations of the episode-counting engine (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <limits>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/epi.h"
+
+namespace epi {
+
+constexpr int kMaxN = EPI_MAX_N;
+constexpr int kMaxK = 4096;        // LDS histogram bound of the index build
+constexpr int kMaxQueue = 16;      // deepest merged-interval ring (LDS) per node
+constexpr int kTile = 2048;        // events per stream tile
+
+// Device error flags (int32 each), set by kernels with atomicOr / atomicAdd.
+enum DevFlag { kFlagQueueOverflow = 0, kFlagUnsorted = 1, kFlagBadType = 2, kFlagBadTime = 3, kNumFlags = 4 };
+
+template <typename T>
+struct TsLimits {
+    static constexpr T lo() { return std::numeric_limits<T>::min(); }
+    static constexpr T hi() { return std::numeric_limits<T>::max(); }
+};
+
+// Owning device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b) {
+        reset();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = b;
+        return hipSuccess;
+    }
+    template <typename U>
+    U *as() const {
+        return static_cast<U *>(p);
+    }
+};
+
+struct Stream {
+    int64_t n = 0;
+    int32_t K = 0;
+    int ts_kind = EPI_TS_I32;
+    int64_t tmin = 0, tmax = 0;
+    DevBuf types;       // int32[n]
+    DevBuf times;       // T[n]
+    DevBuf type_off;    // int32[K+1]
+    DevBuf ts_by_type;  // T[n], grouped by type, each group in time order
+    // Tile-major copy of the index: tile b holds stream positions
+    // [b*kTile, (b+1)*kTile); inside a tile the events are grouped by type
+    // (each group in time order) starting at tile_loff[b*(K+1) + type].
+    int64_t B = 0;      // number of tiles
+    DevBuf tiled_ts;    // T[B*kTile] (the last tile is padded)
+    DevBuf tile_loff;   // uint16[B*(K+1)]
+    DevBuf tile_t0;     // T[B+1]: time of each tile's first event; [B] = type maximum
+    std::vector<int32_t> h_off;  // host copy of type_off
+    std::vector<int64_t> h_tile_t0;  // host copy of tile_t0 (widened)
+    size_t ts_bytes() const { return ts_kind == EPI_TS_I64 ? 8 : 4; }
+};
+
+// Candidates of one launch class: same episode size N and queue capacity Q.
+struct Group {
+    int N = 0;
+    int Q = 0;
+    int64_t begin = 0, end = 0;  // slots [begin, end) of the grouped layout
+};
+
+struct CandSet {
+    int32_t stream_id = 0;
+    int64_t m = 0;
+    // Grouped (launch-class-major) structure-of-arrays on the device; slot s
+    // holds submission index orig[s].
+    DevBuf types;   // int32 [8][m]
+    DevBuf lo, hi;  // T [7][m]
+    DevBuf orig;    // int32 [m]
+    DevBuf counts;  // int32 [m], submission order
+    DevBuf scratch; // per-segment speculative records of the last count
+    std::vector<Group> groups;
+    bool counted = false;
+};
+
+// Launch options (epi_set_option).
+struct CountOptions {
+    int64_t segments = 0;          // 0: automatic; k >= 1: k segments per launch class
+    int lanes = 0;                 // 0: automatic; else lanes per workgroup (64, 128 or 256)
+    int64_t target_lanes = 262144; // automatic segmentation aims at this many (candidate, segment) lanes
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::map<int32_t, std::unique_ptr<Stream>> streams;
+    std::map<int32_t, std::unique_ptr<CandSet>> sets;
+    int32_t next_id = 1;
+    DevBuf flags;  // int32[kNumFlags]
+    CountOptions opt;
+};
+
+// Queue capacity bound of one constraint (lo, hi]: at most
+// 1 + floor(hi / (hi - lo + 1)) disjoint merged acceptance intervals can be
+// live at once.
+inline int64_t queue_bound(int64_t lo, int64_t hi) {
+    return 1 + hi / (hi - lo + 1);
+}
+
+// ---- launchers -------------------------------------------------------------
+hipError_t build_type_index(Stream &s, hipStream_t st);
+hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
+                                  int32_t K, int32_t *d_flags, hipStream_t st);
+hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st);
+
+}  // namespace epi

@@ -1,0 +1,245 @@
+"""Thin ctypes binding of ``libepi.so`` (the C ABI declared in include/epi.h).
+
+Every function here only marshals arguments: host arrays are numpy arrays,
+device arrays are torch tensors on the ROCm device (torch supplies device
+memory and streams), and every count is computed by the library's HIP
+kernels.  A missing library is an error, never a fallback.
+
+Status codes other than EPI_OK raise ``EpiError`` carrying the code and the
+context's last error message.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libepi.so")
+
+EPI_OK = 0
+EPI_EINVAL = -1
+EPI_EUNSORTED = -2
+EPI_ETYPE = -3
+EPI_EINTERVAL = -4
+EPI_ESIZE = -5
+EPI_EREPEAT = -6
+EPI_EOVERFLOW = -7
+EPI_ENOMEM = -8
+EPI_EDEVICE = -9
+EPI_ESTATE = -10
+EPI_TS_I32 = 0
+EPI_TS_I64 = 1
+EPI_MODE_PLAIN = 0
+EPI_MODE_BATCHED = 1
+EPI_SCHED_RR = 0
+EPI_SCHED_LEARNED = 1
+
+EXPORTS = [
+    "epi_create", "epi_destroy", "epi_last_error", "epi_status_string",
+    "epi_validate_stream", "epi_validate_candidates",
+    "epi_load_stream", "epi_load_stream_device", "epi_stream_info", "epi_read_type_index",
+    "epi_release_stream", "epi_submit_candidates", "epi_release_set",
+    "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device",
+]
+EPI_OPT_SEGMENTS = 1
+EPI_OPT_LANES = 2
+EPI_OPT_TARGET_LANES = 3
+
+
+class EpiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{status_string(code)} ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+INT = ctypes.c_int
+
+
+def lib():
+    """Load libepi.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_0905_2203_amd/build.py")
+        # torch bundles its own libamdhip64 (same soname as the system one).
+        # Loading torch first makes libepi bind to that copy, so the process
+        # holds a single HIP runtime and device pointers are shared with torch.
+        import torch  # noqa: F401
+
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "epi_create": ([INT, ctypes.POINTER(P)], I32),
+            "epi_destroy": ([P], None),
+            "epi_last_error": ([P], ctypes.c_char_p),
+            "epi_status_string": ([I32], ctypes.c_char_p),
+            "epi_validate_stream": ([P, P, I64, INT, I32], I32),
+            "epi_validate_candidates": ([I64, P, P, P, P, I32, INT], I32),
+            "epi_load_stream": ([P, P, P, I64, INT, I32, ctypes.POINTER(I32)], I32),
+            "epi_load_stream_device": ([P, P, P, I64, INT, I32, P, ctypes.POINTER(I32)], I32),
+            "epi_stream_info": ([P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(INT)], I32),
+            "epi_read_type_index": ([P, I32, P, P], I32),
+            "epi_release_stream": ([P, I32], I32),
+            "epi_submit_candidates": ([P, I32, I64, P, P, P, P, ctypes.POINTER(I32)], I32),
+            "epi_release_set": ([P, I32], I32),
+            "epi_count": ([P, P, I32, INT, INT, P], I32),
+            "epi_sync": ([P], I32),
+            "epi_set_option": ([P, INT, I64], I32),
+            "epi_read_counts": ([P, I32, P, I64], I32),
+            "epi_counts_device": ([P, I32, ctypes.POINTER(P)], I32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().epi_status_string(int(code)).decode()
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(P)
+    return P(a.data_ptr())  # torch tensor
+
+
+def _ts_kind(times) -> int:
+    dt = str(times.dtype)
+    if dt.endswith("int64"):
+        return EPI_TS_I64
+    if dt.endswith("int32"):
+        return EPI_TS_I32
+    raise TypeError("times must be int32 or int64")
+
+
+def epi_validate_stream(types: np.ndarray, times: np.ndarray, K: int) -> int:
+    types = np.ascontiguousarray(types, np.int32)
+    times = np.ascontiguousarray(times)
+    return int(lib().epi_validate_stream(_ptr(types), _ptr(times), types.size, _ts_kind(times), int(K)))
+
+
+def _cand_arrays(c):
+    N = np.ascontiguousarray(c["N"], np.uint8)
+    ty = np.ascontiguousarray(c["types"], np.int32)
+    lo = np.ascontiguousarray(c["lo"], np.int64)
+    hi = np.ascontiguousarray(c["hi"], np.int64)
+    m = N.size
+    if ty.shape != (m, 8) or lo.shape != (m, 7) or hi.shape != (m, 7):
+        raise ValueError("candidate arrays must be N[m], types[m,8], lo[m,7], hi[m,7]")
+    return N, ty, lo, hi
+
+
+def epi_validate_candidates(cands, K: int, ts_kind: int) -> int:
+    N, ty, lo, hi = _cand_arrays(cands)
+    return int(lib().epi_validate_candidates(N.size, _ptr(N), _ptr(ty), _ptr(lo), _ptr(hi), int(K), int(ts_kind)))
+
+
+class Context:
+    """An epi_ctx bound to one HIP device.  Methods are the ABI calls."""
+
+    def __init__(self, device: int = 0):
+        h = P()
+        rc = lib().epi_create(int(device), ctypes.byref(h))
+        if rc != EPI_OK:
+            raise EpiError(rc, lib().epi_last_error(None).decode())
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            lib().epi_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != EPI_OK:
+            raise EpiError(rc, lib().epi_last_error(self.h).decode())
+
+    def last_error(self) -> str:
+        return lib().epi_last_error(self.h).decode()
+
+    # streams -------------------------------------------------------------
+    def epi_load_stream(self, types: np.ndarray, times: np.ndarray, K: int) -> int:
+        types = np.ascontiguousarray(types, np.int32)
+        times = np.ascontiguousarray(times)
+        sid = I32()
+        self._check(lib().epi_load_stream(self.h, _ptr(types), _ptr(times), types.size, _ts_kind(times),
+                                          int(K), ctypes.byref(sid)))
+        return sid.value
+
+    def epi_load_stream_device(self, d_types, d_times, K: int, hip_stream=None) -> int:
+        """d_types / d_times: contiguous torch tensors on the device."""
+        sid = I32()
+        st = None if hip_stream is None else P(int(hip_stream))
+        self._check(lib().epi_load_stream_device(self.h, _ptr(d_types), _ptr(d_times), int(d_types.numel()),
+                                                 _ts_kind(d_times), int(K), st, ctypes.byref(sid)))
+        return sid.value
+
+    def epi_stream_info(self, sid: int):
+        n, K, kind = I64(), I32(), INT()
+        self._check(lib().epi_stream_info(self.h, int(sid), ctypes.byref(n), ctypes.byref(K), ctypes.byref(kind)))
+        return n.value, K.value, kind.value
+
+    def epi_read_type_index(self, sid: int):
+        n, K, kind = self.epi_stream_info(sid)
+        off = np.zeros(K + 1, np.int32)
+        ts = np.zeros(n, np.int64 if kind == EPI_TS_I64 else np.int32)
+        self._check(lib().epi_read_type_index(self.h, int(sid), _ptr(off), _ptr(ts)))
+        return off, ts
+
+    def epi_release_stream(self, sid: int):
+        self._check(lib().epi_release_stream(self.h, int(sid)))
+
+    # candidates ------------------------------------------------------------
+    def epi_submit_candidates(self, sid: int, cands) -> int:
+        N, ty, lo, hi = _cand_arrays(cands)
+        out = I32()
+        self._check(lib().epi_submit_candidates(self.h, int(sid), N.size, _ptr(N), _ptr(ty), _ptr(lo), _ptr(hi),
+                                                ctypes.byref(out)))
+        return out.value
+
+    def epi_release_set(self, set_id: int):
+        self._check(lib().epi_release_set(self.h, int(set_id)))
+
+    # counting ----------------------------------------------------------------
+    def epi_count(self, set_ids, mode: int = EPI_MODE_PLAIN, sched: int = EPI_SCHED_RR, hip_stream=None):
+        ids = np.ascontiguousarray(np.atleast_1d(np.asarray(set_ids, np.int32)))
+        st = None if hip_stream is None else P(int(hip_stream))
+        self._check(lib().epi_count(self.h, _ptr(ids), ids.size, int(mode), int(sched), st))
+
+    def epi_set_option(self, option: int, value: int):
+        self._check(lib().epi_set_option(self.h, int(option), int(value)))
+
+    def epi_sync(self):
+        self._check(lib().epi_sync(self.h))
+
+    def epi_read_counts(self, set_id: int, m: int) -> np.ndarray:
+        out = np.zeros(int(m), np.int32)
+        self._check(lib().epi_read_counts(self.h, int(set_id), _ptr(out), int(m)))
+        return out
+
+    def epi_counts_device(self, set_id: int) -> int:
+        p = P()
+        self._check(lib().epi_counts_device(self.h, int(set_id), ctypes.byref(p)))
+        return p.value or 0
