@@ -181,6 +181,45 @@ epi_status epi_read_counts(epi_ctx *ctx, int32_t set_id, int32_t *counts, int64_
  * complete. */
 epi_status epi_counts_device(epi_ctx *ctx, int32_t set_id, const int32_t **d_counts);
 
+/* ------------------------------------------------------------------------
+ * Level-wise discovery (Sec. II-C: candidates of size N are generated from
+ * the frequent episodes of size N-1 and counted in one pass per level; an
+ * episode is frequent when its count is greater than the threshold)
+ * ---------------------------------------------------------------------- */
+
+/* Mine the loaded stream level by level, up to episodes of max_size nodes
+ * (1..8), with inter-event intervals drawn from a menu of n_menu (1..255)
+ * intervals (menu_lo[i], menu_hi[i]].
+ *   level 1: every type as a 1-node episode;
+ *   level 2: ordered pairs of distinct frequent types x every menu interval;
+ *   level N+1: alpha + (last node of beta) for frequent N-node alpha, beta
+ *     whose nodes 2..N of alpha equal nodes 1..N-1 of beta, intervals
+ *     included, when the new type is not alpha's first.
+ * Stops early when a level has no frequent episode.  Synchronous: returns
+ * when every level is counted; *mine_id receives a handle.
+ * Errors: EPI_EINTERVAL / EPI_EOVERFLOW for a bad menu, EPI_ESIZE for a bad
+ * max_size, plus those of counting. */
+epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64_t *menu_lo,
+                    const int64_t *menu_hi, int32_t max_size, int64_t threshold, void *hip_stream,
+                    int32_t *mine_id);
+
+/* Number of levels counted by a mining run (level numbers are 1..n). */
+epi_status epi_mine_levels(epi_ctx *ctx, int32_t mine_id, int32_t *n_levels);
+
+/* Candidates and frequent episodes of a level; times_ms (may be null)
+ * receives 3 doubles: candidate generation, count incl. transfers, and
+ * counting kernels alone (HIP events), in milliseconds. */
+epi_status epi_mine_level_info(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_t *n_candidates,
+                               int64_t *n_frequent, double *times_ms);
+
+/* Copy a level's candidates (frequent_only = 0) or frequent episodes (1) with
+ * their counts, in the layout of epi_submit_candidates; m must equal the
+ * level's candidate or frequent count.  Unused type slots are -1. */
+epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequent_only, int64_t m,
+                         uint8_t *N, int32_t *types, int64_t *lo, int64_t *hi, int32_t *counts);
+
+epi_status epi_mine_release(epi_ctx *ctx, int32_t mine_id);
+
 #ifdef __cplusplus
 }
 #endif

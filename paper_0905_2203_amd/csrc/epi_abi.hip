@@ -2,6 +2,7 @@
 // candidate ingest, counting and readback.  Kernels live in epi_index.hip
 // (per-type index) and epi_tiled.hip (counting and reconciliation).
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -275,6 +276,7 @@ void epi_destroy(epi_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->c.device);
     (void)hipDeviceSynchronize();
+    ctx->c.mines.clear();
     ctx->c.sets.clear();
     ctx->c.streams.clear();
     ctx->c.flags.reset();
@@ -518,6 +520,116 @@ epi_status epi_read_counts(epi_ctx *ctx, int32_t set_id, int32_t *counts, int64_
     epi_status f = epi_sync(ctx);
     if (f != EPI_OK) return f;
     if (m > 0) HIPTRY(ctx, hipMemcpy(counts, cs->counts.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64_t *menu_lo, const int64_t *menu_hi,
+                    int32_t max_size, int64_t threshold, void *hip_stream, int32_t *mine_id) {
+    if (!ctx || !mine_id) return fail(ctx, EPI_EINVAL, "null argument");
+    Stream *s = find_stream(ctx, stream_id);
+    if (!s) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
+    if (n_menu < 1 || n_menu > 255 || !menu_lo || !menu_hi)
+        return fail(ctx, EPI_EINVAL, "the interval menu must hold 1..255 intervals");
+    if (max_size < 1 || max_size > kMaxN) return fail(ctx, EPI_ESIZE, "max_size must be in 1..8");
+    int64_t hmax = 0;
+    for (int i = 0; i < n_menu; ++i) {
+        if (!(0 <= menu_lo[i] && menu_lo[i] < menu_hi[i]))
+            return fail(ctx, EPI_EINTERVAL, "menu interval %d must satisfy 0 <= lo < hi", i);
+        if (queue_bound(menu_lo[i], menu_hi[i]) > kMaxQueue)
+            return fail(ctx, EPI_EINTERVAL, "menu interval %d exceeds the supported queue depth", i);
+        hmax = std::max(hmax, menu_hi[i]);
+    }
+    const int64_t tlo = s->ts_kind == EPI_TS_I64 ? INT64_MIN : INT32_MIN;
+    const int64_t thi = s->ts_kind == EPI_TS_I64 ? INT64_MAX : INT32_MAX;
+    if (hmax > (thi / 2) / kMaxN) return fail(ctx, EPI_EOVERFLOW, "menu interval too long for the timestamp type");
+    const int64_t span = hmax * (max_size - 1);
+    if (s->n > 0 && (s->tmax > thi - 1 - span || s->tmin < tlo + 1 + span))
+        return fail(ctx, EPI_EOVERFLOW, "stream times +- the longest span leave the timestamp type");
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    auto mn = std::make_unique<Mine>();
+    mn->stream_id = stream_id;
+    mn->menu_lo.assign(menu_lo, menu_lo + n_menu);
+    mn->menu_hi.assign(menu_hi, menu_hi + n_menu);
+    mn->threshold = threshold;
+    for (int N = 1; N <= max_size; ++N) {
+        MineLevel L;
+        auto t0 = std::chrono::steady_clock::now();
+        if (N == 1) gen_level1(s->K, L);
+        else if (N == 2) gen_level2(mn->levels.back(), n_menu, L);
+        else gen_join(mn->levels.back(), L);
+        L.gen_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (L.m == 0) break;
+        HIPTRY(ctx, count_mine_level(*s, *mn, L, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "counting a level");
+        epi_status f = check_flags(ctx);
+        if (f != EPI_OK) return f;
+        select_frequent(L, threshold);
+        const bool none = L.freq.empty();
+        mn->levels.push_back(std::move(L));
+        if (none) break;
+    }
+    const int32_t id = ctx->c.next_id++;
+    ctx->c.mines[id] = std::move(mn);
+    *mine_id = id;
+    return EPI_OK;
+}
+
+epi_status epi_mine_levels(epi_ctx *ctx, int32_t mine_id, int32_t *n_levels) {
+    if (!ctx || !n_levels) return fail(ctx, EPI_EINVAL, "null argument");
+    auto it = ctx->c.mines.find(mine_id);
+    if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
+    *n_levels = (int32_t)it->second->levels.size();
+    return EPI_OK;
+}
+
+epi_status epi_mine_level_info(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_t *n_candidates,
+                               int64_t *n_frequent, double *times_ms) {
+    if (!ctx) return EPI_EINVAL;
+    auto it = ctx->c.mines.find(mine_id);
+    if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
+    const auto &lv = it->second->levels;
+    if (level < 1 || level > (int32_t)lv.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
+    const MineLevel &L = lv[level - 1];
+    if (n_candidates) *n_candidates = L.m;
+    if (n_frequent) *n_frequent = (int64_t)L.freq.size();
+    if (times_ms) {
+        times_ms[0] = L.gen_ms;
+        times_ms[1] = L.count_ms;
+        times_ms[2] = L.kernel_ms;
+    }
+    return EPI_OK;
+}
+
+epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequent_only, int64_t m, uint8_t *N,
+                         int32_t *types, int64_t *lo, int64_t *hi, int32_t *counts) {
+    if (!ctx) return EPI_EINVAL;
+    auto it = ctx->c.mines.find(mine_id);
+    if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
+    const Mine &mn = *it->second;
+    if (level < 1 || level > (int32_t)mn.levels.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
+    const MineLevel &L = mn.levels[level - 1];
+    const int64_t want = frequent_only ? (int64_t)L.freq.size() : L.m;
+    if (m != want) return fail(ctx, EPI_EINVAL, "level %d has %lld entries, not %lld", level, (long long)want,
+                               (long long)m);
+    if (m > 0 && (!N || !types || !lo || !hi || !counts)) return fail(ctx, EPI_EINVAL, "null output");
+    for (int64_t r = 0; r < m; ++r) {
+        const int64_t i = frequent_only ? L.freq[r] : r;
+        N[r] = (uint8_t)L.N;
+        for (int k = 0; k < kMaxN; ++k) types[r * 8 + k] = k < L.N ? L.types[(size_t)k * L.m + i] : -1;
+        for (int k = 0; k < kMaxN - 1; ++k) {
+            const bool live = k + 1 < L.N;
+            const int id = live ? L.iv[(size_t)k * L.m + i] : 0;
+            lo[r * 7 + k] = live ? mn.menu_lo[id] : 0;
+            hi[r * 7 + k] = live ? mn.menu_hi[id] : 0;
+        }
+        counts[r] = L.counts[i];
+    }
+    return EPI_OK;
+}
+
+epi_status epi_mine_release(epi_ctx *ctx, int32_t mine_id) {
+    if (!ctx) return EPI_EINVAL;
+    if (!ctx->c.mines.erase(mine_id)) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
     return EPI_OK;
 }
 

@@ -96,6 +96,11 @@ struct CandSet {
     DevBuf orig;    // int32 [m]
     DevBuf counts;  // int32 [m], submission order
     DevBuf scratch; // per-segment speculative records of the last count
+    // Compact layout (level-wise mining): one episode size, types uint16
+    // [N][m], interval ids uint8 [N-1][m] into a menu of (lo, hi) pairs
+    // (T[2*n_menu]); slots are in submission order (orig unused).
+    bool compact = false;
+    DevBuf t16, iv, menu;
     std::vector<Group> groups;
     bool counted = false;
 };
@@ -107,12 +112,32 @@ struct CountOptions {
     int64_t target_lanes = 262144; // automatic segmentation aims at this many (candidate, segment) lanes
 };
 
+// One level of a level-wise discovery run: candidates of size N in
+// structure-of-arrays form (types[k*m + i], interval ids iv[k*m + i]).
+struct MineLevel {
+    int N = 0;
+    int64_t m = 0;
+    std::vector<uint16_t> types;  // [N][m]
+    std::vector<uint8_t> iv;      // [N-1][m]
+    std::vector<int32_t> counts;  // [m]
+    std::vector<int64_t> freq;    // indices with count > threshold
+    double gen_ms = 0, count_ms = 0, kernel_ms = 0;
+};
+
+struct Mine {
+    int32_t stream_id = 0;
+    std::vector<int64_t> menu_lo, menu_hi;
+    int64_t threshold = 0;
+    std::vector<MineLevel> levels;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
     std::map<int32_t, std::unique_ptr<Stream>> streams;
     std::map<int32_t, std::unique_ptr<CandSet>> sets;
+    std::map<int32_t, std::unique_ptr<Mine>> mines;
     int32_t next_id = 1;
     DevBuf flags;  // int32[kNumFlags]
     CountOptions opt;
@@ -130,5 +155,15 @@ hipError_t build_type_index(Stream &s, hipStream_t st);
 hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
                                   int32_t K, int32_t *d_flags, hipStream_t st);
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st);
+// Count every candidate of one mining level on the device (compact layout);
+// fills L.counts and the timing fields.
+hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const CountOptions &opt, int32_t *d_flags,
+                            hipStream_t st);
+int queue_class_of(int64_t bound);
+// Candidate generation of level-wise discovery (epi_mine.hip).
+void gen_level1(int32_t K, MineLevel &L);
+void gen_level2(const MineLevel &F1, int n_menu, MineLevel &L);
+void gen_join(const MineLevel &prev, MineLevel &L);
+void select_frequent(MineLevel &L, int64_t threshold);
 
 }  // namespace epi

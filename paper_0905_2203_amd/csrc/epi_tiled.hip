@@ -50,6 +50,9 @@ struct CountArgs {
     const int32_t *ctypes;
     const T *clo;
     const T *chi;
+    const uint16_t *t16;  // compact layout (when non-null): types
+    const uint8_t *iv;    //   interval ids into menu
+    const T *menu;        //   (lo, hi) pairs
     int64_t m;
     int64_t begin;  // first slot of the group
     int64_t G;      // group size
@@ -68,6 +71,20 @@ struct CountArgs {
 template <typename T, int N>
 __device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N> &f, int64_t slot, int32_t *ty) {
     T H = 0;
+    if (a.t16) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) ty[k] = a.t16[(int64_t)k * a.m + slot];
+#pragma unroll
+        for (int k = 0; k + 1 < N; ++k) {
+            const int id = a.iv[(int64_t)k * a.m + slot];
+            Pair<T> v;
+            v.s = a.menu[2 * id];
+            v.e = a.menu[2 * id + 1];
+            f.lohi[k * f.W + f.lane] = v;
+            H += v.e;
+        }
+        return H;
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) ty[k] = a.ctypes[(int64_t)k * a.m + slot];
 #pragma unroll
@@ -189,7 +206,7 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
     }
     if (!active) return;
     if (a.P == 1) {
-        a.counts[a.orig[slot]] = cnt;
+        a.counts[a.orig ? a.orig[slot] : slot] = cnt;
     } else {
         a.rec_cnt[(int64_t)p * a.G + s] = cnt;
         a.rec_last[(int64_t)p * a.G + s] = last;
@@ -198,7 +215,7 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
 
 __global__ void k_zero_counts(const int32_t *__restrict__ orig, int64_t G, int32_t *__restrict__ counts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < G) counts[orig[i]] = 0;
+    if (i < G) counts[orig ? orig[i] : i] = 0;
 }
 
 // first index in [lo, hi) with ts[index] > x
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
             tau = flast;
         }
     }
-    a.counts[a.orig[slot]] = (int32_t)total;
+    a.counts[a.orig ? a.orig[slot] : slot] = (int32_t)total;
 }
 
 template <typename T>
@@ -399,8 +416,8 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         const int64_t G = g.end - g.begin;
         if (G <= 0) continue;
         if (s.n == 0) {  // no events: every count is zero
-            k_zero_counts<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(c.orig.as<int32_t>() + g.begin, G,
-                                                                      c.counts.as<int32_t>());
+            k_zero_counts<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(
+                c.compact ? nullptr : c.orig.as<int32_t>() + g.begin, G, c.counts.as<int32_t>() + (c.compact ? g.begin : 0));
             if ((e = hipGetLastError()) != hipSuccess) return e;
             continue;
         }
@@ -437,13 +454,16 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.ctypes = c.types.as<int32_t>();
         a.clo = c.lo.as<T>();
         a.chi = c.hi.as<T>();
+        a.t16 = c.compact ? c.t16.as<uint16_t>() : nullptr;
+        a.iv = c.compact ? c.iv.as<uint8_t>() : nullptr;
+        a.menu = c.compact ? c.menu.as<T>() : nullptr;
         a.m = c.m;
         a.begin = g.begin;
         a.G = G;
         a.Q = g.Q;
         a.P = (int32_t)P;
         a.S = S;
-        a.orig = c.orig.as<int32_t>();
+        a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
         a.counts = c.counts.as<int32_t>();
         a.flags = d_flags;
         a.off_qse = L.off_qse;

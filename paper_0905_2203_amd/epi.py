@@ -42,6 +42,7 @@ EXPORTS = [
     "epi_load_stream", "epi_load_stream_device", "epi_stream_info", "epi_read_type_index",
     "epi_release_stream", "epi_submit_candidates", "epi_release_set",
     "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device",
+    "epi_mine", "epi_mine_levels", "epi_mine_level_info", "epi_mine_read", "epi_mine_release",
 ]
 EPI_OPT_SEGMENTS = 1
 EPI_OPT_LANES = 2
@@ -92,6 +93,11 @@ def lib():
             "epi_set_option": ([P, INT, I64], I32),
             "epi_read_counts": ([P, I32, P, I64], I32),
             "epi_counts_device": ([P, I32, ctypes.POINTER(P)], I32),
+            "epi_mine": ([P, I32, I32, P, P, I32, I64, P, ctypes.POINTER(I32)], I32),
+            "epi_mine_levels": ([P, I32, ctypes.POINTER(I32)], I32),
+            "epi_mine_level_info": ([P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
+            "epi_mine_read": ([P, I32, I32, INT, I64, P, P, P, P, P], I32),
+            "epi_mine_release": ([P, I32], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -243,3 +249,41 @@ class Context:
         p = P()
         self._check(lib().epi_counts_device(self.h, int(set_id), ctypes.byref(p)))
         return p.value or 0
+
+    # level-wise discovery ------------------------------------------------------
+    def epi_mine(self, sid: int, menu, max_size: int, threshold: int, hip_stream=None) -> int:
+        """menu: sequence of (lo, hi) intervals."""
+        lo = np.ascontiguousarray([a for a, _ in menu], np.int64)
+        hi = np.ascontiguousarray([b for _, b in menu], np.int64)
+        out = I32()
+        st = None if hip_stream is None else P(int(hip_stream))
+        self._check(lib().epi_mine(self.h, int(sid), lo.size, _ptr(lo), _ptr(hi), int(max_size), int(threshold),
+                                   st, ctypes.byref(out)))
+        return out.value
+
+    def epi_mine_levels(self, mid: int) -> int:
+        n = I32()
+        self._check(lib().epi_mine_levels(self.h, int(mid), ctypes.byref(n)))
+        return n.value
+
+    def epi_mine_level_info(self, mid: int, level: int):
+        """(n_candidates, n_frequent, (gen_ms, count_ms, kernel_ms))."""
+        m, f = I64(), I64()
+        t = np.zeros(3, np.float64)
+        self._check(lib().epi_mine_level_info(self.h, int(mid), int(level), ctypes.byref(m), ctypes.byref(f),
+                                              _ptr(t)))
+        return m.value, f.value, tuple(float(x) for x in t)
+
+    def epi_mine_read(self, mid: int, level: int, frequent_only: bool = False):
+        """Candidate dict (N, types, lo, hi) plus int32 counts."""
+        m, f, _ = self.epi_mine_level_info(mid, level)
+        k = f if frequent_only else m
+        c = dict(N=np.zeros(k, np.uint8), types=np.zeros((k, 8), np.int32), lo=np.zeros((k, 7), np.int64),
+                 hi=np.zeros((k, 7), np.int64))
+        counts = np.zeros(k, np.int32)
+        self._check(lib().epi_mine_read(self.h, int(mid), int(level), int(bool(frequent_only)), k, _ptr(c["N"]),
+                                        _ptr(c["types"]), _ptr(c["lo"]), _ptr(c["hi"]), _ptr(counts)))
+        return c, counts
+
+    def epi_mine_release(self, mid: int):
+        self._check(lib().epi_mine_release(self.h, int(mid)))

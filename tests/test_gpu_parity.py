@@ -224,3 +224,40 @@ def test_lane_widths(ctx, lanes):
     say(f"lanes={lanes}")
     got = gpu_counts_opts(ctx, s, c, segments=3, lanes=lanes)
     assert np.array_equal(got, oracle.count(s, c))
+
+
+def _episode_key(c, i):
+    N = int(c["N"][i])
+    return (tuple(int(x) for x in c["types"][i, :N]), tuple(int(x) for x in c["lo"][i, : N - 1]),
+            tuple(int(x) for x in c["hi"][i, : N - 1]))
+
+
+def test_levelwise_mining_matches_oracle(ctx):
+    """Every level's candidates and counts, and the frequent sets, equal the
+    oracle's level-wise discovery (reduced mining workload)."""
+    from oracle import apriori
+
+    rng = np.random.Generator(np.random.PCG64(12))
+    s = sg.poisson_stream(rng, K=16, rate_hz=20.0, dur_s=120.0, ts_kind=0, unit_per_ms=1000,
+                          cascades=[4, 5], cascade_trigger_hz=[4.0, 6.0])
+    menu = [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS]
+    theta = 90
+    say(f"mining n={s['types'].size}: oracle level-wise pass")
+    ref = apriori.mine(s, menu, 5, theta)
+    say(f"oracle levels: {[len(r['counts']) for r in ref]}")
+    sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
+    mid = ctx.epi_mine(sid, menu, 5, theta)
+    nl = ctx.epi_mine_levels(mid)
+    assert nl == len(ref)
+    for L in range(1, nl + 1):
+        c, counts = ctx.epi_mine_read(mid, L)
+        got = {_episode_key(c, i): int(counts[i]) for i in range(c["N"].size)}
+        want = {}
+        for (ty, iv), cnt in ref[L - 1]["counts"].items():
+            want[(ty, tuple(menu[v][0] for v in iv), tuple(menu[v][1] for v in iv))] = cnt
+        assert got == want, f"level {L}"
+        fc, _ = ctx.epi_mine_read(mid, L, frequent_only=True)
+        assert fc["N"].size == len(ref[L - 1]["frequent"])
+        say(f"level {L}: {c['N'].size} candidates, {fc['N'].size} frequent")
+    ctx.epi_mine_release(mid)
+    ctx.epi_release_stream(sid)
