@@ -49,6 +49,26 @@ def algorithmic_bytes(cands, type_counts, ts_bytes):
     return int((ev * ts_bytes).sum() + (N * 2 + (N - 1) + 4).sum())
 
 
+def profiled_traffic(kernel_name):
+    """HBM bytes per launch of ``kernel_name`` from the committed rocprofv3
+    counter summary, or None when the summary is for another kernel or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_count_tiled_mining.md")
+    srcs = [os.path.join(ROOT, "paper_0905_2203_amd", "csrc", f) for f in ("epi_tiled.hip", "epi_fsm.h")]
+    try:
+        h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
+        for line in open(path):
+            if line.startswith("traffic_bytes_per_launch:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec["kernel"] == kernel_name and rec["source_hash"] == h:
+                    return int(rec["bytes"])
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +76,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="level-3 candidates timed on the CPU")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a device-to-device copy of 1 GiB (scale reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",
               file=sys.stderr)
@@ -131,6 +163,7 @@ def main():
     dom_cands, dom_counts = ctx.epi_mine_read(mid, dom)
     alg = algorithmic_bytes(dom_cands, type_counts, 4)
     achieved_gbs = alg / (kern_ms[dom - 1] / 1e3) / 1e9
+    traffic = profiled_traffic(f"k_count_tiled<int, {dom}>")
 
     # parity spot check (outside the timed region): sampled counts vs the oracle
     parity = "not checked"
@@ -202,7 +235,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "algorithmic_bytes": alg,
         },
         "cpu_baseline": cpu,
         "parity": parity,
