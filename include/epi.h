@@ -164,8 +164,13 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *                         engine uses the widest one whose state fits LDS
  *   EPI_OPT_TARGET_LANES  automatic segmentation aims at this many
  *                         (episode, segment) work lanes (default 262144)
+ *   EPI_OPT_PAIR_FILTER   1 (default) / 0: in level-wise discovery, precompute
+ *                         for each event, event type and menu interval
+ *                         whether a constrained neighbour exists before and
+ *                         after it (the tracking step of Sec. IV-C, for all
+ *                         pairs at once) and skip events with none
  * EPI_EINVAL for an unknown option or value.  Counts never depend on them. */
-enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3 };
+enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Wait for all work of the context and report device-side check failures. */

@@ -497,6 +497,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
             if (value < 1) return fail(ctx, EPI_EINVAL, "target lanes must be >= 1");
             ctx->c.opt.target_lanes = value;
             return EPI_OK;
+        case EPI_OPT_PAIR_FILTER:
+            if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "pair filter must be 0 or 1");
+            ctx->c.opt.pair_filter = value != 0;
+            return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);
     }
@@ -552,6 +556,13 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     mn->menu_lo.assign(menu_lo, menu_lo + n_menu);
     mn->menu_hi.assign(menu_hi, menu_hi + n_menu);
     mn->threshold = threshold;
+    // pair-existence bitmaps of the menu (skipped when they would be too big)
+    const double bits_bytes = 2.0 * 8.0 * n_menu * (double)s->K * (double)s->B * (kTile / 64);
+    if (ctx->c.opt.pair_filter && max_size > 1 && s->n > 0 && bits_bytes <= (double)ctx->c.opt.pair_filter_max_bytes) {
+        auto tb = std::chrono::steady_clock::now();
+        HIPTRY(ctx, build_pair_bits(*s, *mn, st), "building pair-existence bitmaps");
+        mn->bits_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+    }
     for (int N = 1; N <= max_size; ++N) {
         MineLevel L;
         auto t0 = std::chrono::steady_clock::now();

@@ -65,8 +65,10 @@ struct LaneFsm {
         for (int k = 0; k < N - 1; ++k) qh[k * W + lane] = gen << 16;
     }
 
-    // Is t inside the acceptance intervals recorded at node slot k?
-    __device__ __forceinline__ bool query(int k, T t) {
+    // Is t inside the acceptance intervals recorded at node slot k?  On a
+    // miss, *nv receives the earliest time a later query can succeed with the
+    // current intervals (front start + 1, or the type maximum when empty).
+    __device__ __forceinline__ bool query(int k, T t, T *nv) {
         uint32_t hd, n;
         load_hdr(k, hd, n);
         const uint32_t n0 = n;
@@ -80,11 +82,14 @@ struct LaneFsm {
             --n;
         }
         if (n != n0) qh[k * W + lane] = pack(hd, n);
-        return n > 0 && f.s < t;
+        const bool ok = n > 0 && f.s < t;
+        *nv = n > 0 ? (T)(f.s + 1) : TsLimits<T>::hi();
+        return ok;
     }
 
-    // Record an event of node slot k at time t.
-    __device__ __forceinline__ void record(int k, T t, int32_t *flags) {
+    // Record an event of node slot k at time t; returns the start of its
+    // acceptance interval.
+    __device__ __forceinline__ T record(int k, T t, int32_t *flags) {
         const Pair<T> lh = lohi[k * W + lane];
         const T ns = t + lh.s, ne = t + lh.e;
         uint32_t hd, n;
@@ -105,12 +110,12 @@ struct LaneFsm {
             if (ns <= be) {
                 slot(k, bk).e = ne;
                 qh[k * W + lane] = pack(hd, n);
-                return;
+                return ns;
             }
         }
         if (n >= (uint32_t)Q) {
             atomicAdd(&flags[kFlagQueueOverflow], 1);  // cannot happen within the bound
-            return;
+            return ns;
         }
         uint32_t tl = hd + n;
         if (tl >= (uint32_t)Q) tl -= Q;
@@ -119,18 +124,20 @@ struct LaneFsm {
         v.e = ne;
         slot(k, tl) = v;
         qh[k * W + lane] = pack(hd, n + 1);
+        return ns;
     }
 
     // One event of node j (0-based) at time t; true on a completion.
     __device__ __forceinline__ bool step(int j, T t, int32_t *flags) {
-        const bool ok = j == 0 ? t > e : query(j - 1, t);
+        T nv;
+        const bool ok = j == 0 ? t > e : query(j - 1, t, &nv);
         if (!ok) return false;
         if (j == N - 1) {
             e = t;
             gen ^= 1u;
             return true;
         }
-        record(j, t, flags);
+        (void)record(j, t, flags);
         return false;
     }
 };

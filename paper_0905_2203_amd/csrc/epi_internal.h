@@ -101,6 +101,12 @@ struct CandSet {
     // (T[2*n_menu]); slots are in submission order (orig unused).
     bool compact = false;
     DevBuf t16, iv, menu;
+    // Optional pair-existence bitmaps of the menu (compact layout only; not
+    // owned): bit (i, x, pos) of pred_bits says the event at tiled position
+    // pos has an event of type x at a gap in menu interval i before it;
+    // succ_bits the same after it.  Rows of B*kTile bits.
+    const uint64_t *pred_bits = nullptr;
+    const uint64_t *succ_bits = nullptr;
     std::vector<Group> groups;
     bool counted = false;
 };
@@ -110,6 +116,8 @@ struct CountOptions {
     int64_t segments = 0;          // 0: automatic; k >= 1: k segments per launch class
     int lanes = 0;                 // 0: automatic; else lanes per workgroup (64, 128 or 256)
     int64_t target_lanes = 262144; // automatic segmentation aims at this many (candidate, segment) lanes
+    bool pair_filter = true;       // level-wise discovery: skip events with no constrained neighbour
+    int64_t pair_filter_max_bytes = int64_t(1) << 30;
 };
 
 // One level of a level-wise discovery run: candidates of size N in
@@ -129,6 +137,8 @@ struct Mine {
     std::vector<int64_t> menu_lo, menu_hi;
     int64_t threshold = 0;
     std::vector<MineLevel> levels;
+    DevBuf pred_bits, succ_bits;  // pair-existence bitmaps of the menu (may be empty)
+    double bits_ms = 0;
 };
 
 struct Ctx {
@@ -160,6 +170,8 @@ hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, in
 hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const CountOptions &opt, int32_t *d_flags,
                             hipStream_t st);
 int queue_class_of(int64_t bound);
+// Pair-existence bitmaps of an interval menu over a stream (epi_pairs.hip).
+hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st);
 // Candidate generation of level-wise discovery (epi_mine.hip).
 void gen_level1(int32_t K, MineLevel &L);
 void gen_level2(const MineLevel &F1, int n_menu, MineLevel &L);

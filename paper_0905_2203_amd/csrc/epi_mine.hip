@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <numeric>
+#include <thread>
 
 #include "epi_internal.h"
 
@@ -64,6 +65,10 @@ hipError_t count_level_t(const Stream &s, const Mine &mn, MineLevel &L, const Co
     g.begin = 0;
     g.end = m;
     cs.groups.push_back(g);
+    if (mn.pred_bits.p && mn.succ_bits.p && L.N > 1) {
+        cs.pred_bits = mn.pred_bits.as<uint64_t>();
+        cs.succ_bits = mn.succ_bits.as<uint64_t>();
+    }
     hipEvent_t ev0, ev1;
     if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
@@ -158,36 +163,54 @@ void gen_join(const MineLevel &P, MineLevel &L) {
     };
     const int64_t nf = (int64_t)F.size();
     std::vector<int64_t> rlo(nf), rhi(nf), cnt(nf + 1, 0);
-    for (int64_t x = 0; x < nf; ++x) {
-        const int64_t a = F[x];
-        const auto lo = std::partition_point(byprefix.begin(), byprefix.end(),
-                                             [&](int64_t b) { return cmp_prefix_suffix(b, a) < 0; });
-        const auto hi = std::partition_point(lo, byprefix.end(), [&](int64_t b) { return cmp_prefix_suffix(b, a) == 0; });
-        rlo[x] = lo - byprefix.begin();
-        rhi[x] = hi - byprefix.begin();
-        int64_t c = 0;
-        for (int64_t r = rlo[x]; r < rhi[x]; ++r)
-            if (ty(byprefix[r], N - 1) != ty(a, 0)) ++c;
-        cnt[x + 1] = cnt[x] + c;
-    }
+    // both passes split the frequent episodes over host threads
+    const int nt = (int)std::max<unsigned>(1, std::min<unsigned>(32, std::thread::hardware_concurrency()));
+    auto parallel = [&](auto &&body) {
+        std::vector<std::thread> th;
+        const int64_t chunk = (nf + nt - 1) / nt;
+        for (int q = 0; q < nt; ++q) {
+            const int64_t x0 = q * chunk, x1 = std::min(nf, x0 + chunk);
+            if (x0 >= x1) break;
+            th.emplace_back([&, x0, x1] { body(x0, x1); });
+        }
+        for (auto &t : th) t.join();
+    };
+    parallel([&](int64_t x0, int64_t x1) {
+        for (int64_t x = x0; x < x1; ++x) {
+            const int64_t a = F[x];
+            const auto lo = std::partition_point(byprefix.begin(), byprefix.end(),
+                                                 [&](int64_t b) { return cmp_prefix_suffix(b, a) < 0; });
+            const auto hi =
+                std::partition_point(lo, byprefix.end(), [&](int64_t b) { return cmp_prefix_suffix(b, a) == 0; });
+            rlo[x] = lo - byprefix.begin();
+            rhi[x] = hi - byprefix.begin();
+            int64_t c = 0;
+            for (int64_t r = rlo[x]; r < rhi[x]; ++r)
+                if (ty(byprefix[r], N - 1) != ty(a, 0)) ++c;
+            cnt[x + 1] = c;
+        }
+    });
+    for (int64_t x = 0; x < nf; ++x) cnt[x + 1] += cnt[x];
     const int64_t m = cnt[nf];
     L.N = N + 1;
     L.m = m;
-    L.types.assign((size_t)(N + 1) * m, 0);
-    L.iv.assign((size_t)N * m, 0);
-    for (int64_t x = 0; x < nf; ++x) {
-        const int64_t a = F[x];
-        int64_t c = cnt[x];
-        for (int64_t r = rlo[x]; r < rhi[x]; ++r) {
-            const int64_t b = byprefix[r];
-            if (ty(b, N - 1) == ty(a, 0)) continue;
-            for (int k = 0; k < N; ++k) L.types[(size_t)k * m + c] = ty(a, k);
-            L.types[(size_t)N * m + c] = ty(b, N - 1);
-            for (int k = 0; k < N - 1; ++k) L.iv[(size_t)k * m + c] = iv(a, k);
-            L.iv[(size_t)(N - 1) * m + c] = iv(b, N - 2);
-            ++c;
+    L.types.resize((size_t)(N + 1) * m);
+    L.iv.resize((size_t)N * m);
+    parallel([&](int64_t x0, int64_t x1) {
+        for (int64_t x = x0; x < x1; ++x) {
+            const int64_t a = F[x];
+            int64_t c = cnt[x];
+            for (int64_t r = rlo[x]; r < rhi[x]; ++r) {
+                const int64_t b = byprefix[r];
+                if (ty(b, N - 1) == ty(a, 0)) continue;
+                for (int k = 0; k < N; ++k) L.types[(size_t)k * m + c] = ty(a, k);
+                L.types[(size_t)N * m + c] = ty(b, N - 1);
+                for (int k = 0; k < N - 1; ++k) L.iv[(size_t)k * m + c] = iv(a, k);
+                L.iv[(size_t)(N - 1) * m + c] = iv(b, N - 2);
+                ++c;
+            }
         }
-    }
+    });
 }
 
 void select_frequent(MineLevel &L, int64_t threshold) {

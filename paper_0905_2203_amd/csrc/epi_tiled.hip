@@ -53,6 +53,9 @@ struct CountArgs {
     const uint16_t *t16;  // compact layout (when non-null): types
     const uint8_t *iv;    //   interval ids into menu
     const T *menu;        //   (lo, hi) pairs
+    const uint64_t *pbits;  // pair-existence bitmaps (filtered mode)
+    const uint64_t *sbits;
+    int64_t rwords;         // words per bitmap row (B * kTile / 64)
     int64_t m;
     int64_t begin;  // first slot of the group
     int64_t G;      // group size
@@ -69,7 +72,8 @@ struct CountArgs {
 };
 
 template <typename T, int N>
-__device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N> &f, int64_t slot, int32_t *ty) {
+__device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N> &f, int64_t slot, int32_t *ty,
+                                           T *lo, T *hi) {
     T H = 0;
     if (a.t16) {
 #pragma unroll
@@ -77,32 +81,35 @@ __device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N>
 #pragma unroll
         for (int k = 0; k + 1 < N; ++k) {
             const int id = a.iv[(int64_t)k * a.m + slot];
-            Pair<T> v;
-            v.s = a.menu[2 * id];
-            v.e = a.menu[2 * id + 1];
-            f.lohi[k * f.W + f.lane] = v;
-            H += v.e;
+            lo[k] = a.menu[2 * id];
+            hi[k] = a.menu[2 * id + 1];
         }
-        return H;
-    }
+    } else {
 #pragma unroll
-    for (int k = 0; k < N; ++k) ty[k] = a.ctypes[(int64_t)k * a.m + slot];
+        for (int k = 0; k < N; ++k) ty[k] = a.ctypes[(int64_t)k * a.m + slot];
+#pragma unroll
+        for (int k = 0; k + 1 < N; ++k) {
+            lo[k] = a.clo[(int64_t)k * a.m + slot];
+            hi[k] = a.chi[(int64_t)k * a.m + slot];
+        }
+    }
 #pragma unroll
     for (int k = 0; k + 1 < N; ++k) {
         Pair<T> v;
-        v.s = a.clo[(int64_t)k * a.m + slot];
-        v.e = a.chi[(int64_t)k * a.m + slot];
+        v.s = lo[k];
+        v.e = hi[k];
         f.lohi[k * f.W + f.lane] = v;
-        H += v.e;
+        H += hi[k];
     }
     return H;
 }
 
-template <typename T, int N>
+template <typename T, int N, bool FILT>
 __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kEnd = TsLimits<T>::hi();
+    constexpr int L = N > 1 ? N - 1 : 1;
     const int W = blockDim.x, lane = threadIdx.x;
     const int64_t s = (int64_t)blockIdx.x * W + lane;
     const bool active = s < a.G;
@@ -121,8 +128,26 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
     f.Q = a.Q;
     f.gen = 0;
     int32_t ty[N];
-    const T H = load_candidate<T, N>(a, f, slot, ty);
+    T lo[L], hi[L];
+    const T H = load_candidate<T, N>(a, f, slot, ty, lo, hi);
     f.clear_all();
+    // vf[k] (k >= 1): no node-k event before this time can meet constraint k
+    // with the intervals currently recorded at node k-1 (a lower bound on the
+    // earliest interval start + 1; the type maximum when none is recorded).
+    T vf[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) vf[k] = kEnd;
+    // pair-existence rows of each node (filtered mode)
+    int64_t prow[N], srow[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        prow[k] = 0;
+        srow[k] = 0;
+        if (FILT) {
+            if (k >= 1) prow[k] = ((int64_t)a.iv[(int64_t)(k - 1) * a.m + slot] * a.K + ty[k - 1]) * a.rwords;
+            if (k + 1 < N) srow[k] = ((int64_t)a.iv[(int64_t)k * a.m + slot] * a.K + ty[k + 1]) * a.rwords;
+        }
+    }
 
     const int64_t b0 = (int64_t)p * a.S;
     const int64_t b1 = b0 + a.S < a.B ? b0 + a.S : a.B;
@@ -144,16 +169,16 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
             T mx = 0;
             for (int w = 0; w < (W + 63) / 64; ++w) mx = misc[w] > mx ? misc[w] : mx;
             const T target = (T)(Bp - mx);
-            int64_t lo = 0, hi = b0;  // last b in [0, b0] with tile_t0[b] < target, else 0
+            int64_t blo = 0, bhi = b0;  // last b in [0, b0] with tile_t0[b] < target, else 0
             if (a.tile_t0[0] >= target) {
-                hi = 0;
+                bhi = 0;
             } else {
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi + 1) / 2;
-                    if (a.tile_t0[mid] < target) lo = mid; else hi = mid - 1;
+                while (blo < bhi) {
+                    const int64_t mid = (blo + bhi + 1) / 2;
+                    if (a.tile_t0[mid] < target) blo = mid; else bhi = mid - 1;
                 }
             }
-            misc[8] = (T)lo;
+            misc[8] = (T)blo;
         }
         __syncthreads();
         bs = (int64_t)misc[8];
@@ -169,16 +194,66 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
         for (int i = lane; i <= a.K; i += W) obuf[i] = a.loff[b * (a.K + 1) + i];
         __syncthreads();
         if (!active) continue;
+        // Per node: the tile range [rs, re) of its type; unfiltered lanes walk
+        // it with a cursor, filtered lanes walk the set bits of the words of
+        // (range & predecessor-exists & successor-exists).
         int cur[N], stop[N];
+        int wi[N], we[N];
+        uint64_t msk[N], nmsk[N];  // current word's bits, next word's (prefetched)
         T head[N];
+        const int64_t wbase = b * (kTile / 64);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             cur[k] = obuf[ty[k]];
             stop[k] = obuf[ty[k] + 1];
-            const T v = cur[k] < stop[k] ? tbuf[cur[k]] : kEnd;
-            head[k] = v < Ep ? v : kEnd;
+            wi[k] = 0;
+            we[k] = -1;
+            msk[k] = 0;
+            nmsk[k] = 0;
+        }
+        // bits of word w of node k's range that may matter
+        auto word_bits = [&](const int k, const int w) -> uint64_t {
+            const int base = w << 6;
+            const int l0 = (cur[k] > base ? cur[k] : base) - base;
+            const int l1 = (stop[k] < base + 64 ? stop[k] : base + 64) - base;
+            if (l1 <= l0) return 0;
+            uint64_t m = (l1 - l0 == 64 ? ~0ull : ((1ull << (l1 - l0)) - 1ull)) << l0;
+            if (k >= 1) m &= a.pbits[prow[k] + wbase + w];
+            if (k + 1 < N) m &= a.sbits[srow[k] + wbase + w];
+            return m;
+        };
+        auto filt_head = [&](const int k) -> T {
+            while (msk[k] == 0 && wi[k] < we[k]) {
+                ++wi[k];
+                msk[k] = nmsk[k];
+                nmsk[k] = wi[k] < we[k] ? word_bits(k, wi[k] + 1) : 0ull;
+            }
+            if (msk[k] == 0) return kEnd;
+            const T v = tbuf[(wi[k] << 6) + (int)__builtin_ctzll(msk[k])];
+            return v < Ep ? v : kEnd;
+        };
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (FILT) {
+                if (cur[k] < stop[k]) {
+                    wi[k] = cur[k] >> 6;
+                    we[k] = (stop[k] - 1) >> 6;
+                    msk[k] = word_bits(k, wi[k]);
+                    nmsk[k] = wi[k] < we[k] ? word_bits(k, wi[k] + 1) : 0ull;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (FILT) {
+                head[k] = filt_head(k);
+            } else {
+                const T v = cur[k] < stop[k] ? tbuf[cur[k]] : kEnd;
+                head[k] = v < Ep ? v : kEnd;
+            }
         }
         while (true) {
+            // next event of the lane's types (any order among equal times)
             T t = head[0];
             int j = 0;
 #pragma unroll
@@ -189,17 +264,87 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
                 }
             }
             if (t == kEnd) break;
-            if (f.step(j, t, a.flags) && t >= Bp) {
-                if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = t;
-                ++cnt;
-                last = t;
-            }
+            // per-node values of the selected node
+            T vfj = vf[0], nxt = kEnd, hij = T(0);
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
+            for (int k = 1; k < N; ++k)
+                if (k == j) vfj = vf[k];
+#pragma unroll
+            for (int k = 0; k + 1 < N; ++k) {
                 if (k == j) {
-                    ++cur[k];
-                    const T v = cur[k] < stop[k] ? tbuf[cur[k]] : kEnd;
-                    head[k] = v < Ep ? v : kEnd;
+                    nxt = head[k + 1];
+                    hij = hi[k];
+                }
+            }
+            // Exact rejections that need no LDS state: a start not after the
+            // last completion; a query below vf; a record whose acceptance
+            // interval ends before the next event of the following node
+            // (only when that event is known, i.e. inside this tile).
+            const bool late_next = j + 1 < N && nxt != kEnd && nxt > (T)(t + hij);
+            const bool useless = (j == 0 ? t <= f.e : t < vfj) || late_next;
+            if (!useless) {
+                bool done = false;
+                if (j == 0) {
+                    if (N == 1) {
+                        f.e = t;
+                        done = true;
+                    } else {
+                        const T ns = f.record(0, t, a.flags);
+                        vf[1] = vf[1] < (T)(ns + 1) ? vf[1] : (T)(ns + 1);
+                    }
+                } else {
+                    T nv;
+                    const bool ok = f.query(j - 1, t, &nv);
+                    if (!ok) {
+#pragma unroll
+                        for (int k = 1; k < N; ++k)
+                            if (k == j) vf[k] = nv;
+                    } else if (j == N - 1) {
+                        f.e = t;
+                        f.gen ^= 1u;
+#pragma unroll
+                        for (int k = 0; k < N; ++k) vf[k] = kEnd;
+                        done = true;
+                    } else {
+                        const T ns = f.record(j, t, a.flags);
+#pragma unroll
+                        for (int k = 1; k + 1 < N; ++k)
+                            if (k == j) vf[k + 1] = vf[k + 1] < (T)(ns + 1) ? vf[k + 1] : (T)(ns + 1);
+                    }
+                }
+                if (done && t >= Bp) {
+                    if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = t;
+                    ++cnt;
+                    last = t;
+                }
+            }
+            // advance the selected node
+            if (FILT) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (k == j) {
+                        msk[k] &= msk[k] - 1ull;
+                        head[k] = filt_head(k);
+                    }
+                }
+            } else {
+                int c = cur[0], st = stop[0];
+#pragma unroll
+                for (int k = 1; k < N; ++k) {
+                    if (k == j) {
+                        c = cur[k];
+                        st = stop[k];
+                    }
+                }
+                ++c;
+                T v = c < st ? tbuf[c] : kEnd;
+                v = v < Ep ? v : kEnd;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (k == j) {
+                        cur[k] = c;
+                        head[k] = v;
+                    }
                 }
             }
         }
@@ -245,8 +390,10 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
     f.lane = lane;
     f.Q = a.Q;
     f.gen = 0;
+    constexpr int L = N > 1 ? N - 1 : 1;
     int32_t ty[N];
-    const T H = load_candidate<T, N>(a, f, slot, ty);
+    T lo[L], hi[L];
+    const T H = load_candidate<T, N>(a, f, slot, ty, lo, hi);
     int32_t lo_[N], hi_[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -325,19 +472,24 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
 template <typename T>
 using KFn = void (*)(CountArgs<T>);
 
-template <typename T>
-KFn<T> pick_count(int N) {
+template <typename T, bool F>
+KFn<T> pick_count_f(int N) {
     switch (N) {
-        case 1: return k_count_tiled<T, 1>;
-        case 2: return k_count_tiled<T, 2>;
-        case 3: return k_count_tiled<T, 3>;
-        case 4: return k_count_tiled<T, 4>;
-        case 5: return k_count_tiled<T, 5>;
-        case 6: return k_count_tiled<T, 6>;
-        case 7: return k_count_tiled<T, 7>;
-        case 8: return k_count_tiled<T, 8>;
+        case 1: return k_count_tiled<T, 1, F>;
+        case 2: return k_count_tiled<T, 2, F>;
+        case 3: return k_count_tiled<T, 3, F>;
+        case 4: return k_count_tiled<T, 4, F>;
+        case 5: return k_count_tiled<T, 5, F>;
+        case 6: return k_count_tiled<T, 6, F>;
+        case 7: return k_count_tiled<T, 7, F>;
+        case 8: return k_count_tiled<T, 8, F>;
         default: return nullptr;
     }
+}
+
+template <typename T>
+KFn<T> pick_count(int N, bool filtered) {
+    return filtered ? pick_count_f<T, true>(N) : pick_count_f<T, false>(N);
 }
 
 template <typename T>
@@ -482,7 +634,11 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
             a.rec_first = a.rec_last + (size_t)P * G;
             a.rec_cnt = reinterpret_cast<int32_t *>(a.rec_first + (size_t)P * G * kRecFirst);
         }
-        KFn<T> fn = pick_count<T>(g.N);
+        const bool filtered = c.compact && c.pred_bits && c.succ_bits;
+        a.pbits = filtered ? c.pred_bits : nullptr;
+        a.sbits = filtered ? c.succ_bits : nullptr;
+        a.rwords = s.B * (kTile / 64);
+        KFn<T> fn = pick_count<T>(g.N, filtered);
         if (!fn) return hipErrorInvalidValue;
         if ((e = ensure_lds_attr<T>(fn, lds)) != hipSuccess) return e;
         const dim3 grid((unsigned)((G + W - 1) / W), (unsigned)P);

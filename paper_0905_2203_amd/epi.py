@@ -47,6 +47,7 @@ EXPORTS = [
 EPI_OPT_SEGMENTS = 1
 EPI_OPT_LANES = 2
 EPI_OPT_TARGET_LANES = 3
+EPI_OPT_PAIR_FILTER = 4
 
 
 class EpiError(RuntimeError):

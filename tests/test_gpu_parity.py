@@ -232,9 +232,14 @@ def _episode_key(c, i):
             tuple(int(x) for x in c["hi"][i, : N - 1]))
 
 
-def test_levelwise_mining_matches_oracle(ctx):
+_MINING_REF = {}
+
+
+@pytest.mark.parametrize("opts", [{}, {"filter": 0}, {"segments": 5}], ids=["default", "nofilter", "segments5"])
+def test_levelwise_mining_matches_oracle(ctx, opts):
     """Every level's candidates and counts, and the frequent sets, equal the
-    oracle's level-wise discovery (reduced mining workload)."""
+    oracle's level-wise discovery (reduced mining workload); with and without
+    the pair-existence filter, and with forced segments."""
     from oracle import apriori
 
     rng = np.random.Generator(np.random.PCG64(12))
@@ -242,11 +247,19 @@ def test_levelwise_mining_matches_oracle(ctx):
                           cascades=[4, 5], cascade_trigger_hz=[4.0, 6.0])
     menu = [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS]
     theta = 90
-    say(f"mining n={s['types'].size}: oracle level-wise pass")
-    ref = apriori.mine(s, menu, 5, theta)
-    say(f"oracle levels: {[len(r['counts']) for r in ref]}")
+    if "ref" not in _MINING_REF:
+        say(f"mining n={s['types'].size}: oracle level-wise pass")
+        _MINING_REF["ref"] = apriori.mine(s, menu, 5, theta)
+    ref = _MINING_REF["ref"]
+    say(f"oracle levels: {[len(r['counts']) for r in ref]} opts={opts}")
+    ctx.epi_set_option(epi.EPI_OPT_PAIR_FILTER, opts.get("filter", 1))
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, opts.get("segments", 0))
     sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
-    mid = ctx.epi_mine(sid, menu, 5, theta)
+    try:
+        mid = ctx.epi_mine(sid, menu, 5, theta)
+    finally:
+        ctx.epi_set_option(epi.EPI_OPT_PAIR_FILTER, 1)
+        ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
     nl = ctx.epi_mine_levels(mid)
     assert nl == len(ref)
     for L in range(1, nl + 1):
