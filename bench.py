@@ -31,6 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PROFILE = "k_ext_count_mining.md"
+KERNEL_SOURCES = ("epi_extend.hip", "epi_fsm.h")
 THRESHOLD = 100
 MAX_SIZE = 6
 
@@ -39,24 +41,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(cands, type_counts, ts_bytes):
-    """Bytes the method must read for a candidate set: the timestamps of each
-    candidate's own types, its descriptor (uint16 types + uint8 interval ids)
-    and its 4-byte count."""
-    N = cands["N"].astype(np.int64)
-    ty = cands["types"]
-    ev = np.where(ty >= 0, type_counts[np.maximum(ty, 0)], 0).sum(axis=1)
-    return int((ev * ts_bytes).sum() + (N * 2 + (N - 1) + 4).sum())
-
-
 def profiled_traffic(kernel_name):
     """HBM bytes per launch of ``kernel_name`` from the committed rocprofv3
     counter summary, or None when the summary is for another kernel or the
     kernel sources changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_count_tiled_mining.md")
-    srcs = [os.path.join(ROOT, "paper_0905_2203_amd", "csrc", f) for f in ("epi_tiled.hip", "epi_fsm.h")]
+    path = os.path.join(ROOT, "profiles", PROFILE)
+    srcs = [os.path.join(ROOT, "paper_0905_2203_amd", "csrc", f) for f in KERNEL_SOURCES]
     try:
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
         for line in open(path):
@@ -159,11 +151,10 @@ def main():
     gen_ms = [float(np.mean([x[2][0] for x in lv])) for lv in level_info]
     cnt_ms = [float(np.mean([x[2][1] for x in lv])) for lv in level_info]
     dom = int(np.argmax(kern_ms)) + 1
-    type_counts = np.bincount(s["types"], minlength=K).astype(np.int64)
-    dom_cands, dom_counts = ctx.epi_mine_read(mid, dom)
-    alg = algorithmic_bytes(dom_cands, type_counts, 4)
+    alg = ctx.epi_mine_level_bytes(mid, dom)
     achieved_gbs = alg / (kern_ms[dom - 1] / 1e3) / 1e9
-    traffic = profiled_traffic(f"k_count_tiled<int, {dom}>")
+    kname = "k_ext_count1<int>" if dom >= 3 else ("k_ext_count0<int>" if dom == 2 else "k_level1<int>")
+    traffic = profiled_traffic(kname)
 
     # parity spot check (outside the timed region): sampled counts vs the oracle
     parity = "not checked"
@@ -175,11 +166,11 @@ def main():
         bad = 0
         checked = 0
         for L in range(1, nl + 1):
-            c, got = (dom_cands, dom_counts) if L == dom else ctx.epi_mine_read(mid, L)
-            idx = rng.choice(c["N"].size, size=min(300, c["N"].size), replace=False)
-            sub = sg.take_candidates(c, idx)
+            m_l = cand_per_level[L - 1]
+            idx = np.sort(rng.choice(m_l, size=min(300, m_l), replace=False))
+            sub, got = ctx.epi_mine_read_at(mid, L, idx)
             want = oracle.count(s, sub)
-            bad += int((want != got[idx]).sum())
+            bad += int((want != got).sum())
             checked += idx.size
         parity = f"{'ok' if bad == 0 else 'MISMATCH'}: {checked} sampled counts over {nl} levels, {bad} differ"
 
@@ -230,7 +221,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_count_tiled (level {dom}, {cand_per_level[dom - 1]} candidates)",
+            "kernel": f"{kname} (level {dom}, {cand_per_level[dom - 1]} candidates)",
             "achieved": achieved_gbs,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",

@@ -169,8 +169,14 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *                         whether a constrained neighbour exists before and
  *                         after it (the tracking step of Sec. IV-C, for all
  *                         pairs at once) and skip events with none
+ *                         (state-machine mining engine only)
+ *   EPI_OPT_MINE_ENGINE   level-wise discovery engine: 1 (default) extends the
+ *                         previous level's chain lists (decomposition of
+ *                         Sec. IV-A, one merge per candidate); 0 counts every
+ *                         candidate with the state machines of epi_count
  * EPI_EINVAL for an unknown option or value.  Counts never depend on them. */
-enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4 };
+enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
+       EPI_OPT_MINE_ENGINE = 5 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Wait for all work of the context and report device-side check failures. */
@@ -185,6 +191,49 @@ epi_status epi_read_counts(epi_ctx *ctx, int32_t set_id, int32_t *counts, int64_
  * the set is released; contents are defined once the count's stream work is
  * complete. */
 epi_status epi_counts_device(epi_ctx *ctx, int32_t set_id, const int32_t **d_counts);
+
+/* ------------------------------------------------------------------------
+ * Cost model of the scheduler: a perceptron with two hidden ReLU layers of
+ * 64 units (FP32), y = relu(relu(x W1 + b1) W2 + b2) w3 + b3, trained on the
+ * mean squared error with Adam (b1 0.9, b2 0.999, eps 1e-8) by the
+ * library's own HIP kernels.  Parameters are one flat FP32 vector:
+ * W1[F][64], b1[64], W2[64][64], b2[64], w3[64], b3[1].  The model only
+ * orders work; counts never depend on it.
+ * ---------------------------------------------------------------------- */
+
+/* Create the context's model for n_features inputs (1..4096): He-uniform
+ * weights from a SplitMix64 stream seeded by `seed`, zero biases, Adam state
+ * cleared. */
+epi_status epi_mlp_init(epi_ctx *ctx, int32_t n_features, uint64_t seed);
+
+/* Number of inputs and parameters of the model (EPI_ESTATE before init). */
+epi_status epi_mlp_params(epi_ctx *ctx, int32_t *n_features, int64_t *n_params);
+
+/* Copy the parameters out / in (n = number of parameters); setting them
+ * clears the Adam state. */
+epi_status epi_mlp_get_params(epi_ctx *ctx, float *p, int64_t n);
+epi_status epi_mlp_set_params(epi_ctx *ctx, const float *p, int64_t n);
+
+/* Forward pass on B host samples X[B][F] -> y[B] (host). */
+epi_status epi_mlp_forward(epi_ctx *ctx, const float *X, int64_t B, float *y);
+
+/* Loss mean_i (y_i - t_i)^2 and its gradient g[n_params] (host), for host
+ * samples X[B][F] and targets t[B]. */
+epi_status epi_mlp_grad(epi_ctx *ctx, const float *X, const float *t, int64_t B, float *loss, float *g);
+
+/* One Adam step with gradient g (host) and learning rate lr. */
+epi_status epi_mlp_adam_step(epi_ctx *ctx, const float *g, float lr);
+
+/* Train on B host samples for `epochs` passes of consecutive mini-batches
+ * of `batch` samples (order as given); losses[epochs] (may be null)
+ * receives each epoch's mean loss. */
+epi_status epi_mlp_train(epi_ctx *ctx, const float *X, const float *t, int64_t B, int32_t epochs, int32_t batch,
+                         float lr, float *losses);
+
+/* The model's 23 input features of every candidate of a set (submission
+ * order, X[m][23]): log1p of the event count of each node's type (8, zero
+ * padded), log1p(hi - lo) and log1p(hi) of each constraint (7 + 7), and N. */
+epi_status epi_costmodel_features(epi_ctx *ctx, int32_t set_id, float *X, int64_t m);
 
 /* ------------------------------------------------------------------------
  * Level-wise discovery (Sec. II-C: candidates of size N are generated from
@@ -222,6 +271,14 @@ epi_status epi_mine_level_info(epi_ctx *ctx, int32_t mine_id, int32_t level, int
  * level's candidate or frequent count.  Unused type slots are -1. */
 epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequent_only, int64_t m,
                          uint8_t *N, int32_t *types, int64_t *lo, int64_t *hi, int32_t *counts);
+
+/* Copy k candidates of a level chosen by index (0 <= idx[r] < candidates). */
+epi_status epi_mine_read_at(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_t k, const int64_t *idx,
+                            uint8_t *N, int32_t *types, int64_t *lo, int64_t *hi, int32_t *counts);
+
+/* Bytes the level's counting method must read and write (inputs per
+ * candidate plus its outputs), for bandwidth accounting. */
+epi_status epi_mine_level_bytes(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_t *alg_bytes);
 
 epi_status epi_mine_release(epi_ctx *ctx, int32_t mine_id);
 

@@ -501,6 +501,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
             if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "pair filter must be 0 or 1");
             ctx->c.opt.pair_filter = value != 0;
             return EPI_OK;
+        case EPI_OPT_MINE_ENGINE:
+            if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "mining engine must be 0 or 1");
+            ctx->c.opt.mine_engine = (int)value;
+            return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);
     }
@@ -556,28 +560,49 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     mn->menu_lo.assign(menu_lo, menu_lo + n_menu);
     mn->menu_hi.assign(menu_hi, menu_hi + n_menu);
     mn->threshold = threshold;
-    // pair-existence bitmaps of the menu (skipped when they would be too big)
-    const double bits_bytes = 2.0 * 8.0 * n_menu * (double)s->K * (double)s->B * (kTile / 64);
-    if (ctx->c.opt.pair_filter && max_size > 1 && s->n > 0 && bits_bytes <= (double)ctx->c.opt.pair_filter_max_bytes) {
-        auto tb = std::chrono::steady_clock::now();
-        HIPTRY(ctx, build_pair_bits(*s, *mn, st), "building pair-existence bitmaps");
-        mn->bits_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
-    }
-    for (int N = 1; N <= max_size; ++N) {
-        MineLevel L;
+    mn->engine = ctx->c.opt.mine_engine;
+    if (mn->engine == 1) {
+        // extension engine: each level extends the previous level's chain lists
         auto t0 = std::chrono::steady_clock::now();
-        if (N == 1) gen_level1(s->K, L);
-        else if (N == 2) gen_level2(mn->levels.back(), n_menu, L);
-        else gen_join(mn->levels.back(), L);
-        L.gen_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        if (L.m == 0) break;
-        HIPTRY(ctx, count_mine_level(*s, *mn, L, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "counting a level");
-        epi_status f = check_flags(ctx);
-        if (f != EPI_OK) return f;
-        select_frequent(L, threshold);
-        const bool none = L.freq.empty();
-        mn->levels.push_back(std::move(L));
-        if (none) break;
+        HIPTRY(ctx, extend_level1(*s, *mn, st), "counting level 1");
+        mn->levels.back().gen_ms = 0;
+        (void)t0;
+        for (int N = 2; N <= max_size; ++N) {
+            const MineLevel &prev = mn->levels.back();
+            if (prev.nf == 0 || (N == 2 && prev.nf < 2)) break;
+            HIPTRY(ctx, extend_level(*s, *mn, N, ctx->c.flags.as<int32_t>(), st), "counting a level");
+            epi_status f = check_flags(ctx);
+            if (f != EPI_OK) return f;
+            if (mn->levels.back().m == 0) {
+                mn->levels.pop_back();
+                break;
+            }
+        }
+    } else {
+        // pair-existence bitmaps of the menu (skipped when they would be too big)
+        const double bits_bytes = 2.0 * 8.0 * n_menu * (double)s->K * (double)s->B * (kTile / 64);
+        if (ctx->c.opt.pair_filter && max_size > 1 && s->n > 0 &&
+            bits_bytes <= (double)ctx->c.opt.pair_filter_max_bytes) {
+            auto tb = std::chrono::steady_clock::now();
+            HIPTRY(ctx, build_pair_bits(*s, *mn, st), "building pair-existence bitmaps");
+            mn->bits_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+        }
+        for (int N = 1; N <= max_size; ++N) {
+            MineLevel L;
+            auto t0 = std::chrono::steady_clock::now();
+            if (N == 1) gen_level1(s->K, L);
+            else if (N == 2) gen_level2(mn->levels.back(), n_menu, L);
+            else gen_join(mn->levels.back(), L);
+            L.gen_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (L.m == 0) break;
+            HIPTRY(ctx, count_mine_level(*s, *mn, L, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "counting a level");
+            epi_status f = check_flags(ctx);
+            if (f != EPI_OK) return f;
+            select_frequent(L, threshold);
+            const bool none = L.freq.empty();
+            mn->levels.push_back(std::move(L));
+            if (none) break;
+        }
     }
     const int32_t id = ctx->c.next_id++;
     ctx->c.mines[id] = std::move(mn);
@@ -611,6 +636,41 @@ epi_status epi_mine_level_info(epi_ctx *ctx, int32_t mine_id, int32_t level, int
     return EPI_OK;
 }
 
+namespace {
+
+// Episode r of a level: explicit candidate, implicit candidate, or (when
+// frequent) the frequent-episode arrays; writes the ABI layout.
+void mine_episode(const Mine &mn, int level, bool frequent, int64_t r, uint8_t *N, int32_t *types, int64_t *lo,
+                  int64_t *hi, int32_t *counts) {
+    const MineLevel &L = mn.levels[level - 1];
+    int32_t ty[kMaxN];
+    int ivs[kMaxN];
+    int64_t c;
+    if (frequent && L.implicit) {
+        c = L.freq[r];
+        for (int k = 0; k < L.N; ++k) ty[k] = L.ftypes[(size_t)k * L.nf + r];
+        for (int k = 0; k + 1 < L.N; ++k) ivs[k] = L.fiv[(size_t)k * L.nf + r];
+    } else {
+        c = frequent ? L.freq[r] : r;
+        if (L.implicit) {
+            implicit_candidate(mn, level, c, ty, ivs);
+        } else {
+            for (int k = 0; k < L.N; ++k) ty[k] = L.types[(size_t)k * L.m + c];
+            for (int k = 0; k + 1 < L.N; ++k) ivs[k] = L.iv[(size_t)k * L.m + c];
+        }
+    }
+    N[0] = (uint8_t)L.N;
+    for (int k = 0; k < kMaxN; ++k) types[k] = k < L.N ? ty[k] : -1;
+    for (int k = 0; k < kMaxN - 1; ++k) {
+        const bool live = k + 1 < L.N;
+        lo[k] = live ? mn.menu_lo[ivs[k]] : 0;
+        hi[k] = live ? mn.menu_hi[ivs[k]] : 0;
+    }
+    counts[0] = L.counts[c];
+}
+
+}  // namespace
+
 epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequent_only, int64_t m, uint8_t *N,
                          int32_t *types, int64_t *lo, int64_t *hi, int32_t *counts) {
     if (!ctx) return EPI_EINVAL;
@@ -623,24 +683,199 @@ epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequ
     if (m != want) return fail(ctx, EPI_EINVAL, "level %d has %lld entries, not %lld", level, (long long)want,
                                (long long)m);
     if (m > 0 && (!N || !types || !lo || !hi || !counts)) return fail(ctx, EPI_EINVAL, "null output");
-    for (int64_t r = 0; r < m; ++r) {
-        const int64_t i = frequent_only ? L.freq[r] : r;
-        N[r] = (uint8_t)L.N;
-        for (int k = 0; k < kMaxN; ++k) types[r * 8 + k] = k < L.N ? L.types[(size_t)k * L.m + i] : -1;
-        for (int k = 0; k < kMaxN - 1; ++k) {
-            const bool live = k + 1 < L.N;
-            const int id = live ? L.iv[(size_t)k * L.m + i] : 0;
-            lo[r * 7 + k] = live ? mn.menu_lo[id] : 0;
-            hi[r * 7 + k] = live ? mn.menu_hi[id] : 0;
-        }
-        counts[r] = L.counts[i];
+    for (int64_t r = 0; r < m; ++r)
+        mine_episode(mn, level, frequent_only != 0, r, N + r, types + r * 8, lo + r * 7, hi + r * 7, counts + r);
+    return EPI_OK;
+}
+
+epi_status epi_mine_read_at(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_t k, const int64_t *idx, uint8_t *N,
+                            int32_t *types, int64_t *lo, int64_t *hi, int32_t *counts) {
+    if (!ctx) return EPI_EINVAL;
+    auto it = ctx->c.mines.find(mine_id);
+    if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
+    const Mine &mn = *it->second;
+    if (level < 1 || level > (int32_t)mn.levels.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
+    const MineLevel &L = mn.levels[level - 1];
+    if (k < 0 || (k > 0 && (!idx || !N || !types || !lo || !hi || !counts))) return fail(ctx, EPI_EINVAL, "bad arguments");
+    for (int64_t r = 0; r < k; ++r) {
+        if (idx[r] < 0 || idx[r] >= L.m) return fail(ctx, EPI_EINVAL, "index %lld outside the level", (long long)idx[r]);
+        mine_episode(mn, level, false, idx[r], N + r, types + r * 8, lo + r * 7, hi + r * 7, counts + r);
     }
+    return EPI_OK;
+}
+
+epi_status epi_mine_level_bytes(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_t *alg_bytes) {
+    if (!ctx || !alg_bytes) return fail(ctx, EPI_EINVAL, "null argument");
+    auto it = ctx->c.mines.find(mine_id);
+    if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
+    const auto &lv = it->second->levels;
+    if (level < 1 || level > (int32_t)lv.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
+    *alg_bytes = lv[level - 1].alg_bytes;
     return EPI_OK;
 }
 
 epi_status epi_mine_release(epi_ctx *ctx, int32_t mine_id) {
     if (!ctx) return EPI_EINVAL;
     if (!ctx->c.mines.erase(mine_id)) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
+    return EPI_OK;
+}
+
+// ---- cost model ------------------------------------------------------------
+
+namespace {
+
+struct HostToDev {
+    DevBuf d;
+    hipError_t put(const void *h, size_t bytes, hipStream_t st) {
+        hipError_t e = d.alloc(bytes);
+        if (e != hipSuccess) return e;
+        if (bytes) e = hipMemcpyAsync(d.p, h, bytes, hipMemcpyHostToDevice, st);
+        return e;
+    }
+};
+
+epi_status need_mlp(epi_ctx *ctx, int64_t F) {
+    if (!ctx->c.mlp.ready()) return fail(ctx, EPI_ESTATE, "the cost model has not been initialised");
+    if (F >= 0 && F != ctx->c.mlp.F) return fail(ctx, EPI_EINVAL, "the cost model takes %d features", ctx->c.mlp.F);
+    return EPI_OK;
+}
+
+}  // namespace
+
+epi_status epi_mlp_init(epi_ctx *ctx, int32_t n_features, uint64_t seed) {
+    if (!ctx) return EPI_EINVAL;
+    if (n_features < 1 || n_features > 4096) return fail(ctx, EPI_EINVAL, "n_features must be in 1..4096");
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    HIPTRY(ctx, mlp_init(ctx->c.mlp, n_features, seed), "initialising the cost model");
+    return EPI_OK;
+}
+
+epi_status epi_mlp_params(epi_ctx *ctx, int32_t *n_features, int64_t *n_params) {
+    if (!ctx) return EPI_EINVAL;
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    if (n_features) *n_features = ctx->c.mlp.F;
+    if (n_params) *n_params = mlp_n_params(ctx->c.mlp.F);
+    return EPI_OK;
+}
+
+epi_status epi_mlp_get_params(epi_ctx *ctx, float *p, int64_t n) {
+    if (!ctx || !p) return fail(ctx, EPI_EINVAL, "null argument");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    if (n != mlp_n_params(ctx->c.mlp.F)) return fail(ctx, EPI_EINVAL, "expected %lld parameters",
+                                                     (long long)mlp_n_params(ctx->c.mlp.F));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->c.stream), "sync");
+    HIPTRY(ctx, hipMemcpy(p, ctx->c.mlp.p.p, sizeof(float) * n, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_mlp_set_params(epi_ctx *ctx, const float *p, int64_t n) {
+    if (!ctx || !p) return fail(ctx, EPI_EINVAL, "null argument");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    if (n != mlp_n_params(ctx->c.mlp.F)) return fail(ctx, EPI_EINVAL, "expected %lld parameters",
+                                                     (long long)mlp_n_params(ctx->c.mlp.F));
+    HIPTRY(ctx, hipMemcpy(ctx->c.mlp.p.p, p, sizeof(float) * n, hipMemcpyHostToDevice), "copy");
+    HIPTRY(ctx, hipMemset(ctx->c.mlp.m.p, 0, sizeof(float) * n), "reset");
+    HIPTRY(ctx, hipMemset(ctx->c.mlp.v.p, 0, sizeof(float) * n), "reset");
+    ctx->c.mlp.step = 0;
+    return EPI_OK;
+}
+
+epi_status epi_mlp_forward(epi_ctx *ctx, const float *X, int64_t B, float *y) {
+    if (!ctx || (B > 0 && (!X || !y))) return fail(ctx, EPI_EINVAL, "null argument");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    hipStream_t st = ctx->c.stream;
+    HostToDev dx;
+    DevBuf dy;
+    HIPTRY(ctx, dx.put(X, sizeof(float) * B * ctx->c.mlp.F, st), "copy");
+    HIPTRY(ctx, dy.alloc(sizeof(float) * B), "alloc");
+    HIPTRY(ctx, mlp_forward_device(ctx->c.mlp, dx.d.as<float>(), B, dy.as<float>(), st), "forward");
+    HIPTRY(ctx, hipStreamSynchronize(st), "sync");
+    if (B > 0) HIPTRY(ctx, hipMemcpy(y, dy.p, sizeof(float) * B, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_mlp_grad(epi_ctx *ctx, const float *X, const float *t, int64_t B, float *loss, float *g) {
+    if (!ctx || B < 1 || !X || !t || !g) return fail(ctx, EPI_EINVAL, "bad arguments");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    hipStream_t st = ctx->c.stream;
+    const int64_t np = mlp_n_params(ctx->c.mlp.F);
+    HostToDev dx, dt;
+    HIPTRY(ctx, dx.put(X, sizeof(float) * B * ctx->c.mlp.F, st), "copy");
+    HIPTRY(ctx, dt.put(t, sizeof(float) * B, st), "copy");
+    float L = 0;
+    HIPTRY(ctx, mlp_grad_device(ctx->c.mlp, dx.d.as<float>(), dt.d.as<float>(), B, ctx->c.mlp.g.as<float>(), &L, st),
+           "gradient");
+    HIPTRY(ctx, hipStreamSynchronize(st), "sync");
+    HIPTRY(ctx, hipMemcpy(g, ctx->c.mlp.g.p, sizeof(float) * np, hipMemcpyDeviceToHost), "copy");
+    if (loss) *loss = L;
+    return EPI_OK;
+}
+
+epi_status epi_mlp_adam_step(epi_ctx *ctx, const float *g, float lr) {
+    if (!ctx || !g) return fail(ctx, EPI_EINVAL, "null argument");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    const int64_t np = mlp_n_params(ctx->c.mlp.F);
+    HIPTRY(ctx, hipMemcpy(ctx->c.mlp.g.p, g, sizeof(float) * np, hipMemcpyHostToDevice), "copy");
+    ctx->c.mlp.lr = lr;
+    HIPTRY(ctx, mlp_adam_device(ctx->c.mlp, ctx->c.mlp.g.as<float>(), ctx->c.stream), "adam");
+    HIPTRY(ctx, hipStreamSynchronize(ctx->c.stream), "sync");
+    return EPI_OK;
+}
+
+epi_status epi_mlp_train(epi_ctx *ctx, const float *X, const float *t, int64_t B, int32_t epochs, int32_t batch,
+                         float lr, float *losses) {
+    if (!ctx || B < 1 || !X || !t || epochs < 1 || batch < 1) return fail(ctx, EPI_EINVAL, "bad arguments");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    hipStream_t st = ctx->c.stream;
+    Mlp &net = ctx->c.mlp;
+    net.lr = lr;
+    HostToDev dx, dt;
+    HIPTRY(ctx, dx.put(X, sizeof(float) * B * net.F, st), "copy");
+    HIPTRY(ctx, dt.put(t, sizeof(float) * B, st), "copy");
+    for (int32_t ep = 0; ep < epochs; ++ep) {
+        double acc = 0;
+        for (int64_t b0 = 0; b0 < B; b0 += batch) {
+            const int64_t nb = std::min<int64_t>(batch, B - b0);
+            float L = 0;
+            HIPTRY(ctx, mlp_grad_device(net, dx.d.as<float>() + b0 * net.F, dt.d.as<float>() + b0, nb,
+                                        net.g.as<float>(), losses ? &L : nullptr, st),
+                   "gradient");
+            HIPTRY(ctx, mlp_adam_device(net, net.g.as<float>(), st), "adam");
+            acc += (double)L * nb;
+        }
+        if (losses) losses[ep] = (float)(acc / (double)B);
+    }
+    HIPTRY(ctx, hipStreamSynchronize(st), "sync");
+    return EPI_OK;
+}
+
+epi_status epi_costmodel_features(epi_ctx *ctx, int32_t set_id, float *X, int64_t m) {
+    if (!ctx) return EPI_EINVAL;
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (cs->compact) return fail(ctx, EPI_EINVAL, "set %d has no features", set_id);
+    if (m != cs->m || (m > 0 && !X)) return fail(ctx, EPI_EINVAL, "set %d holds %lld candidates", set_id,
+                                                 (long long)cs->m);
+    Stream *s = find_stream(ctx, cs->stream_id);
+    hipStream_t st = ctx->c.stream;
+    DevBuf dX;
+    HIPTRY(ctx, dX.alloc(sizeof(float) * m * kFeatures), "alloc");
+    HIPTRY(ctx, candidate_features(*s, *cs, dX.as<float>(), st), "features");
+    std::vector<float> grouped((size_t)m * kFeatures);
+    std::vector<int32_t> orig(m);
+    if (m > 0) {
+        HIPTRY(ctx, hipMemcpy(grouped.data(), dX.p, sizeof(float) * grouped.size(), hipMemcpyDeviceToHost), "copy");
+        HIPTRY(ctx, hipMemcpy(orig.data(), cs->orig.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "copy");
+    }
+    for (int64_t i = 0; i < m; ++i)
+        std::copy(grouped.begin() + i * kFeatures, grouped.begin() + (i + 1) * kFeatures, X + (int64_t)orig[i] * kFeatures);
     return EPI_OK;
 }
 

@@ -1,0 +1,522 @@
+// Extension engine of level-wise discovery: the decomposition of Sec. IV-A
+// organised around Apriori's candidate families.
+//
+// Subproblem-1 (Sec. IV-A) needs only, for every end event x of an episode,
+// the latest start s(x) among its occurrences ending at x: an occurrence set
+// holding one such occurrence per end event has the same optimum.  For a
+// candidate alpha + (B, (lo, hi]), where alpha is a frequent episode of the
+// previous level, an event y of type B ends an occurrence iff some end event
+// x of alpha has lo < t_y - t_x <= hi, and then
+//     s(y) = max over such x of s(x).
+// Over alpha's end events s is non-decreasing in time (the latest occurrence
+// end before a window edge carries the latest start), so the maximum is taken
+// at the latest x with t_x < t_y - lo, provided t_x >= t_y - hi.  So with
+// alpha's chain list -- its end events in time order with their latest
+// starts -- one merge of two sorted lists gives s(y) for every y, and the
+// greedy of Alg. 1 over the y in time order (keep y when s(y) > the last kept
+// end, starting from minus infinity) gives the count.  This is Parallel Local
+// Tracking (Sec. IV-C) advanced by one node per level, with book-keeping of
+// start times and the end-ordered list for free.
+//
+// Level 1 counts distinct timestamps per type.  Level 2 candidates extend a
+// frequent type (its chain list is its own events, s = t).  The chain lists
+// of a level's frequent episodes are written by a second pass over those
+// episodes only, at offsets from an exclusive scan of their end-event counts
+// (the count / scan / write compaction of Sec. IV-E).
+//
+// Counting: one wave per alpha; its lanes take alpha's extensions (the
+// Apriori join's matches, minus the one repeating alpha's first type),
+// 64 at a time; every lane of the wave reads the same chain list.
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+#include <thread>
+
+#include "epi_fsm.h"
+
+namespace epi {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
+
+template <typename T>
+struct ExtArgs {
+    const T *ts;             // per-type index (time order per type)
+    const int32_t *type_off; // [K+1]
+    int64_t nA;              // number of alphas
+    // level 2 (MODE 0): alphas are frequent types
+    const uint16_t *f1;      // [nf1] frequent types
+    int32_t nf1;
+    // level >= 3 (MODE 1): alphas are frequent episodes of the previous level
+    const Pair<T> *chains;   // chain lists of the previous level's frequent episodes
+    const int64_t *coff;     // [nfprev + 1]
+    const uint16_t *ftype0;  // [nfprev] first type
+    const uint16_t *flast;   // [nfprev] last type
+    const uint8_t *fliv;     // [nfprev] last interval id
+    const int32_t *rlo, *rhi, *byprefix;
+    const int64_t *out_off;  // [nA + 1]
+    const T *menu;           // (lo, hi) pairs
+    int32_t M;
+    int32_t *counts;         // [m]
+    int32_t *nvalid;         // [m]
+    // write pass: explicit list of candidates
+    int64_t nw;
+    const int32_t *w_alpha;
+    const uint16_t *w_type;
+    const uint8_t *w_iv;
+    const int64_t *w_off;
+    Pair<T> *w_out;
+};
+
+// One candidate: merge alpha's chain list with the events of type B; returns
+// the count, the number of end events, and optionally writes the new chain.
+template <typename T, int MODE, bool WRITE>
+__device__ __forceinline__ int32_t ext_core(const ExtArgs<T> &a, int64_t alpha, int32_t B, int iv, int32_t *nval,
+                                            Pair<T> *out) {
+    constexpr T kMin = TsLimits<T>::lo();
+    const T lo = a.menu[2 * iv], hi = a.menu[2 * iv + 1];
+    // alpha's chain list
+    const T *at = nullptr;
+    const Pair<T> *ap = nullptr;
+    int32_t alen;
+    if (MODE == 0) {
+        const int32_t ty = a.f1[alpha];
+        at = a.ts + a.type_off[ty];
+        alen = a.type_off[ty + 1] - a.type_off[ty];
+    } else {
+        ap = a.chains + a.coff[alpha];
+        alen = (int32_t)(a.coff[alpha + 1] - a.coff[alpha]);
+    }
+    const T *y = a.ts + a.type_off[B];
+    const int32_t ylen = a.type_off[B + 1] - a.type_off[B];
+    int32_t p = 0, cnt = 0, nv = 0;
+    T prev_e = kMin;
+    T xt = kMin, xs = kMin;  // latest entry with time < t_y - lo (when p > 0)
+    T nt = alen > 0 ? (MODE == 0 ? at[0] : ap[0].s) : TsLimits<T>::hi();
+    for (int32_t i = 0; i < ylen; ++i) {
+        const T ty = y[i];
+        const T lim = (T)(ty - lo);
+        while (nt < lim) {
+            if (MODE == 0) {
+                xt = nt;
+                xs = nt;
+            } else {
+                xt = ap[p].s;
+                xs = ap[p].e;
+            }
+            ++p;
+            nt = p < alen ? (MODE == 0 ? at[p] : ap[p].s) : TsLimits<T>::hi();
+        }
+        if (p > 0 && xt >= (T)(ty - hi)) {
+            if (WRITE) {
+                Pair<T> v;
+                v.s = ty;
+                v.e = xs;
+                out[nv] = v;
+            }
+            ++nv;
+            if (xs > prev_e) {
+                ++cnt;
+                prev_e = ty;
+            }
+        }
+    }
+    *nval = nv;
+    return cnt;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_ext_count0(ExtArgs<T> a) {
+    const int64_t alpha = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t R = a.nf1 * a.M;
+    const int64_t o0 = a.out_off[alpha];
+    for (int32_t rb = 0; rb < R; rb += 64) {
+        const int32_t r = rb + lane;
+        if (r >= R) break;
+        const int32_t bi = r / a.M, iv = r % a.M;
+        if (bi == alpha) continue;
+        const int64_t c = o0 + (bi < alpha ? r : r - a.M);
+        int32_t nv;
+        a.counts[c] = ext_core<T, 0, false>(a, alpha, a.f1[bi], iv, &nv, nullptr);
+        a.nvalid[c] = nv;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_ext_count1(ExtArgs<T> a) {
+    const int64_t alpha = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t r0 = a.rlo[alpha], r1 = a.rhi[alpha];
+    const int64_t o0 = a.out_off[alpha];
+    const uint16_t first = a.ftype0[alpha];
+    int32_t skipped = 0;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int32_t rb = r0; rb < r1; rb += 64) {  // uniform across the wave
+        const int32_t r = rb + lane;
+        const bool in = r < r1;
+        const int32_t beta = in ? a.byprefix[r] : 0;
+        const bool excl = in && a.flast[beta] == first;
+        const uint64_t em = __ballot(excl);
+        if (in && !excl) {
+            const int64_t c = o0 + (r - r0) - skipped - __popcll(em & lt);
+            int32_t nv;
+            a.counts[c] = ext_core<T, 1, false>(a, alpha, a.flast[beta], a.fliv[beta], &nv, nullptr);
+            a.nvalid[c] = nv;
+        }
+        skipped += __popcll(em);
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_ext_write(ExtArgs<T> a) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.nw) return;
+    int32_t nv;
+    (void)ext_core<T, MODE, true>(a, a.w_alpha[f], a.w_type[f], a.w_iv[f], &nv, a.w_out + a.w_off[f]);
+}
+
+template <typename T>
+__global__ void k_level1(const T *__restrict__ ts, const int32_t *__restrict__ type_off, int32_t K,
+                         int32_t *__restrict__ counts) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    int32_t c = 0;
+    for (int32_t i = type_off[k]; i < type_off[k + 1]; ++i)
+        if (i == type_off[k] || ts[i] != ts[i - 1]) ++c;
+    counts[k] = c;
+}
+
+template <typename U>
+hipError_t upload(DevBuf &d, const std::vector<U> &h, hipStream_t st) {
+    hipError_t e = d.alloc(sizeof(U) * h.size());
+    if (e != hipSuccess) return e;
+    if (!h.empty()) e = hipMemcpyAsync(d.p, h.data(), sizeof(U) * h.size(), hipMemcpyHostToDevice, st);
+    return e;
+}
+
+int nthreads() { return (int)std::max<unsigned>(1, std::min<unsigned>(32, std::thread::hardware_concurrency())); }
+
+template <typename F>
+void parallel_for(int64_t n, F &&body) {
+    const int nt = nthreads();
+    if (n < 4096 || nt == 1) {
+        body(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int q = 0; q < nt; ++q) {
+        const int64_t x0 = q * chunk, x1 = std::min(n, x0 + chunk);
+        if (x0 >= x1) break;
+        th.emplace_back([&, x0, x1] { body(x0, x1); });
+    }
+    for (auto &t : th) t.join();
+}
+
+// local extension index e of alpha (level >= 3) -> position r in byprefix
+int32_t ext_position(const MineLevel &L, const MineLevel &P, int64_t alpha, int64_t e) {
+    const uint16_t first = P.ftypes[alpha];  // row 0 of the previous level
+    int64_t k = -1;
+    for (int32_t r = L.rlo[alpha]; r < L.rhi[alpha]; ++r) {
+        const int32_t beta = L.byprefix[r];
+        if (P.ftypes[(size_t)(P.N - 1) * P.nf + beta] == first) continue;
+        if (++k == e) return r;
+    }
+    return -1;
+}
+
+template <typename T>
+hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st) {
+    (void)d_flags;
+    hipError_t e;
+    MineLevel &P = mn.levels.back();  // level N-1
+    MineLevel L;
+    L.N = N;
+    L.implicit = true;
+    const int M = (int)mn.menu_lo.size();
+    const size_t tsb = sizeof(T);
+    auto t0 = Clock::now();
+    const std::vector<int32_t> &off = s.h_off;
+    auto ntype = [&](int32_t ty) { return (int64_t)off[ty + 1] - off[ty]; };
+    // ---- the candidate family of each alpha
+    int64_t nA = P.nf;
+    L.out_off.assign(nA + 1, 0);
+    if (N == 2) {
+        for (int64_t a = 0; a < nA; ++a) L.out_off[a + 1] = L.out_off[a] + (nA - 1) * M;
+    } else {
+        const int Pn = P.N;  // episodes of the previous level have Pn = N-1 nodes
+        auto pty = [&](int64_t i, int k) { return P.ftypes[(size_t)k * P.nf + i]; };
+        auto piv = [&](int64_t i, int k) { return P.fiv[(size_t)k * P.nf + i]; };
+        L.byprefix.resize(P.nf);
+        std::iota(L.byprefix.begin(), L.byprefix.end(), 0);
+        // prefix of beta = its first Pn-1 nodes and Pn-2 intervals
+        auto prefix_less = [&](int32_t a, int32_t b) {
+            for (int k = 0; k < Pn - 1; ++k) {
+                if (pty(a, k) != pty(b, k)) return pty(a, k) < pty(b, k);
+                if (k < Pn - 2 && piv(a, k) != piv(b, k)) return piv(a, k) < piv(b, k);
+            }
+            return false;
+        };
+        std::sort(L.byprefix.begin(), L.byprefix.end(), prefix_less);
+        // compare prefix(beta) with suffix(alpha) = last Pn-1 nodes of alpha
+        auto cmp = [&](int32_t beta, int64_t alpha) {
+            for (int k = 0; k < Pn - 1; ++k) {
+                if (pty(beta, k) != pty(alpha, k + 1)) return pty(beta, k) < pty(alpha, k + 1) ? -1 : 1;
+                if (k < Pn - 2 && piv(beta, k) != piv(alpha, k + 1)) return piv(beta, k) < piv(alpha, k + 1) ? -1 : 1;
+            }
+            return 0;
+        };
+        L.rlo.resize(nA);
+        L.rhi.resize(nA);
+        std::vector<int64_t> cnt(nA, 0);
+        parallel_for(nA, [&](int64_t x0, int64_t x1) {
+            for (int64_t a = x0; a < x1; ++a) {
+                const auto lo = std::partition_point(L.byprefix.begin(), L.byprefix.end(),
+                                                     [&](int32_t b) { return cmp(b, a) < 0; });
+                const auto hi =
+                    std::partition_point(lo, L.byprefix.end(), [&](int32_t b) { return cmp(b, a) == 0; });
+                L.rlo[a] = (int32_t)(lo - L.byprefix.begin());
+                L.rhi[a] = (int32_t)(hi - L.byprefix.begin());
+                int64_t c = 0;
+                for (int32_t r = L.rlo[a]; r < L.rhi[a]; ++r)
+                    if (pty(L.byprefix[r], Pn - 1) != pty(a, 0)) ++c;
+                cnt[a] = c;
+            }
+        });
+        for (int64_t a = 0; a < nA; ++a) L.out_off[a + 1] = L.out_off[a] + cnt[a];
+    }
+    const int64_t m = L.out_off[nA];
+    L.m = m;
+    // bytes read and written per candidate: events of the new node's type,
+    // alpha's chain list (pairs), count and end-event count
+    {
+        std::vector<int64_t> part(nA, 0);
+        parallel_for(nA, [&](int64_t x0, int64_t x1) {
+            for (int64_t a = x0; a < x1; ++a) {
+                const int64_t k = L.out_off[a + 1] - L.out_off[a];
+                if (k == 0) continue;
+                int64_t b = 0;
+                const int64_t alen = N == 2 ? ntype(P.ftypes[a]) : P.h_chain_off[a + 1] - P.h_chain_off[a];
+                b += k * (alen * (N == 2 ? 1 : 2) * (int64_t)tsb + 8);
+                if (N == 2) {
+                    for (int64_t bi = 0; bi < nA; ++bi)
+                        if (bi != a) b += M * ntype(P.ftypes[bi]) * (int64_t)tsb;
+                } else {
+                    for (int32_t r = L.rlo[a]; r < L.rhi[a]; ++r) {
+                        const int32_t beta = L.byprefix[r];
+                        if (P.ftypes[(size_t)(P.N - 1) * P.nf + beta] == P.ftypes[a]) continue;
+                        b += ntype(P.ftypes[(size_t)(P.N - 1) * P.nf + beta]) * (int64_t)tsb;
+                    }
+                }
+                part[a] = b;
+            }
+        });
+        for (int64_t a = 0; a < nA; ++a) L.alg_bytes += part[a];
+    }
+    // ---- device inputs
+    DevBuf d_out_off, d_f1, d_menu, d_rlo, d_rhi, d_by, d_f0, d_fl, d_fliv, d_counts, d_nval;
+    std::vector<T> menu(2 * M);
+    for (int i = 0; i < M; ++i) {
+        menu[2 * i] = (T)mn.menu_lo[i];
+        menu[2 * i + 1] = (T)mn.menu_hi[i];
+    }
+    if ((e = upload(d_out_off, L.out_off, st)) != hipSuccess) return e;
+    if ((e = upload(d_menu, menu, st)) != hipSuccess) return e;
+    ExtArgs<T> a{};
+    a.ts = s.ts_by_type.as<T>();
+    a.type_off = s.type_off.as<int32_t>();
+    a.nA = nA;
+    a.out_off = d_out_off.as<int64_t>();
+    a.menu = d_menu.as<T>();
+    a.M = M;
+    if (N == 2) {
+        std::vector<uint16_t> f1(P.ftypes.begin(), P.ftypes.begin() + P.nf);
+        if ((e = upload(d_f1, f1, st)) != hipSuccess) return e;
+        a.f1 = d_f1.as<uint16_t>();
+        a.nf1 = (int32_t)P.nf;
+    } else {
+        std::vector<uint16_t> f0(P.ftypes.begin(), P.ftypes.begin() + P.nf);
+        std::vector<uint16_t> fl(P.ftypes.begin() + (size_t)(P.N - 1) * P.nf, P.ftypes.begin() + (size_t)P.N * P.nf);
+        std::vector<uint8_t> fliv(P.fiv.begin() + (size_t)(P.N - 2) * P.nf, P.fiv.begin() + (size_t)(P.N - 1) * P.nf);
+        if ((e = upload(d_f0, f0, st)) != hipSuccess) return e;
+        if ((e = upload(d_fl, fl, st)) != hipSuccess) return e;
+        if ((e = upload(d_fliv, fliv, st)) != hipSuccess) return e;
+        if ((e = upload(d_rlo, L.rlo, st)) != hipSuccess) return e;
+        if ((e = upload(d_rhi, L.rhi, st)) != hipSuccess) return e;
+        if ((e = upload(d_by, L.byprefix, st)) != hipSuccess) return e;
+        a.chains = P.chains.as<Pair<T>>();
+        a.coff = P.chain_off.as<int64_t>();
+        a.ftype0 = d_f0.as<uint16_t>();
+        a.flast = d_fl.as<uint16_t>();
+        a.fliv = d_fliv.as<uint8_t>();
+        a.rlo = d_rlo.as<int32_t>();
+        a.rhi = d_rhi.as<int32_t>();
+        a.byprefix = d_by.as<int32_t>();
+    }
+    if ((e = d_counts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    if ((e = d_nval.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    a.counts = d_counts.as<int32_t>();
+    a.nvalid = d_nval.as<int32_t>();
+    L.gen_ms = ms_since(t0);
+    auto t1 = Clock::now();
+    // ---- count
+    hipEvent_t ev0, ev1;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
+    (void)hipEventRecord(ev0, st);
+    if (m > 0) {
+        if (N == 2) k_ext_count0<T><<<(unsigned)nA, 64, 0, st>>>(a);
+        else k_ext_count1<T><<<(unsigned)nA, 64, 0, st>>>(a);
+    }
+    (void)hipEventRecord(ev1, st);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    float kms = 0;
+    if (e == hipSuccess) (void)hipEventElapsedTime(&kms, ev0, ev1);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (e != hipSuccess) return e;
+    L.kernel_ms = kms;
+    L.counts.resize(m);
+    std::vector<int32_t> nval(m);
+    if (m > 0) {
+        if ((e = hipMemcpy(L.counts.data(), d_counts.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpy(nval.data(), d_nval.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost)) != hipSuccess)
+            return e;
+    }
+    // ---- frequent episodes: reconstruct them and write their chain lists
+    for (int64_t c = 0; c < m; ++c)
+        if (L.counts[c] > mn.threshold) L.freq.push_back(c);
+    const int64_t nf = (int64_t)L.freq.size();
+    L.nf = nf;
+    L.ftypes.assign((size_t)N * nf, 0);
+    L.fiv.assign((size_t)(N - 1) * nf, 0);
+    std::vector<int32_t> w_alpha(nf);
+    std::vector<uint16_t> w_type(nf);
+    std::vector<uint8_t> w_iv(nf);
+    parallel_for(nf, [&](int64_t x0, int64_t x1) {
+        for (int64_t f = x0; f < x1; ++f) {
+            const int64_t c = L.freq[f];
+            const int64_t alpha = std::upper_bound(L.out_off.begin(), L.out_off.end(), c) - L.out_off.begin() - 1;
+            const int64_t le = c - L.out_off[alpha];
+            uint16_t bt;
+            uint8_t biv;
+            if (N == 2) {
+                int64_t r = le < alpha * M ? le : le + M;
+                bt = P.ftypes[r / M];
+                biv = (uint8_t)(r % M);
+            } else {
+                const int32_t r = ext_position(L, P, alpha, le);
+                const int32_t beta = L.byprefix[r];
+                bt = P.ftypes[(size_t)(P.N - 1) * P.nf + beta];
+                biv = P.fiv[(size_t)(P.N - 2) * P.nf + beta];
+            }
+            for (int k = 0; k < N - 1; ++k) L.ftypes[(size_t)k * nf + f] = P.ftypes[(size_t)k * P.nf + alpha];
+            L.ftypes[(size_t)(N - 1) * nf + f] = bt;
+            for (int k = 0; k < N - 2; ++k) L.fiv[(size_t)k * nf + f] = P.fiv[(size_t)k * P.nf + alpha];
+            L.fiv[(size_t)(N - 2) * nf + f] = biv;
+            w_alpha[f] = (int32_t)alpha;
+            w_type[f] = bt;
+            w_iv[f] = biv;
+        }
+    });
+    L.h_chain_off.assign(nf + 1, 0);
+    for (int64_t f = 0; f < nf; ++f) L.h_chain_off[f + 1] = L.h_chain_off[f] + nval[L.freq[f]];
+    DevBuf d_wa, d_wt, d_wi;
+    if ((e = upload(d_wa, w_alpha, st)) != hipSuccess) return e;
+    if ((e = upload(d_wt, w_type, st)) != hipSuccess) return e;
+    if ((e = upload(d_wi, w_iv, st)) != hipSuccess) return e;
+    if ((e = upload(L.chain_off, L.h_chain_off, st)) != hipSuccess) return e;
+    if ((e = L.chains.alloc(sizeof(Pair<T>) * (size_t)L.h_chain_off[nf])) != hipSuccess) return e;
+    if (nf > 0) {
+        a.nw = nf;
+        a.w_alpha = d_wa.as<int32_t>();
+        a.w_type = d_wt.as<uint16_t>();
+        a.w_iv = d_wi.as<uint8_t>();
+        a.w_off = L.chain_off.as<int64_t>();
+        a.w_out = L.chains.as<Pair<T>>();
+        const unsigned blocks = (unsigned)((nf + 255) / 256);
+        if (N == 2) k_ext_write<T, 0><<<blocks, 256, 0, st>>>(a);
+        else k_ext_write<T, 1><<<blocks, 256, 0, st>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    L.count_ms = ms_since(t1);
+    // chain lists two levels back are no longer needed
+    if (mn.levels.size() >= 2) {
+        MineLevel &Q = mn.levels[mn.levels.size() - 2];
+        Q.chains.reset();
+        Q.chain_off.reset();
+    }
+    mn.levels.push_back(std::move(L));
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t level1_t(const Stream &s, Mine &mn, hipStream_t st) {
+    hipError_t e;
+    MineLevel L;
+    L.N = 1;
+    L.m = s.K;
+    L.implicit = false;
+    auto t1 = Clock::now();
+    DevBuf d_counts;
+    if ((e = d_counts.alloc(sizeof(int32_t) * s.K)) != hipSuccess) return e;
+    k_level1<T><<<(s.K + 63) / 64, 64, 0, st>>>(s.ts_by_type.as<T>(), s.type_off.as<int32_t>(), s.K,
+                                              d_counts.as<int32_t>());
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    L.counts.resize(s.K);
+    if ((e = hipMemcpyAsync(L.counts.data(), d_counts.p, sizeof(int32_t) * s.K, hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    L.count_ms = ms_since(t1);
+    L.types.resize(s.K);
+    for (int32_t k = 0; k < s.K; ++k) L.types[k] = (uint16_t)k;
+    for (int32_t k = 0; k < s.K; ++k)
+        if (L.counts[k] > mn.threshold) L.freq.push_back(k);
+    L.nf = (int64_t)L.freq.size();
+    for (int64_t f : L.freq) L.ftypes.push_back((uint16_t)f);
+    L.alg_bytes = s.n * (int64_t)s.ts_bytes() + 4 * (int64_t)s.K;
+    mn.levels.push_back(std::move(L));
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st) {
+    if (s.ts_kind == EPI_TS_I64) return level1_t<int64_t>(s, mn, st);
+    return level1_t<int32_t>(s, mn, st);
+}
+
+hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st) {
+    if (s.ts_kind == EPI_TS_I64) return level_t<int64_t>(s, mn, N, d_flags, st);
+    return level_t<int32_t>(s, mn, N, d_flags, st);
+}
+
+void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs) {
+    const MineLevel &L = mn.levels[level - 1];
+    const MineLevel &P = mn.levels[level - 2];
+    const int M = (int)mn.menu_lo.size();
+    const int N = L.N;
+    const int64_t alpha = std::upper_bound(L.out_off.begin(), L.out_off.end(), c) - L.out_off.begin() - 1;
+    const int64_t le = c - L.out_off[alpha];
+    for (int k = 0; k < N - 1; ++k) types[k] = P.ftypes[(size_t)k * P.nf + alpha];
+    for (int k = 0; k < N - 2; ++k) ivs[k] = P.fiv[(size_t)k * P.nf + alpha];
+    if (N == 2) {
+        const int64_t r = le < alpha * M ? le : le + M;
+        types[1] = P.ftypes[r / M];
+        ivs[0] = (int)(r % M);
+    } else {
+        const int32_t r = ext_position(L, P, alpha, le);
+        const int32_t beta = L.byprefix[r];
+        types[N - 1] = P.ftypes[(size_t)(P.N - 1) * P.nf + beta];
+        ivs[N - 2] = P.fiv[(size_t)(P.N - 2) * P.nf + beta];
+    }
+}
+
+}  // namespace epi

@@ -18,6 +18,9 @@ constexpr int kMaxN = EPI_MAX_N;
 constexpr int kMaxK = 4096;        // LDS histogram bound of the index build
 constexpr int kMaxQueue = 16;      // deepest merged-interval ring (LDS) per node
 constexpr int kTile = 2048;        // events per stream tile
+constexpr int kMlpHidden = 64;     // hidden units of the cost model
+constexpr int kFeatures = 23;      // cost-model features per candidate
+constexpr int kWork = 5;           // work-log counters per candidate
 
 // Device error flags (int32 each), set by kernels with atomicOr / atomicAdd.
 enum DevFlag { kFlagQueueOverflow = 0, kFlagUnsorted = 1, kFlagBadType = 2, kFlagBadTime = 3, kNumFlags = 4 };
@@ -35,6 +38,20 @@ struct DevBuf {
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            reset();
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
     ~DevBuf() { reset(); }
     void reset() {
         if (p) (void)hipFree(p);
@@ -117,6 +134,7 @@ struct CountOptions {
     int lanes = 0;                 // 0: automatic; else lanes per workgroup (64, 128 or 256)
     int64_t target_lanes = 262144; // automatic segmentation aims at this many (candidate, segment) lanes
     bool pair_filter = true;       // level-wise discovery: skip events with no constrained neighbour
+    int mine_engine = 1;           // level-wise discovery: 1 extension engine, 0 state machines
     int64_t pair_filter_max_bytes = int64_t(1) << 30;
 };
 
@@ -125,20 +143,47 @@ struct CountOptions {
 struct MineLevel {
     int N = 0;
     int64_t m = 0;
-    std::vector<uint16_t> types;  // [N][m]
-    std::vector<uint8_t> iv;      // [N-1][m]
+    // explicit candidates (state-machine engine): types [N][m], ids [N-1][m]
+    std::vector<uint16_t> types;
+    std::vector<uint8_t> iv;
     std::vector<int32_t> counts;  // [m]
     std::vector<int64_t> freq;    // indices with count > threshold
     double gen_ms = 0, count_ms = 0, kernel_ms = 0;
+    int64_t alg_bytes = 0;        // bytes the counting method must read and write
+    // Extension engine: candidate c of level N >= 2 is alpha + one node, where
+    // alpha indexes the frequent episodes of level N-1 (alpha-major order).
+    bool implicit = false;
+    std::vector<int64_t> out_off;  // [nA + 1] first candidate of each alpha
+    std::vector<int32_t> rlo, rhi; // level >= 3: range of alpha's extensions in byprefix
+    std::vector<int32_t> byprefix; // level >= 3: level N-1 frequent, ordered by first N-2 nodes
+    // frequent episodes of this level (structure of arrays) and their chain
+    // lists: for every end event with an occurrence, (end time, latest start)
+    int64_t nf = 0;
+    std::vector<uint16_t> ftypes;  // [N][nf]
+    std::vector<uint8_t> fiv;      // [N-1][nf]
+    DevBuf chains;                 // Pair<T>[...]
+    DevBuf chain_off;              // int64 [nf + 1]
+    std::vector<int64_t> h_chain_off;
 };
 
 struct Mine {
+    int engine = 1;  // 1: extension engine (default), 0: state-machine engine
     int32_t stream_id = 0;
     std::vector<int64_t> menu_lo, menu_hi;
     int64_t threshold = 0;
     std::vector<MineLevel> levels;
     DevBuf pred_bits, succ_bits;  // pair-existence bitmaps of the menu (may be empty)
     double bits_ms = 0;
+};
+
+// Cost model (epi_mlp.hip): parameters, Adam moments, gradient, activations.
+struct Mlp {
+    int F = 0;
+    int step = 0;
+    float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    DevBuf p, m, v, g, act;
+    size_t cap = 0;
+    bool ready() const { return p.p != nullptr; }
 };
 
 struct Ctx {
@@ -151,6 +196,7 @@ struct Ctx {
     int32_t next_id = 1;
     DevBuf flags;  // int32[kNumFlags]
     CountOptions opt;
+    Mlp mlp;
 };
 
 // Queue capacity bound of one constraint (lo, hi]: at most
@@ -170,6 +216,23 @@ hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, in
 hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const CountOptions &opt, int32_t *d_flags,
                             hipStream_t st);
 int queue_class_of(int64_t bound);
+// Extension engine of level-wise discovery (epi_extend.hip): count level 1,
+// then count level N (>= 2) from level N-1's frequent episodes and chain lists,
+// select its frequent episodes and write their chain lists.
+hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st);
+hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st);
+// Reconstruct candidate c of an implicit level: types[8], interval ids[7].
+void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs);
+// Cost model (epi_mlp.hip).
+int64_t mlp_n_params(int F);
+hipError_t mlp_init(Mlp &net, int F, uint64_t seed);
+hipError_t mlp_forward_device(Mlp &net, const float *dX, int64_t B, float *dy, hipStream_t st);
+hipError_t mlp_grad_device(Mlp &net, const float *dX, const float *dt, int64_t B, float *dg, float *loss,
+                           hipStream_t st);
+hipError_t mlp_adam_device(Mlp &net, const float *dg, hipStream_t st);
+// Cost-model features of every candidate of a set, in grouped slot order
+// (float [G][kFeatures]) (epi_sched.hip).
+hipError_t candidate_features(const Stream &s, const CandSet &c, float *dX, hipStream_t st);
 // Pair-existence bitmaps of an interval menu over a stream (epi_pairs.hip).
 hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st);
 // Candidate generation of level-wise discovery (epi_mine.hip).

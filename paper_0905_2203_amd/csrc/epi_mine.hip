@@ -87,6 +87,15 @@ hipError_t count_level_t(const Stream &s, const Mine &mn, MineLevel &L, const Co
         return e;
     L.kernel_ms = kms;
     L.count_ms = ms_since(t0);
+    // bytes the state-machine method reads per candidate: the times of each of
+    // its N types, its descriptor, and its count
+    int64_t ab = 0;
+    for (int k = 0; k < L.N; ++k)
+        for (int64_t i = 0; i < m; ++i) {
+            const int ty = L.types[(size_t)k * m + i];
+            ab += (int64_t)(s.h_off[ty + 1] - s.h_off[ty]) * (int64_t)sizeof(T);
+        }
+    L.alg_bytes = ab + m * (int64_t)(2 * L.N + (L.N - 1) + 4);
     return hipSuccess;
 }
 

@@ -42,12 +42,16 @@ EXPORTS = [
     "epi_load_stream", "epi_load_stream_device", "epi_stream_info", "epi_read_type_index",
     "epi_release_stream", "epi_submit_candidates", "epi_release_set",
     "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device",
-    "epi_mine", "epi_mine_levels", "epi_mine_level_info", "epi_mine_read", "epi_mine_release",
+    "epi_mine", "epi_mine_levels", "epi_mine_level_info", "epi_mine_read", "epi_mine_read_at",
+    "epi_mine_level_bytes", "epi_mine_release",
+    "epi_mlp_init", "epi_mlp_params", "epi_mlp_get_params", "epi_mlp_set_params", "epi_mlp_forward",
+    "epi_mlp_grad", "epi_mlp_adam_step", "epi_mlp_train", "epi_costmodel_features",
 ]
 EPI_OPT_SEGMENTS = 1
 EPI_OPT_LANES = 2
 EPI_OPT_TARGET_LANES = 3
 EPI_OPT_PAIR_FILTER = 4
+EPI_OPT_MINE_ENGINE = 5
 
 
 class EpiError(RuntimeError):
@@ -99,6 +103,17 @@ def lib():
             "epi_mine_level_info": ([P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
             "epi_mine_read": ([P, I32, I32, INT, I64, P, P, P, P, P], I32),
             "epi_mine_release": ([P, I32], I32),
+            "epi_mine_read_at": ([P, I32, I32, I64, P, P, P, P, P, P], I32),
+            "epi_mine_level_bytes": ([P, I32, I32, ctypes.POINTER(I64)], I32),
+            "epi_mlp_init": ([P, I32, ctypes.c_uint64], I32),
+            "epi_mlp_params": ([P, ctypes.POINTER(I32), ctypes.POINTER(I64)], I32),
+            "epi_mlp_get_params": ([P, P, I64], I32),
+            "epi_mlp_set_params": ([P, P, I64], I32),
+            "epi_mlp_forward": ([P, P, I64, P], I32),
+            "epi_mlp_grad": ([P, P, P, I64, ctypes.POINTER(ctypes.c_float), P], I32),
+            "epi_mlp_adam_step": ([P, P, ctypes.c_float], I32),
+            "epi_mlp_train": ([P, P, P, I64, I32, I32, ctypes.c_float, P], I32),
+            "epi_costmodel_features": ([P, I32, P, I64], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -286,5 +301,71 @@ class Context:
                                         _ptr(c["types"]), _ptr(c["lo"]), _ptr(c["hi"]), _ptr(counts)))
         return c, counts
 
+    def epi_mine_read_at(self, mid: int, level: int, idx):
+        idx = np.ascontiguousarray(idx, np.int64)
+        k = idx.size
+        c = dict(N=np.zeros(k, np.uint8), types=np.zeros((k, 8), np.int32), lo=np.zeros((k, 7), np.int64),
+                 hi=np.zeros((k, 7), np.int64))
+        counts = np.zeros(k, np.int32)
+        self._check(lib().epi_mine_read_at(self.h, int(mid), int(level), k, _ptr(idx), _ptr(c["N"]),
+                                           _ptr(c["types"]), _ptr(c["lo"]), _ptr(c["hi"]), _ptr(counts)))
+        return c, counts
+
+    def epi_mine_level_bytes(self, mid: int, level: int) -> int:
+        v = I64()
+        self._check(lib().epi_mine_level_bytes(self.h, int(mid), int(level), ctypes.byref(v)))
+        return v.value
+
     def epi_mine_release(self, mid: int):
         self._check(lib().epi_mine_release(self.h, int(mid)))
+
+    # cost model ---------------------------------------------------------------
+    def epi_mlp_init(self, n_features: int, seed: int):
+        self._check(lib().epi_mlp_init(self.h, int(n_features), int(seed)))
+
+    def epi_mlp_params(self):
+        f, n = I32(), I64()
+        self._check(lib().epi_mlp_params(self.h, ctypes.byref(f), ctypes.byref(n)))
+        return f.value, n.value
+
+    def epi_mlp_get_params(self) -> np.ndarray:
+        _, n = self.epi_mlp_params()
+        p = np.zeros(n, np.float32)
+        self._check(lib().epi_mlp_get_params(self.h, _ptr(p), n))
+        return p
+
+    def epi_mlp_set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self._check(lib().epi_mlp_set_params(self.h, _ptr(p), p.size))
+
+    def epi_mlp_forward(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.zeros(X.shape[0], np.float32)
+        self._check(lib().epi_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(y)))
+        return y
+
+    def epi_mlp_grad(self, X, t):
+        X = np.ascontiguousarray(X, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        _, n = self.epi_mlp_params()
+        g = np.zeros(n, np.float32)
+        L = ctypes.c_float()
+        self._check(lib().epi_mlp_grad(self.h, _ptr(X), _ptr(t), X.shape[0], ctypes.byref(L), _ptr(g)))
+        return float(L.value), g
+
+    def epi_mlp_adam_step(self, g, lr: float):
+        g = np.ascontiguousarray(g, np.float32)
+        self._check(lib().epi_mlp_adam_step(self.h, _ptr(g), float(lr)))
+
+    def epi_mlp_train(self, X, t, epochs: int, batch: int, lr: float) -> np.ndarray:
+        X = np.ascontiguousarray(X, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        losses = np.zeros(int(epochs), np.float32)
+        self._check(lib().epi_mlp_train(self.h, _ptr(X), _ptr(t), X.shape[0], int(epochs), int(batch), float(lr),
+                                        _ptr(losses)))
+        return losses
+
+    def epi_costmodel_features(self, set_id: int, m: int) -> np.ndarray:
+        X = np.zeros((int(m), 23), np.float32)
+        self._check(lib().epi_costmodel_features(self.h, int(set_id), _ptr(X), int(m)))
+        return X

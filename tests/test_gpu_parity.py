@@ -235,7 +235,8 @@ def _episode_key(c, i):
 _MINING_REF = {}
 
 
-@pytest.mark.parametrize("opts", [{}, {"filter": 0}, {"segments": 5}], ids=["default", "nofilter", "segments5"])
+@pytest.mark.parametrize("opts", [{}, {"engine": 0}, {"engine": 0, "filter": 0}, {"engine": 0, "segments": 5}],
+                         ids=["extend", "fsm", "fsm-nofilter", "fsm-segments5"])
 def test_levelwise_mining_matches_oracle(ctx, opts):
     """Every level's candidates and counts, and the frequent sets, equal the
     oracle's level-wise discovery (reduced mining workload); with and without
@@ -254,12 +255,14 @@ def test_levelwise_mining_matches_oracle(ctx, opts):
     say(f"oracle levels: {[len(r['counts']) for r in ref]} opts={opts}")
     ctx.epi_set_option(epi.EPI_OPT_PAIR_FILTER, opts.get("filter", 1))
     ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, opts.get("segments", 0))
+    ctx.epi_set_option(epi.EPI_OPT_MINE_ENGINE, opts.get("engine", 1))
     sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
     try:
         mid = ctx.epi_mine(sid, menu, 5, theta)
     finally:
         ctx.epi_set_option(epi.EPI_OPT_PAIR_FILTER, 1)
         ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+        ctx.epi_set_option(epi.EPI_OPT_MINE_ENGINE, 1)
     nl = ctx.epi_mine_levels(mid)
     assert nl == len(ref)
     for L in range(1, nl + 1):
@@ -269,8 +272,13 @@ def test_levelwise_mining_matches_oracle(ctx, opts):
         for (ty, iv), cnt in ref[L - 1]["counts"].items():
             want[(ty, tuple(menu[v][0] for v in iv), tuple(menu[v][1] for v in iv))] = cnt
         assert got == want, f"level {L}"
-        fc, _ = ctx.epi_mine_read(mid, L, frequent_only=True)
+        fc, fcounts = ctx.epi_mine_read(mid, L, frequent_only=True)
         assert fc["N"].size == len(ref[L - 1]["frequent"])
+        fgot = {_episode_key(fc, i): int(fcounts[i]) for i in range(fc["N"].size)}
+        assert all(want[k] == v and v > theta for k, v in fgot.items())
+        idx = np.arange(0, c["N"].size, 7)
+        sc, scounts = ctx.epi_mine_read_at(mid, L, idx)
+        assert all(_episode_key(sc, r) == _episode_key(c, i) and scounts[r] == counts[i] for r, i in enumerate(idx))
         say(f"level {L}: {c['N'].size} candidates, {fc['N'].size} frequent")
     ctx.epi_mine_release(mid)
     ctx.epi_release_stream(sid)
