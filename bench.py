@@ -61,6 +61,92 @@ def profiled_traffic(kernel_name):
     return None
 
 
+def _timed(ctx, fn, reps):
+    import torch
+
+    out = []
+    for _ in range(reps):
+        ctx.epi_sync()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        fn()
+        ctx.epi_sync()
+        out.append(time.perf_counter() - a)
+    return float(np.median(out))
+
+
+def ablation(k, scale, reps):
+    """Plain engine vs the batched persistent engine under round-robin, the
+    event-count heuristic and the learned cost model, on workload preset k.
+    Every mode's counts are checked equal; one JSON line per preset."""
+    import spikegen as sg
+    from paper_0905_2203_amd import epi
+
+    ctx = epi.Context(0)
+    if k == 3:
+        sets = []
+        for r in range(16):
+            s = sg.config_stream(3, scale=scale, recording=r)
+            sets.append((s, sg.config_candidates(3, s, scale=scale, recording=r)))
+        train_sets = []
+        for r in range(4):
+            s, _ = sets[r]
+            train_sets.append((r, sg.random_candidates(sg.rng_for(3, offset=3000 + r), max(int(5000 * scale), 64), 60,
+                                                       2, 8, 1_000_000)))
+    else:
+        s = sg.config_stream(k, scale=scale)
+        sets = [(s, sg.config_candidates(k, s, scale=scale))]
+        if k == 4:
+            train_sets = [(0, sg.config_candidates(4, s, scale=scale, training=True))]
+        else:
+            train_sets = [(0, sg.random_candidates(sg.rng_for(k, offset=100), max(int(50_000 * scale), 64), s["K"], 2,
+                                                   8, 1_000_000))]
+    log(f"ablation preset {k}: {len(sets)} sets, {sum(c['N'].size for _, c in sets)} candidates")
+    sids = [ctx.epi_load_stream(s["types"], s["times"], s["K"]) for s, _ in sets]
+    cids = [ctx.epi_submit_candidates(sid, c) for sid, (_, c) in zip(sids, sets)]
+    units = sum(c["N"].size * s["types"].size for s, c in sets)
+    res = {}
+
+    def counts():
+        return [ctx.epi_read_counts(cid, c["N"].size) for cid, (_, c) in zip(cids, sets)]
+
+    res["plain"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_PLAIN), reps)
+    ref = counts()
+    for name, sched in (("batched_rr", epi.EPI_SCHED_RR), ("batched_heuristic", epi.EPI_SCHED_HEURISTIC)):
+        res[name] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=sched), reps)
+        assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), name
+        log(f"  {name}: {res[name]:.3f}s")
+    # learned: work log of disjoint training candidates on the same streams
+    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)  # log each episode's own work
+    a = time.perf_counter()
+    tids = [ctx.epi_submit_candidates(sids[r], c) for r, c in train_sets]
+    ctx.epi_count(tids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
+    losses = ctx.epi_costmodel_train(tids, epochs=40, seed=7)
+    train_s = time.perf_counter() - a
+    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+    res["batched_learned"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                               sched=epi.EPI_SCHED_LEARNED), reps)
+    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "learned"
+    log(f"  plain {res['plain']:.3f}s learned {res['batched_learned']:.3f}s (training {train_s:.1f}s)")
+    line = {
+        "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
+        "ablation_preset": k, "scale": scale, "unit": "cand*ev/s",
+        "value": {m: units / t for m, t in res.items()},
+        "seconds": res,
+        "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
+        "learned_vs_heuristic": res["batched_heuristic"] / res["batched_learned"],
+        "learned_vs_plain": res["plain"] / res["batched_learned"],
+        "cost_model": {"train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                       "train_candidates": int(sum(c["N"].size for _, c in train_sets))},
+        "counts_equal_across_modes": True,
+        "candidates": int(sum(c["N"].size for _, c in sets)), "events": int(sum(s["types"].size for s, _ in sets)),
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,7 +156,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="level-3 candidates timed on the CPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (scale reference for HBM byte counters)")
+    ap.add_argument("--ablation", default="",
+                    help="comma list of workload presets (3, 4, 5): plain vs batched schedules, one JSON line each")
+    ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
     args = ap.parse_args()
+    if args.ablation:
+        for k in [int(x) for x in args.ablation.split(",") if x]:
+            ablation(k, args.abl_scale, max(1, args.steps))
+        return
     if args.calibrate_copy:
         import torch
 

@@ -58,7 +58,7 @@ enum {
 
 enum { EPI_TS_I32 = 0, EPI_TS_I64 = 1 };
 enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1 };
-enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1 };
+enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1, EPI_SCHED_HEURISTIC = 2 };
 
 #define EPI_MAX_N 8 /* largest episode size */
 
@@ -148,9 +148,20 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  * ---------------------------------------------------------------------- */
 
 /* Enqueue the count of k candidate sets on `hip_stream` (null = the
- * context's stream).  Asynchronous.  mode: EPI_MODE_PLAIN (one launch per
- * set and episode-size class) or EPI_MODE_BATCHED (one persistent launch over
- * all sets); sched: EPI_SCHED_RR or EPI_SCHED_LEARNED (batched mode only).
+ * context's stream).  mode:
+ *   EPI_MODE_PLAIN    one launch per set and episode-size class, candidates
+ *                     in submission order (asynchronous);
+ *   EPI_MODE_BATCHED  all sets (possibly on different streams of one
+ *                     timestamp kind) in one captured graph: one persistent
+ *                     kernel per episode size pulls (set, lane block,
+ *                     segment) work items from a device queue, then the
+ *                     segmented ones are reconciled (returns when done).
+ * sched (batched mode): EPI_SCHED_RR keeps submission order;
+ * EPI_SCHED_LEARNED orders each class's episodes by the cost model's
+ * predicted work (see epi_costmodel_train; without a trained model it falls
+ * back to EPI_SCHED_RR), cuts costly lane blocks into more time segments and
+ * queues items longest first; EPI_SCHED_HEURISTIC does the same with the
+ * sum of the types' event counts as the cost.
  * The counts never depend on mode or sched. */
 epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched,
                      void *hip_stream);
@@ -174,10 +185,30 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *                         previous level's chain lists (decomposition of
  *                         Sec. IV-A, one merge per candidate); 0 counts every
  *                         candidate with the state machines of epi_count
+ *   EPI_OPT_WORKLOG       1 / 0 (default): counts also record, per episode,
+ *                         kWork = 5 int32 counters (events visited, partial
+ *                         occurrences recorded, predecessor queries,
+ *                         completions, deepest interval ring) and, in batched
+ *                         mode, a wall-clock start/end per work item
+ *   EPI_OPT_TARGET_ITEMS  batched mode: number of work items the scheduler
+ *                         aims at (0 = 8 per compute unit)
  * EPI_EINVAL for an unknown option or value.  Counts never depend on them. */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
-       EPI_OPT_MINE_ENGINE = 5 };
+       EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
+
+/* Autotune the batched engine for these sets and schedule: time every
+ * setting of lanes per workgroup {64, 128, 256} x work items per compute
+ * unit {4, 8, 16, 32} (each trial is a full batched count; the counts do
+ * not depend on the setting), keep the fastest and apply it to the context
+ * (EPI_OPT_LANES, EPI_OPT_TARGET_ITEMS).  With cache_path (may be null) the
+ * choice is appended to that text file under a key of the workload's shape
+ * (timestamp kind, schedule, K, log2 sizes of events, candidates and
+ * candidates per episode size); a later call with the same key reads it
+ * instead of timing (unreadable or malformed entries are ignored).
+ * chosen[2] (may be null) receives lanes and work items per compute unit. */
+epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched, const char *cache_path,
+                        int64_t *chosen);
 
 /* Wait for all work of the context and report device-side check failures. */
 epi_status epi_sync(epi_ctx *ctx);
@@ -186,6 +217,15 @@ epi_status epi_sync(epi_ctx *ctx);
  * host memory counts[m]; m must equal the set's size.  EPI_ESTATE if the set
  * was never counted. */
 epi_status epi_read_counts(epi_ctx *ctx, int32_t set_id, int32_t *counts, int64_t m);
+
+/* Work log of the set's last count (EPI_OPT_WORKLOG): work[m][5] int32,
+ * submission order.  EPI_ESTATE when the last count did not record one. */
+epi_status epi_read_worklog(epi_ctx *ctx, int32_t set_id, int32_t *work, int64_t m);
+
+/* Wall-clock (constant-rate device counter) start and end of every work item
+ * of the last batched count that included this set (cycles[n_items][2]);
+ * with cycles = null only *n_out receives the number of items. */
+epi_status epi_read_item_cycles(epi_ctx *ctx, int32_t set_id, int64_t *cycles, int64_t n_items, int64_t *n_out);
 
 /* Device pointer to a set's counts (int32[m], submission order), valid until
  * the set is released; contents are defined once the count's stream work is
@@ -229,6 +269,15 @@ epi_status epi_mlp_adam_step(epi_ctx *ctx, const float *g, float lr);
  * receives each epoch's mean loss. */
 epi_status epi_mlp_train(epi_ctx *ctx, const float *X, const float *t, int64_t B, int32_t epochs, int32_t batch,
                          float lr, float *losses);
+
+/* Train the cost model on sets counted with the work log on (best without
+ * time segments, EPI_OPT_SEGMENTS = 1, so each episode's logged work is its
+ * own): features of each episode -> log1p(events visited + records +
+ * queries), shuffled once,
+ * `epochs` passes of Adam (lr 3e-3, mini-batches of 512) from a fresh model
+ * seeded by `seed`; losses[epochs] (may be null) receives the epoch losses. */
+epi_status epi_costmodel_train(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int32_t epochs, uint64_t seed,
+                               float *losses);
 
 /* The model's 23 input features of every candidate of a set (submission
  * order, X[m][23]): log1p of the event count of each node's type (8, zero

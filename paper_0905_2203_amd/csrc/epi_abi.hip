@@ -3,6 +3,7 @@
 // (per-type index) and epi_tiled.hip (counting and reconciliation).
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -466,12 +467,38 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
     if (!ctx) return EPI_EINVAL;
     if (k < 0 || (k > 0 && !set_ids)) return fail(ctx, EPI_EINVAL, "bad set list");
     if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED) return fail(ctx, EPI_EINVAL, "unknown mode %d", mode);
-    if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED) return fail(ctx, EPI_EINVAL, "unknown sched %d", sched);
-    if (mode == EPI_MODE_BATCHED) return fail(ctx, EPI_EINVAL, "batched mode is not available in this build");
+    if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED && sched != EPI_SCHED_HEURISTIC)
+        return fail(ctx, EPI_EINVAL, "unknown sched %d", sched);
     for (int32_t i = 0; i < k; ++i)
         if (!find_set(ctx, set_ids[i])) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
     hipStream_t st = pick_stream(ctx, hip_stream);
+    // work log: cleared before the count
+    for (int32_t i = 0; i < k; ++i) {
+        CandSet *cs = find_set(ctx, set_ids[i]);
+        cs->logged = ctx->c.opt.worklog;
+        if (ctx->c.opt.worklog) {
+            if (cs->work.bytes < sizeof(int32_t) * kWork * (size_t)std::max<int64_t>(cs->m, 1))
+                HIPTRY(ctx, cs->work.alloc(sizeof(int32_t) * kWork * std::max<int64_t>(cs->m, 1)), "work log");
+            HIPTRY(ctx, hipMemsetAsync(cs->work.p, 0, cs->work.bytes, st), "work log");
+        }
+    }
+    if (mode == EPI_MODE_BATCHED) {
+        std::vector<BatchRef> refs;
+        int kind = -1;
+        for (int32_t i = 0; i < k; ++i) {
+            CandSet *cs = find_set(ctx, set_ids[i]);
+            Stream *s = find_stream(ctx, cs->stream_id);
+            if (kind >= 0 && s->ts_kind != kind)
+                return fail(ctx, EPI_EINVAL, "a batched count needs streams of one timestamp kind");
+            kind = s->ts_kind;
+            refs.push_back(BatchRef{s, cs});
+        }
+        HIPTRY(ctx, launch_count_batched(refs, sched, ctx->c.opt, ctx->c.mlp, ctx->c.flags.as<int32_t>(), st),
+               "batched count");
+        for (auto &r : refs) r.c->counted = true;
+        return EPI_OK;
+    }
     for (int32_t i = 0; i < k; ++i) {
         CandSet *cs = find_set(ctx, set_ids[i]);
         Stream *s = find_stream(ctx, cs->stream_id);
@@ -504,6 +531,14 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
         case EPI_OPT_MINE_ENGINE:
             if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "mining engine must be 0 or 1");
             ctx->c.opt.mine_engine = (int)value;
+            return EPI_OK;
+        case EPI_OPT_WORKLOG:
+            if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "work log must be 0 or 1");
+            ctx->c.opt.worklog = value != 0;
+            return EPI_OK;
+        case EPI_OPT_TARGET_ITEMS:
+            if (value < 0) return fail(ctx, EPI_EINVAL, "target items must be >= 0");
+            ctx->c.opt.target_items = value;
             return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);
@@ -638,6 +673,15 @@ epi_status epi_mine_level_info(epi_ctx *ctx, int32_t mine_id, int32_t level, int
 
 namespace {
 
+// Host copy of a level's counts (levels counted by the extension engine keep
+// them on the device until read).
+hipError_t host_counts(MineLevel &L) {
+    if ((int64_t)L.counts.size() == L.m || !L.dcounts.p) return hipSuccess;
+    L.counts.resize(L.m);
+    if (L.m == 0) return hipSuccess;
+    return hipMemcpy(L.counts.data(), L.dcounts.p, sizeof(int32_t) * L.m, hipMemcpyDeviceToHost);
+}
+
 // Episode r of a level: explicit candidate, implicit candidate, or (when
 // frequent) the frequent-episode arrays; writes the ABI layout.
 void mine_episode(const Mine &mn, int level, bool frequent, int64_t r, uint8_t *N, int32_t *types, int64_t *lo,
@@ -676,9 +720,10 @@ epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequ
     if (!ctx) return EPI_EINVAL;
     auto it = ctx->c.mines.find(mine_id);
     if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
-    const Mine &mn = *it->second;
+    Mine &mn = *it->second;
     if (level < 1 || level > (int32_t)mn.levels.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
-    const MineLevel &L = mn.levels[level - 1];
+    MineLevel &L = mn.levels[level - 1];
+    HIPTRY(ctx, host_counts(L), "reading counts");
     const int64_t want = frequent_only ? (int64_t)L.freq.size() : L.m;
     if (m != want) return fail(ctx, EPI_EINVAL, "level %d has %lld entries, not %lld", level, (long long)want,
                                (long long)m);
@@ -693,10 +738,11 @@ epi_status epi_mine_read_at(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_
     if (!ctx) return EPI_EINVAL;
     auto it = ctx->c.mines.find(mine_id);
     if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
-    const Mine &mn = *it->second;
+    Mine &mn = *it->second;
     if (level < 1 || level > (int32_t)mn.levels.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
-    const MineLevel &L = mn.levels[level - 1];
+    MineLevel &L = mn.levels[level - 1];
     if (k < 0 || (k > 0 && (!idx || !N || !types || !lo || !hi || !counts))) return fail(ctx, EPI_EINVAL, "bad arguments");
+    HIPTRY(ctx, host_counts(L), "reading counts");
     for (int64_t r = 0; r < k; ++r) {
         if (idx[r] < 0 || idx[r] >= L.m) return fail(ctx, EPI_EINVAL, "index %lld outside the level", (long long)idx[r]);
         mine_episode(mn, level, false, idx[r], N + r, types + r * 8, lo + r * 7, hi + r * 7, counts + r);
@@ -876,6 +922,187 @@ epi_status epi_costmodel_features(epi_ctx *ctx, int32_t set_id, float *X, int64_
     }
     for (int64_t i = 0; i < m; ++i)
         std::copy(grouped.begin() + i * kFeatures, grouped.begin() + (i + 1) * kFeatures, X + (int64_t)orig[i] * kFeatures);
+    return EPI_OK;
+}
+
+epi_status epi_read_worklog(epi_ctx *ctx, int32_t set_id, int32_t *work, int64_t m) {
+    if (!ctx) return EPI_EINVAL;
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (!cs->counted || !cs->logged) return fail(ctx, EPI_ESTATE, "set %d has no work log", set_id);
+    if (m != cs->m || (m > 0 && !work)) return fail(ctx, EPI_EINVAL, "set %d holds %lld candidates", set_id,
+                                                    (long long)cs->m);
+    epi_status f = epi_sync(ctx);
+    if (f != EPI_OK) return f;
+    if (m > 0) HIPTRY(ctx, hipMemcpy(work, cs->work.p, sizeof(int32_t) * kWork * m, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_read_item_cycles(epi_ctx *ctx, int32_t set_id, int64_t *cycles, int64_t n_items, int64_t *n_out) {
+    if (!ctx) return EPI_EINVAL;
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (n_out) *n_out = cs->cycles.p ? cs->n_items : 0;
+    if (!cycles) return EPI_OK;
+    if (!cs->cycles.p || n_items != cs->n_items)
+        return fail(ctx, EPI_EINVAL, "the last batched count of set %d stamped %lld items", set_id,
+                    (long long)(cs->cycles.p ? cs->n_items : 0));
+    epi_status f = epi_sync(ctx);
+    if (f != EPI_OK) return f;
+    HIPTRY(ctx, hipMemcpy(cycles, cs->cycles.p, sizeof(int64_t) * 2 * n_items, hipMemcpyDeviceToHost), "copy");
+    return EPI_OK;
+}
+
+epi_status epi_costmodel_train(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int32_t epochs, uint64_t seed,
+                               float *losses) {
+    if (!ctx || k < 1 || !set_ids || epochs < 1) return fail(ctx, EPI_EINVAL, "bad arguments");
+    std::vector<float> X, t;
+    for (int32_t i = 0; i < k; ++i) {
+        CandSet *cs = find_set(ctx, set_ids[i]);
+        if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+        if (!cs->counted || !cs->logged) return fail(ctx, EPI_ESTATE, "set %d has no work log", set_ids[i]);
+        std::vector<float> Xi((size_t)cs->m * kFeatures);
+        std::vector<int32_t> w((size_t)cs->m * kWork);
+        epi_status v = epi_costmodel_features(ctx, set_ids[i], Xi.data(), cs->m);
+        if (v != EPI_OK) return v;
+        v = epi_read_worklog(ctx, set_ids[i], w.data(), cs->m);
+        if (v != EPI_OK) return v;
+        X.insert(X.end(), Xi.begin(), Xi.end());
+        // target: log1p of the lane's work (events visited + state-machine operations)
+        for (int64_t c = 0; c < cs->m; ++c)
+            t.push_back(std::log1p((float)w[c * kWork + 0] + (float)w[c * kWork + 1] + (float)w[c * kWork + 2]));
+    }
+    const int64_t B = (int64_t)t.size();
+    // shuffle once (SplitMix64-driven Fisher-Yates) so mini-batches mix sets
+    std::vector<int64_t> ord(B);
+    std::iota(ord.begin(), ord.end(), 0);
+    uint64_t st = seed ^ 0x5DEECE66Dull;
+    for (int64_t i = B - 1; i > 0; --i) {
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        std::swap(ord[i], ord[(int64_t)(z % (uint64_t)(i + 1))]);
+    }
+    std::vector<float> Xs((size_t)B * kFeatures), ts(B);
+    for (int64_t i = 0; i < B; ++i) {
+        std::copy(X.begin() + ord[i] * kFeatures, X.begin() + (ord[i] + 1) * kFeatures, Xs.begin() + i * kFeatures);
+        ts[i] = t[ord[i]];
+    }
+    epi_status v = epi_mlp_init(ctx, kFeatures, seed);
+    if (v != EPI_OK) return v;
+    return epi_mlp_train(ctx, Xs.data(), ts.data(), B, epochs, 512, 3e-3f, losses);
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+namespace {
+
+int log2_bucket(int64_t x) {
+    int b = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// Workload shape: timestamp kind, schedule, max K, and log2 buckets of the
+// events, of the candidates and of the candidates of each episode size.
+std::string tune_key(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched) {
+    int64_t n = 0, m = 0;
+    int32_t K = 0;
+    int kind = 0;
+    int64_t byN[kMaxN + 1] = {0};
+    for (int32_t i = 0; i < k; ++i) {
+        CandSet *cs = find_set(ctx, set_ids[i]);
+        Stream *s = find_stream(ctx, cs->stream_id);
+        n += s->n;
+        m += cs->m;
+        K = std::max(K, s->K);
+        kind = s->ts_kind;
+        for (const Group &g : cs->groups) byN[g.N] += g.end - g.begin;
+    }
+    std::string key = "ts" + std::to_string(kind) + "_s" + std::to_string(sched) + "_K" + std::to_string(K) + "_n" +
+                      std::to_string(log2_bucket(n)) + "_m" + std::to_string(log2_bucket(m)) + "_N";
+    for (int N = 1; N <= kMaxN; ++N) key += "." + std::to_string(byN[N] ? log2_bucket(byN[N]) + 1 : 0);
+    return key;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int64_t *lanes, int64_t *items) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char kb[512];
+    long long a, b;
+    bool found = false;
+    while (fscanf(f, "%511s %lld %lld", kb, &a, &b) == 3) {
+        if (key == kb && (a == 64 || a == 128 || a == 256) && b >= 1 && b <= 4096) {
+            *lanes = a;
+            *items = b;
+            found = true;  // the last valid entry wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched, const char *cache_path,
+                        int64_t *chosen) {
+    if (!ctx || k < 1 || !set_ids) return fail(ctx, EPI_EINVAL, "bad arguments");
+    for (int32_t i = 0; i < k; ++i)
+        if (!find_set(ctx, set_ids[i])) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+    const std::string key = tune_key(ctx, set_ids, k, sched);
+    int64_t lanes = 0, per_cu = 8;
+    int ncu = 0;
+    HIPTRY(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->c.device), "attribute");
+    if (!cache_lookup(cache_path, key, &lanes, &per_cu)) {
+        const CountOptions saved = ctx->c.opt;
+        double best = 1e300;
+        hipEvent_t a, b;
+        HIPTRY(ctx, hipEventCreate(&a), "event");
+        HIPTRY(ctx, hipEventCreate(&b), "event");
+        for (int64_t W : {64, 128, 256}) {
+            for (int64_t pc : {4, 8, 16, 32}) {
+                ctx->c.opt.lanes = (int)W;
+                ctx->c.opt.target_items = pc * ncu;
+                (void)hipEventRecord(a, ctx->c.stream);
+                epi_status v = epi_count(ctx, set_ids, k, EPI_MODE_BATCHED, sched, nullptr);
+                (void)hipEventRecord(b, ctx->c.stream);
+                if (v != EPI_OK) {
+                    ctx->c.opt = saved;
+                    return v;
+                }
+                HIPTRY(ctx, hipEventSynchronize(b), "sync");
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (ms < best) {
+                    best = ms;
+                    lanes = W;
+                    per_cu = pc;
+                }
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        ctx->c.opt = saved;
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%s %lld %lld\n", key.c_str(), (long long)lanes, (long long)per_cu);
+                fclose(f);
+            }
+        }
+    }
+    ctx->c.opt.lanes = (int)lanes;
+    ctx->c.opt.target_items = per_cu * ncu;
+    if (chosen) {
+        chosen[0] = lanes;
+        chosen[1] = per_cu;
+    }
     return EPI_OK;
 }
 

@@ -95,31 +95,39 @@ __device__ __forceinline__ int32_t ext_core(const ExtArgs<T> &a, int64_t alpha, 
     T prev_e = kMin;
     T xt = kMin, xs = kMin;  // latest entry with time < t_y - lo (when p > 0)
     T nt = alen > 0 ? (MODE == 0 ? at[0] : ap[0].s) : TsLimits<T>::hi();
-    for (int32_t i = 0; i < ylen; ++i) {
-        const T ty = y[i];
-        const T lim = (T)(ty - lo);
-        while (nt < lim) {
-            if (MODE == 0) {
-                xt = nt;
-                xs = nt;
-            } else {
-                xt = ap[p].s;
-                xs = ap[p].e;
+    for (int32_t i0 = 0; i0 < ylen; i0 += 4) {
+        // four independent loads in flight per lane
+        T yy[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yy[u] = i0 + u < ylen ? y[i0 + u] : TsLimits<T>::hi();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u >= ylen) break;
+            const T ty = yy[u];
+            const T lim = (T)(ty - lo);
+            while (nt < lim) {
+                if (MODE == 0) {
+                    xt = nt;
+                    xs = nt;
+                } else {
+                    xt = ap[p].s;
+                    xs = ap[p].e;
+                }
+                ++p;
+                nt = p < alen ? (MODE == 0 ? at[p] : ap[p].s) : TsLimits<T>::hi();
             }
-            ++p;
-            nt = p < alen ? (MODE == 0 ? at[p] : ap[p].s) : TsLimits<T>::hi();
-        }
-        if (p > 0 && xt >= (T)(ty - hi)) {
-            if (WRITE) {
-                Pair<T> v;
-                v.s = ty;
-                v.e = xs;
-                out[nv] = v;
-            }
-            ++nv;
-            if (xs > prev_e) {
-                ++cnt;
-                prev_e = ty;
+            if (p > 0 && xt >= (T)(ty - hi)) {
+                if (WRITE) {
+                    Pair<T> v;
+                    v.s = ty;
+                    v.e = xs;
+                    out[nv] = v;
+                }
+                ++nv;
+                if (xs > prev_e) {
+                    ++cnt;
+                    prev_e = ty;
+                }
             }
         }
     }
@@ -176,6 +184,59 @@ __global__ __launch_bounds__(256) void k_ext_write(ExtArgs<T> a) {
     if (f >= a.nw) return;
     int32_t nv;
     (void)ext_core<T, MODE, true>(a, a.w_alpha[f], a.w_type[f], a.w_iv[f], &nv, a.w_out + a.w_off[f]);
+}
+
+// Frequent selection (count > threshold), order preserving: per-block flag
+// counts, then each block writes its indices at its scanned offset.
+constexpr int kSelBlock = 256;
+constexpr int kSelItems = 8;
+
+__global__ __launch_bounds__(kSelBlock) void k_sel_count(const int32_t *__restrict__ counts, int64_t m, int32_t thr,
+                                                         int32_t *__restrict__ bcnt) {
+    __shared__ int32_t red[kSelBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock * kSelItems;
+    int32_t c = 0;
+    for (int k = 0; k < kSelItems; ++k) {
+        const int64_t i = base + (int64_t)k * kSelBlock + threadIdx.x;
+        if (i < m && counts[i] > thr) ++c;
+    }
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kSelBlock / 64; ++w) t += red[w];
+        bcnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kSelBlock) void k_sel_write(const int32_t *__restrict__ counts,
+                                                         const int32_t *__restrict__ nvalid, int64_t m, int32_t thr,
+                                                         const int64_t *__restrict__ boff, int64_t *__restrict__ idx,
+                                                         int32_t *__restrict__ nv) {
+    __shared__ int32_t wsum[kSelBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock * kSelItems;
+    int64_t off = boff[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = 0; k < kSelItems; ++k) {  // uniform
+        const int64_t i = base + (int64_t)k * kSelBlock + threadIdx.x;
+        const bool f = i < m && counts[i] > thr;
+        const uint64_t bal = __ballot(f);
+        if (lane == 0) wsum[w] = __popcll(bal);
+        __syncthreads();
+        int32_t before = 0, total = 0;
+        for (int q = 0; q < kSelBlock / 64; ++q) {
+            if (q < w) before += wsum[q];
+            total += wsum[q];
+        }
+        if (f) {
+            const int64_t o = off + before + __popcll(bal & ((1ull << lane) - 1ull));
+            idx[o] = i;
+            nv[o] = nvalid[i];
+        }
+        off += total;
+        __syncthreads();
+    }
 }
 
 template <typename T>
@@ -380,17 +441,53 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     (void)hipEventDestroy(ev1);
     if (e != hipSuccess) return e;
     L.kernel_ms = kms;
-    L.counts.resize(m);
-    std::vector<int32_t> nval(m);
-    if (m > 0) {
-        if ((e = hipMemcpy(L.counts.data(), d_counts.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost)) != hipSuccess)
-            return e;
-        if ((e = hipMemcpy(nval.data(), d_nval.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost)) != hipSuccess)
-            return e;
+    // ---- frequent episodes, selected on the device (counts stay there)
+    std::vector<int32_t> nval;
+    {
+        const int64_t per = (int64_t)kSelBlock * kSelItems;
+        const int64_t nb = m > 0 ? (m + per - 1) / per : 0;
+        DevBuf d_bcnt, d_boff;
+        if ((e = d_bcnt.alloc(sizeof(int32_t) * (nb + 1))) != hipSuccess) return e;
+        const int32_t thr = (int32_t)std::min<int64_t>(mn.threshold, INT32_MAX);
+        int64_t nf = 0;
+        std::vector<int64_t> boff(nb + 1, 0);
+        if (nb > 0) {
+            if (mn.threshold < 0) {
+                // every candidate is frequent
+                for (int64_t b = 0; b < nb; ++b) boff[b + 1] = boff[b] + std::min(per, m - b * per);
+            } else {
+                k_sel_count<<<(unsigned)nb, kSelBlock, 0, st>>>(a.counts, m, thr, d_bcnt.as<int32_t>());
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                std::vector<int32_t> bc(nb);
+                if ((e = hipMemcpyAsync(bc.data(), d_bcnt.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st)) !=
+                    hipSuccess)
+                    return e;
+                if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+                for (int64_t b = 0; b < nb; ++b) boff[b + 1] = boff[b] + bc[b];
+            }
+            nf = boff[nb];
+        }
+        L.freq.assign(nf, 0);
+        nval.assign(nf, 0);
+        if (nf > 0) {
+            DevBuf d_idx, d_nv;
+            if ((e = upload(d_boff, boff, st)) != hipSuccess) return e;
+            if ((e = d_idx.alloc(sizeof(int64_t) * nf)) != hipSuccess) return e;
+            if ((e = d_nv.alloc(sizeof(int32_t) * nf)) != hipSuccess) return e;
+            k_sel_write<<<(unsigned)nb, kSelBlock, 0, st>>>(a.counts, a.nvalid, m, mn.threshold < 0 ? INT32_MIN : thr,
+                                                            d_boff.as<int64_t>(), d_idx.as<int64_t>(),
+                                                            d_nv.as<int32_t>());
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(L.freq.data(), d_idx.p, sizeof(int64_t) * nf, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = hipMemcpyAsync(nval.data(), d_nv.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        }
     }
-    // ---- frequent episodes: reconstruct them and write their chain lists
-    for (int64_t c = 0; c < m; ++c)
-        if (L.counts[c] > mn.threshold) L.freq.push_back(c);
+    L.dcounts = std::move(d_counts);
     const int64_t nf = (int64_t)L.freq.size();
     L.nf = nf;
     L.ftypes.assign((size_t)N * nf, 0);
@@ -425,7 +522,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
         }
     });
     L.h_chain_off.assign(nf + 1, 0);
-    for (int64_t f = 0; f < nf; ++f) L.h_chain_off[f + 1] = L.h_chain_off[f] + nval[L.freq[f]];
+    for (int64_t f = 0; f < nf; ++f) L.h_chain_off[f + 1] = L.h_chain_off[f] + nval[f];
     DevBuf d_wa, d_wt, d_wi;
     if ((e = upload(d_wa, w_alpha, st)) != hipSuccess) return e;
     if ((e = upload(d_wt, w_type, st)) != hipSuccess) return e;

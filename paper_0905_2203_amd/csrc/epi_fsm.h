@@ -47,6 +47,7 @@ struct LaneFsm {
     int W, lane, Q;
     T e;            // time of the last completion (type minimum: none)
     uint32_t gen;   // generation bit
+    uint32_t maxq = 0;  // deepest ring seen (work log)
 
     __device__ __forceinline__ uint32_t pack(uint32_t hd, uint32_t n) const { return n | (hd << 8) | (gen << 16); }
 
@@ -119,6 +120,7 @@ struct LaneFsm {
         }
         uint32_t tl = hd + n;
         if (tl >= (uint32_t)Q) tl -= Q;
+        if (n + 1 > maxq) maxq = n + 1;
         Pair<T> v;
         v.s = ns;
         v.e = ne;

@@ -113,6 +113,10 @@ struct CandSet {
     DevBuf orig;    // int32 [m]
     DevBuf counts;  // int32 [m], submission order
     DevBuf scratch; // per-segment speculative records of the last count
+    DevBuf work;    // work log: int32 [m][kWork] (submission order) when enabled
+    DevBuf cycles;  // work log: int64 [items][2] wall-clock start/end of the last count
+    int64_t n_items = 0;  // work items of the last count
+    bool logged = false;  // the last count recorded a work log
     // Compact layout (level-wise mining): one episode size, types uint16
     // [N][m], interval ids uint8 [N-1][m] into a menu of (lo, hi) pairs
     // (T[2*n_menu]); slots are in submission order (orig unused).
@@ -135,6 +139,8 @@ struct CountOptions {
     int64_t target_lanes = 262144; // automatic segmentation aims at this many (candidate, segment) lanes
     bool pair_filter = true;       // level-wise discovery: skip events with no constrained neighbour
     int mine_engine = 1;           // level-wise discovery: 1 extension engine, 0 state machines
+    bool worklog = false;          // record per-candidate work counts and per-item times
+    int64_t target_items = 0;      // batched mode: work items aimed at (0: 8 per compute unit)
     int64_t pair_filter_max_bytes = int64_t(1) << 30;
 };
 
@@ -146,7 +152,8 @@ struct MineLevel {
     // explicit candidates (state-machine engine): types [N][m], ids [N-1][m]
     std::vector<uint16_t> types;
     std::vector<uint8_t> iv;
-    std::vector<int32_t> counts;  // [m]
+    std::vector<int32_t> counts;  // [m] (host copy; for device-counted levels made on demand)
+    DevBuf dcounts;               // int32 [m] on the device (extension engine)
     std::vector<int64_t> freq;    // indices with count > threshold
     double gen_ms = 0, count_ms = 0, kernel_ms = 0;
     int64_t alg_bytes = 0;        // bytes the counting method must read and write
@@ -211,6 +218,17 @@ hipError_t build_type_index(Stream &s, hipStream_t st);
 hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
                                   int32_t K, int32_t *d_flags, hipStream_t st);
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st);
+// Batched count of several candidate sets (possibly on different streams) in
+// one graph launch of persistent kernels, one per episode size.  sched:
+// EPI_SCHED_RR (submission order), EPI_SCHED_LEARNED (the cost model's
+// predictions; round robin without a model) or EPI_SCHED_HEURISTIC (sum of
+// the types' event counts).
+struct BatchRef {
+    const Stream *s;
+    CandSet *c;
+};
+hipError_t launch_count_batched(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp,
+                                int32_t *d_flags, hipStream_t st);
 // Count every candidate of one mining level on the device (compact layout);
 // fills L.counts and the timing fields.
 hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const CountOptions &opt, int32_t *d_flags,

@@ -28,6 +28,8 @@
 // of the speculative count is taken as is; otherwise the re-run covers the
 // whole segment.
 #include <algorithm>
+#include <cmath>
+#include <numeric>
 #include <vector>
 
 #include "epi_fsm.h"
@@ -69,6 +71,9 @@ struct CountArgs {
     T *rec_first;
     int32_t *flags;
     uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc;
+    const int32_t *perm;  // lane slot -> candidate slot (scheduler order); null = identity
+    int32_t *work;        // work log: kWork counters per candidate (submission order); null = off
+    int64_t *cycles;      // work log: wall-clock start/end per work item; null = off
 };
 
 template <typename T, int N>
@@ -104,17 +109,19 @@ __device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N>
     return H;
 }
 
+// One work item: lane block `blk` of a launch unit, time segment p.
 template <typename T, int N, bool FILT>
-__global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, int p, int64_t item,
+                                           unsigned char *smem) {
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kEnd = TsLimits<T>::hi();
     constexpr int L = N > 1 ? N - 1 : 1;
     const int W = blockDim.x, lane = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * W + lane;
+    const int64_t s = blk * W + lane;
     const bool active = s < a.G;
-    const int64_t slot = a.begin + (active ? s : 0);
-    const int p = blockIdx.y;
+    const int64_t lslot = a.begin + (active ? s : 0);
+    const int64_t slot = a.perm ? (int64_t)a.perm[lslot] : lslot;
+    if (a.cycles && lane == 0) a.cycles[2 * item] = (int64_t)wall_clock64();
     T *tbuf = reinterpret_cast<T *>(smem + a.off_tbuf);
     uint16_t *obuf = reinterpret_cast<uint16_t *>(smem + a.off_obuf);
     T *misc = reinterpret_cast<T *>(smem + a.off_misc);
@@ -186,6 +193,7 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
 
     int32_t cnt = 0;
     T last = kMin;
+    uint32_t w_visits = 0, w_records = 0, w_queries = 0, w_done = 0;
     for (int64_t b = bs; b < b1; ++b) {
         __syncthreads();
         const uint4 *src = reinterpret_cast<const uint4 *>(a.tiled + b * kTile);
@@ -264,6 +272,7 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
                 }
             }
             if (t == kEnd) break;
+            ++w_visits;
             // per-node values of the selected node
             T vfj = vf[0], nxt = kEnd, hij = T(0);
 #pragma unroll
@@ -290,10 +299,12 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
                         done = true;
                     } else {
                         const T ns = f.record(0, t, a.flags);
+                        ++w_records;
                         vf[1] = vf[1] < (T)(ns + 1) ? vf[1] : (T)(ns + 1);
                     }
                 } else {
                     T nv;
+                    ++w_queries;
                     const bool ok = f.query(j - 1, t, &nv);
                     if (!ok) {
 #pragma unroll
@@ -307,11 +318,13 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
                         done = true;
                     } else {
                         const T ns = f.record(j, t, a.flags);
+                        ++w_records;
 #pragma unroll
                         for (int k = 1; k + 1 < N; ++k)
                             if (k == j) vf[k + 1] = vf[k + 1] < (T)(ns + 1) ? vf[k + 1] : (T)(ns + 1);
                     }
                 }
+                if (done) ++w_done;
                 if (done && t >= Bp) {
                     if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = t;
                     ++cnt;
@@ -349,13 +362,60 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
             }
         }
     }
+    if (a.cycles && lane == 0) a.cycles[2 * item + 1] = (int64_t)wall_clock64();
     if (!active) return;
+    const int64_t o = a.orig ? a.orig[slot] : slot;
+    if (a.work) {
+        int32_t *w = a.work + o * kWork;
+        atomicAdd(w + 0, (int32_t)w_visits);
+        atomicAdd(w + 1, (int32_t)w_records);
+        atomicAdd(w + 2, (int32_t)w_queries);
+        atomicAdd(w + 3, (int32_t)w_done);
+        atomicMax(w + 4, (int32_t)f.maxq);
+    }
     if (a.P == 1) {
-        a.counts[a.orig ? a.orig[slot] : slot] = cnt;
+        a.counts[o] = cnt;
     } else {
         a.rec_cnt[(int64_t)p * a.G + s] = cnt;
         a.rec_last[(int64_t)p * a.G + s] = last;
     }
+}
+
+template <typename T, int N, bool FILT>
+__global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    count_item<T, N, FILT>(a, blockIdx.x, blockIdx.y, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, smem);
+}
+
+// Persistent form: every workgroup takes work items (unit, lane block,
+// segment) from a device queue until it is empty.  Units may belong to
+// different streams and candidate sets; they share the LDS layout.
+struct WorkItem {
+    int32_t unit;
+    int32_t p;
+    int64_t blk;
+};
+
+template <typename T, int N, bool FILT>
+__global__ __launch_bounds__(256) void k_count_persistent(const CountArgs<T> *__restrict__ units,
+                                                          const WorkItem *__restrict__ items, int64_t n_items,
+                                                          int64_t item_base, unsigned long long *__restrict__ queue) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t next;
+    while (true) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t it = next;
+        __syncthreads();
+        if (it >= n_items) break;  // uniform: every wave of the group exits
+        const WorkItem w = items[it];
+        const CountArgs<T> a = units[w.unit];
+        count_item<T, N, FILT>(a, w.blk, w.p, item_base + it, smem);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
 __global__ void k_zero_counts(const int32_t *__restrict__ orig, int64_t G, int32_t *__restrict__ counts) {
@@ -381,7 +441,7 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
     const int W = blockDim.x, lane = threadIdx.x;
     const int64_t s = (int64_t)blockIdx.x * W + lane;
     if (s >= a.G) return;  // no barriers below
-    const int64_t slot = a.begin + s;
+    const int64_t slot = a.perm ? (int64_t)a.perm[a.begin + s] : a.begin + s;
     LaneFsm<T, N> f;
     f.lohi = reinterpret_cast<Pair<T> *>(smem);
     f.qse = reinterpret_cast<Pair<T> *>(smem + a.off_qse);
@@ -618,6 +678,9 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
         a.counts = c.counts.as<int32_t>();
         a.flags = d_flags;
+        a.perm = nullptr;
+        a.work = opt.worklog && c.work.p ? c.work.as<int32_t>() : nullptr;
+        a.cycles = nullptr;
         a.off_qse = L.off_qse;
         a.off_tbuf = L.off_tbuf;
         a.off_qh = L.off_qh;
@@ -667,6 +730,339 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st) {
     if (s.ts_kind == EPI_TS_I64) return count_t<int64_t>(s, c, opt, d_flags, st);
     return count_t<int32_t>(s, c, opt, d_flags, st);
+}
+
+}  // namespace epi
+
+// ---------------------------------------------------------------------------
+// Batched mode and its scheduler.
+// ---------------------------------------------------------------------------
+namespace epi {
+
+namespace {
+
+template <typename T>
+using PFn = void (*)(const CountArgs<T> *, const WorkItem *, int64_t, int64_t, unsigned long long *);
+
+template <typename T, bool F>
+PFn<T> pick_persistent_f(int N) {
+    switch (N) {
+        case 1: return k_count_persistent<T, 1, F>;
+        case 2: return k_count_persistent<T, 2, F>;
+        case 3: return k_count_persistent<T, 3, F>;
+        case 4: return k_count_persistent<T, 4, F>;
+        case 5: return k_count_persistent<T, 5, F>;
+        case 6: return k_count_persistent<T, 6, F>;
+        case 7: return k_count_persistent<T, 7, F>;
+        case 8: return k_count_persistent<T, 8, F>;
+        default: return nullptr;
+    }
+}
+
+// Per-candidate predicted costs (grouped slot order) for the learned or the
+// heuristic schedule; empty when the schedule is round robin.
+hipError_t predicted_costs(const Stream &s, const CandSet &c, int sched, Mlp &mlp, hipStream_t st,
+                           std::vector<float> &cost) {
+    cost.clear();
+    if (sched == EPI_SCHED_RR || c.m == 0) return hipSuccess;
+    if (sched == EPI_SCHED_LEARNED && !(mlp.ready() && mlp.F == kFeatures)) return hipSuccess;  // fallback: RR
+    hipError_t e;
+    DevBuf dX;
+    if ((e = dX.alloc(sizeof(float) * c.m * kFeatures)) != hipSuccess) return e;
+    if ((e = candidate_features(s, c, dX.as<float>(), st)) != hipSuccess) return e;
+    cost.assign(c.m, 0.f);
+    if (sched == EPI_SCHED_LEARNED) {
+        DevBuf dy;
+        if ((e = dy.alloc(sizeof(float) * c.m)) != hipSuccess) return e;
+        if ((e = mlp_forward_device(mlp, dX.as<float>(), c.m, dy.as<float>(), st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(cost.data(), dy.p, sizeof(float) * c.m, hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        for (float &x : cost) x = std::exp(std::min(x, 60.f));  // the model predicts log1p(work)
+    } else {
+        std::vector<float> X((size_t)c.m * kFeatures);
+        if ((e = hipMemcpy(X.data(), dX.p, sizeof(float) * X.size(), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+        for (int64_t i = 0; i < c.m; ++i) {
+            double v = 0;
+            for (int k = 0; k < 8; ++k) v += std::expm1((double)X[i * kFeatures + k]);
+            cost[i] = (float)v;
+        }
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp, int32_t *d_flags,
+                     hipStream_t st) {
+    hipError_t e;
+    int dev = 0, ncu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int64_t target_items = opt.target_items > 0 ? opt.target_items : (int64_t)ncu * 8;
+
+    struct UnitH {
+        int set, N, Q, W;
+        int64_t begin, G, P, S;
+        bool filt;
+        std::vector<float> bcost;  // per lane block
+    };
+    std::vector<UnitH> units;
+    std::vector<DevBuf> perms(sets.size());
+    std::vector<std::vector<float>> costs(sets.size());
+    // 1. costs and schedule order per set
+    double total_cost = 0;
+    for (size_t si = 0; si < sets.size(); ++si) {
+        const Stream &s = *sets[si].s;
+        CandSet &c = *sets[si].c;
+        if ((e = predicted_costs(s, c, sched, mlp, st, costs[si])) != hipSuccess) return e;
+        if (!costs[si].empty()) {
+            std::vector<int32_t> perm(c.m);
+            std::iota(perm.begin(), perm.end(), 0);
+            for (const Group &g : c.groups)
+                std::stable_sort(perm.begin() + g.begin, perm.begin() + g.end,
+                                 [&](int32_t x, int32_t y) { return costs[si][x] > costs[si][y]; });
+            if ((e = perms[si].alloc(sizeof(int32_t) * c.m)) != hipSuccess) return e;
+            if ((e = hipMemcpy(perms[si].p, perm.data(), sizeof(int32_t) * c.m, hipMemcpyHostToDevice)) != hipSuccess)
+                return e;
+            std::vector<float> sorted(c.m);
+            for (int64_t i = 0; i < c.m; ++i) sorted[i] = costs[si][perm[i]];
+            costs[si] = std::move(sorted);
+            for (float x : costs[si]) total_cost += x;
+        }
+    }
+    // 2. launch units: lane blocks with the same segment count
+    for (size_t si = 0; si < sets.size(); ++si) {
+        const Stream &s = *sets[si].s;
+        CandSet &c = *sets[si].c;
+        if (s.n == 0) continue;
+        for (const Group &g : c.groups) {
+            const int64_t G = g.end - g.begin;
+            if (G <= 0) continue;
+            const bool filt = c.compact && c.pred_bits && c.succ_bits;
+            const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes);
+            const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
+            if (costs[si].empty()) {
+                // round robin: submission order, segments as in plain mode
+                int64_t P = G >= opt.target_lanes ? 1 : (opt.target_lanes + G - 1) / G;
+                if (opt.segments > 0) P = opt.segments;
+                P = std::max<int64_t>(1, std::min<int64_t>(P, opt.segments > 0 ? s.B : pmax));
+                const int64_t S = (s.B + P - 1) / P;
+                P = (s.B + S - 1) / S;
+                UnitH u{(int)si, g.N, g.Q, W, g.begin, G, P, S, filt, {}};
+                u.bcost.assign((G + W - 1) / W, 1.f);
+                units.push_back(std::move(u));
+                continue;
+            }
+            // learned / heuristic: blocks of similar predicted cost (sorted),
+            // heavy blocks cut into more segments, cost per item ~ uniform
+            const double cstar = std::max(total_cost / (double)target_items, 1.0);
+            int64_t b0 = 0;
+            const int64_t nb = (G + W - 1) / W;
+            while (b0 < nb) {
+                auto pfor = [&](int64_t b) {
+                    const double bc = (double)costs[si][g.begin + b * W] * std::min<int64_t>(W, G - b * W);
+                    int64_t P = (int64_t)std::ceil(bc / cstar);
+                    if (opt.segments > 0) P = opt.segments;
+                    return std::max<int64_t>(1, std::min<int64_t>(P, opt.segments > 0 ? s.B : pmax));
+                };
+                const int64_t P0 = pfor(b0);
+                int64_t b1 = b0 + 1;
+                while (b1 < nb && pfor(b1) == P0) ++b1;
+                const int64_t S = (s.B + P0 - 1) / P0;
+                const int64_t P = (s.B + S - 1) / S;
+                UnitH u{(int)si, g.N, g.Q, W, g.begin + b0 * W, std::min<int64_t>(G - b0 * W, (b1 - b0) * W), P, S,
+                        filt, {}};
+                for (int64_t b = b0; b < b1; ++b)
+                    u.bcost.push_back(costs[si][g.begin + b * W] * (float)std::min<int64_t>(W, G - b * W));
+                units.push_back(std::move(u));
+                b0 = b1;
+            }
+        }
+    }
+    // 3. per-unit arguments (records, work log) and work items per episode size
+    size_t rec_bytes = 0;
+    for (const UnitH &u : units)
+        if (u.P > 1) rec_bytes += (size_t)u.P * u.G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst)) + 64;
+    DevBuf rec;
+    if ((e = rec.alloc(rec_bytes)) != hipSuccess) return e;
+    std::vector<CountArgs<T>> ua(units.size());
+    std::vector<std::vector<WorkItem>> items(kMaxN + 1);
+    std::vector<std::vector<float>> icost(kMaxN + 1);
+    std::vector<int> maxQ(kMaxN + 1, 1), maxK(kMaxN + 1, 1), Wn(kMaxN + 1, 256);
+    std::vector<bool> filtN(kMaxN + 1, false);
+    size_t ro = 0;
+    for (size_t ui = 0; ui < units.size(); ++ui) {
+        const UnitH &u = units[ui];
+        const Stream &s = *sets[u.set].s;
+        CandSet &c = *sets[u.set].c;
+        CountArgs<T> a{};
+        a.tiled = s.tiled_ts.as<T>();
+        a.loff = s.tile_loff.as<uint16_t>();
+        a.tile_t0 = s.tile_t0.as<T>();
+        a.ts_by_type = s.ts_by_type.as<T>();
+        a.type_off = s.type_off.as<int32_t>();
+        a.B = s.B;
+        a.K = s.K;
+        a.ctypes = c.types.as<int32_t>();
+        a.clo = c.lo.as<T>();
+        a.chi = c.hi.as<T>();
+        a.t16 = c.compact ? c.t16.as<uint16_t>() : nullptr;
+        a.iv = c.compact ? c.iv.as<uint8_t>() : nullptr;
+        a.menu = c.compact ? c.menu.as<T>() : nullptr;
+        a.pbits = u.filt ? c.pred_bits : nullptr;
+        a.sbits = u.filt ? c.succ_bits : nullptr;
+        a.rwords = s.B * (kTile / 64);
+        a.m = c.m;
+        a.begin = u.begin;
+        a.G = u.G;
+        a.Q = u.Q;
+        a.P = (int32_t)u.P;
+        a.S = u.S;
+        a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
+        a.counts = c.counts.as<int32_t>();
+        a.flags = d_flags;
+        a.perm = perms[u.set].p ? perms[u.set].template as<int32_t>() : nullptr;
+        a.work = opt.worklog ? c.work.as<int32_t>() : nullptr;
+        if (u.P > 1) {
+            unsigned char *base = rec.as<unsigned char>() + ro;
+            a.rec_last = reinterpret_cast<T *>(base);
+            a.rec_first = a.rec_last + (size_t)u.P * u.G;
+            a.rec_cnt = reinterpret_cast<int32_t *>(a.rec_first + (size_t)u.P * u.G * kRecFirst);
+            ro += ((size_t)u.P * u.G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst)) + 64) & ~size_t(15);
+        }
+        ua[ui] = a;
+        maxQ[u.N] = std::max(maxQ[u.N], u.Q);
+        maxK[u.N] = std::max(maxK[u.N], (int)s.K);
+        filtN[u.N] = filtN[u.N] || u.filt;
+        for (int64_t b = 0; b < (int64_t)u.bcost.size(); ++b)
+            for (int64_t p = 0; p < u.P; ++p) {
+                items[u.N].push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
+                icost[u.N].push_back(u.bcost[b] / (float)u.P);
+            }
+    }
+    // lanes per workgroup per size: common to its units
+    for (int N = 1; N <= kMaxN; ++N) Wn[N] = pick_lanes<T>(N, maxQ[N], maxK[N], opt.lanes);
+    for (size_t ui = 0; ui < units.size(); ++ui) {
+        const int N = units[ui].N;
+        const Layout<T> L = layout<T>(N, maxQ[N], Wn[N], maxK[N], true);
+        ua[ui].Q = maxQ[N];
+        ua[ui].off_qse = L.off_qse;
+        ua[ui].off_tbuf = L.off_tbuf;
+        ua[ui].off_qh = L.off_qh;
+        ua[ui].off_obuf = L.off_obuf;
+        ua[ui].off_misc = L.off_misc;
+    }
+    // lane blocks were cut for the unit's own width; re-cut for the common one
+    for (int N = 1; N <= kMaxN; ++N) {
+        items[N].clear();
+        icost[N].clear();
+    }
+    for (size_t ui = 0; ui < units.size(); ++ui) {
+        const UnitH &u = units[ui];
+        const int W = Wn[u.N];
+        const int64_t nb = (u.G + W - 1) / W;
+        for (int64_t b = 0; b < nb; ++b) {
+            const float bc = u.bcost[std::min<int64_t>((b * W) / u.W, (int64_t)u.bcost.size() - 1)];
+            for (int64_t p = 0; p < u.P; ++p) {
+                items[u.N].push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
+                icost[u.N].push_back(bc / (float)u.P);
+            }
+        }
+    }
+    int64_t n_items = 0;
+    for (int N = 1; N <= kMaxN; ++N) {
+        if (sched != EPI_SCHED_RR && !items[N].empty()) {
+            // longest processing time first
+            std::vector<int64_t> ord(items[N].size());
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return icost[N][x] > icost[N][y]; });
+            std::vector<WorkItem> sorted(ord.size());
+            for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[N][ord[i]];
+            items[N] = std::move(sorted);
+        }
+        n_items += (int64_t)items[N].size();
+    }
+    // work-log buffers (per-item wall-clock stamps live with the first set)
+    for (auto &r : sets) r.c->logged = opt.worklog;
+    if (opt.worklog) {
+        if ((e = sets[0].c->cycles.alloc(sizeof(int64_t) * 2 * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+        for (auto &a : ua) a.cycles = sets[0].c->cycles.as<int64_t>();
+    }
+    DevBuf d_units, d_items, d_queue;
+    if ((e = d_units.alloc(sizeof(CountArgs<T>) * std::max<size_t>(1, ua.size()))) != hipSuccess) return e;
+    if (!ua.empty() && (e = hipMemcpy(d_units.p, ua.data(), sizeof(CountArgs<T>) * ua.size(),
+                                      hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if ((e = d_items.alloc(sizeof(WorkItem) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+    if ((e = d_queue.alloc(sizeof(unsigned long long) * (kMaxN + 1))) != hipSuccess) return e;
+    std::vector<int64_t> ioff(kMaxN + 2, 0);
+    for (int N = 1; N <= kMaxN; ++N) {
+        if (!items[N].empty() &&
+            (e = hipMemcpy(d_items.as<WorkItem>() + ioff[N], items[N].data(), sizeof(WorkItem) * items[N].size(),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        ioff[N + 1] = ioff[N] + (int64_t)items[N].size();
+    }
+    // 4. one graph: clear the queues, one persistent launch per episode size,
+    //    then the reconciliation of every segmented unit
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kMaxN + 1, 0ull);
+    for (int N = 1; N <= kMaxN && e == hipSuccess; ++N) {
+        if (items[N].empty()) continue;
+        const bool filt = filtN[N];
+        PFn<T> fn = filt ? pick_persistent_f<T, true>(N) : pick_persistent_f<T, false>(N);
+        const Layout<T> L = layout<T>(N, maxQ[N], Wn[N], maxK[N], true);
+        e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total);
+        if (e != hipSuccess) break;
+        int per = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(fn), Wn[N], L.total);
+        if (e != hipSuccess) break;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)items[N].size(), (int64_t)ncu * std::max(per, 1)));
+        fn<<<(unsigned)grid, Wn[N], L.total, st>>>(d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[N],
+                                                   (int64_t)items[N].size(), ioff[N],
+                                                   reinterpret_cast<unsigned long long *>(d_queue.p) + N);
+        e = hipGetLastError();
+    }
+    for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
+        if (units[ui].P <= 1) continue;
+        const int N = units[ui].N;
+        KFn<T> rf = pick_reconcile<T>(N);
+        const int RW = 64;
+        const Layout<T> RL = layout<T>(N, maxQ[N], RW, maxK[N], false);
+        CountArgs<T> r = ua[ui];
+        r.off_qse = RL.off_qse;
+        r.off_qh = RL.off_qh;
+        r.off_tbuf = RL.off_tbuf;
+        r.off_obuf = RL.off_obuf;
+        r.off_misc = RL.off_misc;
+        e = ensure_lds_attr<T>(rf, RL.total);
+        if (e != hipSuccess) break;
+        rf<<<(unsigned)((r.G + RW - 1) / RW), RW, RL.total, st>>>(r);
+        e = hipGetLastError();
+    }
+    hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (e == hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the descriptors die here
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto &r : sets) r.c->n_items = n_items;
+    return e;
+}
+
+}  // namespace
+
+hipError_t launch_count_batched(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp,
+                                int32_t *d_flags, hipStream_t st) {
+    if (sets.empty()) return hipSuccess;
+    const int kind = sets[0].s->ts_kind;
+    for (auto &r : sets)
+        if (r.s->ts_kind != kind) return hipErrorInvalidValue;
+    if (kind == EPI_TS_I64) return batched_t<int64_t>(sets, sched, opt, mlp, d_flags, st);
+    return batched_t<int32_t>(sets, sched, opt, mlp, d_flags, st);
 }
 
 }  // namespace epi

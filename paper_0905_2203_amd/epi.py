@@ -35,6 +35,7 @@ EPI_MODE_PLAIN = 0
 EPI_MODE_BATCHED = 1
 EPI_SCHED_RR = 0
 EPI_SCHED_LEARNED = 1
+EPI_SCHED_HEURISTIC = 2
 
 EXPORTS = [
     "epi_create", "epi_destroy", "epi_last_error", "epi_status_string",
@@ -46,12 +47,15 @@ EXPORTS = [
     "epi_mine_level_bytes", "epi_mine_release",
     "epi_mlp_init", "epi_mlp_params", "epi_mlp_get_params", "epi_mlp_set_params", "epi_mlp_forward",
     "epi_mlp_grad", "epi_mlp_adam_step", "epi_mlp_train", "epi_costmodel_features",
+    "epi_read_worklog", "epi_read_item_cycles", "epi_costmodel_train", "epi_autotune",
 ]
 EPI_OPT_SEGMENTS = 1
 EPI_OPT_LANES = 2
 EPI_OPT_TARGET_LANES = 3
 EPI_OPT_PAIR_FILTER = 4
 EPI_OPT_MINE_ENGINE = 5
+EPI_OPT_WORKLOG = 6
+EPI_OPT_TARGET_ITEMS = 7
 
 
 class EpiError(RuntimeError):
@@ -114,6 +118,10 @@ def lib():
             "epi_mlp_adam_step": ([P, P, ctypes.c_float], I32),
             "epi_mlp_train": ([P, P, P, I64, I32, I32, ctypes.c_float, P], I32),
             "epi_costmodel_features": ([P, I32, P, I64], I32),
+            "epi_read_worklog": ([P, I32, P, I64], I32),
+            "epi_read_item_cycles": ([P, I32, P, I64, ctypes.POINTER(I64)], I32),
+            "epi_costmodel_train": ([P, P, I32, I32, ctypes.c_uint64, P], I32),
+            "epi_autotune": ([P, P, I32, INT, ctypes.c_char_p, P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -369,3 +377,31 @@ class Context:
         X = np.zeros((int(m), 23), np.float32)
         self._check(lib().epi_costmodel_features(self.h, int(set_id), _ptr(X), int(m)))
         return X
+
+    # work log -------------------------------------------------------------------
+    def epi_read_worklog(self, set_id: int, m: int) -> np.ndarray:
+        w = np.zeros((int(m), 5), np.int32)
+        self._check(lib().epi_read_worklog(self.h, int(set_id), _ptr(w), int(m)))
+        return w
+
+    def epi_read_item_cycles(self, set_id: int) -> np.ndarray:
+        n = I64()
+        self._check(lib().epi_read_item_cycles(self.h, int(set_id), None, 0, ctypes.byref(n)))
+        c = np.zeros((n.value, 2), np.int64)
+        if n.value:
+            self._check(lib().epi_read_item_cycles(self.h, int(set_id), _ptr(c), n.value, ctypes.byref(n)))
+        return c
+
+    def epi_costmodel_train(self, set_ids, epochs: int, seed: int) -> np.ndarray:
+        ids = np.ascontiguousarray(np.atleast_1d(np.asarray(set_ids, np.int32)))
+        losses = np.zeros(int(epochs), np.float32)
+        self._check(lib().epi_costmodel_train(self.h, _ptr(ids), ids.size, int(epochs), int(seed), _ptr(losses)))
+        return losses
+
+    def epi_autotune(self, set_ids, sched: int = EPI_SCHED_RR, cache_path=None):
+        """Returns (lanes, work items per compute unit)."""
+        ids = np.ascontiguousarray(np.atleast_1d(np.asarray(set_ids, np.int32)))
+        out = np.zeros(2, np.int64)
+        cp = None if cache_path is None else str(cache_path).encode()
+        self._check(lib().epi_autotune(self.h, _ptr(ids), ids.size, int(sched), cp, _ptr(out)))
+        return int(out[0]), int(out[1])
