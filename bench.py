@@ -130,6 +130,16 @@ def ablation(k, scale, reps):
                                                                sched=epi.EPI_SCHED_LEARNED), reps)
     assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "learned"
     log(f"  plain {res['plain']:.3f}s learned {res['batched_learned']:.3f}s (training {train_s:.1f}s)")
+    # measured: the schedule by each episode's own logged work (an exact cost model)
+    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)
+    ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
+    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+    res["batched_measured"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                                sched=epi.EPI_SCHED_MEASURED), reps)
+    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "measured"
+    log(f"  measured-cost schedule {res['batched_measured']:.3f}s")
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s",
@@ -138,6 +148,7 @@ def ablation(k, scale, reps):
         "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
         "learned_vs_heuristic": res["batched_heuristic"] / res["batched_learned"],
         "learned_vs_plain": res["plain"] / res["batched_learned"],
+        "measured_vs_learned": res["batched_learned"] / res["batched_measured"],
         "cost_model": {"train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                        "train_candidates": int(sum(c["N"].size for _, c in train_sets))},
         "counts_equal_across_modes": True,

@@ -58,7 +58,7 @@ enum {
 
 enum { EPI_TS_I32 = 0, EPI_TS_I64 = 1 };
 enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1 };
-enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1, EPI_SCHED_HEURISTIC = 2 };
+enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1, EPI_SCHED_HEURISTIC = 2, EPI_SCHED_MEASURED = 3 };
 
 #define EPI_MAX_N 8 /* largest episode size */
 
@@ -161,7 +161,10 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  * predicted work (see epi_costmodel_train; without a trained model it falls
  * back to EPI_SCHED_RR), cuts costly lane blocks into more time segments and
  * queues items longest first; EPI_SCHED_HEURISTIC does the same with the
- * sum of the types' event counts as the cost.
+ * sum of the types' event counts as the cost; EPI_SCHED_MEASURED with the
+ * work each episode logged in the set's latest count that kept a work log
+ * (events visited + records + queries; EPI_ESTATE for a set that never
+ * logged): the schedule an exact cost model would give, for comparison.
  * The counts never depend on mode or sched. */
 epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched,
                      void *hip_stream);
@@ -177,10 +180,10 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *                         (episode, segment) work lanes (default 262144)
  *   EPI_OPT_PAIR_FILTER   1 (default) / 0: in level-wise discovery, precompute
  *                         for each event, event type and menu interval
- *                         whether a constrained neighbour exists before and
- *                         after it (the tracking step of Sec. IV-C, for all
- *                         pairs at once) and skip events with none
- *                         (state-machine mining engine only)
+ *                         whether a constrained neighbour exists before (and,
+ *                         for the state-machine engine, after) it (the
+ *                         tracking step of Sec. IV-C, for all pairs at once)
+ *                         and skip events with none
  *   EPI_OPT_MINE_ENGINE   level-wise discovery engine: 1 (default) extends the
  *                         previous level's chain lists (decomposition of
  *                         Sec. IV-A, one merge per candidate); 0 counts every
@@ -272,16 +275,39 @@ epi_status epi_mlp_train(epi_ctx *ctx, const float *X, const float *t, int64_t B
 
 /* Train the cost model on sets counted with the work log on (best without
  * time segments, EPI_OPT_SEGMENTS = 1, so each episode's logged work is its
- * own): features of each episode -> log1p(events visited + records +
- * queries), shuffled once,
- * `epochs` passes of Adam (lr 3e-3, mini-batches of 512) from a fresh model
- * seeded by `seed`; losses[epochs] (may be null) receives the epoch losses. */
+ * own): features x of each episode -> t = log1p(events visited + records +
+ * queries).  Features and target are standardised on the training set
+ * (x' = (x - x_mu) * x_isd with x_isd = 1 / standard deviation, 0 for a
+ * constant feature; t' = (t - y_mu) / y_sd), shuffled once, and a fresh model
+ * seeded by `seed` is trained on (x', t') for `epochs` passes of Adam
+ * (lr 3e-3, mini-batches of 512); losses[epochs] (may be null) receives the
+ * epoch losses in standardised units (1 = the target's variance).  The
+ * cost model's prediction is then y_sd * net(x') + y_mu. */
 epi_status epi_costmodel_train(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int32_t epochs, uint64_t seed,
                                float *losses);
 
-/* The model's 23 input features of every candidate of a set (submission
- * order, X[m][23]): log1p of the event count of each node's type (8, zero
- * padded), log1p(hi - lo) and log1p(hi) of each constraint (7 + 7), and N. */
+/* The cost model's standardisation: x_mu[F], x_isd[F] and y_mu_sd[2] =
+ * {y_mu, y_sd} (identity after epi_mlp_init; any pointer may be null). */
+epi_status epi_costmodel_scaling(epi_ctx *ctx, float *x_mu, float *x_isd, float *y_mu_sd);
+
+/* Save the cost model (parameters and standardisation) to a file / load it
+ * into the context (replacing any model; Adam state cleared).  The file is
+ * binary: "EPICM001", int32 F, int64 n_params, float params[n_params],
+ * float x_mu[F], float x_isd[F], float y_mu, float y_sd, host byte order.
+ * EPI_ESTATE when saving without a model; EPI_EINVAL for a path that cannot
+ * be opened or a file that is not exactly this layout. */
+epi_status epi_costmodel_save(epi_ctx *ctx, const char *path);
+epi_status epi_costmodel_load(epi_ctx *ctx, const char *path);
+
+/* The cost model's predicted log1p(work) of every candidate of a set
+ * (submission order, y[m]); the model must take the 24 features below.
+ * The learned schedule orders work by exp of this prediction. */
+epi_status epi_costmodel_predict(epi_ctx *ctx, int32_t set_id, float *y, int64_t m);
+
+/* The model's 24 input features of every candidate of a set (submission
+ * order, X[m][24]): log1p of the event count of each node's type (8, zero
+ * padded), log1p(hi - lo) and log1p(hi) of each constraint (7 + 7), N, and
+ * log1p of the sum of the nodes' type event counts. */
 epi_status epi_costmodel_features(epi_ctx *ctx, int32_t set_id, float *X, int64_t m);
 
 /* ------------------------------------------------------------------------

@@ -467,12 +467,37 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
     if (!ctx) return EPI_EINVAL;
     if (k < 0 || (k > 0 && !set_ids)) return fail(ctx, EPI_EINVAL, "bad set list");
     if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED) return fail(ctx, EPI_EINVAL, "unknown mode %d", mode);
-    if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED && sched != EPI_SCHED_HEURISTIC)
+    if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED && sched != EPI_SCHED_HEURISTIC &&
+        sched != EPI_SCHED_MEASURED)
         return fail(ctx, EPI_EINVAL, "unknown sched %d", sched);
-    for (int32_t i = 0; i < k; ++i)
-        if (!find_set(ctx, set_ids[i])) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+    for (int32_t i = 0; i < k; ++i) {
+        CandSet *cs = find_set(ctx, set_ids[i]);
+        if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+        if (mode == EPI_MODE_BATCHED && sched == EPI_SCHED_MEASURED && !(cs->counted && cs->logged) &&
+            (int64_t)cs->measured.size() != cs->m)
+            return fail(ctx, EPI_ESTATE, "set %d has no work log to schedule by", set_ids[i]);
+    }
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
     hipStream_t st = pick_stream(ctx, hip_stream);
+    // measured costs: the logged work, per grouped slot, taken before the log
+    // is reset (kept for later counts that log nothing)
+    if (mode == EPI_MODE_BATCHED && sched == EPI_SCHED_MEASURED) {
+        for (int32_t i = 0; i < k; ++i) {
+            CandSet *cs = find_set(ctx, set_ids[i]);
+            if (!(cs->counted && cs->logged)) continue;
+            std::vector<int32_t> w((size_t)cs->m * kWork), orig(cs->m);
+            if (cs->m > 0) {
+                HIPTRY(ctx, hipStreamSynchronize(st), "sync");
+                HIPTRY(ctx, hipMemcpy(w.data(), cs->work.p, sizeof(int32_t) * w.size(), hipMemcpyDeviceToHost), "copy");
+                HIPTRY(ctx, hipMemcpy(orig.data(), cs->orig.p, sizeof(int32_t) * cs->m, hipMemcpyDeviceToHost), "copy");
+            }
+            cs->measured.resize(cs->m);
+            for (int64_t j = 0; j < cs->m; ++j) {
+                const int32_t *x = w.data() + (int64_t)orig[j] * kWork;
+                cs->measured[j] = (float)x[0] + (float)x[1] + (float)x[2];
+            }
+        }
+    }
     // work log: cleared before the count
     for (int32_t i = 0; i < k; ++i) {
         CandSet *cs = find_set(ctx, set_ids[i]);
@@ -598,10 +623,15 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     mn->engine = ctx->c.opt.mine_engine;
     if (mn->engine == 1) {
         // extension engine: each level extends the previous level's chain lists
-        auto t0 = std::chrono::steady_clock::now();
+        const double xbits_bytes = 8.0 * n_menu * (double)s->K * (double)((s->n + 63) / 64);
+        if (ctx->c.opt.pair_filter && max_size > 1 && s->n > 0 &&
+            xbits_bytes <= (double)ctx->c.opt.pair_filter_max_bytes) {
+            auto tb = std::chrono::steady_clock::now();
+            HIPTRY(ctx, build_index_pred_bits(*s, *mn, st), "building predecessor bitmaps");
+            mn->bits_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+        }
         HIPTRY(ctx, extend_level1(*s, *mn, st), "counting level 1");
         mn->levels.back().gen_ms = 0;
-        (void)t0;
         for (int N = 2; N <= max_size; ++N) {
             const MineLevel &prev = mn->levels.back();
             if (prev.nf == 0 || (N == 2 && prev.nf < 2)) break;
@@ -754,9 +784,15 @@ epi_status epi_mine_level_bytes(epi_ctx *ctx, int32_t mine_id, int32_t level, in
     if (!ctx || !alg_bytes) return fail(ctx, EPI_EINVAL, "null argument");
     auto it = ctx->c.mines.find(mine_id);
     if (it == ctx->c.mines.end()) return fail(ctx, EPI_ESTATE, "unknown mining id %d", mine_id);
-    const auto &lv = it->second->levels;
-    if (level < 1 || level > (int32_t)lv.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
-    *alg_bytes = lv[level - 1].alg_bytes;
+    Mine &mn = *it->second;
+    if (level < 1 || level > (int32_t)mn.levels.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
+    MineLevel &L = mn.levels[level - 1];
+    if (L.alg_bytes < 0 && L.implicit && level >= 2) {
+        Stream *s = find_stream(ctx, mn.stream_id);
+        if (!s) return fail(ctx, EPI_ESTATE, "the mined stream has been released");
+        extend_level_bytes(*s, mn, level);
+    }
+    *alg_bytes = std::max<int64_t>(0, L.alg_bytes);
     return EPI_OK;
 }
 
@@ -985,14 +1021,140 @@ epi_status epi_costmodel_train(epi_ctx *ctx, const int32_t *set_ids, int32_t k, 
         z ^= z >> 31;
         std::swap(ord[i], ord[(int64_t)(z % (uint64_t)(i + 1))]);
     }
+    // standardise inputs and target on the training set (a constant feature
+    // gets a zero scale and drops out); the network learns the standardised
+    // problem and the scaling is kept with it
+    std::vector<double> mu(kFeatures, 0.0), var(kFeatures, 0.0);
+    double tmu = 0, tvar = 0;
+    for (int64_t i = 0; i < B; ++i) {
+        for (int f = 0; f < kFeatures; ++f) mu[f] += X[i * kFeatures + f];
+        tmu += t[i];
+    }
+    for (int f = 0; f < kFeatures; ++f) mu[f] /= (double)B;
+    tmu /= (double)B;
+    for (int64_t i = 0; i < B; ++i) {
+        for (int f = 0; f < kFeatures; ++f) {
+            const double d = X[i * kFeatures + f] - mu[f];
+            var[f] += d * d;
+        }
+        tvar += (t[i] - tmu) * (t[i] - tmu);
+    }
+    std::vector<float> x_mu(kFeatures), x_isd(kFeatures);
+    for (int f = 0; f < kFeatures; ++f) {
+        const double sd = std::sqrt(var[f] / (double)B);
+        x_mu[f] = (float)mu[f];
+        x_isd[f] = sd > 1e-6 ? (float)(1.0 / sd) : 0.f;
+    }
+    const double tsd = std::sqrt(tvar / (double)B);
+    const float y_sd = tsd > 1e-6 ? (float)tsd : 1.f;
     std::vector<float> Xs((size_t)B * kFeatures), ts(B);
     for (int64_t i = 0; i < B; ++i) {
-        std::copy(X.begin() + ord[i] * kFeatures, X.begin() + (ord[i] + 1) * kFeatures, Xs.begin() + i * kFeatures);
-        ts[i] = t[ord[i]];
+        for (int f = 0; f < kFeatures; ++f)
+            Xs[i * kFeatures + f] = (X[ord[i] * kFeatures + f] - x_mu[f]) * x_isd[f];
+        ts[i] = (float)((t[ord[i]] - tmu) / y_sd);
     }
     epi_status v = epi_mlp_init(ctx, kFeatures, seed);
     if (v != EPI_OK) return v;
+    HIPTRY(ctx, mlp_set_scaling(ctx->c.mlp, x_mu.data(), x_isd.data(), (float)tmu, y_sd), "scaling");
     return epi_mlp_train(ctx, Xs.data(), ts.data(), B, epochs, 512, 3e-3f, losses);
+}
+
+epi_status epi_costmodel_scaling(epi_ctx *ctx, float *x_mu, float *x_isd, float *y_mu_sd) {
+    if (!ctx) return EPI_EINVAL;
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    const Mlp &net = ctx->c.mlp;
+    if (x_mu) std::copy(net.x_mu.begin(), net.x_mu.end(), x_mu);
+    if (x_isd) std::copy(net.x_isd.begin(), net.x_isd.end(), x_isd);
+    if (y_mu_sd) {
+        y_mu_sd[0] = net.y_mu;
+        y_mu_sd[1] = net.y_sd;
+    }
+    return EPI_OK;
+}
+
+namespace {
+constexpr char kModelMagic[8] = {'E', 'P', 'I', 'C', 'M', '0', '0', '1'};
+}
+
+epi_status epi_costmodel_save(epi_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(ctx, EPI_EINVAL, "bad arguments");
+    epi_status v = need_mlp(ctx, -1);
+    if (v != EPI_OK) return v;
+    const Mlp &net = ctx->c.mlp;
+    const int32_t F = net.F;
+    const int64_t np = mlp_n_params(F);
+    std::vector<float> p(np);
+    HIPTRY(ctx, hipMemcpy(p.data(), net.p.p, sizeof(float) * np, hipMemcpyDeviceToHost), "copy");
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(ctx, EPI_EINVAL, "cannot write %s", path);
+    const float y[2] = {net.y_mu, net.y_sd};
+    bool ok = std::fwrite(kModelMagic, 1, 8, f) == 8 && std::fwrite(&F, sizeof F, 1, f) == 1 &&
+              std::fwrite(&np, sizeof np, 1, f) == 1 && std::fwrite(p.data(), sizeof(float), np, f) == (size_t)np &&
+              std::fwrite(net.x_mu.data(), sizeof(float), F, f) == (size_t)F &&
+              std::fwrite(net.x_isd.data(), sizeof(float), F, f) == (size_t)F && std::fwrite(y, sizeof(float), 2, f) == 2;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? EPI_OK : fail(ctx, EPI_EINVAL, "writing %s failed", path);
+}
+
+epi_status epi_costmodel_load(epi_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(ctx, EPI_EINVAL, "bad arguments");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, EPI_EINVAL, "cannot read %s", path);
+    char magic[8];
+    int32_t F = 0;
+    int64_t np = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kModelMagic, 8) == 0 &&
+              std::fread(&F, sizeof F, 1, f) == 1 && F >= 1 && F <= 4096 && std::fread(&np, sizeof np, 1, f) == 1 &&
+              np == mlp_n_params(F);
+    std::vector<float> p, mu, isd;
+    float y[2] = {0.f, 1.f};
+    if (ok) {
+        p.resize(np);
+        mu.resize(F);
+        isd.resize(F);
+        ok = std::fread(p.data(), sizeof(float), np, f) == (size_t)np &&
+             std::fread(mu.data(), sizeof(float), F, f) == (size_t)F &&
+             std::fread(isd.data(), sizeof(float), F, f) == (size_t)F && std::fread(y, sizeof(float), 2, f) == 2 &&
+             std::fgetc(f) == EOF;
+    }
+    std::fclose(f);
+    if (!ok) return fail(ctx, EPI_EINVAL, "%s is not a cost model file of this library", path);
+    for (float x : p)
+        if (!std::isfinite(x)) return fail(ctx, EPI_EINVAL, "%s holds non-finite parameters", path);
+    if (!(y[1] > 0.f) || !std::isfinite(y[0])) return fail(ctx, EPI_EINVAL, "%s holds a bad output scale", path);
+    epi_status v = epi_mlp_init(ctx, F, 0);
+    if (v != EPI_OK) return v;
+    v = epi_mlp_set_params(ctx, p.data(), np);
+    if (v != EPI_OK) return v;
+    HIPTRY(ctx, mlp_set_scaling(ctx->c.mlp, mu.data(), isd.data(), y[0], y[1]), "scaling");
+    return EPI_OK;
+}
+
+epi_status epi_costmodel_predict(epi_ctx *ctx, int32_t set_id, float *y, int64_t m) {
+    if (!ctx) return EPI_EINVAL;
+    epi_status v = need_mlp(ctx, kFeatures);
+    if (v != EPI_OK) return v;
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (cs->compact) return fail(ctx, EPI_EINVAL, "set %d has no features", set_id);
+    if (m != cs->m || (m > 0 && !y)) return fail(ctx, EPI_EINVAL, "set %d holds %lld candidates", set_id,
+                                                 (long long)cs->m);
+    if (m == 0) return EPI_OK;
+    Stream *s = find_stream(ctx, cs->stream_id);
+    hipStream_t st = ctx->c.stream;
+    DevBuf dX, dy;
+    HIPTRY(ctx, dX.alloc(sizeof(float) * m * kFeatures), "alloc");
+    HIPTRY(ctx, dy.alloc(sizeof(float) * m), "alloc");
+    HIPTRY(ctx, candidate_features(*s, *cs, dX.as<float>(), st), "features");
+    HIPTRY(ctx, costmodel_predict_device(ctx->c.mlp, dX.as<float>(), m, dy.as<float>(), st), "predict");
+    std::vector<float> grouped(m);
+    std::vector<int32_t> orig(m);
+    HIPTRY(ctx, hipMemcpyAsync(grouped.data(), dy.p, sizeof(float) * m, hipMemcpyDeviceToHost, st), "copy");
+    HIPTRY(ctx, hipMemcpyAsync(orig.data(), cs->orig.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st), "copy");
+    HIPTRY(ctx, hipStreamSynchronize(st), "sync");
+    for (int64_t i = 0; i < m; ++i) y[orig[i]] = grouped[i];
+    return EPI_OK;
 }
 
 // ---- autotuner ---------------------------------------------------------------
@@ -1034,10 +1196,13 @@ bool cache_lookup(const char *path, const std::string &key, int64_t *lanes, int6
     if (!path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
-    char kb[512];
+    char line[1024], kb[512];
     long long a, b;
     bool found = false;
-    while (fscanf(f, "%511s %lld %lld", kb, &a, &b) == 3) {
+    // one entry per line: key lanes items; other lines are ignored
+    while (fgets(line, sizeof line, f)) {
+        char extra;
+        if (sscanf(line, "%511s %lld %lld %c", kb, &a, &b, &extra) != 3) continue;
         if (key == kb && (a == 64 || a == 128 || a == 256) && b >= 1 && b <= 4096) {
             *lanes = a;
             *items = b;

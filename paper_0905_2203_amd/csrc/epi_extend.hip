@@ -57,8 +57,12 @@ struct ExtArgs {
     const uint8_t *fliv;     // [nfprev] last interval id
     const int32_t *rlo, *rhi, *byprefix;
     const int64_t *out_off;  // [nA + 1]
+    const int32_t *aorder;   // order in which the workgroups take the alphas (null: index order)
     const T *menu;           // (lo, hi) pairs
     int32_t M;
+    const uint64_t *xbits;   // predecessor bits (interval, type, index position) or null
+    int64_t xwords;
+    int32_t K;
     int32_t *counts;         // [m]
     int32_t *nvalid;         // [m]
     // write pass: explicit list of candidates
@@ -67,15 +71,27 @@ struct ExtArgs {
     const uint16_t *w_type;
     const uint8_t *w_iv;
     const int64_t *w_off;
+    const int32_t *w_order;  // order in which the threads take the write list (null: list order)
     Pair<T> *w_out;
 };
 
 // One candidate: merge alpha's chain list with the events of type B; returns
 // the count, the number of end events, and optionally writes the new chain.
-template <typename T, int MODE, bool WRITE>
-__device__ __forceinline__ int32_t ext_core(const ExtArgs<T> &a, int64_t alpha, int32_t B, int iv, int32_t *nval,
-                                            Pair<T> *out) {
+//
+// The lanes of a wave read 64 different type lists, far more lines than the
+// L1 keeps between a lane's visits; so each lane reads its list in whole
+// 64-byte lines (16-byte loads from a line-aligned address) and consumes
+// them from registers; the elements before the first line boundary and after
+// the last whole line are read one by one.  Alpha's chain list is shared by
+// the wave; its next two entries are held ahead.
+template <typename T, int MODE, bool WRITE, bool FILT>
+__device__ __forceinline__ int32_t ext_core(const ExtArgs<T> &a, int64_t alpha, int32_t X, int32_t B, int iv,
+                                            int32_t *nval, Pair<T> *out) {
     constexpr T kMin = TsLimits<T>::lo();
+    constexpr T kMax = TsLimits<T>::hi();
+    constexpr int kLineBytes = 64;
+    constexpr int kLine = kLineBytes / (int)sizeof(T);
+    constexpr int kVec = kLineBytes / 16;
     const T lo = a.menu[2 * iv], hi = a.menu[2 * iv + 1];
     // alpha's chain list
     const T *at = nullptr;
@@ -89,53 +105,106 @@ __device__ __forceinline__ int32_t ext_core(const ExtArgs<T> &a, int64_t alpha, 
         ap = a.chains + a.coff[alpha];
         alen = (int32_t)(a.coff[alpha + 1] - a.coff[alpha]);
     }
-    const T *y = a.ts + a.type_off[B];
-    const int32_t ylen = a.type_off[B + 1] - a.type_off[B];
+    auto chain_at = [&](int32_t q) {
+        Pair<T> v;
+        if (q < alen) {
+            if (MODE == 0) {
+                v.s = at[q];
+                v.e = v.s;
+            } else {
+                v = ap[q];
+            }
+        } else {
+            v.s = kMax;
+            v.e = kMax;
+        }
+        return v;
+    };
+    const int32_t y0 = a.type_off[B];
+    const int32_t ylen = a.type_off[B + 1] - y0;
+    const T *y = a.ts + y0;
     int32_t p = 0, cnt = 0, nv = 0;
     T prev_e = kMin;
     T xt = kMin, xs = kMin;  // latest entry with time < t_y - lo (when p > 0)
-    T nt = alen > 0 ? (MODE == 0 ? at[0] : ap[0].s) : TsLimits<T>::hi();
-    for (int32_t i0 = 0; i0 < ylen; i0 += 4) {
-        // four independent loads in flight per lane
-        T yy[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) yy[u] = i0 + u < ylen ? y[i0 + u] : TsLimits<T>::hi();
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (i0 + u >= ylen) break;
-            const T ty = yy[u];
-            const T lim = (T)(ty - lo);
-            while (nt < lim) {
-                if (MODE == 0) {
-                    xt = nt;
-                    xs = nt;
-                } else {
-                    xt = ap[p].s;
-                    xs = ap[p].e;
-                }
-                ++p;
-                nt = p < alen ? (MODE == 0 ? at[p] : ap[p].s) : TsLimits<T>::hi();
+    Pair<T> n1 = chain_at(0), n2 = chain_at(1);
+    auto step = [&](const T ty) {
+        const T lim = (T)(ty - lo);
+        while (n1.s < lim) {
+            xt = n1.s;
+            xs = n1.e;
+            ++p;
+            n1 = n2;
+            n2 = chain_at(p + 1);
+        }
+        if (p > 0 && xt >= (T)(ty - hi)) {
+            if (WRITE) {
+                Pair<T> w;
+                w.s = ty;
+                w.e = xs;
+                out[nv] = w;
             }
-            if (p > 0 && xt >= (T)(ty - hi)) {
-                if (WRITE) {
-                    Pair<T> v;
-                    v.s = ty;
-                    v.e = xs;
-                    out[nv] = v;
-                }
-                ++nv;
-                if (xs > prev_e) {
-                    ++cnt;
-                    prev_e = ty;
+            ++nv;
+            if (xs > prev_e) {
+                ++cnt;
+                prev_e = ty;
+            }
+        }
+    };
+    if (FILT) {
+        // only the events of B with an event of alpha's last type X at a gap
+        // in the interval before them can end an occurrence: visit those
+        if (ylen > 0) {
+            const uint64_t *pb = a.xbits + ((int64_t)iv * a.K + X) * a.xwords;
+            const int32_t q1 = y0 + ylen;
+            const int32_t w0 = y0 >> 6, w1 = (q1 - 1) >> 6;
+            for (int32_t w = w0; w <= w1; ++w) {
+                uint64_t bits = pb[w];
+                if (w == w0) bits &= ~0ull << (y0 & 63);
+                if (w == w1 && (q1 & 63)) bits &= (1ull << (q1 & 63)) - 1ull;
+                const T *yw = a.ts + ((int64_t)w << 6);
+                while (bits) {
+                    // up to four loads in flight
+                    T v[4];
+                    int k = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (bits) {
+                            v[u] = yw[__builtin_ctzll(bits)];
+                            bits &= bits - 1ull;
+                            k = u + 1;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (u < k) step(v[u]);
                 }
             }
         }
+        *nval = nv;
+        return cnt;
     }
+    // elements up to the first line boundary
+    const int32_t lead = (int32_t)((uint32_t)y0 & (uint32_t)(kLine - 1));
+    const int32_t head = lead == 0 ? 0 : min(ylen, kLine - lead);
+    int32_t i = 0;
+    for (; i < head; ++i) step(y[i]);
+    // whole lines
+    for (; i + kLine <= ylen; i += kLine) {
+        uint4 raw[kVec];
+        const uint4 *src = reinterpret_cast<const uint4 *>(y + i);
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) raw[k] = src[k];
+        const T *v = reinterpret_cast<const T *>(raw);
+#pragma unroll
+        for (int u = 0; u < kLine; ++u) step(v[u]);
+    }
+    // the rest
+    for (; i < ylen; ++i) step(y[i]);
     *nval = nv;
     return cnt;
 }
 
-template <typename T>
+template <typename T, bool FILT>
 __global__ __launch_bounds__(64) void k_ext_count0(ExtArgs<T> a) {
     const int64_t alpha = blockIdx.x;
     const int lane = threadIdx.x;
@@ -148,18 +217,19 @@ __global__ __launch_bounds__(64) void k_ext_count0(ExtArgs<T> a) {
         if (bi == alpha) continue;
         const int64_t c = o0 + (bi < alpha ? r : r - a.M);
         int32_t nv;
-        a.counts[c] = ext_core<T, 0, false>(a, alpha, a.f1[bi], iv, &nv, nullptr);
+        a.counts[c] = ext_core<T, 0, false, FILT>(a, alpha, a.f1[alpha], a.f1[bi], iv, &nv, nullptr);
         a.nvalid[c] = nv;
     }
 }
 
-template <typename T>
+template <typename T, bool FILT>
 __global__ __launch_bounds__(64) void k_ext_count1(ExtArgs<T> a) {
-    const int64_t alpha = blockIdx.x;
+    const int64_t alpha = a.aorder ? a.aorder[blockIdx.x] : (int64_t)blockIdx.x;
     const int lane = threadIdx.x;
     const int32_t r0 = a.rlo[alpha], r1 = a.rhi[alpha];
     const int64_t o0 = a.out_off[alpha];
     const uint16_t first = a.ftype0[alpha];
+    const int32_t X = a.flast[alpha];
     int32_t skipped = 0;
     const uint64_t lt = (1ull << lane) - 1ull;
     for (int32_t rb = r0; rb < r1; rb += 64) {  // uniform across the wave
@@ -171,19 +241,22 @@ __global__ __launch_bounds__(64) void k_ext_count1(ExtArgs<T> a) {
         if (in && !excl) {
             const int64_t c = o0 + (r - r0) - skipped - __popcll(em & lt);
             int32_t nv;
-            a.counts[c] = ext_core<T, 1, false>(a, alpha, a.flast[beta], a.fliv[beta], &nv, nullptr);
+            a.counts[c] = ext_core<T, 1, false, FILT>(a, alpha, X, a.flast[beta], a.fliv[beta], &nv, nullptr);
             a.nvalid[c] = nv;
         }
         skipped += __popcll(em);
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool FILT>
 __global__ __launch_bounds__(256) void k_ext_write(ExtArgs<T> a) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= a.nw) return;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nw) return;
+    const int64_t f = a.w_order ? a.w_order[g] : g;
     int32_t nv;
-    (void)ext_core<T, MODE, true>(a, a.w_alpha[f], a.w_type[f], a.w_iv[f], &nv, a.w_out + a.w_off[f]);
+    const int32_t alpha = a.w_alpha[f];
+    const int32_t X = MODE == 0 ? a.f1[alpha] : a.flast[alpha];
+    (void)ext_core<T, MODE, true, FILT>(a, alpha, X, a.w_type[f], a.w_iv[f], &nv, a.w_out + a.w_off[f]);
 }
 
 // Frequent selection (count > threshold), order preserving: per-block flag
@@ -277,16 +350,50 @@ void parallel_for(int64_t n, F &&body) {
     for (auto &t : th) t.join();
 }
 
+// Indices 0..n-1 stably ordered by key(i) in [0, K) (counting sort).
+template <typename F>
+std::vector<int32_t> order_by_key(int64_t n, int32_t K, F &&key) {
+    std::vector<int64_t> start(K + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++start[key(i) + 1];
+    for (int32_t k = 0; k < K; ++k) start[k + 1] += start[k];
+    std::vector<int32_t> out(n);
+    for (int64_t i = 0; i < n; ++i) out[start[key(i)]++] = (int32_t)i;
+    return out;
+}
+
 // local extension index e of alpha (level >= 3) -> position r in byprefix
-int32_t ext_position(const MineLevel &L, const MineLevel &P, int64_t alpha, int64_t e) {
-    const uint16_t first = P.ftypes[alpha];  // row 0 of the previous level
-    int64_t k = -1;
-    for (int32_t r = L.rlo[alpha]; r < L.rhi[alpha]; ++r) {
-        const int32_t beta = L.byprefix[r];
-        if (P.ftypes[(size_t)(P.N - 1) * P.nf + beta] == first) continue;
-        if (++k == e) return r;
+// (the excluded extensions, those repeating alpha's first type, are the
+// contiguous range [xlo, xhi) of alpha's range)
+int32_t ext_position(const MineLevel &L, int64_t alpha, int64_t e) {
+    const int64_t r = L.rlo[alpha] + e;
+    return (int32_t)(r < L.xlo[alpha] ? r : r + (L.xhi[alpha] - L.xlo[alpha]));
+}
+
+// Sort with a strict weak order on nt threads: sorted chunks, then merged
+// pairwise in rounds.
+template <typename It, typename Less>
+void parallel_sort(It first, It last, Less less) {
+    const int64_t n = last - first;
+    const int nt = nthreads();
+    if (n < 65536 || nt == 1) {
+        std::sort(first, last, less);
+        return;
     }
-    return -1;
+    std::vector<int64_t> cut(nt + 1);
+    for (int q = 0; q <= nt; ++q) cut[q] = n * q / nt;
+    {
+        std::vector<std::thread> th;
+        for (int q = 0; q < nt; ++q) th.emplace_back([&, q] { std::sort(first + cut[q], first + cut[q + 1], less); });
+        for (auto &t : th) t.join();
+    }
+    for (int width = 1; width < nt; width *= 2) {
+        std::vector<std::thread> th;
+        for (int q = 0; q + width < nt; q += 2 * width) {
+            const int64_t a = cut[q], b = cut[q + width], c = cut[std::min(nt, q + 2 * width)];
+            th.emplace_back([=] { std::inplace_merge(first + a, first + b, first + c, less); });
+        }
+        for (auto &t : th) t.join();
+    }
 }
 
 template <typename T>
@@ -313,15 +420,17 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
         auto piv = [&](int64_t i, int k) { return P.fiv[(size_t)k * P.nf + i]; };
         L.byprefix.resize(P.nf);
         std::iota(L.byprefix.begin(), L.byprefix.end(), 0);
-        // prefix of beta = its first Pn-1 nodes and Pn-2 intervals
+        // prefix of beta = its first Pn-1 nodes and Pn-2 intervals; within a
+        // prefix, by the last node (type, then interval)
         auto prefix_less = [&](int32_t a, int32_t b) {
             for (int k = 0; k < Pn - 1; ++k) {
                 if (pty(a, k) != pty(b, k)) return pty(a, k) < pty(b, k);
                 if (k < Pn - 2 && piv(a, k) != piv(b, k)) return piv(a, k) < piv(b, k);
             }
-            return false;
+            if (pty(a, Pn - 1) != pty(b, Pn - 1)) return pty(a, Pn - 1) < pty(b, Pn - 1);
+            return piv(a, Pn - 2) < piv(b, Pn - 2);
         };
-        std::sort(L.byprefix.begin(), L.byprefix.end(), prefix_less);
+        parallel_sort(L.byprefix.begin(), L.byprefix.end(), prefix_less);
         // compare prefix(beta) with suffix(alpha) = last Pn-1 nodes of alpha
         auto cmp = [&](int32_t beta, int64_t alpha) {
             for (int k = 0; k < Pn - 1; ++k) {
@@ -332,6 +441,8 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
         };
         L.rlo.resize(nA);
         L.rhi.resize(nA);
+        L.xlo.resize(nA);
+        L.xhi.resize(nA);
         std::vector<int64_t> cnt(nA, 0);
         parallel_for(nA, [&](int64_t x0, int64_t x1) {
             for (int64_t a = x0; a < x1; ++a) {
@@ -341,44 +452,21 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
                     std::partition_point(lo, L.byprefix.end(), [&](int32_t b) { return cmp(b, a) == 0; });
                 L.rlo[a] = (int32_t)(lo - L.byprefix.begin());
                 L.rhi[a] = (int32_t)(hi - L.byprefix.begin());
-                int64_t c = 0;
-                for (int32_t r = L.rlo[a]; r < L.rhi[a]; ++r)
-                    if (pty(L.byprefix[r], Pn - 1) != pty(a, 0)) ++c;
-                cnt[a] = c;
+                // extensions whose new type is alpha's first: one run in the range
+                const uint16_t first = pty(a, 0);
+                const auto xl = std::partition_point(lo, hi, [&](int32_t b) { return pty(b, Pn - 1) < first; });
+                const auto xh = std::partition_point(xl, hi, [&](int32_t b) { return pty(b, Pn - 1) == first; });
+                L.xlo[a] = (int32_t)(xl - L.byprefix.begin());
+                L.xhi[a] = (int32_t)(xh - L.byprefix.begin());
+                cnt[a] = (hi - lo) - (xh - xl);
             }
         });
         for (int64_t a = 0; a < nA; ++a) L.out_off[a + 1] = L.out_off[a] + cnt[a];
     }
     const int64_t m = L.out_off[nA];
     L.m = m;
-    // bytes read and written per candidate: events of the new node's type,
-    // alpha's chain list (pairs), count and end-event count
-    {
-        std::vector<int64_t> part(nA, 0);
-        parallel_for(nA, [&](int64_t x0, int64_t x1) {
-            for (int64_t a = x0; a < x1; ++a) {
-                const int64_t k = L.out_off[a + 1] - L.out_off[a];
-                if (k == 0) continue;
-                int64_t b = 0;
-                const int64_t alen = N == 2 ? ntype(P.ftypes[a]) : P.h_chain_off[a + 1] - P.h_chain_off[a];
-                b += k * (alen * (N == 2 ? 1 : 2) * (int64_t)tsb + 8);
-                if (N == 2) {
-                    for (int64_t bi = 0; bi < nA; ++bi)
-                        if (bi != a) b += M * ntype(P.ftypes[bi]) * (int64_t)tsb;
-                } else {
-                    for (int32_t r = L.rlo[a]; r < L.rhi[a]; ++r) {
-                        const int32_t beta = L.byprefix[r];
-                        if (P.ftypes[(size_t)(P.N - 1) * P.nf + beta] == P.ftypes[a]) continue;
-                        b += ntype(P.ftypes[(size_t)(P.N - 1) * P.nf + beta]) * (int64_t)tsb;
-                    }
-                }
-                part[a] = b;
-            }
-        });
-        for (int64_t a = 0; a < nA; ++a) L.alg_bytes += part[a];
-    }
     // ---- device inputs
-    DevBuf d_out_off, d_f1, d_menu, d_rlo, d_rhi, d_by, d_f0, d_fl, d_fliv, d_counts, d_nval;
+    DevBuf d_out_off, d_f1, d_menu, d_rlo, d_rhi, d_by, d_f0, d_fl, d_fliv, d_counts, d_nval, d_order;
     std::vector<T> menu(2 * M);
     for (int i = 0; i < M; ++i) {
         menu[2 * i] = (T)mn.menu_lo[i];
@@ -393,15 +481,22 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     a.out_off = d_out_off.as<int64_t>();
     a.menu = d_menu.as<T>();
     a.M = M;
+    a.K = s.K;
+    a.xbits = mn.xpred.p ? mn.xpred.as<uint64_t>() : nullptr;
+    a.xwords = mn.xwords;
+    // host sources of asynchronous uploads live until the level's last sync
+    std::vector<uint16_t> f1, f0, fl;
+    std::vector<uint8_t> fliv;
+    std::vector<int32_t> order;
     if (N == 2) {
-        std::vector<uint16_t> f1(P.ftypes.begin(), P.ftypes.begin() + P.nf);
+        f1.assign(P.ftypes.begin(), P.ftypes.begin() + P.nf);
         if ((e = upload(d_f1, f1, st)) != hipSuccess) return e;
         a.f1 = d_f1.as<uint16_t>();
         a.nf1 = (int32_t)P.nf;
     } else {
-        std::vector<uint16_t> f0(P.ftypes.begin(), P.ftypes.begin() + P.nf);
-        std::vector<uint16_t> fl(P.ftypes.begin() + (size_t)(P.N - 1) * P.nf, P.ftypes.begin() + (size_t)P.N * P.nf);
-        std::vector<uint8_t> fliv(P.fiv.begin() + (size_t)(P.N - 2) * P.nf, P.fiv.begin() + (size_t)(P.N - 1) * P.nf);
+        f0.assign(P.ftypes.begin(), P.ftypes.begin() + P.nf);
+        fl.assign(P.ftypes.begin() + (size_t)(P.N - 1) * P.nf, P.ftypes.begin() + (size_t)P.N * P.nf);
+        fliv.assign(P.fiv.begin() + (size_t)(P.N - 2) * P.nf, P.fiv.begin() + (size_t)(P.N - 1) * P.nf);
         if ((e = upload(d_f0, f0, st)) != hipSuccess) return e;
         if ((e = upload(d_fl, fl, st)) != hipSuccess) return e;
         if ((e = upload(d_fliv, fliv, st)) != hipSuccess) return e;
@@ -416,6 +511,12 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
         a.rlo = d_rlo.as<int32_t>();
         a.rhi = d_rhi.as<int32_t>();
         a.byprefix = d_by.as<int32_t>();
+        // workgroups take the alphas grouped by their last type: the waves in
+        // flight then read the same type's predecessor bits and nearly the
+        // same type lists, which stay in each XCD's L2
+        order = order_by_key(nA, s.K, [&](int64_t x) { return (int32_t)fl[x]; });
+        if ((e = upload(d_order, order, st)) != hipSuccess) return e;
+        a.aorder = d_order.as<int32_t>();
     }
     if ((e = d_counts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
     if ((e = d_nval.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
@@ -429,8 +530,13 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
     (void)hipEventRecord(ev0, st);
     if (m > 0) {
-        if (N == 2) k_ext_count0<T><<<(unsigned)nA, 64, 0, st>>>(a);
-        else k_ext_count1<T><<<(unsigned)nA, 64, 0, st>>>(a);
+        if (N == 2) {
+            if (a.xbits) k_ext_count0<T, true><<<(unsigned)nA, 64, 0, st>>>(a);
+            else k_ext_count0<T, false><<<(unsigned)nA, 64, 0, st>>>(a);
+        } else {
+            if (a.xbits) k_ext_count1<T, true><<<(unsigned)nA, 64, 0, st>>>(a);
+            else k_ext_count1<T, false><<<(unsigned)nA, 64, 0, st>>>(a);
+        }
     }
     (void)hipEventRecord(ev1, st);
     e = hipGetLastError();
@@ -507,7 +613,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
                 bt = P.ftypes[r / M];
                 biv = (uint8_t)(r % M);
             } else {
-                const int32_t r = ext_position(L, P, alpha, le);
+                const int32_t r = ext_position(L, alpha, le);
                 const int32_t beta = L.byprefix[r];
                 bt = P.ftypes[(size_t)(P.N - 1) * P.nf + beta];
                 biv = P.fiv[(size_t)(P.N - 2) * P.nf + beta];
@@ -523,7 +629,14 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     });
     L.h_chain_off.assign(nf + 1, 0);
     for (int64_t f = 0; f < nf; ++f) L.h_chain_off[f + 1] = L.h_chain_off[f] + nval[f];
-    DevBuf d_wa, d_wt, d_wi;
+    DevBuf d_wa, d_wt, d_wi, d_wo;
+    // the write pass takes the frequent episodes grouped by alpha's last type
+    // (as the counting pass takes the alphas)
+    std::vector<int32_t> w_order = order_by_key(nf, s.K, [&](int64_t f) {
+        const int64_t al = w_alpha[f];
+        return (int32_t)(N == 2 ? P.ftypes[al] : P.ftypes[(size_t)(P.N - 1) * P.nf + al]);
+    });
+    if ((e = upload(d_wo, w_order, st)) != hipSuccess) return e;
     if ((e = upload(d_wa, w_alpha, st)) != hipSuccess) return e;
     if ((e = upload(d_wt, w_type, st)) != hipSuccess) return e;
     if ((e = upload(d_wi, w_iv, st)) != hipSuccess) return e;
@@ -535,10 +648,16 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
         a.w_type = d_wt.as<uint16_t>();
         a.w_iv = d_wi.as<uint8_t>();
         a.w_off = L.chain_off.as<int64_t>();
+        a.w_order = d_wo.as<int32_t>();
         a.w_out = L.chains.as<Pair<T>>();
         const unsigned blocks = (unsigned)((nf + 255) / 256);
-        if (N == 2) k_ext_write<T, 0><<<blocks, 256, 0, st>>>(a);
-        else k_ext_write<T, 1><<<blocks, 256, 0, st>>>(a);
+        if (N == 2) {
+            if (a.xbits) k_ext_write<T, 0, true><<<blocks, 256, 0, st>>>(a);
+            else k_ext_write<T, 0, false><<<blocks, 256, 0, st>>>(a);
+        } else {
+            if (a.xbits) k_ext_write<T, 1, true><<<blocks, 256, 0, st>>>(a);
+            else k_ext_write<T, 1, false><<<blocks, 256, 0, st>>>(a);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
@@ -595,6 +714,54 @@ hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipS
     return level_t<int32_t>(s, mn, N, d_flags, st);
 }
 
+// Bytes read and written per candidate: the events of the new node's type
+// that the merge visits (with predecessor bits: the bit words over the
+// type's index range and the events whose bit is set), alpha's chain list,
+// the count and the end-event count.
+int64_t extend_level_bytes(const Stream &s, Mine &mn, int level) {
+    MineLevel &L = mn.levels[level - 1];
+    if (L.alg_bytes >= 0) return L.alg_bytes;
+    const MineLevel &P = mn.levels[level - 2];
+    const int N = L.N;
+    const int M = (int)mn.menu_lo.size();
+    const int64_t tsb = s.ts_bytes();
+    const std::vector<int32_t> &off = s.h_off;
+    auto ntype = [&](int32_t ty) { return (int64_t)off[ty + 1] - off[ty]; };
+    const bool filt = mn.xpred.p != nullptr && !mn.xpop.empty();
+    auto node_bytes = [&](int iv, int32_t X, int32_t B) -> int64_t {
+        if (!filt) return ntype(B) * tsb;
+        const int64_t y0 = off[B], q1 = off[B + 1];
+        const int64_t words = q1 > y0 ? ((q1 - 1) >> 6) - (y0 >> 6) + 1 : 0;
+        return words * 8 + (int64_t)mn.xpop[((int64_t)iv * s.K + X) * s.K + B] * tsb;
+    };
+    const int64_t nA = P.nf;
+    std::vector<int64_t> part(nA, 0);
+    parallel_for(nA, [&](int64_t x0, int64_t x1) {
+        for (int64_t a = x0; a < x1; ++a) {
+            const int64_t k = L.out_off[a + 1] - L.out_off[a];
+            if (k == 0) continue;
+            const int64_t alen = N == 2 ? ntype(P.ftypes[a]) : P.h_chain_off[a + 1] - P.h_chain_off[a];
+            int64_t b = k * (alen * (N == 2 ? 1 : 2) * tsb + 8);
+            if (N == 2) {
+                for (int64_t bi = 0; bi < nA; ++bi)
+                    if (bi != a)
+                        for (int iv = 0; iv < M; ++iv) b += node_bytes(iv, P.ftypes[a], P.ftypes[bi]);
+            } else {
+                const int32_t X = P.ftypes[(size_t)(P.N - 1) * P.nf + a];
+                for (int64_t e = 0; e < k; ++e) {
+                    const int32_t beta = L.byprefix[ext_position(L, a, e)];
+                    b += node_bytes(P.fiv[(size_t)(P.N - 2) * P.nf + beta], X, P.ftypes[(size_t)(P.N - 1) * P.nf + beta]);
+                }
+            }
+            part[a] = b;
+        }
+    });
+    int64_t total = 0;
+    for (int64_t a = 0; a < nA; ++a) total += part[a];
+    L.alg_bytes = total;
+    return total;
+}
+
 void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs) {
     const MineLevel &L = mn.levels[level - 1];
     const MineLevel &P = mn.levels[level - 2];
@@ -609,7 +776,7 @@ void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, in
         types[1] = P.ftypes[r / M];
         ivs[0] = (int)(r % M);
     } else {
-        const int32_t r = ext_position(L, P, alpha, le);
+        const int32_t r = ext_position(L, alpha, le);
         const int32_t beta = L.byprefix[r];
         types[N - 1] = P.ftypes[(size_t)(P.N - 1) * P.nf + beta];
         ivs[N - 2] = P.fiv[(size_t)(P.N - 2) * P.nf + beta];

@@ -19,7 +19,7 @@ constexpr int kMaxK = 4096;        // LDS histogram bound of the index build
 constexpr int kMaxQueue = 16;      // deepest merged-interval ring (LDS) per node
 constexpr int kTile = 2048;        // events per stream tile
 constexpr int kMlpHidden = 64;     // hidden units of the cost model
-constexpr int kFeatures = 23;      // cost-model features per candidate
+constexpr int kFeatures = 24;      // cost-model features per candidate
 constexpr int kWork = 5;           // work-log counters per candidate
 
 // Device error flags (int32 each), set by kernels with atomicOr / atomicAdd.
@@ -117,6 +117,7 @@ struct CandSet {
     DevBuf cycles;  // work log: int64 [items][2] wall-clock start/end of the last count
     int64_t n_items = 0;  // work items of the last count
     bool logged = false;  // the last count recorded a work log
+    std::vector<float> measured;  // EPI_SCHED_MEASURED: logged work per grouped slot, taken before the count
     // Compact layout (level-wise mining): one episode size, types uint16
     // [N][m], interval ids uint8 [N-1][m] into a menu of (lo, hi) pairs
     // (T[2*n_menu]); slots are in submission order (orig unused).
@@ -156,13 +157,14 @@ struct MineLevel {
     DevBuf dcounts;               // int32 [m] on the device (extension engine)
     std::vector<int64_t> freq;    // indices with count > threshold
     double gen_ms = 0, count_ms = 0, kernel_ms = 0;
-    int64_t alg_bytes = 0;        // bytes the counting method must read and write
+    int64_t alg_bytes = -1;       // bytes the counting method must read and write (-1: not yet computed)
     // Extension engine: candidate c of level N >= 2 is alpha + one node, where
     // alpha indexes the frequent episodes of level N-1 (alpha-major order).
     bool implicit = false;
     std::vector<int64_t> out_off;  // [nA + 1] first candidate of each alpha
     std::vector<int32_t> rlo, rhi; // level >= 3: range of alpha's extensions in byprefix
-    std::vector<int32_t> byprefix; // level >= 3: level N-1 frequent, ordered by first N-2 nodes
+    std::vector<int32_t> byprefix; // level >= 3: level N-1 frequent, ordered by first N-2 nodes, then last node
+    std::vector<int32_t> xlo, xhi; // level >= 3: the extensions repeating alpha's first type, [xlo, xhi)
     // frequent episodes of this level (structure of arrays) and their chain
     // lists: for every end event with an occurrence, (end time, latest start)
     int64_t nf = 0;
@@ -180,6 +182,12 @@ struct Mine {
     int64_t threshold = 0;
     std::vector<MineLevel> levels;
     DevBuf pred_bits, succ_bits;  // pair-existence bitmaps of the menu (may be empty)
+    // extension engine: bit (i, x, q) says the event at per-type index
+    // position q has an event of type x at a gap in menu interval i before
+    // it; rows of xwords 64-bit words (may be empty)
+    DevBuf xpred;
+    int64_t xwords = 0;
+    std::vector<int32_t> xpop;  // [i][x][B]: events of type B whose bit (i, x) is set
     double bits_ms = 0;
 };
 
@@ -190,6 +198,11 @@ struct Mlp {
     float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     DevBuf p, m, v, g, act;
     size_t cap = 0;
+    // standardisation of the cost model around the network:
+    // prediction = y_sd * net((x - x_mu) * x_isd) + y_mu (identity after init)
+    std::vector<float> x_mu, x_isd;
+    float y_mu = 0.f, y_sd = 1.f;
+    DevBuf norm;  // x_mu[F], x_isd[F] on the device
     bool ready() const { return p.p != nullptr; }
 };
 
@@ -221,7 +234,8 @@ hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, in
 // Batched count of several candidate sets (possibly on different streams) in
 // one graph launch of persistent kernels, one per episode size.  sched:
 // EPI_SCHED_RR (submission order), EPI_SCHED_LEARNED (the cost model's
-// predictions; round robin without a model) or EPI_SCHED_HEURISTIC (sum of
+// predictions; round robin without a model), EPI_SCHED_MEASURED (the work
+// the set's previous count logged) or EPI_SCHED_HEURISTIC (sum of
 // the types' event counts).
 struct BatchRef {
     const Stream *s;
@@ -239,6 +253,8 @@ int queue_class_of(int64_t bound);
 // select its frequent episodes and write their chain lists.
 hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st);
 hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st);
+// algorithmic bytes of an extension-engine level (computed on first use)
+int64_t extend_level_bytes(const Stream &s, Mine &mn, int level);
 // Reconstruct candidate c of an implicit level: types[8], interval ids[7].
 void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs);
 // Cost model (epi_mlp.hip).
@@ -248,11 +264,15 @@ hipError_t mlp_forward_device(Mlp &net, const float *dX, int64_t B, float *dy, h
 hipError_t mlp_grad_device(Mlp &net, const float *dX, const float *dt, int64_t B, float *dg, float *loss,
                            hipStream_t st);
 hipError_t mlp_adam_device(Mlp &net, const float *dg, hipStream_t st);
+hipError_t mlp_set_scaling(Mlp &net, const float *x_mu, const float *x_isd, float y_mu, float y_sd);
+// the cost model's prediction for B device samples; standardises dX in place
+hipError_t costmodel_predict_device(Mlp &net, float *dX, int64_t B, float *dy, hipStream_t st);
 // Cost-model features of every candidate of a set, in grouped slot order
 // (float [G][kFeatures]) (epi_sched.hip).
 hipError_t candidate_features(const Stream &s, const CandSet &c, float *dX, hipStream_t st);
 // Pair-existence bitmaps of an interval menu over a stream (epi_pairs.hip).
 hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st);
+hipError_t build_index_pred_bits(const Stream &s, Mine &mn, hipStream_t st);
 // Candidate generation of level-wise discovery (epi_mine.hip).
 void gen_level1(int32_t K, MineLevel &L);
 void gen_level2(const MineLevel &F1, int n_menu, MineLevel &L);

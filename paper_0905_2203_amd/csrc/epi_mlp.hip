@@ -14,7 +14,8 @@
 // k_mlp_reduce: one thread per parameter; sums its gradient over the batch in
 //   a fixed order (deterministic), e.g. dL/dW2[a][j] = sum_i h1[i][a] dz2[i][j].
 // k_mlp_adam:   one thread per parameter; Adam step k.
-// k_features:   per candidate, the 23 features the model reads (see below).
+// k_standardize, k_affine: the cost model's input and output scaling around
+//   the network, (x - mu) * isd per feature and y * sd + mu.
 #include <cmath>
 #include <vector>
 
@@ -125,9 +126,44 @@ __global__ void k_mlp_adam(float *__restrict__ p, const float *__restrict__ g, f
     p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
 }
 
+__global__ void k_standardize(float *__restrict__ X, int64_t n, int F, const float *__restrict__ norm) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int f = (int)(q % F);
+    X[q] = (X[q] - norm[f]) * norm[F + f];
+}
+
+__global__ void k_affine(float *__restrict__ y, int64_t n, float sd, float mu) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = fmaf(y[q], sd, mu);
+}
+
 }  // namespace
 
 int64_t mlp_n_params(int F) { return n_params_of(F); }
+
+hipError_t mlp_set_scaling(Mlp &net, const float *x_mu, const float *x_isd, float y_mu, float y_sd) {
+    net.x_mu.assign(x_mu, x_mu + net.F);
+    net.x_isd.assign(x_isd, x_isd + net.F);
+    net.y_mu = y_mu;
+    net.y_sd = y_sd;
+    std::vector<float> h(net.x_mu);
+    h.insert(h.end(), net.x_isd.begin(), net.x_isd.end());
+    hipError_t e;
+    if (!net.norm.p && (e = net.norm.alloc(sizeof(float) * 2 * net.F)) != hipSuccess) return e;
+    return hipMemcpy(net.norm.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t costmodel_predict_device(Mlp &net, float *dX, int64_t B, float *dy, hipStream_t st) {
+    if (B == 0) return hipSuccess;
+    const int64_t n = B * net.F;
+    k_standardize<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(dX, n, net.F, net.norm.as<float>());
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = mlp_forward_device(net, dX, B, dy, st)) != hipSuccess) return e;
+    k_affine<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(dy, B, net.y_sd, net.y_mu);
+    return hipGetLastError();
+}
 
 hipError_t mlp_forward_device(Mlp &net, const float *dX, int64_t B, float *dy, hipStream_t st) {
     if (B == 0) return hipSuccess;
@@ -209,7 +245,10 @@ hipError_t mlp_init(Mlp &net, int F, uint64_t seed) {
     if ((e = net.g.alloc(sizeof(float) * np)) != hipSuccess) return e;
     if ((e = hipMemcpy(net.p.p, h.data(), sizeof(float) * np, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemset(net.m.p, 0, sizeof(float) * np)) != hipSuccess) return e;
-    return hipMemset(net.v.p, 0, sizeof(float) * np);
+    if ((e = hipMemset(net.v.p, 0, sizeof(float) * np)) != hipSuccess) return e;
+    net.norm.reset();
+    const std::vector<float> zero(F, 0.f), one(F, 1.f);
+    return mlp_set_scaling(net, zero.data(), one.data(), 0.f, 1.f);
 }
 
 }  // namespace epi

@@ -1,11 +1,14 @@
 // Scheduler inputs: the cost-model features of each candidate episode.
 //
-// Features (kFeatures = 23), from the stream's per-type event counts and the
+// Features (kFeatures = 24), from the stream's per-type event counts and the
 // episode's constraints, in stream time units:
 //   [0..7]   log1p(number of events of node j's type), 0 for absent nodes
 //   [8..14]  log1p(hi_j - lo_j) (window width of constraint j), 0 if absent
 //   [15..21] log1p(hi_j), 0 if absent
 //   [22]     N
+//   [23]     log1p(sum over the nodes of their types' event counts): the
+//            events a lane visits, which the per-node features give only
+//            through a sum of exponentials the network would have to learn
 // The number of events a lane visits grows with the first group, and the
 // number of partial occurrences it tracks with the window widths and
 // offsets (the runtime of Sec. V-C grows with episode frequency and length).
@@ -23,11 +26,14 @@ __global__ void k_features(const int32_t *__restrict__ type_off, const int32_t *
     if (s >= m) return;
     const int N = Nof[s];
     float *x = X + s * kFeatures;
+    int64_t visits = 0;
     for (int k = 0; k < 8; ++k) {
         float v = 0.f;
         if (k < N) {
             const int32_t ty = ctypes[(int64_t)k * m + s];
-            v = log1pf((float)(type_off[ty + 1] - type_off[ty]));
+            const int32_t n_ty = type_off[ty + 1] - type_off[ty];
+            visits += n_ty;
+            v = log1pf((float)n_ty);
         }
         x[k] = v;
     }
@@ -42,6 +48,7 @@ __global__ void k_features(const int32_t *__restrict__ type_off, const int32_t *
         x[15 + k] = h;
     }
     x[22] = (float)N;
+    x[23] = log1pf((float)visits);
 }
 
 }  // namespace

@@ -766,6 +766,10 @@ hipError_t predicted_costs(const Stream &s, const CandSet &c, int sched, Mlp &ml
     cost.clear();
     if (sched == EPI_SCHED_RR || c.m == 0) return hipSuccess;
     if (sched == EPI_SCHED_LEARNED && !(mlp.ready() && mlp.F == kFeatures)) return hipSuccess;  // fallback: RR
+    if (sched == EPI_SCHED_MEASURED) {
+        if ((int64_t)c.measured.size() == c.m) cost = c.measured;
+        return hipSuccess;
+    }
     hipError_t e;
     DevBuf dX;
     if ((e = dX.alloc(sizeof(float) * c.m * kFeatures)) != hipSuccess) return e;
@@ -774,7 +778,7 @@ hipError_t predicted_costs(const Stream &s, const CandSet &c, int sched, Mlp &ml
     if (sched == EPI_SCHED_LEARNED) {
         DevBuf dy;
         if ((e = dy.alloc(sizeof(float) * c.m)) != hipSuccess) return e;
-        if ((e = mlp_forward_device(mlp, dX.as<float>(), c.m, dy.as<float>(), st)) != hipSuccess) return e;
+        if ((e = costmodel_predict_device(mlp, dX.as<float>(), c.m, dy.as<float>(), st)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(cost.data(), dy.p, sizeof(float) * c.m, hipMemcpyDeviceToHost, st)) != hipSuccess)
             return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;

@@ -36,6 +36,7 @@ EPI_MODE_BATCHED = 1
 EPI_SCHED_RR = 0
 EPI_SCHED_LEARNED = 1
 EPI_SCHED_HEURISTIC = 2
+EPI_SCHED_MEASURED = 3
 
 EXPORTS = [
     "epi_create", "epi_destroy", "epi_last_error", "epi_status_string",
@@ -47,7 +48,8 @@ EXPORTS = [
     "epi_mine_level_bytes", "epi_mine_release",
     "epi_mlp_init", "epi_mlp_params", "epi_mlp_get_params", "epi_mlp_set_params", "epi_mlp_forward",
     "epi_mlp_grad", "epi_mlp_adam_step", "epi_mlp_train", "epi_costmodel_features",
-    "epi_read_worklog", "epi_read_item_cycles", "epi_costmodel_train", "epi_autotune",
+    "epi_read_worklog", "epi_read_item_cycles", "epi_costmodel_train", "epi_costmodel_scaling",
+    "epi_costmodel_predict", "epi_costmodel_save", "epi_costmodel_load", "epi_autotune",
 ]
 EPI_OPT_SEGMENTS = 1
 EPI_OPT_LANES = 2
@@ -121,6 +123,10 @@ def lib():
             "epi_read_worklog": ([P, I32, P, I64], I32),
             "epi_read_item_cycles": ([P, I32, P, I64, ctypes.POINTER(I64)], I32),
             "epi_costmodel_train": ([P, P, I32, I32, ctypes.c_uint64, P], I32),
+            "epi_costmodel_scaling": ([P, P, P, P], I32),
+            "epi_costmodel_predict": ([P, I32, P, I64], I32),
+            "epi_costmodel_save": ([P, ctypes.c_char_p], I32),
+            "epi_costmodel_load": ([P, ctypes.c_char_p], I32),
             "epi_autotune": ([P, P, I32, INT, ctypes.c_char_p, P], I32),
         }
         for name, (args, res) in sig.items():
@@ -374,7 +380,7 @@ class Context:
         return losses
 
     def epi_costmodel_features(self, set_id: int, m: int) -> np.ndarray:
-        X = np.zeros((int(m), 23), np.float32)
+        X = np.zeros((int(m), 24), np.float32)
         self._check(lib().epi_costmodel_features(self.h, int(set_id), _ptr(X), int(m)))
         return X
 
@@ -397,6 +403,26 @@ class Context:
         losses = np.zeros(int(epochs), np.float32)
         self._check(lib().epi_costmodel_train(self.h, _ptr(ids), ids.size, int(epochs), int(seed), _ptr(losses)))
         return losses
+
+    def epi_costmodel_scaling(self):
+        """Returns (x_mu[F], x_isd[F], y_mu, y_sd)."""
+        F, _ = self.epi_mlp_params()
+        mu = np.zeros(F, np.float32)
+        isd = np.zeros(F, np.float32)
+        y = np.zeros(2, np.float32)
+        self._check(lib().epi_costmodel_scaling(self.h, _ptr(mu), _ptr(isd), _ptr(y)))
+        return mu, isd, float(y[0]), float(y[1])
+
+    def epi_costmodel_predict(self, set_id: int, m: int) -> np.ndarray:
+        y = np.zeros(int(m), np.float32)
+        self._check(lib().epi_costmodel_predict(self.h, int(set_id), _ptr(y), int(m)))
+        return y
+
+    def epi_costmodel_save(self, path):
+        self._check(lib().epi_costmodel_save(self.h, str(path).encode()))
+
+    def epi_costmodel_load(self, path):
+        self._check(lib().epi_costmodel_load(self.h, str(path).encode()))
 
     def epi_autotune(self, set_ids, sched: int = EPI_SCHED_RR, cache_path=None):
         """Returns (lanes, work items per compute unit)."""

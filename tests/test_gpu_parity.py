@@ -235,8 +235,9 @@ def _episode_key(c, i):
 _MINING_REF = {}
 
 
-@pytest.mark.parametrize("opts", [{}, {"engine": 0}, {"engine": 0, "filter": 0}, {"engine": 0, "segments": 5}],
-                         ids=["extend", "fsm", "fsm-nofilter", "fsm-segments5"])
+@pytest.mark.parametrize("opts", [{}, {"filter": 0}, {"engine": 0}, {"engine": 0, "filter": 0},
+                                  {"engine": 0, "segments": 5}],
+                         ids=["extend", "extend-nofilter", "fsm", "fsm-nofilter", "fsm-segments5"])
 def test_levelwise_mining_matches_oracle(ctx, opts):
     """Every level's candidates and counts, and the frequent sets, equal the
     oracle's level-wise discovery (reduced mining workload); with and without
