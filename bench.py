@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PROFILE = "k_ext_count_mining.md"
-KERNEL_SOURCES = ("epi_extend.hip", "epi_fsm.h")
+KERNEL_SOURCES = ("epi_extend.hip",)
 THRESHOLD = 100
 MAX_SIZE = 6
 
@@ -257,7 +257,7 @@ def main():
     dom = int(np.argmax(kern_ms)) + 1
     alg = ctx.epi_mine_level_bytes(mid, dom)
     achieved_gbs = alg / (kern_ms[dom - 1] / 1e3) / 1e9
-    kname = "k_ext_count1<int>" if dom >= 3 else ("k_ext_count0<int>" if dom == 2 else "k_level1<int>")
+    kname = f"k_ext_walk<int, 4, {'true' if dom == 2 else 'false'}, false>" if dom >= 2 else "k_level1<int>"
     traffic = profiled_traffic(kname)
 
     # parity spot check (outside the timed region): sampled counts vs the oracle

@@ -178,15 +178,18 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *                         engine uses the widest one whose state fits LDS
  *   EPI_OPT_TARGET_LANES  automatic segmentation aims at this many
  *                         (episode, segment) work lanes (default 262144)
- *   EPI_OPT_PAIR_FILTER   1 (default) / 0: in level-wise discovery, precompute
- *                         for each event, event type and menu interval
- *                         whether a constrained neighbour exists before (and,
- *                         for the state-machine engine, after) it (the
- *                         tracking step of Sec. IV-C, for all pairs at once)
- *                         and skip events with none
+ *   EPI_OPT_PAIR_FILTER   1 (default) / 0: in level-wise discovery with the
+ *                         state-machine engine, precompute for each event,
+ *                         event type and menu interval whether a constrained
+ *                         neighbour exists before and after it (the tracking
+ *                         step of Sec. IV-C, for all pairs at once) and skip
+ *                         events with none
  *   EPI_OPT_MINE_ENGINE   level-wise discovery engine: 1 (default) extends the
  *                         previous level's chain lists (decomposition of
- *                         Sec. IV-A, one merge per candidate); 0 counts every
+ *                         Sec. IV-A: one walk over the stream windows that
+ *                         follow each frequent episode's end events serves
+ *                         all of its extensions; menus of up to 8 intervals,
+ *                         longer menus use engine 0); 0 counts every
  *                         candidate with the state machines of epi_count
  *   EPI_OPT_WORKLOG       1 / 0 (default): counts also record, per episode,
  *                         kWork = 5 int32 counters (events visited, partial

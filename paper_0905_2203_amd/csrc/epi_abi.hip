@@ -620,16 +620,14 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     mn->menu_lo.assign(menu_lo, menu_lo + n_menu);
     mn->menu_hi.assign(menu_hi, menu_hi + n_menu);
     mn->threshold = threshold;
-    mn->engine = ctx->c.opt.mine_engine;
+    // the extension engine takes menus of up to kExtMaxMenu intervals; longer
+    // menus go to the state-machine engine
+    mn->engine = n_menu <= kExtMaxMenu ? ctx->c.opt.mine_engine : 0;
     if (mn->engine == 1) {
         // extension engine: each level extends the previous level's chain lists
-        const double xbits_bytes = 8.0 * n_menu * (double)s->K * (double)((s->n + 63) / 64);
-        if (ctx->c.opt.pair_filter && max_size > 1 && s->n > 0 &&
-            xbits_bytes <= (double)ctx->c.opt.pair_filter_max_bytes) {
-            auto tb = std::chrono::steady_clock::now();
-            HIPTRY(ctx, build_index_pred_bits(*s, *mn, st), "building predecessor bitmaps");
-            mn->bits_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
-        }
+        auto tb = std::chrono::steady_clock::now();
+        HIPTRY(ctx, extend_prepare(*s, *mn, st), "preparing the window walk");
+        mn->bits_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
         HIPTRY(ctx, extend_level1(*s, *mn, st), "counting level 1");
         mn->levels.back().gen_ms = 0;
         for (int N = 2; N <= max_size; ++N) {

@@ -10,29 +10,41 @@
 //     s(y) = max over such x of s(x).
 // Over alpha's end events s is non-decreasing in time (the latest occurrence
 // end before a window edge carries the latest start), so the maximum is taken
-// at the latest x with t_x < t_y - lo, provided t_x >= t_y - hi.  So with
-// alpha's chain list -- its end events in time order with their latest
-// starts -- one merge of two sorted lists gives s(y) for every y, and the
-// greedy of Alg. 1 over the y in time order (keep y when s(y) > the last kept
-// end, starting from minus infinity) gives the count.  This is Parallel Local
-// Tracking (Sec. IV-C) advanced by one node per level, with book-keeping of
-// start times and the end-ordered list for free.
+// at the latest x with t_x < t_y - lo, provided t_x >= t_y - hi.  The greedy
+// of Alg. 1 over the y in time order (keep y when s(y) > the last kept end,
+// starting from minus infinity) gives the count.
 //
-// Level 1 counts distinct timestamps per type.  Level 2 candidates extend a
-// frequent type (its chain list is its own events, s = t).  The chain lists
-// of a level's frequent episodes are written by a second pass over those
-// episodes only, at offsets from an exclusive scan of their end-event counts
-// (the count / scan / write compaction of Sec. IV-E).
+// Window walk.  Every candidate of alpha needs only the stream events that
+// follow one of alpha's end events by at most H (the longest interval end of
+// the menu): the union U(alpha) of the windows (t_x, t_x + H].  One wave per
+// alpha walks U(alpha) once, 64 stream positions at a time, for all of
+// alpha's extensions together:
+//   * the runs of U are cut from alpha's chain list 64 entries at a time
+//     (entry x covers stream positions (p_x, wend(p_x)); overlaps are
+//     removed with a prefix maximum) and packed into full batches;
+//   * each lane of a batch holds one stream event y and finds, for every menu
+//     interval m, s_m(y) from the few end events that precede the batch by at
+//     most H (uniform loop, scalar reads);
+//   * each extension type B of alpha owns a lane that keeps one greedy state
+//     per menu interval; a batch's events reach the lanes of their types
+//     through one LDS mask per lane (an atomic OR per event), and each lane
+//     runs its greedy over its events in time order, reading them with
+//     cross-lane permutes.
+// This is the tracking step of Parallel Local Tracking (Sec. IV-C) done for
+// all extensions of an episode at once: the work per alpha is |U(alpha)|
+// stream events whatever the number of its extensions.
 //
-// Counting: one wave per alpha; its lanes take alpha's extensions (the
-// Apriori join's matches, minus the one repeating alpha's first type),
-// 64 at a time; every lane of the wave reads the same chain list.
+// Level 1 counts distinct timestamps per type.  Level 2 extends a frequent
+// type (its chain list is its own events, s = t).  The chain lists of a
+// level's frequent episodes are written by a second walk over the alphas that
+// have frequent extensions, at offsets from an exclusive scan of their
+// end-event counts (the count / scan / write compaction of Sec. IV-E).
 #include <algorithm>
 #include <chrono>
 #include <numeric>
 #include <thread>
 
-#include "epi_fsm.h"
+#include "epi_internal.h"
 
 namespace epi {
 
@@ -41,222 +53,333 @@ namespace {
 using Clock = std::chrono::steady_clock;
 double ms_since(Clock::time_point t0) { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
 
+constexpr int kWave = 64;
+constexpr uint8_t kNoSlot = 0xFF;
+
 template <typename T>
-struct ExtArgs {
-    const T *ts;             // per-type index (time order per type)
-    const int32_t *type_off; // [K+1]
-    int64_t nA;              // number of alphas
-    // level 2 (MODE 0): alphas are frequent types
-    const uint16_t *f1;      // [nf1] frequent types
+struct WalkArgs {
+    const uint16_t *ty16;     // [n] event types, stream order
+    const T *times;           // [n]
+    const int32_t *wend;      // [n] first position whose time exceeds times[p] + H
+    T H;                      // longest menu interval end
+    // the alphas' chain lists
+    const T *ct, *cs;         // level >= 3: end times, latest starts
+    const int32_t *cp;        // level >= 3: stream positions
+    const int64_t *coff;      // level >= 3: [nA + 1]
+    const T *ts_by_type;      // level 2: a frequent type's chain is its own events
+    const int32_t *pos_by_type;
+    const int32_t *type_off;
+    const uint16_t *f1;       // level 2: the frequent types
     int32_t nf1;
-    // level >= 3 (MODE 1): alphas are frequent episodes of the previous level
-    const Pair<T> *chains;   // chain lists of the previous level's frequent episodes
-    const int64_t *coff;     // [nfprev + 1]
-    const uint16_t *ftype0;  // [nfprev] first type
-    const uint16_t *flast;   // [nfprev] last type
-    const uint8_t *fliv;     // [nfprev] last interval id
-    const int32_t *rlo, *rhi, *byprefix;
-    const int64_t *out_off;  // [nA + 1]
-    const int32_t *aorder;   // order in which the workgroups take the alphas (null: index order)
-    const T *menu;           // (lo, hi) pairs
-    int32_t M;
-    const uint64_t *xbits;   // predecessor bits (interval, type, index position) or null
-    int64_t xwords;
-    int32_t K;
-    int32_t *counts;         // [m]
-    int32_t *nvalid;         // [m]
-    // write pass: explicit list of candidates
-    int64_t nw;
-    const int32_t *w_alpha;
+    // one job per workgroup
+    const int32_t *job_alpha; // alpha of each job (null: the job index)
+    const int32_t *order;     // order in which the workgroups take the jobs (null: index order)
+    // counting pass: each alpha's extensions and their outputs
+    const int64_t *out_off;   // [nA + 1]
+    const int32_t *rlo, *rhi, *xlo, *xhi, *byprefix;
+    const uint16_t *flast;    // last type of each frequent episode of the previous level
+    const uint8_t *fliv;      // its last interval id
+    int32_t *counts, *nvalid;
+    unsigned long long *walked;  // stream positions walked, summed over the jobs
+    // write pass: each job's range of the frequent list
+    const int64_t *job_f;     // [njobs + 1]
     const uint16_t *w_type;
     const uint8_t *w_iv;
-    const int64_t *w_off;
-    const int32_t *w_order;  // order in which the threads take the write list (null: list order)
-    Pair<T> *w_out;
+    const int64_t *w_off;     // first chain-list slot of each frequent episode
+    T *wct, *wcs;
+    int32_t *wcp;
+    T menu_lo[kExtMaxMenu], menu_hi[kExtMaxMenu];
+    int32_t M;
+    int32_t K;
 };
 
-// One candidate: merge alpha's chain list with the events of type B; returns
-// the count, the number of end events, and optionally writes the new chain.
-//
-// The lanes of a wave read 64 different type lists, far more lines than the
-// L1 keeps between a lane's visits; so each lane reads its list in whole
-// 64-byte lines (16-byte loads from a line-aligned address) and consumes
-// them from registers; the elements before the first line boundary and after
-// the last whole line are read one by one.  Alpha's chain list is shared by
-// the wave; its next two entries are held ahead.
-template <typename T, int MODE, bool WRITE, bool FILT>
-__device__ __forceinline__ int32_t ext_core(const ExtArgs<T> &a, int64_t alpha, int32_t X, int32_t B, int iv,
-                                            int32_t *nval, Pair<T> *out) {
+// Read-only data seen through the constant address space: uniform reads of
+// it become scalar loads (scalar cache) instead of vector loads.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int l) {
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_readlane((int)v, l);
+    } else {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int src) {
+    if constexpr (sizeof(T) == 4) {
+        return (T)__shfl((int)v, src, kWave);
+    } else {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)u, src, kWave);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(u >> 32), src, kWave);
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Extension r of a job: its new type B, interval id and key (counting: the
+// candidate's index; writing: the first slot of its chain list).  Within a
+// job the extensions are ordered by B.
+template <typename T, bool L2, bool WRITE>
+__device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int64_t alpha, int64_t r, int32_t &B,
+                                          int &iv, int64_t &key) {
+    if (WRITE) {
+        const int64_t f = a.job_f[job] + r;
+        B = a.w_type[f];
+        iv = a.w_iv[f];
+        key = a.w_off[f];
+    } else if (L2) {
+        const int64_t bi0 = r / a.M;
+        iv = (int)(r - bi0 * a.M);
+        const int64_t bi = bi0 >= alpha ? bi0 + 1 : bi0;
+        B = a.f1[bi];
+        key = a.out_off[alpha] + r;
+    } else {
+        int64_t rr = a.rlo[alpha] + r;
+        if (rr >= a.xlo[alpha]) rr += a.xhi[alpha] - a.xlo[alpha];
+        const int32_t beta = a.byprefix[rr];
+        B = a.flast[beta];
+        iv = a.fliv[beta];
+        key = a.out_off[alpha] + r;
+    }
+}
+
+template <typename T, bool L2, bool WRITE>
+__device__ __forceinline__ int64_t n_extensions(const WalkArgs<T> &a, int64_t job, int64_t alpha) {
+    if (WRITE) return a.job_f[job + 1] - a.job_f[job];
+    if (L2) return (int64_t)(a.nf1 - 1) * a.M;
+    return (int64_t)(a.rhi[alpha] - a.rlo[alpha]) - (a.xhi[alpha] - a.xlo[alpha]);
+}
+
+// One job: alpha, all of its extensions (or, writing, its frequent ones).
+// MP >= M greedy states per lane, one per menu interval.
+template <typename T, int MP, bool L2, bool WRITE>
+__global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kMax = TsLimits<T>::hi();
-    constexpr int kLineBytes = 64;
-    constexpr int kLine = kLineBytes / (int)sizeof(T);
-    constexpr int kVec = kLineBytes / 16;
-    const T lo = a.menu[2 * iv], hi = a.menu[2 * iv + 1];
+    extern __shared__ uint8_t slot_of[];            // [K] lane owning each type this round
+    __shared__ unsigned long long want[kWave];      // batch lanes holding each owner's events
+    __shared__ int32_t gtype[kWave];
+    __shared__ int64_t gkey[MP][kWave];
+    const int lane = threadIdx.x;
+    const int64_t job = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t alpha = a.job_alpha ? (int64_t)a.job_alpha[job] : job;
+    const int M = a.M;
     // alpha's chain list
-    const T *at = nullptr;
-    const Pair<T> *ap = nullptr;
-    int32_t alen;
-    if (MODE == 0) {
+    const_ptr<T> xt, xs;
+    const int32_t *xp;
+    int32_t clen;
+    if (L2) {
         const int32_t ty = a.f1[alpha];
-        at = a.ts + a.type_off[ty];
-        alen = a.type_off[ty + 1] - a.type_off[ty];
+        const int32_t o = a.type_off[ty];
+        clen = a.type_off[ty + 1] - o;
+        xt = (const_ptr<T>)(a.ts_by_type + o);
+        xs = xt;
+        xp = a.pos_by_type + o;
     } else {
-        ap = a.chains + a.coff[alpha];
-        alen = (int32_t)(a.coff[alpha + 1] - a.coff[alpha]);
+        const int64_t o = a.coff[alpha];
+        clen = (int32_t)(a.coff[alpha + 1] - o);
+        xt = (const_ptr<T>)(a.ct + o);
+        xs = (const_ptr<T>)(a.cs + o);
+        xp = a.cp + o;
     }
-    auto chain_at = [&](int32_t q) {
-        Pair<T> v;
-        if (q < alen) {
-            if (MODE == 0) {
-                v.s = at[q];
-                v.e = v.s;
-            } else {
-                v = ap[q];
-            }
-        } else {
-            v.s = kMax;
-            v.e = kMax;
-        }
-        return v;
-    };
-    const int32_t y0 = a.type_off[B];
-    const int32_t ylen = a.type_off[B + 1] - y0;
-    const T *y = a.ts + y0;
-    int32_t p = 0, cnt = 0, nv = 0;
-    T prev_e = kMin;
-    T xt = kMin, xs = kMin;  // latest entry with time < t_y - lo (when p > 0)
-    Pair<T> n1 = chain_at(0), n2 = chain_at(1);
-    auto step = [&](const T ty) {
-        const T lim = (T)(ty - lo);
-        while (n1.s < lim) {
-            xt = n1.s;
-            xs = n1.e;
-            ++p;
-            n1 = n2;
-            n2 = chain_at(p + 1);
-        }
-        if (p > 0 && xt >= (T)(ty - hi)) {
-            if (WRITE) {
-                Pair<T> w;
-                w.s = ty;
-                w.e = xs;
-                out[nv] = w;
-            }
-            ++nv;
-            if (xs > prev_e) {
-                ++cnt;
-                prev_e = ty;
-            }
-        }
-    };
-    if (FILT) {
-        // only the events of B with an event of alpha's last type X at a gap
-        // in the interval before them can end an occurrence: visit those
-        if (ylen > 0) {
-            const uint64_t *pb = a.xbits + ((int64_t)iv * a.K + X) * a.xwords;
-            const int32_t q1 = y0 + ylen;
-            const int32_t w0 = y0 >> 6, w1 = (q1 - 1) >> 6;
-            for (int32_t w = w0; w <= w1; ++w) {
-                uint64_t bits = pb[w];
-                if (w == w0) bits &= ~0ull << (y0 & 63);
-                if (w == w1 && (q1 & 63)) bits &= (1ull << (q1 & 63)) - 1ull;
-                const T *yw = a.ts + ((int64_t)w << 6);
-                while (bits) {
-                    // up to four loads in flight
-                    T v[4];
-                    int k = 0;
+    const int64_t R = n_extensions<T, L2, WRITE>(a, job, alpha);
+    for (int k = lane; k < a.K; k += kWave) slot_of[k] = kNoSlot;
+    want[lane] = 0;
+    unsigned long long walked = 0;
+    // rounds of up to 64 distinct extension types (one lane each)
+    for (int64_t r_start = 0; r_start < R;) {
+        gtype[lane] = -1;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (bits) {
-                            v[u] = yw[__builtin_ctzll(bits)];
-                            bits &= bits - 1ull;
-                            k = u + 1;
+        for (int m = 0; m < MP; ++m) gkey[m][lane] = -1;
+        __syncthreads();
+        int32_t ng = 0, prevB = -1;
+        int64_t r_next = R;
+        for (int64_t rb = r_start; rb < R; rb += kWave) {  // uniform
+            const int64_t r = rb + lane;
+            const bool in = r < R;
+            int32_t B = -1;
+            int iv = 0;
+            int64_t key = -1;
+            if (in) extension<T, L2, WRITE>(a, job, alpha, r, B, iv, key);
+            int32_t pB = __shfl_up(B, 1, kWave);
+            if (lane == 0) pB = prevB;
+            const uint64_t st = __ballot(in && B != pB);
+            const int32_t g = ng + __popcll(st & (~0ull >> (63 - lane))) - 1;
+            if (in && g < kWave) {
+                gtype[g] = B;
+                gkey[iv][g] = key;
+            }
+            const uint64_t over = __ballot(in && g >= kWave);
+            if (over) {
+                r_next = rb + __builtin_ctzll(over);
+                ng = kWave;
+                break;
+            }
+            ng += __popcll(st);
+            prevB = __shfl(B, 63 - __builtin_clzll(__ballot(in)), kWave);
+        }
+        __syncthreads();
+        const bool has = lane < ng;
+        const int32_t myB = has ? gtype[lane] : -1;
+        int64_t key[MP];
+        T pe[MP];
+        int32_t cnt[MP], nv[MP];
+#pragma unroll
+        for (int m = 0; m < MP; ++m) {
+            key[m] = has ? gkey[m][lane] : -1;
+            pe[m] = kMin;
+            cnt[m] = 0;
+            nv[m] = 0;
+        }
+        if (has) slot_of[myB] = (uint8_t)lane;
+        __syncthreads();
+        // ---- the walk over U(alpha)
+        int32_t carry = 0;  // coverage end of the entries already taken
+        int32_t ilo = 0;    // first entry that can still be a predecessor
+        for (int32_t i0 = 0; i0 < clen; i0 += kWave) {  // uniform
+            const int32_t i = i0 + lane;
+            const bool ci = i < clen;
+            const int32_t p = ci ? xp[i] : 0;
+            const int32_t e = ci ? a.wend[p] : 0;
+            int32_t prev_e = __shfl_up(e, 1, kWave);
+            if (lane == 0) prev_e = carry;
+            const int32_t beg = max(p + 1, prev_e);
+            const int32_t len = ci ? max(0, e - beg) : 0;
+            int32_t S = len;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const int32_t y = __shfl_up(S, d, kWave);
+                if (lane >= d) S += y;
+            }
+            const int32_t X = S - len;
+            const int32_t total = __builtin_amdgcn_readlane(S, 63);
+            carry = max(carry, __builtin_amdgcn_readlane(e, 63 - __builtin_clzll(__ballot(ci))));
+            walked += (unsigned long long)total;
+            for (int32_t b = 0; b < total; b += kWave) {  // uniform
+                const int32_t o = b + lane;
+                const bool ev = o < total;
+                uint64_t runs = __ballot(len > 0 && X < b + kWave && S > b);
+                int32_t P = 0;
+                while (runs) {
+                    const int j = __builtin_ctzll(runs);
+                    runs &= runs - 1;
+                    const int32_t Xj = __builtin_amdgcn_readlane(X, j);
+                    const int32_t bj = __builtin_amdgcn_readlane(beg, j);
+                    if (o >= Xj) P = bj + (o - Xj);
+                }
+                const int32_t ty = ev ? (int32_t)a.ty16[P] : 0;
+                const T t = ev ? a.times[P] : kMax;
+                const int nb = min(total - b, kWave);
+                const T tf = read_lane(t, 0), tl = read_lane(t, nb - 1);
+                while (ilo < clen && xt[ilo] < (T)(tf - a.H)) ++ilo;
+                T cx[MP], cxs[MP], lim[MP];
+#pragma unroll
+                for (int m = 0; m < MP; ++m) {
+                    cx[m] = kMin;
+                    cxs[m] = kMin;
+                    lim[m] = m < M ? (T)(t - a.menu_lo[m]) : kMin;
+                }
+                for (int32_t q = ilo; q < clen; ++q) {  // uniform
+                    const T qt = xt[q];
+                    if (qt >= tl) break;
+                    const T qs = xs[q];
+#pragma unroll
+                    for (int m = 0; m < MP; ++m) {
+                        if (qt < lim[m]) {
+                            cx[m] = qt;
+                            cxs[m] = qs;
                         }
                     }
+                }
+                T sv[MP];
+                bool any = false;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (u < k) step(v[u]);
+                for (int m = 0; m < MP; ++m) {
+                    sv[m] = (m < M && ev && cx[m] >= (T)(t - a.menu_hi[m])) ? cxs[m] : kMin;
+                    any |= sv[m] != kMin;
+                }
+                if (any) {
+                    const uint8_t sl = slot_of[ty];
+                    if (sl != kNoSlot) atomicOr(&want[sl], 1ull << lane);
+                }
+                __syncthreads();
+                uint64_t wm = want[lane];
+                want[lane] = 0;
+                while (__ballot(wm != 0)) {  // uniform
+                    const int k = wm ? __builtin_ctzll(wm) : lane;
+                    const T yt = lane_value(t, k);
+                    const int32_t yp = __shfl(P, k, kWave);
+                    T ys[MP];
+#pragma unroll
+                    for (int m = 0; m < MP; ++m) ys[m] = m < M ? lane_value(sv[m], k) : kMin;
+                    if (wm) {
+#pragma unroll
+                        for (int m = 0; m < MP; ++m) {
+                            if (key[m] >= 0 && ys[m] != kMin) {
+                                if (WRITE) {
+                                    const int64_t w = key[m] + nv[m];
+                                    a.wct[w] = yt;
+                                    a.wcs[w] = ys[m];
+                                    a.wcp[w] = yp;
+                                }
+                                ++nv[m];
+                                if (ys[m] > pe[m]) {
+                                    ++cnt[m];
+                                    pe[m] = yt;
+                                }
+                            }
+                        }
+                        wm &= wm - 1;
+                    }
                 }
             }
         }
-        *nval = nv;
-        return cnt;
-    }
-    // elements up to the first line boundary
-    const int32_t lead = (int32_t)((uint32_t)y0 & (uint32_t)(kLine - 1));
-    const int32_t head = lead == 0 ? 0 : min(ylen, kLine - lead);
-    int32_t i = 0;
-    for (; i < head; ++i) step(y[i]);
-    // whole lines
-    for (; i + kLine <= ylen; i += kLine) {
-        uint4 raw[kVec];
-        const uint4 *src = reinterpret_cast<const uint4 *>(y + i);
+        if (!WRITE) {
 #pragma unroll
-        for (int k = 0; k < kVec; ++k) raw[k] = src[k];
-        const T *v = reinterpret_cast<const T *>(raw);
-#pragma unroll
-        for (int u = 0; u < kLine; ++u) step(v[u]);
-    }
-    // the rest
-    for (; i < ylen; ++i) step(y[i]);
-    *nval = nv;
-    return cnt;
-}
-
-template <typename T, bool FILT>
-__global__ __launch_bounds__(64) void k_ext_count0(ExtArgs<T> a) {
-    const int64_t alpha = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int32_t R = a.nf1 * a.M;
-    const int64_t o0 = a.out_off[alpha];
-    for (int32_t rb = 0; rb < R; rb += 64) {
-        const int32_t r = rb + lane;
-        if (r >= R) break;
-        const int32_t bi = r / a.M, iv = r % a.M;
-        if (bi == alpha) continue;
-        const int64_t c = o0 + (bi < alpha ? r : r - a.M);
-        int32_t nv;
-        a.counts[c] = ext_core<T, 0, false, FILT>(a, alpha, a.f1[alpha], a.f1[bi], iv, &nv, nullptr);
-        a.nvalid[c] = nv;
-    }
-}
-
-template <typename T, bool FILT>
-__global__ __launch_bounds__(64) void k_ext_count1(ExtArgs<T> a) {
-    const int64_t alpha = a.aorder ? a.aorder[blockIdx.x] : (int64_t)blockIdx.x;
-    const int lane = threadIdx.x;
-    const int32_t r0 = a.rlo[alpha], r1 = a.rhi[alpha];
-    const int64_t o0 = a.out_off[alpha];
-    const uint16_t first = a.ftype0[alpha];
-    const int32_t X = a.flast[alpha];
-    int32_t skipped = 0;
-    const uint64_t lt = (1ull << lane) - 1ull;
-    for (int32_t rb = r0; rb < r1; rb += 64) {  // uniform across the wave
-        const int32_t r = rb + lane;
-        const bool in = r < r1;
-        const int32_t beta = in ? a.byprefix[r] : 0;
-        const bool excl = in && a.flast[beta] == first;
-        const uint64_t em = __ballot(excl);
-        if (in && !excl) {
-            const int64_t c = o0 + (r - r0) - skipped - __popcll(em & lt);
-            int32_t nv;
-            a.counts[c] = ext_core<T, 1, false, FILT>(a, alpha, X, a.flast[beta], a.fliv[beta], &nv, nullptr);
-            a.nvalid[c] = nv;
+            for (int m = 0; m < MP; ++m) {
+                if (key[m] >= 0) {
+                    a.counts[key[m]] = cnt[m];
+                    a.nvalid[key[m]] = nv[m];
+                }
+            }
         }
-        skipped += __popcll(em);
+        if (has) slot_of[myB] = kNoSlot;
+        __syncthreads();
+        r_start = r_next;
     }
+    if (!WRITE && a.walked && lane == 0) atomicAdd(a.walked, walked);
 }
 
-template <typename T, int MODE, bool FILT>
-__global__ __launch_bounds__(256) void k_ext_write(ExtArgs<T> a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.nw) return;
-    const int64_t f = a.w_order ? a.w_order[g] : g;
-    int32_t nv;
-    const int32_t alpha = a.w_alpha[f];
-    const int32_t X = MODE == 0 ? a.f1[alpha] : a.flast[alpha];
-    (void)ext_core<T, MODE, true, FILT>(a, alpha, X, a.w_type[f], a.w_iv[f], &nv, a.w_out + a.w_off[f]);
+template <typename T, bool L2, bool WRITE>
+hipError_t launch_walk(const WalkArgs<T> &a, int64_t njobs, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    const size_t lds = (size_t)(a.K + 15) / 16 * 16;
+    if (a.M <= 4) k_ext_walk<T, 4, L2, WRITE><<<(unsigned)njobs, kWave, lds, st>>>(a);
+    else k_ext_walk<T, 8, L2, WRITE><<<(unsigned)njobs, kWave, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+// Types as uint16 and the window end of every position.
+template <typename T>
+__global__ void k_walk_prep(const int32_t *__restrict__ types, const T *__restrict__ times, int64_t n, T H,
+                            uint16_t *__restrict__ ty16, int32_t *__restrict__ wend) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ty16[i] = (uint16_t)types[i];
+    const T lim = (T)(times[i] + H);
+    int64_t lo = i + 1, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (times[mid] <= lim) lo = mid + 1;
+        else hi = mid;
+    }
+    wend[i] = (int32_t)lo;
 }
 
 // Frequent selection (count > threshold), order preserving: per-block flag
@@ -312,15 +435,17 @@ __global__ __launch_bounds__(kSelBlock) void k_sel_write(const int32_t *__restri
     }
 }
 
+// Level 1: distinct timestamps of each type, one wave per type.
 template <typename T>
-__global__ void k_level1(const T *__restrict__ ts, const int32_t *__restrict__ type_off, int32_t K,
-                         int32_t *__restrict__ counts) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
+__global__ __launch_bounds__(kWave) void k_level1(const T *__restrict__ ts, const int32_t *__restrict__ type_off,
+                                                  int32_t *__restrict__ counts) {
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t b = type_off[k], e = type_off[k + 1];
     int32_t c = 0;
-    for (int32_t i = type_off[k]; i < type_off[k + 1]; ++i)
-        if (i == type_off[k] || ts[i] != ts[i - 1]) ++c;
-    counts[k] = c;
+    for (int32_t i = b + lane; i < e; i += kWave) c += (i == b || ts[i] != ts[i - 1]) ? 1 : 0;
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, kWave);
+    if (lane == 0) counts[k] = c;
 }
 
 template <typename U>
@@ -405,10 +530,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     L.N = N;
     L.implicit = true;
     const int M = (int)mn.menu_lo.size();
-    const size_t tsb = sizeof(T);
     auto t0 = Clock::now();
-    const std::vector<int32_t> &off = s.h_off;
-    auto ntype = [&](int32_t ty) { return (int64_t)off[ty + 1] - off[ty]; };
     // ---- the candidate family of each alpha
     int64_t nA = P.nf;
     L.out_off.assign(nA + 1, 0);
@@ -466,26 +588,25 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     const int64_t m = L.out_off[nA];
     L.m = m;
     // ---- device inputs
-    DevBuf d_out_off, d_f1, d_menu, d_rlo, d_rhi, d_by, d_f0, d_fl, d_fliv, d_counts, d_nval, d_order;
-    std::vector<T> menu(2 * M);
-    for (int i = 0; i < M; ++i) {
-        menu[2 * i] = (T)mn.menu_lo[i];
-        menu[2 * i + 1] = (T)mn.menu_hi[i];
-    }
+    DevBuf d_out_off, d_f1, d_rlo, d_rhi, d_xlo, d_xhi, d_by, d_fl, d_fliv, d_counts, d_nval, d_order, d_walked;
     if ((e = upload(d_out_off, L.out_off, st)) != hipSuccess) return e;
-    if ((e = upload(d_menu, menu, st)) != hipSuccess) return e;
-    ExtArgs<T> a{};
-    a.ts = s.ts_by_type.as<T>();
+    WalkArgs<T> a{};
+    a.ty16 = mn.ty16.as<uint16_t>();
+    a.times = s.times.as<T>();
+    a.wend = mn.wend.as<int32_t>();
+    a.H = (T)*std::max_element(mn.menu_hi.begin(), mn.menu_hi.end());
+    a.ts_by_type = s.ts_by_type.as<T>();
+    a.pos_by_type = s.pos_by_type.as<int32_t>();
     a.type_off = s.type_off.as<int32_t>();
-    a.nA = nA;
     a.out_off = d_out_off.as<int64_t>();
-    a.menu = d_menu.as<T>();
     a.M = M;
     a.K = s.K;
-    a.xbits = mn.xpred.p ? mn.xpred.as<uint64_t>() : nullptr;
-    a.xwords = mn.xwords;
+    for (int i = 0; i < M; ++i) {
+        a.menu_lo[i] = (T)mn.menu_lo[i];
+        a.menu_hi[i] = (T)mn.menu_hi[i];
+    }
     // host sources of asynchronous uploads live until the level's last sync
-    std::vector<uint16_t> f1, f0, fl;
+    std::vector<uint16_t> f1, fl;
     std::vector<uint8_t> fliv;
     std::vector<int32_t> order;
     if (N == 2) {
@@ -494,34 +615,39 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
         a.f1 = d_f1.as<uint16_t>();
         a.nf1 = (int32_t)P.nf;
     } else {
-        f0.assign(P.ftypes.begin(), P.ftypes.begin() + P.nf);
         fl.assign(P.ftypes.begin() + (size_t)(P.N - 1) * P.nf, P.ftypes.begin() + (size_t)P.N * P.nf);
         fliv.assign(P.fiv.begin() + (size_t)(P.N - 2) * P.nf, P.fiv.begin() + (size_t)(P.N - 1) * P.nf);
-        if ((e = upload(d_f0, f0, st)) != hipSuccess) return e;
         if ((e = upload(d_fl, fl, st)) != hipSuccess) return e;
         if ((e = upload(d_fliv, fliv, st)) != hipSuccess) return e;
         if ((e = upload(d_rlo, L.rlo, st)) != hipSuccess) return e;
         if ((e = upload(d_rhi, L.rhi, st)) != hipSuccess) return e;
+        if ((e = upload(d_xlo, L.xlo, st)) != hipSuccess) return e;
+        if ((e = upload(d_xhi, L.xhi, st)) != hipSuccess) return e;
         if ((e = upload(d_by, L.byprefix, st)) != hipSuccess) return e;
-        a.chains = P.chains.as<Pair<T>>();
+        a.ct = P.ct.as<T>();
+        a.cs = P.cs.as<T>();
+        a.cp = P.cp.as<int32_t>();
         a.coff = P.chain_off.as<int64_t>();
-        a.ftype0 = d_f0.as<uint16_t>();
         a.flast = d_fl.as<uint16_t>();
         a.fliv = d_fliv.as<uint8_t>();
         a.rlo = d_rlo.as<int32_t>();
         a.rhi = d_rhi.as<int32_t>();
+        a.xlo = d_xlo.as<int32_t>();
+        a.xhi = d_xhi.as<int32_t>();
         a.byprefix = d_by.as<int32_t>();
         // workgroups take the alphas grouped by their last type: the waves in
-        // flight then read the same type's predecessor bits and nearly the
-        // same type lists, which stay in each XCD's L2
+        // flight then walk the neighbourhoods of the same type's events
         order = order_by_key(nA, s.K, [&](int64_t x) { return (int32_t)fl[x]; });
         if ((e = upload(d_order, order, st)) != hipSuccess) return e;
-        a.aorder = d_order.as<int32_t>();
+        a.order = d_order.as<int32_t>();
     }
     if ((e = d_counts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
     if ((e = d_nval.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    if ((e = d_walked.alloc(sizeof(unsigned long long))) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(d_walked.p, 0, sizeof(unsigned long long), st)) != hipSuccess) return e;
     a.counts = d_counts.as<int32_t>();
     a.nvalid = d_nval.as<int32_t>();
+    a.walked = d_walked.as<unsigned long long>();
     L.gen_ms = ms_since(t0);
     auto t1 = Clock::now();
     // ---- count
@@ -529,17 +655,8 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
     (void)hipEventRecord(ev0, st);
-    if (m > 0) {
-        if (N == 2) {
-            if (a.xbits) k_ext_count0<T, true><<<(unsigned)nA, 64, 0, st>>>(a);
-            else k_ext_count0<T, false><<<(unsigned)nA, 64, 0, st>>>(a);
-        } else {
-            if (a.xbits) k_ext_count1<T, true><<<(unsigned)nA, 64, 0, st>>>(a);
-            else k_ext_count1<T, false><<<(unsigned)nA, 64, 0, st>>>(a);
-        }
-    }
+    if (m > 0) e = N == 2 ? launch_walk<T, true, false>(a, nA, st) : launch_walk<T, false, false>(a, nA, st);
     (void)hipEventRecord(ev1, st);
-    e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     float kms = 0;
     if (e == hipSuccess) (void)hipEventElapsedTime(&kms, ev0, ev1);
@@ -547,6 +664,11 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     (void)hipEventDestroy(ev1);
     if (e != hipSuccess) return e;
     L.kernel_ms = kms;
+    {
+        unsigned long long wk = 0;
+        if ((e = hipMemcpy(&wk, d_walked.p, sizeof(wk), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+        L.walked = (int64_t)wk;
+    }
     // ---- frequent episodes, selected on the device (counts stay there)
     std::vector<int32_t> nval;
     {
@@ -629,43 +751,55 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     });
     L.h_chain_off.assign(nf + 1, 0);
     for (int64_t f = 0; f < nf; ++f) L.h_chain_off[f + 1] = L.h_chain_off[f] + nval[f];
-    DevBuf d_wa, d_wt, d_wi, d_wo;
-    // the write pass takes the frequent episodes grouped by alpha's last type
-    // (as the counting pass takes the alphas)
-    std::vector<int32_t> w_order = order_by_key(nf, s.K, [&](int64_t f) {
-        const int64_t al = w_alpha[f];
+    // write jobs: the alphas with frequent extensions (the frequent list is in
+    // candidate order, so each alpha's frequent extensions are contiguous)
+    std::vector<int32_t> job_alpha;
+    std::vector<int64_t> job_f;
+    for (int64_t f = 0; f < nf; ++f) {
+        if (f == 0 || w_alpha[f] != w_alpha[f - 1]) {
+            job_alpha.push_back(w_alpha[f]);
+            job_f.push_back(f);
+        }
+    }
+    job_f.push_back(nf);
+    const int64_t nj = (int64_t)job_alpha.size();
+    // taken grouped by alpha's last type, as the counting pass takes them
+    std::vector<int32_t> w_order = order_by_key(nj, s.K, [&](int64_t j) {
+        const int64_t al = job_alpha[j];
         return (int32_t)(N == 2 ? P.ftypes[al] : P.ftypes[(size_t)(P.N - 1) * P.nf + al]);
     });
+    DevBuf d_ja, d_jf, d_wt, d_wi, d_wo;
+    if ((e = upload(d_ja, job_alpha, st)) != hipSuccess) return e;
+    if ((e = upload(d_jf, job_f, st)) != hipSuccess) return e;
     if ((e = upload(d_wo, w_order, st)) != hipSuccess) return e;
-    if ((e = upload(d_wa, w_alpha, st)) != hipSuccess) return e;
     if ((e = upload(d_wt, w_type, st)) != hipSuccess) return e;
     if ((e = upload(d_wi, w_iv, st)) != hipSuccess) return e;
     if ((e = upload(L.chain_off, L.h_chain_off, st)) != hipSuccess) return e;
-    if ((e = L.chains.alloc(sizeof(Pair<T>) * (size_t)L.h_chain_off[nf])) != hipSuccess) return e;
-    if (nf > 0) {
-        a.nw = nf;
-        a.w_alpha = d_wa.as<int32_t>();
+    const size_t tot = (size_t)L.h_chain_off[nf];
+    if ((e = L.ct.alloc(sizeof(T) * tot)) != hipSuccess) return e;
+    if ((e = L.cs.alloc(sizeof(T) * tot)) != hipSuccess) return e;
+    if ((e = L.cp.alloc(sizeof(int32_t) * tot)) != hipSuccess) return e;
+    if (nj > 0) {
+        a.job_alpha = d_ja.as<int32_t>();
+        a.job_f = d_jf.as<int64_t>();
+        a.order = d_wo.as<int32_t>();
         a.w_type = d_wt.as<uint16_t>();
         a.w_iv = d_wi.as<uint8_t>();
         a.w_off = L.chain_off.as<int64_t>();
-        a.w_order = d_wo.as<int32_t>();
-        a.w_out = L.chains.as<Pair<T>>();
-        const unsigned blocks = (unsigned)((nf + 255) / 256);
-        if (N == 2) {
-            if (a.xbits) k_ext_write<T, 0, true><<<blocks, 256, 0, st>>>(a);
-            else k_ext_write<T, 0, false><<<blocks, 256, 0, st>>>(a);
-        } else {
-            if (a.xbits) k_ext_write<T, 1, true><<<blocks, 256, 0, st>>>(a);
-            else k_ext_write<T, 1, false><<<blocks, 256, 0, st>>>(a);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        a.wct = L.ct.as<T>();
+        a.wcs = L.cs.as<T>();
+        a.wcp = L.cp.as<int32_t>();
+        e = N == 2 ? launch_walk<T, true, true>(a, nj, st) : launch_walk<T, false, true>(a, nj, st);
+        if (e != hipSuccess) return e;
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     L.count_ms = ms_since(t1);
     // chain lists two levels back are no longer needed
     if (mn.levels.size() >= 2) {
         MineLevel &Q = mn.levels[mn.levels.size() - 2];
-        Q.chains.reset();
+        Q.ct.reset();
+        Q.cs.reset();
+        Q.cp.reset();
         Q.chain_off.reset();
     }
     mn.levels.push_back(std::move(L));
@@ -682,8 +816,7 @@ hipError_t level1_t(const Stream &s, Mine &mn, hipStream_t st) {
     auto t1 = Clock::now();
     DevBuf d_counts;
     if ((e = d_counts.alloc(sizeof(int32_t) * s.K)) != hipSuccess) return e;
-    k_level1<T><<<(s.K + 63) / 64, 64, 0, st>>>(s.ts_by_type.as<T>(), s.type_off.as<int32_t>(), s.K,
-                                              d_counts.as<int32_t>());
+    k_level1<T><<<s.K, kWave, 0, st>>>(s.ts_by_type.as<T>(), s.type_off.as<int32_t>(), d_counts.as<int32_t>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
     L.counts.resize(s.K);
     if ((e = hipMemcpyAsync(L.counts.data(), d_counts.p, sizeof(int32_t) * s.K, hipMemcpyDeviceToHost, st)) !=
@@ -714,52 +847,39 @@ hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipS
     return level_t<int32_t>(s, mn, N, d_flags, st);
 }
 
-// Bytes read and written per candidate: the events of the new node's type
-// that the merge visits (with predecessor bits: the bit words over the
-// type's index range and the events whose bit is set), alpha's chain list,
-// the count and the end-event count.
+// Bytes the window walk of a level must read and write: the stream positions
+// it walked (type and time of each), the alphas' chain lists (time, start,
+// position and window end of each entry), and each candidate's count and
+// end-event count.
 int64_t extend_level_bytes(const Stream &s, Mine &mn, int level) {
     MineLevel &L = mn.levels[level - 1];
     if (L.alg_bytes >= 0) return L.alg_bytes;
     const MineLevel &P = mn.levels[level - 2];
-    const int N = L.N;
-    const int M = (int)mn.menu_lo.size();
     const int64_t tsb = s.ts_bytes();
-    const std::vector<int32_t> &off = s.h_off;
-    auto ntype = [&](int32_t ty) { return (int64_t)off[ty + 1] - off[ty]; };
-    const bool filt = mn.xpred.p != nullptr && !mn.xpop.empty();
-    auto node_bytes = [&](int iv, int32_t X, int32_t B) -> int64_t {
-        if (!filt) return ntype(B) * tsb;
-        const int64_t y0 = off[B], q1 = off[B + 1];
-        const int64_t words = q1 > y0 ? ((q1 - 1) >> 6) - (y0 >> 6) + 1 : 0;
-        return words * 8 + (int64_t)mn.xpop[((int64_t)iv * s.K + X) * s.K + B] * tsb;
-    };
-    const int64_t nA = P.nf;
-    std::vector<int64_t> part(nA, 0);
-    parallel_for(nA, [&](int64_t x0, int64_t x1) {
-        for (int64_t a = x0; a < x1; ++a) {
-            const int64_t k = L.out_off[a + 1] - L.out_off[a];
-            if (k == 0) continue;
-            const int64_t alen = N == 2 ? ntype(P.ftypes[a]) : P.h_chain_off[a + 1] - P.h_chain_off[a];
-            int64_t b = k * (alen * (N == 2 ? 1 : 2) * tsb + 8);
-            if (N == 2) {
-                for (int64_t bi = 0; bi < nA; ++bi)
-                    if (bi != a)
-                        for (int iv = 0; iv < M; ++iv) b += node_bytes(iv, P.ftypes[a], P.ftypes[bi]);
-            } else {
-                const int32_t X = P.ftypes[(size_t)(P.N - 1) * P.nf + a];
-                for (int64_t e = 0; e < k; ++e) {
-                    const int32_t beta = L.byprefix[ext_position(L, a, e)];
-                    b += node_bytes(P.fiv[(size_t)(P.N - 2) * P.nf + beta], X, P.ftypes[(size_t)(P.N - 1) * P.nf + beta]);
-                }
-            }
-            part[a] = b;
-        }
-    });
-    int64_t total = 0;
-    for (int64_t a = 0; a < nA; ++a) total += part[a];
-    L.alg_bytes = total;
-    return total;
+    int64_t entries = 0;
+    if (L.N == 2) {
+        for (int64_t a = 0; a < P.nf; ++a) entries += s.h_off[P.ftypes[a] + 1] - s.h_off[P.ftypes[a]];
+    } else {
+        entries = P.h_chain_off.empty() ? 0 : P.h_chain_off.back();
+    }
+    L.alg_bytes = L.walked * (2 + tsb) + entries * (2 * tsb + 8) + L.m * 8;
+    return L.alg_bytes;
+}
+
+hipError_t extend_prepare(const Stream &s, Mine &mn, hipStream_t st) {
+    hipError_t e;
+    if ((e = mn.ty16.alloc(sizeof(uint16_t) * (size_t)s.n)) != hipSuccess) return e;
+    if ((e = mn.wend.alloc(sizeof(int32_t) * (size_t)s.n)) != hipSuccess) return e;
+    if (s.n == 0) return hipSuccess;
+    const int64_t H = *std::max_element(mn.menu_hi.begin(), mn.menu_hi.end());
+    const unsigned blocks = (unsigned)((s.n + 255) / 256);
+    if (s.ts_kind == EPI_TS_I64)
+        k_walk_prep<int64_t><<<blocks, 256, 0, st>>>(s.types.as<int32_t>(), s.times.as<int64_t>(), s.n, H,
+                                                     mn.ty16.as<uint16_t>(), mn.wend.as<int32_t>());
+    else
+        k_walk_prep<int32_t><<<blocks, 256, 0, st>>>(s.types.as<int32_t>(), s.times.as<int32_t>(), s.n, (int32_t)H,
+                                                     mn.ty16.as<uint16_t>(), mn.wend.as<int32_t>());
+    return hipGetLastError();
 }
 
 void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs) {

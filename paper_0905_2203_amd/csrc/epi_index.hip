@@ -10,7 +10,8 @@
 //   3. k_scatter: each wave re-reads its chunk 64 events at a time; the
 //                 rank of a lane among earlier lanes of the same type comes
 //                 from a wave-wide compare loop, so the scatter is stable.
-//                 It writes both the per-type index and a tile-major copy in
+//                 It writes the per-type index (times, and the stream
+//                 position of every entry) and a tile-major copy in
 //                 which each chunk of kTile stream positions (a "tile") holds
 //                 its own events grouped by type, with per-tile uint16
 //                 offsets, so that a workgroup can stage a time window of
@@ -43,7 +44,8 @@ template <typename T>
 __global__ __launch_bounds__(kWave) void k_scatter(const int32_t *__restrict__ types, const T *__restrict__ times,
                                                    int64_t n, int32_t K, int64_t B,
                                                    const int32_t *__restrict__ cnt, const int32_t *__restrict__ base,
-                                                   T *__restrict__ out, T *__restrict__ tiled,
+                                                   T *__restrict__ out, int32_t *__restrict__ pos_out,
+                                                   T *__restrict__ tiled,
                                                    uint16_t *__restrict__ loff, T *__restrict__ tile_t0) {
     __shared__ int32_t rank[kMaxK];   // next rank of each type inside this tile
     __shared__ int32_t start[kMaxK];  // tile-local start of each type group
@@ -97,7 +99,9 @@ __global__ __launch_bounds__(kWave) void k_scatter(const int32_t *__restrict__ t
         if (valid) rk = rank[ty] + before;
         __syncthreads();
         if (valid) {
-            out[base[(int64_t)ty * B + b] + rk] = t;
+            const int64_t q = base[(int64_t)ty * B + b] + rk;
+            out[q] = t;
+            pos_out[q] = (int32_t)i;
             tiled[beg + start[ty] + rk] = t;
             if (after == 0) rank[ty] = rk + 1;
         }
@@ -218,6 +222,7 @@ hipError_t build_type_index(Stream &s, hipStream_t st) {
     s.B = B;
     if ((e = s.type_off.alloc(sizeof(int32_t) * (K + 1))) != hipSuccess) return e;
     if ((e = s.ts_by_type.alloc(s.ts_bytes() * (size_t)n)) != hipSuccess) return e;
+    if ((e = s.pos_by_type.alloc(sizeof(int32_t) * (size_t)n)) != hipSuccess) return e;
     if ((e = s.tiled_ts.alloc(s.ts_bytes() * (size_t)B * kTile)) != hipSuccess) return e;
     if ((e = s.tile_loff.alloc(sizeof(uint16_t) * (size_t)B * (K + 1))) != hipSuccess) return e;
     if ((e = s.tile_t0.alloc(s.ts_bytes() * (size_t)(B + 1))) != hipSuccess) return e;
@@ -241,12 +246,14 @@ hipError_t build_type_index(Stream &s, hipStream_t st) {
         if (s.ts_kind == EPI_TS_I64)
             k_scatter<int64_t><<<B, kWave, 0, st>>>(s.types.as<int32_t>(), s.times.as<int64_t>(), n, K, B,
                                                     cnt.as<int32_t>(), base.as<int32_t>(),
-                                                    s.ts_by_type.as<int64_t>(), s.tiled_ts.as<int64_t>(),
+                                                    s.ts_by_type.as<int64_t>(), s.pos_by_type.as<int32_t>(),
+                                                    s.tiled_ts.as<int64_t>(),
                                                     s.tile_loff.as<uint16_t>(), s.tile_t0.as<int64_t>());
         else
             k_scatter<int32_t><<<B, kWave, 0, st>>>(s.types.as<int32_t>(), s.times.as<int32_t>(), n, K, B,
                                                     cnt.as<int32_t>(), base.as<int32_t>(),
-                                                    s.ts_by_type.as<int32_t>(), s.tiled_ts.as<int32_t>(),
+                                                    s.ts_by_type.as<int32_t>(), s.pos_by_type.as<int32_t>(),
+                                                    s.tiled_ts.as<int32_t>(),
                                                     s.tile_loff.as<uint16_t>(), s.tile_t0.as<int32_t>());
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;

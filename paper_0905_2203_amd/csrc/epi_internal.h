@@ -84,6 +84,7 @@ struct Stream {
     DevBuf times;       // T[n]
     DevBuf type_off;    // int32[K+1]
     DevBuf ts_by_type;  // T[n], grouped by type, each group in time order
+    DevBuf pos_by_type; // int32[n], stream position of each ts_by_type entry
     // Tile-major copy of the index: tile b holds stream positions
     // [b*kTile, (b+1)*kTile); inside a tile the events are grouped by type
     // (each group in time order) starting at tile_loff[b*(K+1) + type].
@@ -166,13 +167,16 @@ struct MineLevel {
     std::vector<int32_t> byprefix; // level >= 3: level N-1 frequent, ordered by first N-2 nodes, then last node
     std::vector<int32_t> xlo, xhi; // level >= 3: the extensions repeating alpha's first type, [xlo, xhi)
     // frequent episodes of this level (structure of arrays) and their chain
-    // lists: for every end event with an occurrence, (end time, latest start)
+    // lists: for every end event with an occurrence, in time order, its time,
+    // the latest start of an occurrence ending there, and its stream position
     int64_t nf = 0;
     std::vector<uint16_t> ftypes;  // [N][nf]
     std::vector<uint8_t> fiv;      // [N-1][nf]
-    DevBuf chains;                 // Pair<T>[...]
+    DevBuf ct, cs;                 // T [total]: end time, latest start
+    DevBuf cp;                     // int32 [total]: stream position of the end event
     DevBuf chain_off;              // int64 [nf + 1]
     std::vector<int64_t> h_chain_off;
+    int64_t walked = 0;            // stream positions the extension walk visited (counting pass)
 };
 
 struct Mine {
@@ -182,12 +186,10 @@ struct Mine {
     int64_t threshold = 0;
     std::vector<MineLevel> levels;
     DevBuf pred_bits, succ_bits;  // pair-existence bitmaps of the menu (may be empty)
-    // extension engine: bit (i, x, q) says the event at per-type index
-    // position q has an event of type x at a gap in menu interval i before
-    // it; rows of xwords 64-bit words (may be empty)
-    DevBuf xpred;
-    int64_t xwords = 0;
-    std::vector<int32_t> xpop;  // [i][x][B]: events of type B whose bit (i, x) is set
+    // extension engine: the stream's types as uint16 and, for every position
+    // p, the first position whose time exceeds time[p] + H (H = the longest
+    // menu interval end)
+    DevBuf ty16, wend;
     double bits_ms = 0;
 };
 
@@ -250,7 +252,10 @@ hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const
 int queue_class_of(int64_t bound);
 // Extension engine of level-wise discovery (epi_extend.hip): count level 1,
 // then count level N (>= 2) from level N-1's frequent episodes and chain lists,
-// select its frequent episodes and write their chain lists.
+// select its frequent episodes and write their chain lists.  Menus of up to
+// kExtMaxMenu intervals.
+constexpr int kExtMaxMenu = 8;
+hipError_t extend_prepare(const Stream &s, Mine &mn, hipStream_t st);
 hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st);
 hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st);
 // algorithmic bytes of an extension-engine level (computed on first use)
@@ -272,7 +277,6 @@ hipError_t costmodel_predict_device(Mlp &net, float *dX, int64_t B, float *dy, h
 hipError_t candidate_features(const Stream &s, const CandSet &c, float *dX, hipStream_t st);
 // Pair-existence bitmaps of an interval menu over a stream (epi_pairs.hip).
 hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st);
-hipError_t build_index_pred_bits(const Stream &s, Mine &mn, hipStream_t st);
 // Candidate generation of level-wise discovery (epi_mine.hip).
 void gen_level1(int32_t K, MineLevel &L);
 void gen_level2(const MineLevel &F1, int n_menu, MineLevel &L);
