@@ -257,7 +257,8 @@ def main():
     dom = int(np.argmax(kern_ms)) + 1
     alg = ctx.epi_mine_level_bytes(mid, dom)
     achieved_gbs = alg / (kern_ms[dom - 1] / 1e3) / 1e9
-    kname = f"k_ext_walk<int, 4, {'true' if dom == 2 else 'false'}, false>" if dom >= 2 else "k_level1<int>"
+    mp = len(menu) if len(menu) <= 4 else 8
+    kname = f"k_ext_walk<int, {mp}, false>" if dom >= 2 else "k_level1<int>"
     traffic = profiled_traffic(kname)
 
     # parity spot check (outside the timed region): sampled counts vs the oracle

@@ -633,7 +633,7 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
         for (int N = 2; N <= max_size; ++N) {
             const MineLevel &prev = mn->levels.back();
             if (prev.nf == 0 || (N == 2 && prev.nf < 2)) break;
-            HIPTRY(ctx, extend_level(*s, *mn, N, ctx->c.flags.as<int32_t>(), st), "counting a level");
+            HIPTRY(ctx, extend_level(*s, *mn, N, st), "counting a level");
             epi_status f = check_flags(ctx);
             if (f != EPI_OK) return f;
             if (mn->levels.back().m == 0) {
@@ -690,7 +690,7 @@ epi_status epi_mine_level_info(epi_ctx *ctx, int32_t mine_id, int32_t level, int
     if (level < 1 || level > (int32_t)lv.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
     const MineLevel &L = lv[level - 1];
     if (n_candidates) *n_candidates = L.m;
-    if (n_frequent) *n_frequent = (int64_t)L.freq.size();
+    if (n_frequent) *n_frequent = L.nf;
     if (times_ms) {
         times_ms[0] = L.gen_ms;
         times_ms[1] = L.count_ms;
@@ -720,8 +720,7 @@ void mine_episode(const Mine &mn, int level, bool frequent, int64_t r, uint8_t *
     int64_t c;
     if (frequent && L.implicit) {
         c = L.freq[r];
-        for (int k = 0; k < L.N; ++k) ty[k] = L.ftypes[(size_t)k * L.nf + r];
-        for (int k = 0; k + 1 < L.N; ++k) ivs[k] = L.fiv[(size_t)k * L.nf + r];
+        extend_frequent(mn, level, r, ty, ivs);
     } else {
         c = frequent ? L.freq[r] : r;
         if (L.implicit) {
@@ -752,7 +751,8 @@ epi_status epi_mine_read(epi_ctx *ctx, int32_t mine_id, int32_t level, int frequ
     if (level < 1 || level > (int32_t)mn.levels.size()) return fail(ctx, EPI_ESTATE, "no level %d", level);
     MineLevel &L = mn.levels[level - 1];
     HIPTRY(ctx, host_counts(L), "reading counts");
-    const int64_t want = frequent_only ? (int64_t)L.freq.size() : L.m;
+    if (mn.engine == 1) HIPTRY(ctx, extend_host_view(mn, level), "reading a level");
+    const int64_t want = frequent_only ? L.nf : L.m;
     if (m != want) return fail(ctx, EPI_EINVAL, "level %d has %lld entries, not %lld", level, (long long)want,
                                (long long)m);
     if (m > 0 && (!N || !types || !lo || !hi || !counts)) return fail(ctx, EPI_EINVAL, "null output");
@@ -771,6 +771,7 @@ epi_status epi_mine_read_at(epi_ctx *ctx, int32_t mine_id, int32_t level, int64_
     MineLevel &L = mn.levels[level - 1];
     if (k < 0 || (k > 0 && (!idx || !N || !types || !lo || !hi || !counts))) return fail(ctx, EPI_EINVAL, "bad arguments");
     HIPTRY(ctx, host_counts(L), "reading counts");
+    if (mn.engine == 1) HIPTRY(ctx, extend_host_view(mn, level), "reading a level");
     for (int64_t r = 0; r < k; ++r) {
         if (idx[r] < 0 || idx[r] >= L.m) return fail(ctx, EPI_EINVAL, "index %lld outside the level", (long long)idx[r]);
         mine_episode(mn, level, false, idx[r], N + r, types + r * 8, lo + r * 7, hi + r * 7, counts + r);

@@ -74,9 +74,10 @@ struct WalkArgs {
     // one job per workgroup
     const int32_t *job_alpha; // alpha of each job (null: the job index)
     const int32_t *order;     // order in which the workgroups take the jobs (null: index order)
-    // counting pass: each alpha's extensions and their outputs
-    const int64_t *out_off;   // [nA + 1]
-    const int32_t *rlo, *rhi, *xlo, *xhi, *byprefix;
+    // counting pass (level >= 3): alpha's extensions are the frequent
+    // episodes beta = rlo..rlo+n of the previous level, skipping [xlo, xhi)
+    const int64_t *out_off;   // [nA + 1] first candidate of each alpha
+    const int32_t *rlo, *xlo, *xhi;
     const uint16_t *flast;    // last type of each frequent episode of the previous level
     const uint8_t *fliv;      // its last interval id
     int32_t *counts, *nvalid;
@@ -91,6 +92,7 @@ struct WalkArgs {
     T menu_lo[kExtMaxMenu], menu_hi[kExtMaxMenu];
     int32_t M;
     int32_t K;
+    bool level2;              // alphas are frequent types (level 2)
 };
 
 // Read-only data seen through the constant address space: uniform reads of
@@ -110,14 +112,15 @@ __device__ __forceinline__ T read_lane(T v, int l) {
     }
 }
 
+// Value of v in the lane whose byte address (lane * 4) is addr.
 template <typename T>
-__device__ __forceinline__ T lane_value(T v, int src) {
+__device__ __forceinline__ T permute(int addr, T v) {
     if constexpr (sizeof(T) == 4) {
-        return (T)__shfl((int)v, src, kWave);
+        return (T)__builtin_amdgcn_ds_bpermute(addr, (int)v);
     } else {
         const uint64_t u = (uint64_t)v;
-        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)u, src, kWave);
-        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(u >> 32), src, kWave);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
         return (T)(((uint64_t)hi << 32) | lo);
     }
 }
@@ -125,7 +128,7 @@ __device__ __forceinline__ T lane_value(T v, int src) {
 // Extension r of a job: its new type B, interval id and key (counting: the
 // candidate's index; writing: the first slot of its chain list).  Within a
 // job the extensions are ordered by B.
-template <typename T, bool L2, bool WRITE>
+template <typename T, bool WRITE>
 __device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int64_t alpha, int64_t r, int32_t &B,
                                           int &iv, int64_t &key) {
     if (WRITE) {
@@ -133,35 +136,36 @@ __device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int
         B = a.w_type[f];
         iv = a.w_iv[f];
         key = a.w_off[f];
-    } else if (L2) {
+    } else if (a.level2) {
         const int64_t bi0 = r / a.M;
         iv = (int)(r - bi0 * a.M);
         const int64_t bi = bi0 >= alpha ? bi0 + 1 : bi0;
         B = a.f1[bi];
-        key = a.out_off[alpha] + r;
+        key = alpha * (int64_t)(a.nf1 - 1) * a.M + r;
     } else {
-        int64_t rr = a.rlo[alpha] + r;
-        if (rr >= a.xlo[alpha]) rr += a.xhi[alpha] - a.xlo[alpha];
-        const int32_t beta = a.byprefix[rr];
+        int64_t beta = a.rlo[alpha] + r;
+        if (beta >= a.xlo[alpha]) beta += a.xhi[alpha] - a.xlo[alpha];
         B = a.flast[beta];
         iv = a.fliv[beta];
         key = a.out_off[alpha] + r;
     }
 }
 
-template <typename T, bool L2, bool WRITE>
+template <typename T, bool WRITE>
 __device__ __forceinline__ int64_t n_extensions(const WalkArgs<T> &a, int64_t job, int64_t alpha) {
     if (WRITE) return a.job_f[job + 1] - a.job_f[job];
-    if (L2) return (int64_t)(a.nf1 - 1) * a.M;
-    return (int64_t)(a.rhi[alpha] - a.rlo[alpha]) - (a.xhi[alpha] - a.xlo[alpha]);
+    if (a.level2) return (int64_t)(a.nf1 - 1) * a.M;
+    return a.out_off[alpha + 1] - a.out_off[alpha];
 }
 
-// One job: alpha, all of its extensions (or, writing, its frequent ones).
-// MP >= M greedy states per lane, one per menu interval.
-template <typename T, int MP, bool L2, bool WRITE>
+// One job: alpha and all of its extensions (or, writing, its frequent ones).
+// MP greedy states per lane, one per menu interval: MP = M for menus of up
+// to 4 intervals, else 8 with the unused states idle.
+template <typename T, int MP, bool WRITE>
 __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kMax = TsLimits<T>::hi();
+    constexpr bool kExact = MP <= 4;
     extern __shared__ uint8_t slot_of[];            // [K] lane owning each type this round
     __shared__ unsigned long long want[kWave];      // batch lanes holding each owner's events
     __shared__ int32_t gtype[kWave];
@@ -169,12 +173,12 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     const int lane = threadIdx.x;
     const int64_t job = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int64_t alpha = a.job_alpha ? (int64_t)a.job_alpha[job] : job;
-    const int M = a.M;
+    const int M = kExact ? MP : a.M;
     // alpha's chain list
     const_ptr<T> xt, xs;
     const int32_t *xp;
     int32_t clen;
-    if (L2) {
+    if (a.level2) {
         const int32_t ty = a.f1[alpha];
         const int32_t o = a.type_off[ty];
         clen = a.type_off[ty + 1] - o;
@@ -188,7 +192,14 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         xs = (const_ptr<T>)(a.cs + o);
         xp = a.cp + o;
     }
-    const int64_t R = n_extensions<T, L2, WRITE>(a, job, alpha);
+    // the menu, uniform
+    T mlo[MP], mhi[MP];
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        mlo[m] = a.menu_lo[m];
+        mhi[m] = a.menu_hi[m];
+    }
+    const int64_t R = n_extensions<T, WRITE>(a, job, alpha);
     for (int k = lane; k < a.K; k += kWave) slot_of[k] = kNoSlot;
     want[lane] = 0;
     unsigned long long walked = 0;
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
             int32_t B = -1;
             int iv = 0;
             int64_t key = -1;
-            if (in) extension<T, L2, WRITE>(a, job, alpha, r, B, iv, key);
+            if (in) extension<T, WRITE>(a, job, alpha, r, B, iv, key);
             int32_t pB = __shfl_up(B, 1, kWave);
             if (lane == 0) pB = prevB;
             const uint64_t st = __ballot(in && B != pB);
@@ -228,11 +239,13 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         const bool has = lane < ng;
         const int32_t myB = has ? gtype[lane] : -1;
         int64_t key[MP];
+        bool own[MP];
         T pe[MP];
         int32_t cnt[MP], nv[MP];
 #pragma unroll
         for (int m = 0; m < MP; ++m) {
             key[m] = has ? gkey[m][lane] : -1;
+            own[m] = key[m] >= 0;
             pe[m] = kMin;
             cnt[m] = 0;
             nv[m] = 0;
@@ -262,6 +275,8 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
             carry = max(carry, __builtin_amdgcn_readlane(e, 63 - __builtin_clzll(__ballot(ci))));
             walked += (unsigned long long)total;
             for (int32_t b = 0; b < total; b += kWave) {  // uniform
+                // stream position of this lane: the runs meeting [b, b + 64)
+                // are visited in order
                 const int32_t o = b + lane;
                 const bool ev = o < total;
                 uint64_t runs = __ballot(len > 0 && X < b + kWave && S > b);
@@ -277,13 +292,14 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 const T t = ev ? a.times[P] : kMax;
                 const int nb = min(total - b, kWave);
                 const T tf = read_lane(t, 0), tl = read_lane(t, nb - 1);
+                // s_m(y): start of the latest end event x with
+                // t_x < t - lo_m, when t_x >= t - hi_m
                 while (ilo < clen && xt[ilo] < (T)(tf - a.H)) ++ilo;
-                T cx[MP], cxs[MP], lim[MP];
+                T cx[MP], cxs[MP];
 #pragma unroll
                 for (int m = 0; m < MP; ++m) {
                     cx[m] = kMin;
                     cxs[m] = kMin;
-                    lim[m] = m < M ? (T)(t - a.menu_lo[m]) : kMin;
                 }
                 for (int32_t q = ilo; q < clen; ++q) {  // uniform
                     const T qt = xt[q];
@@ -291,18 +307,20 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     const T qs = xs[q];
 #pragma unroll
                     for (int m = 0; m < MP; ++m) {
-                        if (qt < lim[m]) {
-                            cx[m] = qt;
-                            cxs[m] = qs;
-                        }
+                        const bool c = (T)(qt + mlo[m]) < t;
+                        cx[m] = c ? qt : cx[m];
+                        cxs[m] = c ? qs : cxs[m];
                     }
                 }
                 T sv[MP];
-                bool any = false;
+                uint32_t any = 0;
 #pragma unroll
                 for (int m = 0; m < MP; ++m) {
-                    sv[m] = (m < M && ev && cx[m] >= (T)(t - a.menu_hi[m])) ? cxs[m] : kMin;
-                    any |= sv[m] != kMin;
+                    // bitwise, not short-circuit: keeps the code branch-free
+                    const uint32_t v = (uint32_t)(kExact || m < M) & (uint32_t)ev &
+                                       (uint32_t)(cx[m] != kMin) & (uint32_t)((T)(cx[m] + mhi[m]) >= t);
+                    sv[m] = v ? cxs[m] : kMin;
+                    any |= v;
                 }
                 if (any) {
                     const uint8_t sl = slot_of[ty];
@@ -311,39 +329,39 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 __syncthreads();
                 uint64_t wm = want[lane];
                 want[lane] = 0;
-                while (__ballot(wm != 0)) {  // uniform
-                    const int k = wm ? __builtin_ctzll(wm) : lane;
-                    const T yt = lane_value(t, k);
-                    const int32_t yp = __shfl(P, k, kWave);
+                // each owner lane runs its greedies over its events in time
+                // order (branch-free; lanes with nothing left read themselves)
+                if (__ballot(wm != 0)) do {  // uniform
+                    const uint32_t on = wm != 0;
+                    const int addr = (on ? __builtin_ctzll(wm) : lane) << 2;
+                    const T yt = permute(addr, t);
+                    int32_t yp = 0;
+                    if (WRITE) yp = permute(addr, P);
                     T ys[MP];
 #pragma unroll
-                    for (int m = 0; m < MP; ++m) ys[m] = m < M ? lane_value(sv[m], k) : kMin;
-                    if (wm) {
+                    for (int m = 0; m < MP; ++m) ys[m] = (kExact || m < M) ? permute(addr, sv[m]) : kMin;
 #pragma unroll
-                        for (int m = 0; m < MP; ++m) {
-                            if (key[m] >= 0 && ys[m] != kMin) {
-                                if (WRITE) {
-                                    const int64_t w = key[m] + nv[m];
-                                    a.wct[w] = yt;
-                                    a.wcs[w] = ys[m];
-                                    a.wcp[w] = yp;
-                                }
-                                ++nv[m];
-                                if (ys[m] > pe[m]) {
-                                    ++cnt[m];
-                                    pe[m] = yt;
-                                }
-                            }
+                    for (int m = 0; m < MP; ++m) {
+                        const uint32_t v = on & (uint32_t)own[m] & (uint32_t)(ys[m] != kMin);
+                        if (WRITE && v) {
+                            const int64_t w = key[m] + nv[m];
+                            a.wct[w] = yt;
+                            a.wcs[w] = ys[m];
+                            a.wcp[w] = yp;
                         }
-                        wm &= wm - 1;
+                        nv[m] += (int32_t)v;
+                        const uint32_t g = v & (uint32_t)(ys[m] > pe[m]);
+                        cnt[m] += (int32_t)g;
+                        pe[m] = g ? yt : pe[m];
                     }
-                }
+                    wm &= wm - 1;
+                } while (__ballot(wm != 0));
             }
         }
         if (!WRITE) {
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
-                if (key[m] >= 0) {
+                if (own[m]) {
                     a.counts[key[m]] = cnt[m];
                     a.nvalid[key[m]] = nv[m];
                 }
@@ -356,12 +374,30 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     if (!WRITE && a.walked && lane == 0) atomicAdd(a.walked, walked);
 }
 
-template <typename T, bool L2, bool WRITE>
+// Every array a walk of this kind reads or writes must be present.
+template <typename T, bool WRITE>
+bool walk_args_complete(const WalkArgs<T> &a) {
+    bool ok = a.ty16 && a.times && a.wend && a.M >= 1 && a.M <= kExtMaxMenu && a.K >= 1;
+    if (a.level2) ok = ok && a.f1 && a.ts_by_type && a.pos_by_type && a.type_off && a.nf1 >= 2;
+    else ok = ok && a.ct && a.cs && a.cp && a.coff;
+    if (WRITE) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv && a.w_off && a.wct && a.wcs && a.wcp;
+    else ok = ok && a.counts && a.nvalid && (a.level2 || (a.out_off && a.rlo && a.xlo && a.xhi && a.flast && a.fliv));
+    return ok;
+}
+
+template <typename T, bool WRITE>
 hipError_t launch_walk(const WalkArgs<T> &a, int64_t njobs, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
+    if (!walk_args_complete<T, WRITE>(a)) return hipErrorInvalidValue;
     const size_t lds = (size_t)(a.K + 15) / 16 * 16;
-    if (a.M <= 4) k_ext_walk<T, 4, L2, WRITE><<<(unsigned)njobs, kWave, lds, st>>>(a);
-    else k_ext_walk<T, 8, L2, WRITE><<<(unsigned)njobs, kWave, lds, st>>>(a);
+    const unsigned g = (unsigned)njobs;
+    switch (a.M) {
+        case 1: k_ext_walk<T, 1, WRITE><<<g, kWave, lds, st>>>(a); break;
+        case 2: k_ext_walk<T, 2, WRITE><<<g, kWave, lds, st>>>(a); break;
+        case 3: k_ext_walk<T, 3, WRITE><<<g, kWave, lds, st>>>(a); break;
+        case 4: k_ext_walk<T, 4, WRITE><<<g, kWave, lds, st>>>(a); break;
+        default: k_ext_walk<T, 8, WRITE><<<g, kWave, lds, st>>>(a); break;
+    }
     return hipGetLastError();
 }
 
@@ -382,53 +418,144 @@ __global__ void k_walk_prep(const int32_t *__restrict__ types, const T *__restri
     wend[i] = (int32_t)lo;
 }
 
-// Frequent selection (count > threshold), order preserving: per-block flag
-// counts, then each block writes its indices at its scanned offset.
-constexpr int kSelBlock = 256;
-constexpr int kSelItems = 8;
+// ---- device-side bookkeeping of the levels ----------------------------------
 
-__global__ __launch_bounds__(kSelBlock) void k_sel_count(const int32_t *__restrict__ counts, int64_t m, int32_t thr,
-                                                         int32_t *__restrict__ bcnt) {
-    __shared__ int32_t red[kSelBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kSelBlock * kSelItems;
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+// Block-wide exclusive scan of one int64 per thread.
+__device__ __forceinline__ int64_t block_scan64(int64_t v, int64_t *total) {
+    __shared__ int64_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int64_t x = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+    for (int k = 0; k < kBlock / kWave; ++k) {
+        if (k < w) off += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// Exclusive scan of in[len] into int64 out[len + 1] (out[len] = total), in
+// three passes: tile sums, a one-block scan of the tile sums, tile scans.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const V *__restrict__ in, int64_t len,
+                                                       int64_t *__restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        if (i < len) acc += (int64_t)in[i];
+    }
+    int64_t tot;
+    (void)block_scan64(acc, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums64(int64_t *__restrict__ sums, int64_t nb) {
+    int64_t carry = 0;
+    for (int64_t r = 0; r < nb; r += kBlock) {
+        const int64_t i = r + threadIdx.x;
+        const int64_t v = i < nb ? sums[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_scan64(v, &tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_scan_apply64(const V *__restrict__ in, int64_t len,
+                                                         const int64_t *__restrict__ sums, int64_t nb,
+                                                         int64_t *__restrict__ out) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t v[kScanItems];
+    int64_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        v[k] = i < len ? (int64_t)in[i] : 0;
+        acc += v[k];
+    }
+    int64_t tot;
+    int64_t run = block_scan64(acc, &tot) + sums[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        if (i < len) out[i] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = sums[nb];
+}
+
+// out[len + 1] = exclusive scan of in[len]; the total is left in out[len].
+template <typename V>
+hipError_t scan64(const V *in, int64_t len, int64_t *out, DevBuf &tmp, hipStream_t st) {
+    const int64_t nb = len > 0 ? (len + kScanTile - 1) / kScanTile : 1;
+    hipError_t e;
+    if ((e = tmp.alloc(sizeof(int64_t) * (nb + 1))) != hipSuccess) return e;
+    k_scan_tiles<V><<<(unsigned)nb, kBlock, 0, st>>>(in, len, tmp.as<int64_t>());
+    k_scan_sums64<<<1, kBlock, 0, st>>>(tmp.as<int64_t>(), nb);
+    k_scan_apply64<V><<<(unsigned)nb, kBlock, 0, st>>>(in, len, tmp.as<int64_t>(), nb, out);
+    return hipGetLastError();
+}
+
+// Frequent selection (count > threshold), order preserving: per-block flag
+// counts, their scan, then each block writes its candidates at its offset.
+constexpr int kSelItems = 8;
+constexpr int kSelTile = kBlock * kSelItems;
+
+__global__ __launch_bounds__(kBlock) void k_sel_count(const int32_t *__restrict__ counts, int64_t m, int32_t thr,
+                                                      int32_t *__restrict__ bcnt) {
+    __shared__ int32_t red[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kSelTile;
     int32_t c = 0;
     for (int k = 0; k < kSelItems; ++k) {
-        const int64_t i = base + (int64_t)k * kSelBlock + threadIdx.x;
+        const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
         if (i < m && counts[i] > thr) ++c;
     }
-    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, kWave);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t t = 0;
-        for (int w = 0; w < kSelBlock / 64; ++w) t += red[w];
+        for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
         bcnt[blockIdx.x] = t;
     }
 }
 
-__global__ __launch_bounds__(kSelBlock) void k_sel_write(const int32_t *__restrict__ counts,
-                                                         const int32_t *__restrict__ nvalid, int64_t m, int32_t thr,
-                                                         const int64_t *__restrict__ boff, int64_t *__restrict__ idx,
-                                                         int32_t *__restrict__ nv) {
-    __shared__ int32_t wsum[kSelBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kSelBlock * kSelItems;
+__global__ __launch_bounds__(kBlock) void k_sel_write(const int32_t *__restrict__ counts,
+                                                      const int32_t *__restrict__ nvalid, int64_t m, int32_t thr,
+                                                      const int64_t *__restrict__ boff, int64_t *__restrict__ fcand,
+                                                      int32_t *__restrict__ fnv) {
+    __shared__ int32_t wsum[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kSelTile;
     int64_t off = boff[blockIdx.x];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int k = 0; k < kSelItems; ++k) {  // uniform
-        const int64_t i = base + (int64_t)k * kSelBlock + threadIdx.x;
+        const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
         const bool f = i < m && counts[i] > thr;
         const uint64_t bal = __ballot(f);
         if (lane == 0) wsum[w] = __popcll(bal);
         __syncthreads();
         int32_t before = 0, total = 0;
-        for (int q = 0; q < kSelBlock / 64; ++q) {
+        for (int q = 0; q < kBlock / kWave; ++q) {
             if (q < w) before += wsum[q];
             total += wsum[q];
         }
         if (f) {
             const int64_t o = off + before + __popcll(bal & ((1ull << lane) - 1ull));
-            idx[o] = i;
-            nv[o] = nvalid[i];
+            fcand[o] = i;
+            fnv[o] = nvalid[i];
         }
         off += total;
         __syncthreads();
@@ -448,82 +575,177 @@ __global__ __launch_bounds__(kWave) void k_level1(const T *__restrict__ ts, cons
     if (lane == 0) counts[k] = c;
 }
 
-template <typename U>
-hipError_t upload(DevBuf &d, const std::vector<U> &h, hipStream_t st) {
-    hipError_t e = d.alloc(sizeof(U) * h.size());
-    if (e != hipSuccess) return e;
-    if (!h.empty()) e = hipMemcpyAsync(d.p, h.data(), sizeof(U) * h.size(), hipMemcpyHostToDevice, st);
+// Apriori join on the device.  Every frequent episode of level N-1 >= 2
+// records its prefix parent fpar (the episode of level N-2 it extends) and its
+// suffix parent fsuf (the frequent episode of level N-2 equal to its last N-2
+// nodes: the join took its last node from it).  The candidates of level N
+// are alpha + last(beta) for frequent alpha, beta of level N-1 with
+// fpar[beta] == fsuf[alpha] and a new type other than alpha's first.  The
+// frequent list is in candidate order, hence sorted by fpar and, within one
+// parent, by (last type, interval): the betas of one parent are a contiguous
+// bucket, sorted by last type.
+//
+// Bucket offsets: boff[p] = first f with fpar[f] >= p, p = 0..np.
+__global__ __launch_bounds__(kBlock) void k_bucket_off(const int32_t *__restrict__ fpar, int64_t nf, int64_t np,
+                                                       int32_t *__restrict__ boff) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f > nf) return;
+    const int64_t prev = f == 0 ? -1 : fpar[f - 1];
+    const int64_t cur = f == nf ? np : fpar[f];
+    for (int64_t p = prev + 1; p <= cur; ++p) boff[p] = (int32_t)f;
+}
+
+// Per alpha: its bucket [rlo, rhi) of betas, the run [xlo, xhi) of betas whose
+// last type is alpha's first type (excluded), and its number of candidates.
+__global__ __launch_bounds__(kBlock) void k_join(const int32_t *__restrict__ fsuf, const uint16_t *__restrict__ ffirst,
+                                                 const uint16_t *__restrict__ flast, const int32_t *__restrict__ boff,
+                                                 int64_t nA, int32_t *__restrict__ rlo, int32_t *__restrict__ xlo,
+                                                 int32_t *__restrict__ xhi, int64_t *__restrict__ cnt) {
+    const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nA) return;
+    const int32_t p = fsuf[a];
+    const int32_t lo = boff[p], hi = boff[p + 1];
+    const uint16_t first = ffirst[a];
+    int32_t l = lo, h = hi;
+    while (l < h) {
+        const int32_t mid = (l + h) >> 1;
+        if (flast[mid] < first) l = mid + 1;
+        else h = mid;
+    }
+    const int32_t xl = l;
+    h = hi;
+    while (l < h) {
+        const int32_t mid = (l + h) >> 1;
+        if (flast[mid] <= first) l = mid + 1;
+        else h = mid;
+    }
+    rlo[a] = lo;
+    xlo[a] = xl;
+    xhi[a] = l;
+    cnt[a] = (int64_t)(hi - lo) - (l - xl);
+}
+
+// Fields of each frequent episode of level N from its candidate index.
+struct FreqArgs {
+    int64_t nf;
+    const int64_t *fcand;
+    bool level2;
+    int64_t per;                 // level 2: candidates per alpha ((nf1 - 1) * M)
+    int32_t M;
+    const int64_t *out_off;      // level >= 3: [nA + 1]
+    int64_t nA;
+    const int32_t *rlo, *xlo, *xhi;
+    const uint16_t *pflast;      // level N-1: last type (level 1: the type)
+    const uint8_t *pfliv;        // level N-1: last interval id
+    const uint16_t *pffirst;     // level N-1: first type
+    int32_t *fpar, *fsuf;
+    uint16_t *flast, *ffirst;
+    uint8_t *fliv;
+};
+
+__global__ __launch_bounds__(kBlock) void k_freq_fields(FreqArgs a) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= a.nf) return;
+    const int64_t c = a.fcand[f];
+    int64_t alpha, beta;
+    uint16_t B;
+    uint8_t iv;
+    if (a.level2) {
+        alpha = c / a.per;
+        const int64_t r = c - alpha * a.per;
+        const int64_t bi0 = r / a.M;
+        iv = (uint8_t)(r - bi0 * a.M);
+        beta = bi0 >= alpha ? bi0 + 1 : bi0;
+        B = a.pflast[beta];
+    } else {
+        int64_t l = 0, h = a.nA;  // last alpha with out_off[alpha] <= c
+        while (h - l > 1) {
+            const int64_t mid = (l + h) >> 1;
+            if (a.out_off[mid] <= c) l = mid;
+            else h = mid;
+        }
+        alpha = l;
+        int64_t rr = a.rlo[alpha] + (c - a.out_off[alpha]);
+        if (rr >= a.xlo[alpha]) rr += a.xhi[alpha] - a.xlo[alpha];
+        beta = rr;
+        B = a.pflast[beta];
+        iv = a.pfliv[beta];
+    }
+    a.fpar[f] = (int32_t)alpha;
+    a.fsuf[f] = (int32_t)beta;
+    a.flast[f] = B;
+    a.fliv[f] = iv;
+    a.ffirst[f] = a.pffirst[alpha];
+}
+
+// Write jobs: the alphas with frequent extensions (runs of equal fpar).
+__global__ __launch_bounds__(kBlock) void k_job_flags(const int32_t *__restrict__ fpar, int64_t nf,
+                                                      int32_t *__restrict__ flag) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f < nf) flag[f] = (f == 0 || fpar[f] != fpar[f - 1]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_job_write(const int32_t *__restrict__ fpar, const int32_t *__restrict__ flag,
+                                                      const int64_t *__restrict__ jidx, int64_t nf,
+                                                      int32_t *__restrict__ job_alpha, int64_t *__restrict__ job_f) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f > nf) return;
+    if (f == nf) {
+        job_f[jidx[nf]] = nf;
+        return;
+    }
+    if (flag[f]) {
+        job_alpha[jidx[f]] = fpar[f];
+        job_f[jidx[f]] = f;
+    }
+}
+
+// Jobs grouped by a uint16 key (the alphas' last type): counting sort with
+// atomics (the order inside a key is irrelevant).
+__global__ __launch_bounds__(kBlock) void k_key_hist(const uint16_t *__restrict__ key, const int32_t *__restrict__ idx,
+                                                     int64_t n, int32_t *__restrict__ hist) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < n) atomicAdd(&hist[key[idx ? idx[j] : j]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_key_scatter(const uint16_t *__restrict__ key,
+                                                        const int32_t *__restrict__ idx, int64_t n,
+                                                        int64_t *__restrict__ cursor, int32_t *__restrict__ order) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < n) {
+        const unsigned long long o = atomicAdd((unsigned long long *)&cursor[key[idx ? idx[j] : j]], 1ull);
+        order[o] = (int32_t)j;
+    }
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename V>
+hipError_t read_scalar(const DevBuf &b, int64_t at, V *out, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(out, b.as<V>() + at, sizeof(V), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e;
 }
 
-int nthreads() { return (int)std::max<unsigned>(1, std::min<unsigned>(32, std::thread::hardware_concurrency())); }
-
-template <typename F>
-void parallel_for(int64_t n, F &&body) {
-    const int nt = nthreads();
-    if (n < 4096 || nt == 1) {
-        body(0, n);
-        return;
-    }
-    std::vector<std::thread> th;
-    const int64_t chunk = (n + nt - 1) / nt;
-    for (int q = 0; q < nt; ++q) {
-        const int64_t x0 = q * chunk, x1 = std::min(n, x0 + chunk);
-        if (x0 >= x1) break;
-        th.emplace_back([&, x0, x1] { body(x0, x1); });
-    }
-    for (auto &t : th) t.join();
-}
-
-// Indices 0..n-1 stably ordered by key(i) in [0, K) (counting sort).
-template <typename F>
-std::vector<int32_t> order_by_key(int64_t n, int32_t K, F &&key) {
-    std::vector<int64_t> start(K + 1, 0);
-    for (int64_t i = 0; i < n; ++i) ++start[key(i) + 1];
-    for (int32_t k = 0; k < K; ++k) start[k + 1] += start[k];
-    std::vector<int32_t> out(n);
-    for (int64_t i = 0; i < n; ++i) out[start[key(i)]++] = (int32_t)i;
-    return out;
-}
-
-// local extension index e of alpha (level >= 3) -> position r in byprefix
-// (the excluded extensions, those repeating alpha's first type, are the
-// contiguous range [xlo, xhi) of alpha's range)
-int32_t ext_position(const MineLevel &L, int64_t alpha, int64_t e) {
-    const int64_t r = L.rlo[alpha] + e;
-    return (int32_t)(r < L.xlo[alpha] ? r : r + (L.xhi[alpha] - L.xlo[alpha]));
-}
-
-// Sort with a strict weak order on nt threads: sorted chunks, then merged
-// pairwise in rounds.
-template <typename It, typename Less>
-void parallel_sort(It first, It last, Less less) {
-    const int64_t n = last - first;
-    const int nt = nthreads();
-    if (n < 65536 || nt == 1) {
-        std::sort(first, last, less);
-        return;
-    }
-    std::vector<int64_t> cut(nt + 1);
-    for (int q = 0; q <= nt; ++q) cut[q] = n * q / nt;
-    {
-        std::vector<std::thread> th;
-        for (int q = 0; q < nt; ++q) th.emplace_back([&, q] { std::sort(first + cut[q], first + cut[q + 1], less); });
-        for (auto &t : th) t.join();
-    }
-    for (int width = 1; width < nt; width *= 2) {
-        std::vector<std::thread> th;
-        for (int q = 0; q + width < nt; q += 2 * width) {
-            const int64_t a = cut[q], b = cut[q + width], c = cut[std::min(nt, q + 2 * width)];
-            th.emplace_back([=] { std::inplace_merge(first + a, first + b, first + c, less); });
-        }
-        for (auto &t : th) t.join();
-    }
+// jobs j = 0..n-1 ordered by key[idx[j]] (idx null: key[j])
+hipError_t order_by_key(const uint16_t *key, const int32_t *idx, int64_t n, int32_t K, DevBuf &order,
+                        hipStream_t st) {
+    hipError_t e;
+    DevBuf hist, cursor, tmp;
+    if ((e = order.alloc(sizeof(int32_t) * std::max<int64_t>(1, n))) != hipSuccess) return e;
+    if ((e = hist.alloc(sizeof(int32_t) * K)) != hipSuccess) return e;
+    if ((e = cursor.alloc(sizeof(int64_t) * (K + 1))) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(hist.p, 0, sizeof(int32_t) * K, st)) != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    k_key_hist<<<grid_of(n), kBlock, 0, st>>>(key, idx, n, hist.as<int32_t>());
+    if ((e = scan64(hist.as<int32_t>(), K, cursor.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+    k_key_scatter<<<grid_of(n), kBlock, 0, st>>>(key, idx, n, cursor.as<int64_t>(), order.as<int32_t>());
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipStreamSynchronize(st);  // the temporaries die here
 }
 
 template <typename T>
-hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st) {
-    (void)d_flags;
+hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     hipError_t e;
     MineLevel &P = mn.levels.back();  // level N-1
     MineLevel L;
@@ -531,65 +753,35 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     L.implicit = true;
     const int M = (int)mn.menu_lo.size();
     auto t0 = Clock::now();
-    // ---- the candidate family of each alpha
-    int64_t nA = P.nf;
-    L.out_off.assign(nA + 1, 0);
+    const int64_t nA = P.nf;
+    L.nA = nA;
+    // ---- the candidates: alpha-major, alpha's extensions in (type, interval) order
+    int64_t m;
+    DevBuf d_order, tmp;
     if (N == 2) {
-        for (int64_t a = 0; a < nA; ++a) L.out_off[a + 1] = L.out_off[a] + (nA - 1) * M;
+        m = nA * (nA - 1) * M;
     } else {
-        const int Pn = P.N;  // episodes of the previous level have Pn = N-1 nodes
-        auto pty = [&](int64_t i, int k) { return P.ftypes[(size_t)k * P.nf + i]; };
-        auto piv = [&](int64_t i, int k) { return P.fiv[(size_t)k * P.nf + i]; };
-        L.byprefix.resize(P.nf);
-        std::iota(L.byprefix.begin(), L.byprefix.end(), 0);
-        // prefix of beta = its first Pn-1 nodes and Pn-2 intervals; within a
-        // prefix, by the last node (type, then interval)
-        auto prefix_less = [&](int32_t a, int32_t b) {
-            for (int k = 0; k < Pn - 1; ++k) {
-                if (pty(a, k) != pty(b, k)) return pty(a, k) < pty(b, k);
-                if (k < Pn - 2 && piv(a, k) != piv(b, k)) return piv(a, k) < piv(b, k);
-            }
-            if (pty(a, Pn - 1) != pty(b, Pn - 1)) return pty(a, Pn - 1) < pty(b, Pn - 1);
-            return piv(a, Pn - 2) < piv(b, Pn - 2);
-        };
-        parallel_sort(L.byprefix.begin(), L.byprefix.end(), prefix_less);
-        // compare prefix(beta) with suffix(alpha) = last Pn-1 nodes of alpha
-        auto cmp = [&](int32_t beta, int64_t alpha) {
-            for (int k = 0; k < Pn - 1; ++k) {
-                if (pty(beta, k) != pty(alpha, k + 1)) return pty(beta, k) < pty(alpha, k + 1) ? -1 : 1;
-                if (k < Pn - 2 && piv(beta, k) != piv(alpha, k + 1)) return piv(beta, k) < piv(alpha, k + 1) ? -1 : 1;
-            }
-            return 0;
-        };
-        L.rlo.resize(nA);
-        L.rhi.resize(nA);
-        L.xlo.resize(nA);
-        L.xhi.resize(nA);
-        std::vector<int64_t> cnt(nA, 0);
-        parallel_for(nA, [&](int64_t x0, int64_t x1) {
-            for (int64_t a = x0; a < x1; ++a) {
-                const auto lo = std::partition_point(L.byprefix.begin(), L.byprefix.end(),
-                                                     [&](int32_t b) { return cmp(b, a) < 0; });
-                const auto hi =
-                    std::partition_point(lo, L.byprefix.end(), [&](int32_t b) { return cmp(b, a) == 0; });
-                L.rlo[a] = (int32_t)(lo - L.byprefix.begin());
-                L.rhi[a] = (int32_t)(hi - L.byprefix.begin());
-                // extensions whose new type is alpha's first: one run in the range
-                const uint16_t first = pty(a, 0);
-                const auto xl = std::partition_point(lo, hi, [&](int32_t b) { return pty(b, Pn - 1) < first; });
-                const auto xh = std::partition_point(xl, hi, [&](int32_t b) { return pty(b, Pn - 1) == first; });
-                L.xlo[a] = (int32_t)(xl - L.byprefix.begin());
-                L.xhi[a] = (int32_t)(xh - L.byprefix.begin());
-                cnt[a] = (hi - lo) - (xh - xl);
-            }
-        });
-        for (int64_t a = 0; a < nA; ++a) L.out_off[a + 1] = L.out_off[a] + cnt[a];
+        const MineLevel &PP = mn.levels[mn.levels.size() - 2];  // level N-2
+        DevBuf boff, cnt;
+        if ((e = boff.alloc(sizeof(int32_t) * (PP.nf + 1))) != hipSuccess) return e;
+        if ((e = cnt.alloc(sizeof(int64_t) * std::max<int64_t>(1, nA))) != hipSuccess) return e;
+        if ((e = L.d_rlo.alloc(sizeof(int32_t) * nA)) != hipSuccess) return e;
+        if ((e = L.d_xlo.alloc(sizeof(int32_t) * nA)) != hipSuccess) return e;
+        if ((e = L.d_xhi.alloc(sizeof(int32_t) * nA)) != hipSuccess) return e;
+        if ((e = L.d_out_off.alloc(sizeof(int64_t) * (nA + 1))) != hipSuccess) return e;
+        k_bucket_off<<<grid_of(nA + 1), kBlock, 0, st>>>(P.d_fpar.as<int32_t>(), nA, PP.nf, boff.as<int32_t>());
+        k_join<<<grid_of(nA), kBlock, 0, st>>>(P.d_fsuf.as<int32_t>(), P.d_ffirst.as<uint16_t>(),
+                                               P.d_flast.as<uint16_t>(), boff.as<int32_t>(), nA,
+                                               L.d_rlo.as<int32_t>(), L.d_xlo.as<int32_t>(), L.d_xhi.as<int32_t>(),
+                                               cnt.as<int64_t>());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan64(cnt.as<int64_t>(), nA, L.d_out_off.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+        if ((e = read_scalar(L.d_out_off, nA, &m, st)) != hipSuccess) return e;
+        // workgroups take the alphas grouped by their last type: the waves in
+        // flight then walk the neighbourhoods of the same type's events
+        if ((e = order_by_key(P.d_flast.as<uint16_t>(), nullptr, nA, s.K, d_order, st)) != hipSuccess) return e;
     }
-    const int64_t m = L.out_off[nA];
     L.m = m;
-    // ---- device inputs
-    DevBuf d_out_off, d_f1, d_rlo, d_rhi, d_xlo, d_xhi, d_by, d_fl, d_fliv, d_counts, d_nval, d_order, d_walked;
-    if ((e = upload(d_out_off, L.out_off, st)) != hipSuccess) return e;
     WalkArgs<T> a{};
     a.ty16 = mn.ty16.as<uint16_t>();
     a.times = s.times.as<T>();
@@ -598,54 +790,34 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     a.ts_by_type = s.ts_by_type.as<T>();
     a.pos_by_type = s.pos_by_type.as<int32_t>();
     a.type_off = s.type_off.as<int32_t>();
-    a.out_off = d_out_off.as<int64_t>();
     a.M = M;
     a.K = s.K;
+    a.level2 = N == 2;
     for (int i = 0; i < M; ++i) {
         a.menu_lo[i] = (T)mn.menu_lo[i];
         a.menu_hi[i] = (T)mn.menu_hi[i];
     }
-    // host sources of asynchronous uploads live until the level's last sync
-    std::vector<uint16_t> f1, fl;
-    std::vector<uint8_t> fliv;
-    std::vector<int32_t> order;
-    if (N == 2) {
-        f1.assign(P.ftypes.begin(), P.ftypes.begin() + P.nf);
-        if ((e = upload(d_f1, f1, st)) != hipSuccess) return e;
-        a.f1 = d_f1.as<uint16_t>();
-        a.nf1 = (int32_t)P.nf;
-    } else {
-        fl.assign(P.ftypes.begin() + (size_t)(P.N - 1) * P.nf, P.ftypes.begin() + (size_t)P.N * P.nf);
-        fliv.assign(P.fiv.begin() + (size_t)(P.N - 2) * P.nf, P.fiv.begin() + (size_t)(P.N - 1) * P.nf);
-        if ((e = upload(d_fl, fl, st)) != hipSuccess) return e;
-        if ((e = upload(d_fliv, fliv, st)) != hipSuccess) return e;
-        if ((e = upload(d_rlo, L.rlo, st)) != hipSuccess) return e;
-        if ((e = upload(d_rhi, L.rhi, st)) != hipSuccess) return e;
-        if ((e = upload(d_xlo, L.xlo, st)) != hipSuccess) return e;
-        if ((e = upload(d_xhi, L.xhi, st)) != hipSuccess) return e;
-        if ((e = upload(d_by, L.byprefix, st)) != hipSuccess) return e;
+    a.f1 = P.d_flast.as<uint16_t>();  // level 2: the frequent types
+    a.nf1 = (int32_t)nA;
+    if (N > 2) {
         a.ct = P.ct.as<T>();
         a.cs = P.cs.as<T>();
         a.cp = P.cp.as<int32_t>();
         a.coff = P.chain_off.as<int64_t>();
-        a.flast = d_fl.as<uint16_t>();
-        a.fliv = d_fliv.as<uint8_t>();
-        a.rlo = d_rlo.as<int32_t>();
-        a.rhi = d_rhi.as<int32_t>();
-        a.xlo = d_xlo.as<int32_t>();
-        a.xhi = d_xhi.as<int32_t>();
-        a.byprefix = d_by.as<int32_t>();
-        // workgroups take the alphas grouped by their last type: the waves in
-        // flight then walk the neighbourhoods of the same type's events
-        order = order_by_key(nA, s.K, [&](int64_t x) { return (int32_t)fl[x]; });
-        if ((e = upload(d_order, order, st)) != hipSuccess) return e;
+        a.flast = P.d_flast.as<uint16_t>();
+        a.fliv = P.d_fliv.as<uint8_t>();
+        a.out_off = L.d_out_off.as<int64_t>();
+        a.rlo = L.d_rlo.as<int32_t>();
+        a.xlo = L.d_xlo.as<int32_t>();
+        a.xhi = L.d_xhi.as<int32_t>();
         a.order = d_order.as<int32_t>();
     }
-    if ((e = d_counts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    DevBuf d_nval, d_walked;
+    if ((e = L.dcounts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
     if ((e = d_nval.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
     if ((e = d_walked.alloc(sizeof(unsigned long long))) != hipSuccess) return e;
     if ((e = hipMemsetAsync(d_walked.p, 0, sizeof(unsigned long long), st)) != hipSuccess) return e;
-    a.counts = d_counts.as<int32_t>();
+    a.counts = L.dcounts.as<int32_t>();
     a.nvalid = d_nval.as<int32_t>();
     a.walked = d_walked.as<unsigned long long>();
     L.gen_ms = ms_since(t0);
@@ -655,7 +827,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
     (void)hipEventRecord(ev0, st);
-    if (m > 0) e = N == 2 ? launch_walk<T, true, false>(a, nA, st) : launch_walk<T, false, false>(a, nA, st);
+    if (m > 0) e = launch_walk<T, false>(a, nA, st);
     (void)hipEventRecord(ev1, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     float kms = 0;
@@ -666,133 +838,98 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream
     L.kernel_ms = kms;
     {
         unsigned long long wk = 0;
-        if ((e = hipMemcpy(&wk, d_walked.p, sizeof(wk), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+        if ((e = read_scalar(d_walked, 0, &wk, st)) != hipSuccess) return e;
         L.walked = (int64_t)wk;
     }
-    // ---- frequent episodes, selected on the device (counts stay there)
-    std::vector<int32_t> nval;
-    {
-        const int64_t per = (int64_t)kSelBlock * kSelItems;
-        const int64_t nb = m > 0 ? (m + per - 1) / per : 0;
-        DevBuf d_bcnt, d_boff;
-        if ((e = d_bcnt.alloc(sizeof(int32_t) * (nb + 1))) != hipSuccess) return e;
-        const int32_t thr = (int32_t)std::min<int64_t>(mn.threshold, INT32_MAX);
-        int64_t nf = 0;
-        std::vector<int64_t> boff(nb + 1, 0);
-        if (nb > 0) {
-            if (mn.threshold < 0) {
-                // every candidate is frequent
-                for (int64_t b = 0; b < nb; ++b) boff[b + 1] = boff[b] + std::min(per, m - b * per);
-            } else {
-                k_sel_count<<<(unsigned)nb, kSelBlock, 0, st>>>(a.counts, m, thr, d_bcnt.as<int32_t>());
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-                std::vector<int32_t> bc(nb);
-                if ((e = hipMemcpyAsync(bc.data(), d_bcnt.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st)) !=
-                    hipSuccess)
-                    return e;
-                if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-                for (int64_t b = 0; b < nb; ++b) boff[b + 1] = boff[b] + bc[b];
-            }
-            nf = boff[nb];
-        }
-        L.freq.assign(nf, 0);
-        nval.assign(nf, 0);
-        if (nf > 0) {
-            DevBuf d_idx, d_nv;
-            if ((e = upload(d_boff, boff, st)) != hipSuccess) return e;
-            if ((e = d_idx.alloc(sizeof(int64_t) * nf)) != hipSuccess) return e;
-            if ((e = d_nv.alloc(sizeof(int32_t) * nf)) != hipSuccess) return e;
-            k_sel_write<<<(unsigned)nb, kSelBlock, 0, st>>>(a.counts, a.nvalid, m, mn.threshold < 0 ? INT32_MIN : thr,
-                                                            d_boff.as<int64_t>(), d_idx.as<int64_t>(),
-                                                            d_nv.as<int32_t>());
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((e = hipMemcpyAsync(L.freq.data(), d_idx.p, sizeof(int64_t) * nf, hipMemcpyDeviceToHost, st)) !=
-                hipSuccess)
-                return e;
-            if ((e = hipMemcpyAsync(nval.data(), d_nv.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, st)) !=
-                hipSuccess)
-                return e;
-            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-        }
+    // ---- frequent episodes, selected on the device
+    const int64_t nb = m > 0 ? (m + kSelTile - 1) / kSelTile : 0;
+    int64_t nf = 0;
+    DevBuf bcnt, boffs;
+    if ((e = bcnt.alloc(sizeof(int32_t) * std::max<int64_t>(1, nb))) != hipSuccess) return e;
+    if ((e = boffs.alloc(sizeof(int64_t) * (nb + 1))) != hipSuccess) return e;
+    const int32_t thr = (int32_t)std::max<int64_t>(INT32_MIN, std::min<int64_t>(mn.threshold, INT32_MAX));
+    if (nb > 0) {
+        k_sel_count<<<(unsigned)nb, kBlock, 0, st>>>(a.counts, m, thr, bcnt.as<int32_t>());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan64(bcnt.as<int32_t>(), nb, boffs.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+        if ((e = read_scalar(boffs, nb, &nf, st)) != hipSuccess) return e;
     }
-    L.dcounts = std::move(d_counts);
-    const int64_t nf = (int64_t)L.freq.size();
     L.nf = nf;
-    L.ftypes.assign((size_t)N * nf, 0);
-    L.fiv.assign((size_t)(N - 1) * nf, 0);
-    std::vector<int32_t> w_alpha(nf);
-    std::vector<uint16_t> w_type(nf);
-    std::vector<uint8_t> w_iv(nf);
-    parallel_for(nf, [&](int64_t x0, int64_t x1) {
-        for (int64_t f = x0; f < x1; ++f) {
-            const int64_t c = L.freq[f];
-            const int64_t alpha = std::upper_bound(L.out_off.begin(), L.out_off.end(), c) - L.out_off.begin() - 1;
-            const int64_t le = c - L.out_off[alpha];
-            uint16_t bt;
-            uint8_t biv;
-            if (N == 2) {
-                int64_t r = le < alpha * M ? le : le + M;
-                bt = P.ftypes[r / M];
-                biv = (uint8_t)(r % M);
-            } else {
-                const int32_t r = ext_position(L, alpha, le);
-                const int32_t beta = L.byprefix[r];
-                bt = P.ftypes[(size_t)(P.N - 1) * P.nf + beta];
-                biv = P.fiv[(size_t)(P.N - 2) * P.nf + beta];
-            }
-            for (int k = 0; k < N - 1; ++k) L.ftypes[(size_t)k * nf + f] = P.ftypes[(size_t)k * P.nf + alpha];
-            L.ftypes[(size_t)(N - 1) * nf + f] = bt;
-            for (int k = 0; k < N - 2; ++k) L.fiv[(size_t)k * nf + f] = P.fiv[(size_t)k * P.nf + alpha];
-            L.fiv[(size_t)(N - 2) * nf + f] = biv;
-            w_alpha[f] = (int32_t)alpha;
-            w_type[f] = bt;
-            w_iv[f] = biv;
+    const size_t nfa = (size_t)std::max<int64_t>(1, nf);
+    if ((e = L.d_fcand.alloc(sizeof(int64_t) * nfa)) != hipSuccess) return e;
+    if ((e = L.d_fnv.alloc(sizeof(int32_t) * nfa)) != hipSuccess) return e;
+    if ((e = L.d_fpar.alloc(sizeof(int32_t) * nfa)) != hipSuccess) return e;
+    if ((e = L.d_fsuf.alloc(sizeof(int32_t) * nfa)) != hipSuccess) return e;
+    if ((e = L.d_flast.alloc(sizeof(uint16_t) * nfa)) != hipSuccess) return e;
+    if ((e = L.d_ffirst.alloc(sizeof(uint16_t) * nfa)) != hipSuccess) return e;
+    if ((e = L.d_fliv.alloc(nfa)) != hipSuccess) return e;
+    if ((e = L.chain_off.alloc(sizeof(int64_t) * (nf + 1))) != hipSuccess) return e;
+    L.chain_total = 0;
+    if (nf > 0) {
+        k_sel_write<<<(unsigned)nb, kBlock, 0, st>>>(a.counts, a.nvalid, m, thr, boffs.as<int64_t>(),
+                                                    L.d_fcand.as<int64_t>(), L.d_fnv.as<int32_t>());
+        FreqArgs fa{};
+        fa.nf = nf;
+        fa.fcand = L.d_fcand.as<int64_t>();
+        fa.level2 = N == 2;
+        fa.per = (nA - 1) * M;
+        fa.M = M;
+        fa.out_off = L.d_out_off.as<int64_t>();
+        fa.nA = nA;
+        fa.rlo = L.d_rlo.as<int32_t>();
+        fa.xlo = L.d_xlo.as<int32_t>();
+        fa.xhi = L.d_xhi.as<int32_t>();
+        fa.pflast = P.d_flast.as<uint16_t>();
+        fa.pfliv = P.d_fliv.as<uint8_t>();
+        fa.pffirst = P.d_ffirst.as<uint16_t>();
+        fa.fpar = L.d_fpar.as<int32_t>();
+        fa.fsuf = L.d_fsuf.as<int32_t>();
+        fa.flast = L.d_flast.as<uint16_t>();
+        fa.ffirst = L.d_ffirst.as<uint16_t>();
+        fa.fliv = L.d_fliv.as<uint8_t>();
+        k_freq_fields<<<grid_of(nf), kBlock, 0, st>>>(fa);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // chain lists: offsets from the scan of the end-event counts
+        DevBuf tmp2, flag, jidx, job_alpha, job_f, w_order;
+        if ((e = scan64(L.d_fnv.as<int32_t>(), nf, L.chain_off.as<int64_t>(), tmp2, st)) != hipSuccess) return e;
+        // write jobs: the alphas with frequent extensions
+        if ((e = flag.alloc(sizeof(int32_t) * nf)) != hipSuccess) return e;
+        if ((e = jidx.alloc(sizeof(int64_t) * (nf + 1))) != hipSuccess) return e;
+        k_job_flags<<<grid_of(nf), kBlock, 0, st>>>(L.d_fpar.as<int32_t>(), nf, flag.as<int32_t>());
+        if ((e = scan64(flag.as<int32_t>(), nf, jidx.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+        int64_t nj = 0;
+        if ((e = read_scalar(jidx, nf, &nj, st)) != hipSuccess) return e;
+        if ((e = read_scalar(L.chain_off, nf, &L.chain_total, st)) != hipSuccess) return e;
+        if ((e = job_alpha.alloc(sizeof(int32_t) * nj)) != hipSuccess) return e;
+        if ((e = job_f.alloc(sizeof(int64_t) * (nj + 1))) != hipSuccess) return e;
+        k_job_write<<<grid_of(nf + 1), kBlock, 0, st>>>(L.d_fpar.as<int32_t>(), flag.as<int32_t>(),
+                                                       jidx.as<int64_t>(), nf, job_alpha.as<int32_t>(),
+                                                       job_f.as<int64_t>());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (N > 2) {
+            if ((e = order_by_key(P.d_flast.as<uint16_t>(), job_alpha.as<int32_t>(), nj, s.K, w_order, st)) !=
+                hipSuccess)
+                return e;
         }
-    });
-    L.h_chain_off.assign(nf + 1, 0);
-    for (int64_t f = 0; f < nf; ++f) L.h_chain_off[f + 1] = L.h_chain_off[f] + nval[f];
-    // write jobs: the alphas with frequent extensions (the frequent list is in
-    // candidate order, so each alpha's frequent extensions are contiguous)
-    std::vector<int32_t> job_alpha;
-    std::vector<int64_t> job_f;
-    for (int64_t f = 0; f < nf; ++f) {
-        if (f == 0 || w_alpha[f] != w_alpha[f - 1]) {
-            job_alpha.push_back(w_alpha[f]);
-            job_f.push_back(f);
-        }
-    }
-    job_f.push_back(nf);
-    const int64_t nj = (int64_t)job_alpha.size();
-    // taken grouped by alpha's last type, as the counting pass takes them
-    std::vector<int32_t> w_order = order_by_key(nj, s.K, [&](int64_t j) {
-        const int64_t al = job_alpha[j];
-        return (int32_t)(N == 2 ? P.ftypes[al] : P.ftypes[(size_t)(P.N - 1) * P.nf + al]);
-    });
-    DevBuf d_ja, d_jf, d_wt, d_wi, d_wo;
-    if ((e = upload(d_ja, job_alpha, st)) != hipSuccess) return e;
-    if ((e = upload(d_jf, job_f, st)) != hipSuccess) return e;
-    if ((e = upload(d_wo, w_order, st)) != hipSuccess) return e;
-    if ((e = upload(d_wt, w_type, st)) != hipSuccess) return e;
-    if ((e = upload(d_wi, w_iv, st)) != hipSuccess) return e;
-    if ((e = upload(L.chain_off, L.h_chain_off, st)) != hipSuccess) return e;
-    const size_t tot = (size_t)L.h_chain_off[nf];
-    if ((e = L.ct.alloc(sizeof(T) * tot)) != hipSuccess) return e;
-    if ((e = L.cs.alloc(sizeof(T) * tot)) != hipSuccess) return e;
-    if ((e = L.cp.alloc(sizeof(int32_t) * tot)) != hipSuccess) return e;
-    if (nj > 0) {
-        a.job_alpha = d_ja.as<int32_t>();
-        a.job_f = d_jf.as<int64_t>();
-        a.order = d_wo.as<int32_t>();
-        a.w_type = d_wt.as<uint16_t>();
-        a.w_iv = d_wi.as<uint8_t>();
+        const size_t tot = (size_t)L.chain_total;
+        if ((e = L.ct.alloc(sizeof(T) * tot)) != hipSuccess) return e;
+        if ((e = L.cs.alloc(sizeof(T) * tot)) != hipSuccess) return e;
+        if ((e = L.cp.alloc(sizeof(int32_t) * tot)) != hipSuccess) return e;
+        a.job_alpha = job_alpha.as<int32_t>();
+        a.job_f = job_f.as<int64_t>();
+        a.order = N > 2 ? w_order.as<int32_t>() : nullptr;
+        a.w_type = L.d_flast.as<uint16_t>();
+        a.w_iv = L.d_fliv.as<uint8_t>();
         a.w_off = L.chain_off.as<int64_t>();
         a.wct = L.ct.as<T>();
         a.wcs = L.cs.as<T>();
         a.wcp = L.cp.as<int32_t>();
-        e = N == 2 ? launch_walk<T, true, true>(a, nj, st) : launch_walk<T, false, true>(a, nj, st);
-        if (e != hipSuccess) return e;
+        if ((e = launch_walk<T, true>(a, nj, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;  // the job buffers die here
+    } else {
+        if ((e = hipMemsetAsync(L.chain_off.p, 0, sizeof(int64_t), st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     }
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     L.count_ms = ms_since(t1);
     // chain lists two levels back are no longer needed
     if (mn.levels.size() >= 2) {
@@ -814,25 +951,61 @@ hipError_t level1_t(const Stream &s, Mine &mn, hipStream_t st) {
     L.m = s.K;
     L.implicit = false;
     auto t1 = Clock::now();
-    DevBuf d_counts;
-    if ((e = d_counts.alloc(sizeof(int32_t) * s.K)) != hipSuccess) return e;
-    k_level1<T><<<s.K, kWave, 0, st>>>(s.ts_by_type.as<T>(), s.type_off.as<int32_t>(), d_counts.as<int32_t>());
+    if ((e = L.dcounts.alloc(sizeof(int32_t) * s.K)) != hipSuccess) return e;
+    k_level1<T><<<s.K, kWave, 0, st>>>(s.ts_by_type.as<T>(), s.type_off.as<int32_t>(), L.dcounts.as<int32_t>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
     L.counts.resize(s.K);
-    if ((e = hipMemcpyAsync(L.counts.data(), d_counts.p, sizeof(int32_t) * s.K, hipMemcpyDeviceToHost, st)) !=
+    if ((e = hipMemcpyAsync(L.counts.data(), L.dcounts.p, sizeof(int32_t) * s.K, hipMemcpyDeviceToHost, st)) !=
         hipSuccess)
         return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    L.count_ms = ms_since(t1);
     L.types.resize(s.K);
     for (int32_t k = 0; k < s.K; ++k) L.types[k] = (uint16_t)k;
-    for (int32_t k = 0; k < s.K; ++k)
-        if (L.counts[k] > mn.threshold) L.freq.push_back(k);
+    std::vector<uint16_t> f1;
+    for (int32_t k = 0; k < s.K; ++k) {
+        if (L.counts[k] > mn.threshold) {
+            L.freq.push_back(k);
+            f1.push_back((uint16_t)k);
+        }
+    }
     L.nf = (int64_t)L.freq.size();
-    for (int64_t f : L.freq) L.ftypes.push_back((uint16_t)f);
+    // a 1-node episode's first and last node is its type
+    if ((e = L.d_flast.alloc(sizeof(uint16_t) * std::max<size_t>(1, f1.size()))) != hipSuccess) return e;
+    if ((e = L.d_ffirst.alloc(sizeof(uint16_t) * std::max<size_t>(1, f1.size()))) != hipSuccess) return e;
+    if (!f1.empty()) {
+        if ((e = hipMemcpyAsync(L.d_flast.p, f1.data(), sizeof(uint16_t) * f1.size(), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(L.d_ffirst.p, f1.data(), sizeof(uint16_t) * f1.size(), hipMemcpyHostToDevice,
+                                st)) != hipSuccess)
+            return e;
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    L.count_ms = ms_since(t1);
     L.alg_bytes = s.n * (int64_t)s.ts_bytes() + 4 * (int64_t)s.K;
     mn.levels.push_back(std::move(L));
     return hipSuccess;
+}
+
+template <typename V>
+hipError_t to_host(const DevBuf &d, int64_t n, std::vector<V> &h) {
+    h.resize((size_t)std::max<int64_t>(0, n));
+    if (n <= 0) return hipSuccess;
+    return hipMemcpy(h.data(), d.p, sizeof(V) * (size_t)n, hipMemcpyDeviceToHost);
+}
+
+// Types and interval ids of frequent episode f of a level (host copies).
+void frequent_nodes(const Mine &mn, int level, int64_t f, int32_t *types, int *ivs) {
+    for (int L = level; L >= 1; --L) {
+        const MineLevel &V = mn.levels[L - 1];
+        if (L == 1) {
+            types[0] = (int32_t)V.freq[f];
+            break;
+        }
+        types[L - 1] = V.h_flast[f];
+        ivs[L - 2] = V.h_fliv[f];
+        f = V.h_fpar[f];
+    }
 }
 
 }  // namespace
@@ -842,9 +1015,9 @@ hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st) {
     return level1_t<int32_t>(s, mn, st);
 }
 
-hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st) {
-    if (s.ts_kind == EPI_TS_I64) return level_t<int64_t>(s, mn, N, d_flags, st);
-    return level_t<int32_t>(s, mn, N, d_flags, st);
+hipError_t extend_level(const Stream &s, Mine &mn, int N, hipStream_t st) {
+    if (s.ts_kind == EPI_TS_I64) return level_t<int64_t>(s, mn, N, st);
+    return level_t<int32_t>(s, mn, N, st);
 }
 
 // Bytes the window walk of a level must read and write: the stream positions
@@ -858,9 +1031,9 @@ int64_t extend_level_bytes(const Stream &s, Mine &mn, int level) {
     const int64_t tsb = s.ts_bytes();
     int64_t entries = 0;
     if (L.N == 2) {
-        for (int64_t a = 0; a < P.nf; ++a) entries += s.h_off[P.ftypes[a] + 1] - s.h_off[P.ftypes[a]];
+        for (int64_t f : P.freq) entries += s.h_off[f + 1] - s.h_off[f];
     } else {
-        entries = P.h_chain_off.empty() ? 0 : P.h_chain_off.back();
+        entries = P.chain_total;
     }
     L.alg_bytes = L.walked * (2 + tsb) + entries * (2 * tsb + 8) + L.m * 8;
     return L.alg_bytes;
@@ -882,25 +1055,55 @@ hipError_t extend_prepare(const Stream &s, Mine &mn, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Host copies of the device-side bookkeeping of levels 2..level (made once).
+hipError_t extend_host_view(Mine &mn, int level) {
+    hipError_t e;
+    for (int Lv = 2; Lv <= level; ++Lv) {
+        MineLevel &L = mn.levels[Lv - 1];
+        if (!L.implicit || L.host_view) continue;
+        std::vector<int64_t> fc;
+        if ((e = to_host(L.d_fcand, L.nf, fc)) != hipSuccess) return e;
+        L.freq = std::move(fc);
+        if ((e = to_host(L.d_fpar, L.nf, L.h_fpar)) != hipSuccess) return e;
+        if ((e = to_host(L.d_flast, L.nf, L.h_flast)) != hipSuccess) return e;
+        if ((e = to_host(L.d_fliv, L.nf, L.h_fliv)) != hipSuccess) return e;
+        if (Lv >= 3) {
+            if ((e = to_host(L.d_out_off, L.nA + 1, L.out_off)) != hipSuccess) return e;
+            if ((e = to_host(L.d_rlo, L.nA, L.rlo)) != hipSuccess) return e;
+            if ((e = to_host(L.d_xlo, L.nA, L.xlo)) != hipSuccess) return e;
+            if ((e = to_host(L.d_xhi, L.nA, L.xhi)) != hipSuccess) return e;
+        }
+        L.host_view = true;
+    }
+    return hipSuccess;
+}
+
+void extend_frequent(const Mine &mn, int level, int64_t f, int32_t *types, int *ivs) {
+    frequent_nodes(mn, level, f, types, ivs);
+}
+
 void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs) {
     const MineLevel &L = mn.levels[level - 1];
-    const MineLevel &P = mn.levels[level - 2];
     const int M = (int)mn.menu_lo.size();
     const int N = L.N;
-    const int64_t alpha = std::upper_bound(L.out_off.begin(), L.out_off.end(), c) - L.out_off.begin() - 1;
-    const int64_t le = c - L.out_off[alpha];
-    for (int k = 0; k < N - 1; ++k) types[k] = P.ftypes[(size_t)k * P.nf + alpha];
-    for (int k = 0; k < N - 2; ++k) ivs[k] = P.fiv[(size_t)k * P.nf + alpha];
     if (N == 2) {
-        const int64_t r = le < alpha * M ? le : le + M;
-        types[1] = P.ftypes[r / M];
-        ivs[0] = (int)(r % M);
-    } else {
-        const int32_t r = ext_position(L, alpha, le);
-        const int32_t beta = L.byprefix[r];
-        types[N - 1] = P.ftypes[(size_t)(P.N - 1) * P.nf + beta];
-        ivs[N - 2] = P.fiv[(size_t)(P.N - 2) * P.nf + beta];
+        const MineLevel &P = mn.levels[0];
+        const int64_t per = (L.nA - 1) * M;
+        const int64_t a = c / per, r = c - a * per;
+        const int64_t bi0 = r / M;
+        const int64_t bi = bi0 >= a ? bi0 + 1 : bi0;
+        types[0] = (int32_t)P.freq[a];
+        types[1] = (int32_t)P.freq[bi];
+        ivs[0] = (int)(r - bi0 * M);
+        return;
     }
+    const MineLevel &P = mn.levels[level - 2];
+    const int64_t alpha = std::upper_bound(L.out_off.begin(), L.out_off.end(), c) - L.out_off.begin() - 1;
+    int64_t rr = L.rlo[alpha] + (c - L.out_off[alpha]);
+    if (rr >= L.xlo[alpha]) rr += L.xhi[alpha] - L.xlo[alpha];
+    frequent_nodes(mn, level - 1, alpha, types, ivs);
+    types[N - 1] = P.h_flast[rr];
+    ivs[N - 2] = P.h_fliv[rr];
 }
 
 }  // namespace epi

@@ -156,26 +156,39 @@ struct MineLevel {
     std::vector<uint8_t> iv;
     std::vector<int32_t> counts;  // [m] (host copy; for device-counted levels made on demand)
     DevBuf dcounts;               // int32 [m] on the device (extension engine)
-    std::vector<int64_t> freq;    // indices with count > threshold
+    std::vector<int64_t> freq;    // indices with count > threshold (extension engine: host copy on demand)
     double gen_ms = 0, count_ms = 0, kernel_ms = 0;
     int64_t alg_bytes = -1;       // bytes the counting method must read and write (-1: not yet computed)
+    int64_t nf = 0;                // frequent episodes
     // Extension engine: candidate c of level N >= 2 is alpha + one node, where
     // alpha indexes the frequent episodes of level N-1 (alpha-major order).
+    // Level 2: alpha's extensions are every other frequent type x the menu.
+    // Level >= 3: they are the frequent episodes [rlo, rlo + n) of level N-1
+    // whose prefix is alpha's suffix, less [xlo, xhi), those whose last type
+    // is alpha's first.
     bool implicit = false;
-    std::vector<int64_t> out_off;  // [nA + 1] first candidate of each alpha
-    std::vector<int32_t> rlo, rhi; // level >= 3: range of alpha's extensions in byprefix
-    std::vector<int32_t> byprefix; // level >= 3: level N-1 frequent, ordered by first N-2 nodes, then last node
-    std::vector<int32_t> xlo, xhi; // level >= 3: the extensions repeating alpha's first type, [xlo, xhi)
-    // frequent episodes of this level (structure of arrays) and their chain
-    // lists: for every end event with an occurrence, in time order, its time,
-    // the latest start of an occurrence ending there, and its stream position
-    int64_t nf = 0;
-    std::vector<uint16_t> ftypes;  // [N][nf]
-    std::vector<uint8_t> fiv;      // [N-1][nf]
-    DevBuf ct, cs;                 // T [total]: end time, latest start
-    DevBuf cp;                     // int32 [total]: stream position of the end event
+    int64_t nA = 0;
+    DevBuf d_out_off;              // int64 [nA + 1] first candidate of each alpha (level >= 3)
+    DevBuf d_rlo, d_xlo, d_xhi;    // int32 [nA] (level >= 3)
+    // Frequent episodes on the device: candidate index, prefix parent (alpha:
+    // the level N-1 episode it extends; level 1: unused), suffix parent (the
+    // level N-1 episode its last N-1 nodes form), last type, last interval
+    // id, first type, end-event count.  Level 1 keeps only flast = ffirst =
+    // the frequent types.
+    DevBuf d_fcand, d_fpar, d_fsuf, d_flast, d_fliv, d_ffirst, d_fnv;
+    // host copies, made on demand for reading back (extend_host_view)
+    bool host_view = false;
+    std::vector<int64_t> out_off;
+    std::vector<int32_t> rlo, xlo, xhi, h_fpar;
+    std::vector<uint16_t> h_flast;
+    std::vector<uint8_t> h_fliv;
+    // chain lists of the frequent episodes: for every end event with an
+    // occurrence, in time order, its time, the latest start of an occurrence
+    // ending there, and its stream position
+    DevBuf ct, cs;                 // T [chain_total]
+    DevBuf cp;                     // int32 [chain_total]
     DevBuf chain_off;              // int64 [nf + 1]
-    std::vector<int64_t> h_chain_off;
+    int64_t chain_total = 0;
     int64_t walked = 0;            // stream positions the extension walk visited (counting pass)
 };
 
@@ -257,11 +270,15 @@ int queue_class_of(int64_t bound);
 constexpr int kExtMaxMenu = 8;
 hipError_t extend_prepare(const Stream &s, Mine &mn, hipStream_t st);
 hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st);
-hipError_t extend_level(const Stream &s, Mine &mn, int N, int32_t *d_flags, hipStream_t st);
+hipError_t extend_level(const Stream &s, Mine &mn, int N, hipStream_t st);
 // algorithmic bytes of an extension-engine level (computed on first use)
 int64_t extend_level_bytes(const Stream &s, Mine &mn, int level);
-// Reconstruct candidate c of an implicit level: types[8], interval ids[7].
+// Host copies of an extension-engine run's levels 2..level, for reading back.
+hipError_t extend_host_view(Mine &mn, int level);
+// Candidate c / frequent episode f of an implicit level (after
+// extend_host_view): types[N], interval ids[N-1].
 void implicit_candidate(const Mine &mn, int level, int64_t c, int32_t *types, int *ivs);
+void extend_frequent(const Mine &mn, int level, int64_t f, int32_t *types, int *ivs);
 // Cost model (epi_mlp.hip).
 int64_t mlp_n_params(int F);
 hipError_t mlp_init(Mlp &net, int F, uint64_t seed);

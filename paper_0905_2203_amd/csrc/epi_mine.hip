@@ -226,6 +226,7 @@ void select_frequent(MineLevel &L, int64_t threshold) {
     L.freq.clear();
     for (int64_t i = 0; i < L.m; ++i)
         if (L.counts[i] > threshold) L.freq.push_back(i);
+    L.nf = (int64_t)L.freq.size();
 }
 
 }  // namespace epi
