@@ -54,7 +54,15 @@ using Clock = std::chrono::steady_clock;
 double ms_since(Clock::time_point t0) { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
 
 constexpr int kWave = 64;
-constexpr uint8_t kNoSlot = 0xFF;
+constexpr uint16_t kNoSlot = 0;  // owner-slot entry of a type no lane counts (no intervals)
+
+// One entry of a chain list: an end event of an episode (time, stream
+// position) and the latest start of an occurrence ending there.
+template <typename T>
+struct ChainEntry {
+    T t, s;
+    int32_t p;
+};
 
 template <typename T>
 struct WalkArgs {
@@ -62,12 +70,11 @@ struct WalkArgs {
     const T *times;           // [n]
     const int32_t *wend;      // [n] first position whose time exceeds times[p] + H
     T H;                      // longest menu interval end
-    // the alphas' chain lists
-    const T *ct, *cs;         // level >= 3: end times, latest starts
-    const int32_t *cp;        // level >= 3: stream positions
+    // the alphas' chain lists: level >= 3, those of the previous level's
+    // frequent episodes ([coff[alpha], coff[alpha + 1])); level 2, a frequent
+    // type's own events (the per-type index as chain entries, s = t)
+    const ChainEntry<T> *chain;
     const int64_t *coff;      // level >= 3: [nA + 1]
-    const T *ts_by_type;      // level 2: a frequent type's chain is its own events
-    const int32_t *pos_by_type;
     const int32_t *type_off;
     const uint16_t *f1;       // level 2: the frequent types
     int32_t nf1;
@@ -87,8 +94,7 @@ struct WalkArgs {
     const uint16_t *w_type;
     const uint8_t *w_iv;
     const int64_t *w_off;     // first chain-list slot of each frequent episode
-    T *wct, *wcs;
-    int32_t *wcp;
+    ChainEntry<T> *wchain;
     T menu_lo[kExtMaxMenu], menu_hi[kExtMaxMenu];
     int32_t M;
     int32_t K;
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kMax = TsLimits<T>::hi();
     constexpr bool kExact = MP <= 4;
-    extern __shared__ uint8_t slot_of[];            // [K] lane owning each type this round
+    extern __shared__ uint16_t slot_of[];           // [K] owner lane of each type this round | its intervals << 8
     __shared__ unsigned long long want[kWave];      // batch lanes holding each owner's events
     __shared__ int32_t gtype[kWave];
     __shared__ int64_t gkey[MP][kWave];
@@ -175,23 +181,17 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     const int64_t alpha = a.job_alpha ? (int64_t)a.job_alpha[job] : job;
     const int M = kExact ? MP : a.M;
     // alpha's chain list
-    const_ptr<T> xt, xs;
-    const int32_t *xp;
+    int64_t c0;
     int32_t clen;
     if (a.level2) {
         const int32_t ty = a.f1[alpha];
-        const int32_t o = a.type_off[ty];
-        clen = a.type_off[ty + 1] - o;
-        xt = (const_ptr<T>)(a.ts_by_type + o);
-        xs = xt;
-        xp = a.pos_by_type + o;
+        c0 = a.type_off[ty];
+        clen = a.type_off[ty + 1] - (int32_t)c0;
     } else {
-        const int64_t o = a.coff[alpha];
-        clen = (int32_t)(a.coff[alpha + 1] - o);
-        xt = (const_ptr<T>)(a.ct + o);
-        xs = (const_ptr<T>)(a.cs + o);
-        xp = a.cp + o;
+        c0 = a.coff[alpha];
+        clen = (int32_t)(a.coff[alpha + 1] - c0);
     }
+    const_ptr<ChainEntry<T>> xc = (const_ptr<ChainEntry<T>>)(a.chain + c0);
     // the menu, uniform
     T mlo[MP], mhi[MP];
 #pragma unroll
@@ -250,7 +250,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
             cnt[m] = 0;
             nv[m] = 0;
         }
-        if (has) slot_of[myB] = (uint8_t)lane;
+        uint32_t ownm = 0;
+#pragma unroll
+        for (int m = 0; m < MP; ++m) ownm |= (uint32_t)own[m] << m;
+        if (has) slot_of[myB] = (uint16_t)(lane | ownm << 8);
         __syncthreads();
         // ---- the walk over U(alpha)
         int32_t carry = 0;  // coverage end of the entries already taken
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         for (int32_t i0 = 0; i0 < clen; i0 += kWave) {  // uniform
             const int32_t i = i0 + lane;
             const bool ci = i < clen;
-            const int32_t p = ci ? xp[i] : 0;
+            const int32_t p = ci ? xc[i].p : 0;
             const int32_t e = ci ? a.wend[p] : 0;
             int32_t prev_e = __shfl_up(e, 1, kWave);
             if (lane == 0) prev_e = carry;
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 const T tf = read_lane(t, 0), tl = read_lane(t, nb - 1);
                 // s_m(y): start of the latest end event x with
                 // t_x < t - lo_m, when t_x >= t - hi_m
-                while (ilo < clen && xt[ilo] < (T)(tf - a.H)) ++ilo;
+                while (ilo < clen && xc[ilo].t < (T)(tf - a.H)) ++ilo;
                 T cx[MP], cxs[MP];
 #pragma unroll
                 for (int m = 0; m < MP; ++m) {
@@ -302,9 +305,9 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     cxs[m] = kMin;
                 }
                 for (int32_t q = ilo; q < clen; ++q) {  // uniform
-                    const T qt = xt[q];
+                    const T qt = xc[q].t;
+                    const T qs = xc[q].s;
                     if (qt >= tl) break;
-                    const T qs = xs[q];
 #pragma unroll
                     for (int m = 0; m < MP; ++m) {
                         const bool c = (T)(qt + mlo[m]) < t;
@@ -313,18 +316,20 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     }
                 }
                 T sv[MP];
-                uint32_t any = 0;
+                uint32_t vm = 0;  // menu intervals for which this event ends an occurrence
 #pragma unroll
                 for (int m = 0; m < MP; ++m) {
                     // bitwise, not short-circuit: keeps the code branch-free
                     const uint32_t v = (uint32_t)(kExact || m < M) & (uint32_t)ev &
                                        (uint32_t)(cx[m] != kMin) & (uint32_t)((T)(cx[m] + mhi[m]) >= t);
                     sv[m] = v ? cxs[m] : kMin;
-                    any |= v;
+                    vm |= v << m;
                 }
-                if (any) {
-                    const uint8_t sl = slot_of[ty];
-                    if (sl != kNoSlot) atomicOr(&want[sl], 1ull << lane);
+                // delivered to the owner of its type when that owner counts
+                // one of those intervals
+                if (vm) {
+                    const uint32_t sl = slot_of[ty];
+                    if (vm & (sl >> 8)) atomicOr(&want[sl & 0xFF], 1ull << lane);
                 }
                 __syncthreads();
                 uint64_t wm = want[lane];
@@ -332,7 +337,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 // each owner lane runs its greedies over its events in time
                 // order (branch-free; lanes with nothing left read themselves)
                 if (__ballot(wm != 0)) do {  // uniform
-                    const uint32_t on = wm != 0;
+                    const bool on = wm != 0;
                     const int addr = (on ? __builtin_ctzll(wm) : lane) << 2;
                     const T yt = permute(addr, t);
                     int32_t yp = 0;
@@ -342,16 +347,14 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     for (int m = 0; m < MP; ++m) ys[m] = (kExact || m < M) ? permute(addr, sv[m]) : kMin;
 #pragma unroll
                     for (int m = 0; m < MP; ++m) {
-                        const uint32_t v = on & (uint32_t)own[m] & (uint32_t)(ys[m] != kMin);
+                        const bool v = on & own[m] & (ys[m] != kMin);
                         if (WRITE && v) {
                             const int64_t w = key[m] + nv[m];
-                            a.wct[w] = yt;
-                            a.wcs[w] = ys[m];
-                            a.wcp[w] = yp;
+                            a.wchain[w] = ChainEntry<T>{yt, ys[m], yp};
                         }
-                        nv[m] += (int32_t)v;
-                        const uint32_t g = v & (uint32_t)(ys[m] > pe[m]);
-                        cnt[m] += (int32_t)g;
+                        nv[m] += v;
+                        const bool g = v & (ys[m] > pe[m]);
+                        cnt[m] += g;
                         pe[m] = g ? yt : pe[m];
                     }
                     wm &= wm - 1;
@@ -378,9 +381,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
 template <typename T, bool WRITE>
 bool walk_args_complete(const WalkArgs<T> &a) {
     bool ok = a.ty16 && a.times && a.wend && a.M >= 1 && a.M <= kExtMaxMenu && a.K >= 1;
-    if (a.level2) ok = ok && a.f1 && a.ts_by_type && a.pos_by_type && a.type_off && a.nf1 >= 2;
-    else ok = ok && a.ct && a.cs && a.cp && a.coff;
-    if (WRITE) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv && a.w_off && a.wct && a.wcs && a.wcp;
+    ok = ok && a.chain;
+    if (a.level2) ok = ok && a.f1 && a.type_off && a.nf1 >= 2;
+    else ok = ok && a.coff;
+    if (WRITE) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv && a.w_off && a.wchain;
     else ok = ok && a.counts && a.nvalid && (a.level2 || (a.out_off && a.rlo && a.xlo && a.xhi && a.flast && a.fliv));
     return ok;
 }
@@ -389,7 +393,7 @@ template <typename T, bool WRITE>
 hipError_t launch_walk(const WalkArgs<T> &a, int64_t njobs, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
     if (!walk_args_complete<T, WRITE>(a)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(a.K + 15) / 16 * 16;
+    const size_t lds = (size_t)(2 * a.K + 15) / 16 * 16;
     const unsigned g = (unsigned)njobs;
     switch (a.M) {
         case 1: k_ext_walk<T, 1, WRITE><<<g, kWave, lds, st>>>(a); break;
@@ -399,6 +403,14 @@ hipError_t launch_walk(const WalkArgs<T> &a, int64_t njobs, hipStream_t st) {
         default: k_ext_walk<T, 8, WRITE><<<g, kWave, lds, st>>>(a); break;
     }
     return hipGetLastError();
+}
+
+// The per-type index as chain entries (the chain lists of 1-node episodes).
+template <typename T>
+__global__ void k_type_chain(const T *__restrict__ ts, const int32_t *__restrict__ pos, int64_t n,
+                             ChainEntry<T> *__restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = ChainEntry<T>{ts[q], ts[q], pos[q]};
 }
 
 // Types as uint16 and the window end of every position.
@@ -787,8 +799,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     a.times = s.times.as<T>();
     a.wend = mn.wend.as<int32_t>();
     a.H = (T)*std::max_element(mn.menu_hi.begin(), mn.menu_hi.end());
-    a.ts_by_type = s.ts_by_type.as<T>();
-    a.pos_by_type = s.pos_by_type.as<int32_t>();
+    a.chain = mn.chain1.as<ChainEntry<T>>();  // level 2; level >= 3 below
     a.type_off = s.type_off.as<int32_t>();
     a.M = M;
     a.K = s.K;
@@ -800,9 +811,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     a.f1 = P.d_flast.as<uint16_t>();  // level 2: the frequent types
     a.nf1 = (int32_t)nA;
     if (N > 2) {
-        a.ct = P.ct.as<T>();
-        a.cs = P.cs.as<T>();
-        a.cp = P.cp.as<int32_t>();
+        a.chain = P.chain.as<ChainEntry<T>>();
         a.coff = P.chain_off.as<int64_t>();
         a.flast = P.d_flast.as<uint16_t>();
         a.fliv = P.d_fliv.as<uint8_t>();
@@ -912,18 +921,14 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
                 return e;
         }
         const size_t tot = (size_t)L.chain_total;
-        if ((e = L.ct.alloc(sizeof(T) * tot)) != hipSuccess) return e;
-        if ((e = L.cs.alloc(sizeof(T) * tot)) != hipSuccess) return e;
-        if ((e = L.cp.alloc(sizeof(int32_t) * tot)) != hipSuccess) return e;
+        if ((e = L.chain.alloc(sizeof(ChainEntry<T>) * tot)) != hipSuccess) return e;
         a.job_alpha = job_alpha.as<int32_t>();
         a.job_f = job_f.as<int64_t>();
         a.order = N > 2 ? w_order.as<int32_t>() : nullptr;
         a.w_type = L.d_flast.as<uint16_t>();
         a.w_iv = L.d_fliv.as<uint8_t>();
         a.w_off = L.chain_off.as<int64_t>();
-        a.wct = L.ct.as<T>();
-        a.wcs = L.cs.as<T>();
-        a.wcp = L.cp.as<int32_t>();
+        a.wchain = L.chain.as<ChainEntry<T>>();
         if ((e = launch_walk<T, true>(a, nj, st)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;  // the job buffers die here
     } else {
@@ -934,9 +939,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     // chain lists two levels back are no longer needed
     if (mn.levels.size() >= 2) {
         MineLevel &Q = mn.levels[mn.levels.size() - 2];
-        Q.ct.reset();
-        Q.cs.reset();
-        Q.cp.reset();
+        Q.chain.reset();
         Q.chain_off.reset();
     }
     mn.levels.push_back(std::move(L));
@@ -1021,9 +1024,8 @@ hipError_t extend_level(const Stream &s, Mine &mn, int N, hipStream_t st) {
 }
 
 // Bytes the window walk of a level must read and write: the stream positions
-// it walked (type and time of each), the alphas' chain lists (time, start,
-// position and window end of each entry), and each candidate's count and
-// end-event count.
+// it walked (type and time of each), the alphas' chain lists (one entry and
+// its window end each), and each candidate's count and end-event count.
 int64_t extend_level_bytes(const Stream &s, Mine &mn, int level) {
     MineLevel &L = mn.levels[level - 1];
     if (L.alg_bytes >= 0) return L.alg_bytes;
@@ -1035,7 +1037,8 @@ int64_t extend_level_bytes(const Stream &s, Mine &mn, int level) {
     } else {
         entries = P.chain_total;
     }
-    L.alg_bytes = L.walked * (2 + tsb) + entries * (2 * tsb + 8) + L.m * 8;
+    const int64_t entry = tsb == 8 ? (int64_t)sizeof(ChainEntry<int64_t>) : (int64_t)sizeof(ChainEntry<int32_t>);
+    L.alg_bytes = L.walked * (2 + tsb) + entries * (entry + 4) + L.m * 8;
     return L.alg_bytes;
 }
 
@@ -1046,12 +1049,19 @@ hipError_t extend_prepare(const Stream &s, Mine &mn, hipStream_t st) {
     if (s.n == 0) return hipSuccess;
     const int64_t H = *std::max_element(mn.menu_hi.begin(), mn.menu_hi.end());
     const unsigned blocks = (unsigned)((s.n + 255) / 256);
-    if (s.ts_kind == EPI_TS_I64)
+    if (s.ts_kind == EPI_TS_I64) {
+        if ((e = mn.chain1.alloc(sizeof(ChainEntry<int64_t>) * (size_t)s.n)) != hipSuccess) return e;
         k_walk_prep<int64_t><<<blocks, 256, 0, st>>>(s.types.as<int32_t>(), s.times.as<int64_t>(), s.n, H,
                                                      mn.ty16.as<uint16_t>(), mn.wend.as<int32_t>());
-    else
+        k_type_chain<int64_t><<<blocks, 256, 0, st>>>(s.ts_by_type.as<int64_t>(), s.pos_by_type.as<int32_t>(), s.n,
+                                                      mn.chain1.as<ChainEntry<int64_t>>());
+    } else {
+        if ((e = mn.chain1.alloc(sizeof(ChainEntry<int32_t>) * (size_t)s.n)) != hipSuccess) return e;
         k_walk_prep<int32_t><<<blocks, 256, 0, st>>>(s.types.as<int32_t>(), s.times.as<int32_t>(), s.n, (int32_t)H,
                                                      mn.ty16.as<uint16_t>(), mn.wend.as<int32_t>());
+        k_type_chain<int32_t><<<blocks, 256, 0, st>>>(s.ts_by_type.as<int32_t>(), s.pos_by_type.as<int32_t>(), s.n,
+                                                      mn.chain1.as<ChainEntry<int32_t>>());
+    }
     return hipGetLastError();
 }
 

@@ -185,8 +185,7 @@ struct MineLevel {
     // chain lists of the frequent episodes: for every end event with an
     // occurrence, in time order, its time, the latest start of an occurrence
     // ending there, and its stream position
-    DevBuf ct, cs;                 // T [chain_total]
-    DevBuf cp;                     // int32 [chain_total]
+    DevBuf chain;                  // {T time, T start, int32 position} [chain_total]
     DevBuf chain_off;              // int64 [nf + 1]
     int64_t chain_total = 0;
     int64_t walked = 0;            // stream positions the extension walk visited (counting pass)
@@ -203,6 +202,7 @@ struct Mine {
     // p, the first position whose time exceeds time[p] + H (H = the longest
     // menu interval end)
     DevBuf ty16, wend;
+    DevBuf chain1;  // the per-type index as chain entries (level 2's alphas)
     double bits_ms = 0;
 };
 
