@@ -565,6 +565,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
             if (value < 0) return fail(ctx, EPI_EINVAL, "target items must be >= 0");
             ctx->c.opt.target_items = value;
             return EPI_OK;
+        case EPI_OPT_MINE_LIST_BYTES:
+            if (value < 0) return fail(ctx, EPI_EINVAL, "list bytes must be >= 0");
+            ctx->c.opt.mine_list_bytes = value;
+            return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);
     }
@@ -623,6 +627,7 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     // the extension engine takes menus of up to kExtMaxMenu intervals; longer
     // menus go to the state-machine engine
     mn->engine = n_menu <= kExtMaxMenu ? ctx->c.opt.mine_engine : 0;
+    mn->list_budget = ctx->c.opt.mine_list_bytes;
     if (mn->engine == 1) {
         // extension engine: each level extends the previous level's chain lists
         auto tb = std::chrono::steady_clock::now();

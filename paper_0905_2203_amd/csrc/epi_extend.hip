@@ -74,13 +74,16 @@ struct WalkArgs {
     // frequent episodes ([coff[alpha], coff[alpha + 1])); level 2, a frequent
     // type's own events (the per-type index as chain entries, s = t)
     const ChainEntry<T> *chain;
-    const int64_t *coff;      // level >= 3: [nA + 1]
+    const int64_t *cbeg;      // level >= 3: first entry of each alpha's chain list
+    const int32_t *clen;      // level >= 3: its length
     const int32_t *type_off;
     const uint16_t *f1;       // level 2: the frequent types
     int32_t nf1;
-    // one job per workgroup
+    // one job per workgroup: an alpha, or (nseg > 1) one of nseg pieces of
+    // an alpha's chain list, job = alpha * nseg + piece
     const int32_t *job_alpha; // alpha of each job (null: the job index)
     const int32_t *order;     // order in which the workgroups take the jobs (null: index order)
+    int32_t nseg;
     // counting pass (level >= 3): alpha's extensions are the frequent
     // episodes beta = rlo..rlo+n of the previous level, skipping [xlo, xhi)
     const int64_t *out_off;   // [nA + 1] first candidate of each alpha
@@ -95,6 +98,8 @@ struct WalkArgs {
     const uint8_t *w_iv;
     const int64_t *w_off;     // first chain-list slot of each frequent episode
     ChainEntry<T> *wchain;
+    // list pass: first slot of each (candidate, piece) list
+    const int64_t *lst_off;   // [m * nseg + 1]
     T menu_lo[kExtMaxMenu], menu_hi[kExtMaxMenu];
     int32_t M;
     int32_t K;
@@ -131,13 +136,18 @@ __device__ __forceinline__ T permute(int addr, T v) {
     }
 }
 
-// Extension r of a job: its new type B, interval id and key (counting: the
-// candidate's index; writing: the first slot of its chain list).  Within a
+// Walk kinds: count (greedy counts and end-event counts per candidate),
+// write (chain lists of the frequent episodes), size (end events per
+// candidate and piece), list (end events of every candidate, per piece).
+enum WalkMode { kCount = 0, kWrite = 1, kSize = 2, kList = 3 };
+
+// Extension r of a job: its new type B, interval id and key (count and size:
+// the candidate's index; write: the first slot of its chain list).  Within a
 // job the extensions are ordered by B.
-template <typename T, bool WRITE>
+template <typename T, int MODE>
 __device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int64_t alpha, int64_t r, int32_t &B,
                                           int &iv, int64_t &key) {
-    if (WRITE) {
+    if (MODE == kWrite) {
         const int64_t f = a.job_f[job] + r;
         B = a.w_type[f];
         iv = a.w_iv[f];
@@ -157,18 +167,20 @@ __device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int
     }
 }
 
-template <typename T, bool WRITE>
+template <typename T, int MODE>
 __device__ __forceinline__ int64_t n_extensions(const WalkArgs<T> &a, int64_t job, int64_t alpha) {
-    if (WRITE) return a.job_f[job + 1] - a.job_f[job];
+    if (MODE == kWrite) return a.job_f[job + 1] - a.job_f[job];
     if (a.level2) return (int64_t)(a.nf1 - 1) * a.M;
     return a.out_off[alpha + 1] - a.out_off[alpha];
 }
 
-// One job: alpha and all of its extensions (or, writing, its frequent ones).
-// MP greedy states per lane, one per menu interval: MP = M for menus of up
-// to 4 intervals, else 8 with the unused states idle.
-template <typename T, int MP, bool WRITE>
+// One job: alpha (or a piece of its chain list) and all of its extensions
+// (or, writing, its frequent ones).  MP greedy states per lane, one per menu
+// interval: MP = M for menus of up to 4 intervals, else 8 with the unused
+// states idle.
+template <typename T, int MP, int MODE>
 __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
+    constexpr bool WRITE = MODE == kWrite || MODE == kList;
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kMax = TsLimits<T>::hi();
     constexpr bool kExact = MP <= 4;
@@ -177,7 +189,9 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     __shared__ int32_t gtype[kWave];
     __shared__ int64_t gkey[MP][kWave];
     const int lane = threadIdx.x;
-    const int64_t job = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t jb = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t job = jb / a.nseg;
+    const int32_t seg = (int32_t)(jb - job * a.nseg);
     const int64_t alpha = a.job_alpha ? (int64_t)a.job_alpha[job] : job;
     const int M = kExact ? MP : a.M;
     // alpha's chain list
@@ -188,10 +202,13 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         c0 = a.type_off[ty];
         clen = a.type_off[ty + 1] - (int32_t)c0;
     } else {
-        c0 = a.coff[alpha];
-        clen = (int32_t)(a.coff[alpha + 1] - c0);
+        c0 = a.cbeg[alpha];
+        clen = a.clen[alpha];
     }
     const_ptr<ChainEntry<T>> xc = (const_ptr<ChainEntry<T>>)(a.chain + c0);
+    // this job's piece of the chain list
+    const int32_t e0 = (int32_t)((int64_t)clen * seg / a.nseg);
+    const int32_t e1 = (int32_t)((int64_t)clen * (seg + 1) / a.nseg);
     // the menu, uniform
     T mlo[MP], mhi[MP];
 #pragma unroll
@@ -199,7 +216,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         mlo[m] = a.menu_lo[m];
         mhi[m] = a.menu_hi[m];
     }
-    const int64_t R = n_extensions<T, WRITE>(a, job, alpha);
+    const int64_t R = n_extensions<T, MODE>(a, job, alpha);
     for (int k = lane; k < a.K; k += kWave) slot_of[k] = kNoSlot;
     want[lane] = 0;
     unsigned long long walked = 0;
@@ -217,7 +234,11 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
             int32_t B = -1;
             int iv = 0;
             int64_t key = -1;
-            if (in) extension<T, WRITE>(a, job, alpha, r, B, iv, key);
+            if (in) {
+                extension<T, MODE>(a, job, alpha, r, B, iv, key);
+                if (MODE == kSize) key = key * a.nseg + seg;
+                if (MODE == kList) key = a.lst_off[key * a.nseg + seg];
+            }
             int32_t pB = __shfl_up(B, 1, kWave);
             if (lane == 0) pB = prevB;
             const uint64_t st = __ballot(in && B != pB);
@@ -255,12 +276,16 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         for (int m = 0; m < MP; ++m) ownm |= (uint32_t)own[m] << m;
         if (has) slot_of[myB] = (uint16_t)(lane | ownm << 8);
         __syncthreads();
-        // ---- the walk over U(alpha)
-        int32_t carry = 0;  // coverage end of the entries already taken
-        int32_t ilo = 0;    // first entry that can still be a predecessor
-        for (int32_t i0 = 0; i0 < clen; i0 += kWave) {  // uniform
+        // ---- the walk over U(alpha) (this piece: the runs of entries e0..e1-1)
+        int32_t carry = e0 > 0 ? a.wend[xc[e0 - 1].p] : 0;  // coverage end of the entries already taken
+        int32_t ilo = e0;  // first entry that can still be a predecessor
+        if (e0 < e1) {
+            const T t0 = xc[e0].t;
+            while (ilo > 0 && xc[ilo - 1].t >= (T)(t0 - a.H)) --ilo;
+        }
+        for (int32_t i0 = e0; i0 < e1; i0 += kWave) {  // uniform
             const int32_t i = i0 + lane;
-            const bool ci = i < clen;
+            const bool ci = i < e1;
             const int32_t p = ci ? xc[i].p : 0;
             const int32_t e = ci ? a.wend[p] : 0;
             int32_t prev_e = __shfl_up(e, 1, kWave);
@@ -297,7 +322,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 const T tf = read_lane(t, 0), tl = read_lane(t, nb - 1);
                 // s_m(y): start of the latest end event x with
                 // t_x < t - lo_m, when t_x >= t - hi_m
-                while (ilo < clen && xc[ilo].t < (T)(tf - a.H)) ++ilo;
+                while (ilo < clen && xc[ilo].t < (T)(tf - a.H)) ++ilo;  // (entries past e1 can precede too)
                 T cx[MP], cxs[MP];
 #pragma unroll
                 for (int m = 0; m < MP; ++m) {
@@ -353,19 +378,21 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                             a.wchain[w] = ChainEntry<T>{yt, ys[m], yp};
                         }
                         nv[m] += v;
-                        const bool g = v & (ys[m] > pe[m]);
-                        cnt[m] += g;
-                        pe[m] = g ? yt : pe[m];
+                        if (MODE == kCount) {
+                            const bool g = v & (ys[m] > pe[m]);
+                            cnt[m] += g;
+                            pe[m] = g ? yt : pe[m];
+                        }
                     }
                     wm &= wm - 1;
                 } while (__ballot(wm != 0));
             }
         }
-        if (!WRITE) {
+        if (MODE == kCount || MODE == kSize) {
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
                 if (own[m]) {
-                    a.counts[key[m]] = cnt[m];
+                    if (MODE == kCount) a.counts[key[m]] = cnt[m];
                     a.nvalid[key[m]] = nv[m];
                 }
             }
@@ -374,33 +401,38 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         __syncthreads();
         r_start = r_next;
     }
-    if (!WRITE && a.walked && lane == 0) atomicAdd(a.walked, walked);
+    if ((MODE == kCount || MODE == kSize) && a.walked && lane == 0) atomicAdd(a.walked, walked);
 }
 
 // Every array a walk of this kind reads or writes must be present.
-template <typename T, bool WRITE>
+template <typename T, int MODE>
 bool walk_args_complete(const WalkArgs<T> &a) {
-    bool ok = a.ty16 && a.times && a.wend && a.M >= 1 && a.M <= kExtMaxMenu && a.K >= 1;
+    bool ok = a.ty16 && a.times && a.wend && a.M >= 1 && a.M <= kExtMaxMenu && a.K >= 1 && a.nseg >= 1;
     ok = ok && a.chain;
     if (a.level2) ok = ok && a.f1 && a.type_off && a.nf1 >= 2;
-    else ok = ok && a.coff;
-    if (WRITE) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv && a.w_off && a.wchain;
-    else ok = ok && a.counts && a.nvalid && (a.level2 || (a.out_off && a.rlo && a.xlo && a.xhi && a.flast && a.fliv));
+    else ok = ok && a.cbeg && a.clen;
+    if (MODE == kWrite) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv && a.w_off && a.wchain;
+    else ok = ok && (a.level2 || (a.out_off && a.rlo && a.xlo && a.xhi && a.flast && a.fliv));
+    if (MODE == kCount) ok = ok && a.counts && a.nvalid;
+    if (MODE == kSize) ok = ok && a.nvalid;
+    if (MODE == kList) ok = ok && a.lst_off && a.wchain;
+    if (MODE == kWrite || MODE == kCount) ok = ok && a.nseg == 1;
     return ok;
 }
 
-template <typename T, bool WRITE>
+// njobs workgroups (jobs times pieces).
+template <typename T, int MODE>
 hipError_t launch_walk(const WalkArgs<T> &a, int64_t njobs, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    if (!walk_args_complete<T, WRITE>(a)) return hipErrorInvalidValue;
+    if (!walk_args_complete<T, MODE>(a)) return hipErrorInvalidValue;
     const size_t lds = (size_t)(2 * a.K + 15) / 16 * 16;
     const unsigned g = (unsigned)njobs;
     switch (a.M) {
-        case 1: k_ext_walk<T, 1, WRITE><<<g, kWave, lds, st>>>(a); break;
-        case 2: k_ext_walk<T, 2, WRITE><<<g, kWave, lds, st>>>(a); break;
-        case 3: k_ext_walk<T, 3, WRITE><<<g, kWave, lds, st>>>(a); break;
-        case 4: k_ext_walk<T, 4, WRITE><<<g, kWave, lds, st>>>(a); break;
-        default: k_ext_walk<T, 8, WRITE><<<g, kWave, lds, st>>>(a); break;
+        case 1: k_ext_walk<T, 1, MODE><<<g, kWave, lds, st>>>(a); break;
+        case 2: k_ext_walk<T, 2, MODE><<<g, kWave, lds, st>>>(a); break;
+        case 3: k_ext_walk<T, 3, MODE><<<g, kWave, lds, st>>>(a); break;
+        case 4: k_ext_walk<T, 4, MODE><<<g, kWave, lds, st>>>(a); break;
+        default: k_ext_walk<T, 8, MODE><<<g, kWave, lds, st>>>(a); break;
     }
     return hipGetLastError();
 }
@@ -730,6 +762,50 @@ __global__ __launch_bounds__(kBlock) void k_key_scatter(const uint16_t *__restri
     }
 }
 
+// List path: the count of candidate c is the greedy of Alg. 1 over its end
+// events in time order (its lists of the nseg pieces, consecutive); one wave
+// per candidate loads 64 entries at a time and the greedy steps through them
+// in scalar registers.
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_list_count(const ChainEntry<T> *__restrict__ lst,
+                                                      const int64_t *__restrict__ lst_off, int32_t nseg,
+                                                      int32_t *__restrict__ counts, int32_t *__restrict__ nvalid) {
+    constexpr T kMin = TsLimits<T>::lo();
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t b = lst_off[c * nseg], e = lst_off[(c + 1) * nseg];
+    T pe = kMin;
+    int32_t cnt = 0;
+    for (int64_t q0 = b; q0 < e; q0 += kWave) {  // uniform
+        const int64_t q = q0 + lane;
+        T t = kMin, s = kMin;
+        if (q < e) {
+            t = lst[q].t;
+            s = lst[q].s;
+        }
+        const int nb = (int)(e - q0 < kWave ? e - q0 : kWave);
+        for (int k = 0; k < nb; ++k) {
+            const T sk = read_lane(s, k);
+            if (sk > pe) {
+                ++cnt;
+                pe = read_lane(t, k);
+            }
+        }
+    }
+    if (lane == 0) {
+        counts[c] = cnt;
+        nvalid[c] = (int32_t)(e - b);
+    }
+}
+
+// List path: the chain list of frequent episode f is its candidate's list.
+__global__ __launch_bounds__(kBlock) void k_list_begin(const int64_t *__restrict__ fcand,
+                                                       const int64_t *__restrict__ lst_off, int32_t nseg, int64_t nf,
+                                                       int64_t *__restrict__ cbeg) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f < nf) cbeg[f] = lst_off[fcand[f] * nseg];
+}
+
 unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <typename V>
@@ -810,9 +886,11 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     }
     a.f1 = P.d_flast.as<uint16_t>();  // level 2: the frequent types
     a.nf1 = (int32_t)nA;
+    a.nseg = 1;
     if (N > 2) {
         a.chain = P.chain.as<ChainEntry<T>>();
-        a.coff = P.chain_off.as<int64_t>();
+        a.cbeg = P.cbeg.as<int64_t>();
+        a.clen = P.d_fnv.as<int32_t>();
         a.flast = P.d_flast.as<uint16_t>();
         a.fliv = P.d_fliv.as<uint8_t>();
         a.out_off = L.d_out_off.as<int64_t>();
@@ -836,7 +914,35 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
     (void)hipEventRecord(ev0, st);
-    if (m > 0) e = launch_walk<T, false>(a, nA, st);
+    // Level 2 has as few alphas as frequent types: its walks are cut into
+    // pieces (list path) when every candidate's end events fit the budget.
+    bool listed = false;
+    DevBuf lst_off;
+    if (m > 0 && N == 2) {
+        const int32_t nseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (4096 + nA - 1) / nA));
+        if ((e = lst_off.alloc(sizeof(int64_t) * (m * nseg + 1))) != hipSuccess) return e;
+        DevBuf nvseg;
+        if ((e = nvseg.alloc(sizeof(int32_t) * m * nseg)) != hipSuccess) return e;
+        WalkArgs<T> b = a;
+        b.nseg = nseg;
+        b.nvalid = nvseg.as<int32_t>();
+        if ((e = launch_walk<T, kSize>(b, nA * nseg, st)) != hipSuccess) return e;
+        if ((e = scan64(nvseg.as<int32_t>(), m * nseg, lst_off.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+        int64_t total = 0;
+        if ((e = read_scalar(lst_off, m * nseg, &total, st)) != hipSuccess) return e;
+        if (total * (int64_t)sizeof(ChainEntry<T>) <= mn.list_budget) {
+            if ((e = L.chain.alloc(sizeof(ChainEntry<T>) * (size_t)total)) != hipSuccess) return e;
+            b.lst_off = lst_off.as<int64_t>();
+            b.wchain = L.chain.as<ChainEntry<T>>();
+            if ((e = launch_walk<T, kList>(b, nA * nseg, st)) != hipSuccess) return e;
+            k_list_count<T><<<(unsigned)m, kWave, 0, st>>>(L.chain.as<ChainEntry<T>>(), lst_off.as<int64_t>(), nseg,
+                                                          a.counts, a.nvalid);
+            e = hipGetLastError();
+            listed = true;
+            L.list_seg = nseg;
+        }
+    }
+    if (m > 0 && !listed && e == hipSuccess) e = launch_walk<T, kCount>(a, nA, st);
     (void)hipEventRecord(ev1, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     float kms = 0;
@@ -872,7 +978,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     if ((e = L.d_flast.alloc(sizeof(uint16_t) * nfa)) != hipSuccess) return e;
     if ((e = L.d_ffirst.alloc(sizeof(uint16_t) * nfa)) != hipSuccess) return e;
     if ((e = L.d_fliv.alloc(nfa)) != hipSuccess) return e;
-    if ((e = L.chain_off.alloc(sizeof(int64_t) * (nf + 1))) != hipSuccess) return e;
+    if ((e = L.cbeg.alloc(sizeof(int64_t) * (nf + 1))) != hipSuccess) return e;
     L.chain_total = 0;
     if (nf > 0) {
         k_sel_write<<<(unsigned)nb, kBlock, 0, st>>>(a.counts, a.nvalid, m, thr, boffs.as<int64_t>(),
@@ -898,9 +1004,20 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         fa.fliv = L.d_fliv.as<uint8_t>();
         k_freq_fields<<<grid_of(nf), kBlock, 0, st>>>(fa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // chain lists: offsets from the scan of the end-event counts
+        // chain lists: offsets from the scan of the end-event counts (the
+        // list path keeps every candidate's list; its frequent ones are the
+        // chain lists)
         DevBuf tmp2, flag, jidx, job_alpha, job_f, w_order;
-        if ((e = scan64(L.d_fnv.as<int32_t>(), nf, L.chain_off.as<int64_t>(), tmp2, st)) != hipSuccess) return e;
+        if ((e = scan64(L.d_fnv.as<int32_t>(), nf, L.cbeg.as<int64_t>(), tmp2, st)) != hipSuccess) return e;
+        if ((e = read_scalar(L.cbeg, nf, &L.chain_total, st)) != hipSuccess) return e;
+        if (listed) {
+            k_list_begin<<<grid_of(nf), kBlock, 0, st>>>(L.d_fcand.as<int64_t>(), lst_off.as<int64_t>(), L.list_seg,
+                                                         nf, L.cbeg.as<int64_t>());
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            L.count_ms = ms_since(t1);
+            goto done;
+        }
         // write jobs: the alphas with frequent extensions
         if ((e = flag.alloc(sizeof(int32_t) * nf)) != hipSuccess) return e;
         if ((e = jidx.alloc(sizeof(int64_t) * (nf + 1))) != hipSuccess) return e;
@@ -908,7 +1025,6 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         if ((e = scan64(flag.as<int32_t>(), nf, jidx.as<int64_t>(), tmp, st)) != hipSuccess) return e;
         int64_t nj = 0;
         if ((e = read_scalar(jidx, nf, &nj, st)) != hipSuccess) return e;
-        if ((e = read_scalar(L.chain_off, nf, &L.chain_total, st)) != hipSuccess) return e;
         if ((e = job_alpha.alloc(sizeof(int32_t) * nj)) != hipSuccess) return e;
         if ((e = job_f.alloc(sizeof(int64_t) * (nj + 1))) != hipSuccess) return e;
         k_job_write<<<grid_of(nf + 1), kBlock, 0, st>>>(L.d_fpar.as<int32_t>(), flag.as<int32_t>(),
@@ -927,20 +1043,21 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         a.order = N > 2 ? w_order.as<int32_t>() : nullptr;
         a.w_type = L.d_flast.as<uint16_t>();
         a.w_iv = L.d_fliv.as<uint8_t>();
-        a.w_off = L.chain_off.as<int64_t>();
+        a.w_off = L.cbeg.as<int64_t>();
         a.wchain = L.chain.as<ChainEntry<T>>();
-        if ((e = launch_walk<T, true>(a, nj, st)) != hipSuccess) return e;
+        if ((e = launch_walk<T, kWrite>(a, nj, st)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;  // the job buffers die here
     } else {
-        if ((e = hipMemsetAsync(L.chain_off.p, 0, sizeof(int64_t), st)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(L.cbeg.p, 0, sizeof(int64_t), st)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     }
     L.count_ms = ms_since(t1);
+done:
     // chain lists two levels back are no longer needed
     if (mn.levels.size() >= 2) {
         MineLevel &Q = mn.levels[mn.levels.size() - 2];
         Q.chain.reset();
-        Q.chain_off.reset();
+        Q.cbeg.reset();
     }
     mn.levels.push_back(std::move(L));
     return hipSuccess;

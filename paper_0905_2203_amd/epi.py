@@ -58,6 +58,7 @@ EPI_OPT_PAIR_FILTER = 4
 EPI_OPT_MINE_ENGINE = 5
 EPI_OPT_WORKLOG = 6
 EPI_OPT_TARGET_ITEMS = 7
+EPI_OPT_MINE_LIST_BYTES = 8
 
 
 class EpiError(RuntimeError):

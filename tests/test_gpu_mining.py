@@ -61,13 +61,19 @@ def compare_mining(ctx, name, s, menu, max_size, theta):
     return ref
 
 
-def test_more_extension_types_than_lanes(ctx):
+@pytest.mark.parametrize("list_bytes", [2 << 30, 0], ids=["level2-lists", "level2-walk"])
+def test_more_extension_types_than_lanes(ctx, list_bytes):
     # 80 types: an episode has up to 79 (level 2) or 77 (level 3) extension
-    # types, more than the 64 lanes of one walk round
+    # types, more than the 64 lanes of one walk round; level 2 both from the
+    # end-event lists (walks cut into pieces) and by one walk per type
     rng = np.random.Generator(np.random.PCG64(31))
     s = sg.poisson_stream(rng, K=80, rate_hz=6.0, dur_s=60.0, ts_kind=0, unit_per_ms=1000, cascades=[4],
                           cascade_trigger_hz=[5.0])
-    ref = compare_mining(ctx, "K80", s, [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS], 4, 17)
+    ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_BYTES, list_bytes)
+    try:
+        ref = compare_mining(ctx, "K80", s, [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS], 4, 17)
+    finally:
+        ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_BYTES, 2 << 30)
     assert len(ref[1]["frequent"]) > 0 and len(ref[2]["frequent"]) > 0
 
 
