@@ -199,11 +199,13 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *   EPI_OPT_TARGET_ITEMS  batched mode: number of work items the scheduler
  *                         aims at (0 = 8 per compute unit)
  *   EPI_OPT_MINE_LIST_BYTES  level-wise discovery, extension engine: device
- *                         bytes that the end-event lists of every level-2
- *                         candidate may take (default 2 GiB); within it,
- *                         level 2 is counted from those lists by walks cut
- *                         into pieces, else by one walk per frequent type
- *                         (0 = always the latter)
+ *                         bytes that the end-event lists of every candidate
+ *                         of a level may take (default 8 GiB); a level with
+ *                         few frequent parent episodes is counted from those
+ *                         lists, listed by walks cut into pieces, when they
+ *                         fit; else one walk per parent counts it and a
+ *                         second writes its chain lists (0 = always the
+ *                         latter)
  * EPI_EINVAL for an unknown option or value.  Counts never depend on them. */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
        EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8 };

@@ -55,6 +55,10 @@ double ms_since(Clock::time_point t0) { return std::chrono::duration<double, std
 
 constexpr int kWave = 64;
 constexpr uint16_t kNoSlot = 0;  // owner-slot entry of a type no lane counts (no intervals)
+// List path: taken for levels with fewer alphas than kListAlphas, whose walks
+// are cut into pieces so that about kListJobs workgroups run.
+constexpr int64_t kListAlphas = 65536;
+constexpr int64_t kListJobs = 65536;
 
 // One entry of a chain list: an end event of an episode (time, stream
 // position) and the latest start of an occurrence ending there.
@@ -80,7 +84,7 @@ struct WalkArgs {
     const uint16_t *f1;       // level 2: the frequent types
     int32_t nf1;
     // one job per workgroup: an alpha, or (nseg > 1) one of nseg pieces of
-    // an alpha's chain list, job = alpha * nseg + piece
+    // an alpha's chain list (workgroup = job slot * nseg + piece)
     const int32_t *job_alpha; // alpha of each job (null: the job index)
     const int32_t *order;     // order in which the workgroups take the jobs (null: index order)
     int32_t nseg;
@@ -188,10 +192,16 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     __shared__ unsigned long long want[kWave];      // batch lanes holding each owner's events
     __shared__ int32_t gtype[kWave];
     __shared__ int64_t gkey[MP][kWave];
+    // the batch's events (slot 64: a null event that no greedy keeps)
+    __shared__ T ev_t[kWave + 1];
+    __shared__ T ev_s[MP][kWave + 1];
+    // writing: each owner's first slot and entries so far, per interval
+    __shared__ int64_t okey[WRITE ? MP : 1][kWave];
+    __shared__ int32_t onv[WRITE ? MP : 1][kWave];
     const int lane = threadIdx.x;
-    const int64_t jb = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
-    const int64_t job = jb / a.nseg;
-    const int32_t seg = (int32_t)(jb - job * a.nseg);
+    const int64_t slot = (int64_t)blockIdx.x / a.nseg;
+    const int32_t seg = (int32_t)((int64_t)blockIdx.x - slot * a.nseg);
+    const int64_t job = a.order ? (int64_t)a.order[slot] : slot;
     const int64_t alpha = a.job_alpha ? (int64_t)a.job_alpha[job] : job;
     const int M = kExact ? MP : a.M;
     // alpha's chain list
@@ -219,6 +229,11 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     const int64_t R = n_extensions<T, MODE>(a, job, alpha);
     for (int k = lane; k < a.K; k += kWave) slot_of[k] = kNoSlot;
     want[lane] = 0;
+    if (lane == 0) {
+        ev_t[kWave] = kMin;
+#pragma unroll
+        for (int m = 0; m < MP; ++m) ev_s[m][kWave] = kMin;
+    }
     unsigned long long walked = 0;
     // rounds of up to 64 distinct extension types (one lane each)
     for (int64_t r_start = 0; r_start < R;) {
@@ -275,6 +290,13 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
 #pragma unroll
         for (int m = 0; m < MP; ++m) ownm |= (uint32_t)own[m] << m;
         if (has) slot_of[myB] = (uint16_t)(lane | ownm << 8);
+        if (WRITE) {
+#pragma unroll
+            for (int m = 0; m < MP; ++m) {
+                okey[m][lane] = key[m];
+                onv[m][lane] = 0;
+            }
+        }
         __syncthreads();
         // ---- the walk over U(alpha) (this piece: the runs of entries e0..e1-1)
         int32_t carry = e0 > 0 ? a.wend[xc[e0 - 1].p] : 0;  // coverage end of the entries already taken
@@ -350,42 +372,77 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     sv[m] = v ? cxs[m] : kMin;
                     vm |= v << m;
                 }
+                // the event in LDS, for its owner and its same-type neighbours
+                ev_t[lane] = t;
+#pragma unroll
+                for (int m = 0; m < MP; ++m) ev_s[m][lane] = sv[m];
                 // delivered to the owner of its type when that owner counts
                 // one of those intervals
-                if (vm) {
-                    const uint32_t sl = slot_of[ty];
-                    if (vm & (sl >> 8)) atomicOr(&want[sl & 0xFF], 1ull << lane);
-                }
-                __syncthreads();
-                uint64_t wm = want[lane];
-                want[lane] = 0;
-                // each owner lane runs its greedies over its events in time
-                // order (branch-free; lanes with nothing left read themselves)
-                if (__ballot(wm != 0)) do {  // uniform
-                    const bool on = wm != 0;
-                    const int addr = (on ? __builtin_ctzll(wm) : lane) << 2;
-                    const T yt = permute(addr, t);
-                    int32_t yp = 0;
-                    if (WRITE) yp = permute(addr, P);
-                    T ys[MP];
+                const uint32_t sl = vm ? (uint32_t)slot_of[ty] : 0u;
+                const bool dl = (vm & (sl >> 8)) != 0;
+                const int ow = (int)(sl & 0xFF);
+                if (dl) atomicOr(&want[ow], 1ull << lane);
+                uint64_t vb[MP];  // delivered events that end an occurrence, per interval
 #pragma unroll
-                    for (int m = 0; m < MP; ++m) ys[m] = (kExact || m < M) ? permute(addr, sv[m]) : kMin;
+                for (int m = 0; m < MP; ++m) vb[m] = __ballot(dl & (sv[m] != kMin));
+                __syncthreads();
+                const uint64_t below = (1ull << lane) - 1ull;
+                const uint64_t wo = dl ? want[ow] : 0ull;  // the batch's events of the same owner
+                uint64_t lb = 0;
+                if (MODE == kCount) {
+                    // leaders: events whose s_m differs from that of the
+                    // previous same-owner event; the others can never be kept
+                    // (an earlier event with the same start was kept or
+                    // rejected first)
+                    uint32_t lead = 0;
+                    const uint64_t bm = wo & below;
+                    if (bm == 0) {
+                        lead = vm;
+                    } else {
+                        const int pl = 63 - __builtin_clzll(bm);
+#pragma unroll
+                        for (int m = 0; m < MP; ++m)
+                            lead |= (uint32_t)((sv[m] != kMin) & (sv[m] != ev_s[m][pl])) << m;
+                    }
+                    lb = __ballot(dl & ((lead & (sl >> 8)) != 0));
+                }
+                if (WRITE && dl) {
+                    // each event writes itself, after the owner's entries so
+                    // far and the batch's earlier ones
 #pragma unroll
                     for (int m = 0; m < MP; ++m) {
-                        const bool v = on & own[m] & (ys[m] != kMin);
-                        if (WRITE && v) {
-                            const int64_t w = key[m] + nv[m];
-                            a.wchain[w] = ChainEntry<T>{yt, ys[m], yp};
+                        if ((sv[m] != kMin) & (((sl >> 8) >> m) & 1u)) {
+                            const int64_t w = okey[m][ow] + onv[m][ow] + __popcll(wo & vb[m] & below);
+                            a.wchain[w] = ChainEntry<T>{t, sv[m], P};
                         }
-                        nv[m] += v;
-                        if (MODE == kCount) {
-                            const bool g = v & (ys[m] > pe[m]);
+                    }
+                }
+                __syncthreads();  // every read of want and of the owners' published counts is done
+                uint64_t wm = want[lane];
+                want[lane] = 0;
+#pragma unroll
+                for (int m = 0; m < MP; ++m) nv[m] += __popcll(wm & vb[m]);
+                if (WRITE) {
+#pragma unroll
+                    for (int m = 0; m < MP; ++m) onv[m][lane] = nv[m];
+                }
+                if (MODE == kCount) {
+                    // each owner lane runs its greedies over its leaders in
+                    // time order; lanes with none left read the null event
+                    uint64_t wl = wm & lb;
+                    if (__ballot(wl != 0)) do {  // uniform
+                        const int k = wl ? __builtin_ctzll(wl) : kWave;
+                        const T yt = ev_t[k];
+#pragma unroll
+                        for (int m = 0; m < MP; ++m) {
+                            const T ys = ev_s[m][k];
+                            const bool g = own[m] & (ys > pe[m]);
                             cnt[m] += g;
                             pe[m] = g ? yt : pe[m];
                         }
-                    }
-                    wm &= wm - 1;
-                } while (__ballot(wm != 0));
+                        wl &= wl - 1;
+                    } while (__ballot(wl != 0));
+                }
             }
         }
         if (MODE == kCount || MODE == kSize) {
@@ -744,21 +801,40 @@ __global__ __launch_bounds__(kBlock) void k_job_write(const int32_t *__restrict_
     }
 }
 
-// Jobs grouped by a uint16 key (the alphas' last type): counting sort with
-// atomics (the order inside a key is irrelevant).
-__global__ __launch_bounds__(kBlock) void k_key_hist(const uint16_t *__restrict__ key, const int32_t *__restrict__ idx,
-                                                     int64_t n, int32_t *__restrict__ hist) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < n) atomicAdd(&hist[key[idx ? idx[j] : j]], 1);
+// Jobs grouped by a uint16 key (the alphas' last type): a counting sort whose
+// histogram is kept per block in LDS (kKeyItems jobs per block), so that a
+// block adds each key once; the order inside a key is arbitrary.
+constexpr int kKeyItems = 16;
+
+__global__ __launch_bounds__(kBlock) void k_key_count(const uint16_t *__restrict__ key, const int32_t *__restrict__ idx,
+                                                      int64_t n, int32_t K, int32_t *__restrict__ cnt) {
+    extern __shared__ int32_t h[];
+    for (int k = threadIdx.x; k < K; k += kBlock) h[k] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kKeyItems;
+    for (int q = 0; q < kKeyItems; ++q) {
+        const int64_t j = base + (int64_t)q * kBlock + threadIdx.x;
+        if (j < n) atomicAdd(&h[key[idx ? idx[j] : j]], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kBlock) cnt[(int64_t)k * gridDim.x + blockIdx.x] = h[k];
 }
 
-__global__ __launch_bounds__(kBlock) void k_key_scatter(const uint16_t *__restrict__ key,
-                                                        const int32_t *__restrict__ idx, int64_t n,
-                                                        int64_t *__restrict__ cursor, int32_t *__restrict__ order) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < n) {
-        const unsigned long long o = atomicAdd((unsigned long long *)&cursor[key[idx ? idx[j] : j]], 1ull);
-        order[o] = (int32_t)j;
+// off: exclusive scan of cnt in key-major order (key, block)
+__global__ __launch_bounds__(kBlock) void k_key_place(const uint16_t *__restrict__ key, const int32_t *__restrict__ idx,
+                                                      int64_t n, int32_t K, const int64_t *__restrict__ off,
+                                                      int32_t *__restrict__ order) {
+    extern __shared__ int32_t h[];
+    for (int k = threadIdx.x; k < K; k += kBlock) h[k] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kKeyItems;
+    for (int q = 0; q < kKeyItems; ++q) {
+        const int64_t j = base + (int64_t)q * kBlock + threadIdx.x;
+        if (j < n) {
+            const int32_t k = key[idx ? idx[j] : j];
+            const int32_t r = atomicAdd(&h[k], 1);
+            order[off[(int64_t)k * gridDim.x + blockIdx.x] + r] = (int32_t)j;
+        }
     }
 }
 
@@ -798,6 +874,42 @@ __global__ __launch_bounds__(kWave) void k_list_count(const ChainEntry<T> *__res
     }
 }
 
+// The same with one lane per candidate (many candidates).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_list_count_lane(const ChainEntry<T> *__restrict__ lst,
+                                                            const int64_t *__restrict__ lst_off, int32_t nseg,
+                                                            int64_t m, int32_t *__restrict__ counts,
+                                                            int32_t *__restrict__ nvalid) {
+    constexpr T kMin = TsLimits<T>::lo();
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= m) return;
+    const int64_t b = lst_off[c * nseg], e = lst_off[(c + 1) * nseg];
+    T pe = kMin;
+    int32_t cnt = 0;
+    int64_t q = b;
+    for (; q + 4 <= e; q += 4) {
+        ChainEntry<T> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = lst[q + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u].s > pe) {
+                ++cnt;
+                pe = v[u].t;
+            }
+        }
+    }
+    for (; q < e; ++q) {
+        const ChainEntry<T> v = lst[q];
+        if (v.s > pe) {
+            ++cnt;
+            pe = v.t;
+        }
+    }
+    counts[c] = cnt;
+    nvalid[c] = (int32_t)(e - b);
+}
+
 // List path: the chain list of frequent episode f is its candidate's list.
 __global__ __launch_bounds__(kBlock) void k_list_begin(const int64_t *__restrict__ fcand,
                                                        const int64_t *__restrict__ lst_off, int32_t nseg, int64_t nf,
@@ -815,19 +927,20 @@ hipError_t read_scalar(const DevBuf &b, int64_t at, V *out, hipStream_t st) {
     return e;
 }
 
-// jobs j = 0..n-1 ordered by key[idx[j]] (idx null: key[j])
+// jobs j = 0..n-1 ordered by key[idx[j]] (idx null: key[j]), key < K
 hipError_t order_by_key(const uint16_t *key, const int32_t *idx, int64_t n, int32_t K, DevBuf &order,
                         hipStream_t st) {
     hipError_t e;
-    DevBuf hist, cursor, tmp;
     if ((e = order.alloc(sizeof(int32_t) * std::max<int64_t>(1, n))) != hipSuccess) return e;
-    if ((e = hist.alloc(sizeof(int32_t) * K)) != hipSuccess) return e;
-    if ((e = cursor.alloc(sizeof(int64_t) * (K + 1))) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(hist.p, 0, sizeof(int32_t) * K, st)) != hipSuccess) return e;
     if (n == 0) return hipSuccess;
-    k_key_hist<<<grid_of(n), kBlock, 0, st>>>(key, idx, n, hist.as<int32_t>());
-    if ((e = scan64(hist.as<int32_t>(), K, cursor.as<int64_t>(), tmp, st)) != hipSuccess) return e;
-    k_key_scatter<<<grid_of(n), kBlock, 0, st>>>(key, idx, n, cursor.as<int64_t>(), order.as<int32_t>());
+    const int64_t nb = (n + kBlock * kKeyItems - 1) / (kBlock * kKeyItems);
+    DevBuf cnt, off, tmp;
+    if ((e = cnt.alloc(sizeof(int32_t) * nb * K)) != hipSuccess) return e;
+    if ((e = off.alloc(sizeof(int64_t) * (nb * K + 1))) != hipSuccess) return e;
+    const size_t lds = sizeof(int32_t) * (size_t)K;
+    k_key_count<<<(unsigned)nb, kBlock, lds, st>>>(key, idx, n, K, cnt.as<int32_t>());
+    if ((e = scan64(cnt.as<int32_t>(), nb * K, off.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+    k_key_place<<<(unsigned)nb, kBlock, lds, st>>>(key, idx, n, K, off.as<int64_t>(), order.as<int32_t>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipStreamSynchronize(st);  // the temporaries die here
 }
@@ -914,12 +1027,13 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     if ((e = hipEventCreate(&ev0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&ev1)) != hipSuccess) return e;
     (void)hipEventRecord(ev0, st);
-    // Level 2 has as few alphas as frequent types: its walks are cut into
-    // pieces (list path) when every candidate's end events fit the budget.
+    // With few alphas (level 2 has as many as frequent types) one walk per
+    // alpha leaves the GPU idle: the walks are cut into pieces and every
+    // candidate's end events are listed (list path), when they fit the budget.
     bool listed = false;
     DevBuf lst_off;
-    if (m > 0 && N == 2) {
-        const int32_t nseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (4096 + nA - 1) / nA));
+    if (m > 0 && nA < kListAlphas) {
+        const int32_t nseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (kListJobs + nA - 1) / nA));
         if ((e = lst_off.alloc(sizeof(int64_t) * (m * nseg + 1))) != hipSuccess) return e;
         DevBuf nvseg;
         if ((e = nvseg.alloc(sizeof(int32_t) * m * nseg)) != hipSuccess) return e;
@@ -935,8 +1049,12 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
             b.lst_off = lst_off.as<int64_t>();
             b.wchain = L.chain.as<ChainEntry<T>>();
             if ((e = launch_walk<T, kList>(b, nA * nseg, st)) != hipSuccess) return e;
-            k_list_count<T><<<(unsigned)m, kWave, 0, st>>>(L.chain.as<ChainEntry<T>>(), lst_off.as<int64_t>(), nseg,
-                                                          a.counts, a.nvalid);
+            if (m < kListJobs)
+                k_list_count<T><<<(unsigned)m, kWave, 0, st>>>(L.chain.as<ChainEntry<T>>(), lst_off.as<int64_t>(),
+                                                              nseg, a.counts, a.nvalid);
+            else
+                k_list_count_lane<T><<<grid_of(m), kBlock, 0, st>>>(L.chain.as<ChainEntry<T>>(), lst_off.as<int64_t>(),
+                                                                   nseg, m, a.counts, a.nvalid);
             e = hipGetLastError();
             listed = true;
             L.list_seg = nseg;

@@ -144,7 +144,7 @@ struct CountOptions {
     bool worklog = false;          // record per-candidate work counts and per-item times
     int64_t target_items = 0;      // batched mode: work items aimed at (0: 8 per compute unit)
     int64_t pair_filter_max_bytes = int64_t(1) << 30;
-    int64_t mine_list_bytes = int64_t(2) << 30;  // extension engine: level-2 list budget
+    int64_t mine_list_bytes = int64_t(8) << 30;  // extension engine: list-path budget per level
 };
 
 // One level of a level-wise discovery run: candidates of size N in
@@ -189,7 +189,7 @@ struct MineLevel {
     DevBuf chain;                  // {T time, T start, int32 position} entries
     DevBuf cbeg;                   // int64 [nf + 1]: first entry of each chain list (length: d_fnv)
     int64_t chain_total = 0;       // entries in the chain lists of the frequent episodes
-    int32_t list_seg = 0;          // level 2 list path: pieces per alpha (0: not taken)
+    int32_t list_seg = 0;          // list path: pieces per alpha (0: not taken)
     int64_t walked = 0;            // stream positions the extension walk visited (counting pass)
 };
 
@@ -205,8 +205,8 @@ struct Mine {
     // menu interval end)
     DevBuf ty16, wend;
     DevBuf chain1;  // the per-type index as chain entries (level 2's alphas)
-    // level 2 list path: device bytes the end-event lists of every level-2
-    // candidate may take (larger: the plain walk)
+    // list path: device bytes the end-event lists of every candidate of a
+    // level may take (larger: count and write walks)
     int64_t list_budget = 0;
     double bits_ms = 0;
 };

@@ -61,11 +61,11 @@ def compare_mining(ctx, name, s, menu, max_size, theta):
     return ref
 
 
-@pytest.mark.parametrize("list_bytes", [2 << 30, 0], ids=["level2-lists", "level2-walk"])
+@pytest.mark.parametrize("list_bytes", [8 << 30, 0], ids=["lists", "walks"])
 def test_more_extension_types_than_lanes(ctx, list_bytes):
     # 80 types: an episode has up to 79 (level 2) or 77 (level 3) extension
-    # types, more than the 64 lanes of one walk round; level 2 both from the
-    # end-event lists (walks cut into pieces) and by one walk per type
+    # types, more than the 64 lanes of one walk round; every level both from
+    # the end-event lists (walks cut into pieces) and by count and write walks
     rng = np.random.Generator(np.random.PCG64(31))
     s = sg.poisson_stream(rng, K=80, rate_hz=6.0, dur_s=60.0, ts_kind=0, unit_per_ms=1000, cascades=[4],
                           cascade_trigger_hz=[5.0])
@@ -73,7 +73,7 @@ def test_more_extension_types_than_lanes(ctx, list_bytes):
     try:
         ref = compare_mining(ctx, "K80", s, [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS], 4, 17)
     finally:
-        ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_BYTES, 2 << 30)
+        ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_BYTES, 8 << 30)
     assert len(ref[1]["frequent"]) > 0 and len(ref[2]["frequent"]) > 0
 
 
