@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PROFILE = "k_ext_count_mining.md"
+PROFILE = "k_ext_walk_mining.md"
 KERNEL_SOURCES = ("epi_extend.hip",)
 THRESHOLD = 100
 MAX_SIZE = 6
@@ -258,7 +258,7 @@ def main():
     alg = ctx.epi_mine_level_bytes(mid, dom)
     achieved_gbs = alg / (kern_ms[dom - 1] / 1e3) / 1e9
     mp = len(menu) if len(menu) <= 4 else 8
-    kname = f"k_ext_walk<int, {mp}, false>" if dom >= 2 else "k_level1<int>"
+    kname = f"k_ext_walk<int, {mp}, 0>" if dom >= 2 else "k_level1<int>"
     traffic = profiled_traffic(kname)
 
     # parity spot check (outside the timed region): sampled counts vs the oracle

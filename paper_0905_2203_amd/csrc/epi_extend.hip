@@ -127,19 +127,6 @@ __device__ __forceinline__ T read_lane(T v, int l) {
     }
 }
 
-// Value of v in the lane whose byte address (lane * 4) is addr.
-template <typename T>
-__device__ __forceinline__ T permute(int addr, T v) {
-    if constexpr (sizeof(T) == 4) {
-        return (T)__builtin_amdgcn_ds_bpermute(addr, (int)v);
-    } else {
-        const uint64_t u = (uint64_t)v;
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
-        return (T)(((uint64_t)hi << 32) | lo);
-    }
-}
-
 // Walk kinds: count (greedy counts and end-event counts per candidate),
 // write (chain lists of the frequent episodes), size (end events per
 // candidate and piece), list (end events of every candidate, per piece).
