@@ -26,7 +26,8 @@
 // the same state right after any completion time they share, so as soon as
 // the re-run completes at a time the speculative run also recorded, the rest
 // of the speculative count is taken as is; otherwise the re-run covers the
-// whole segment.
+// whole segment.  It also stops at B_p + H if neither machine has completed
+// by then: from there on both hold the same state.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -486,6 +487,13 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
             head[k] = v < Ep ? v : kEnd;
         }
         const int nspec = c < kRecFirst ? c : kRecFirst;
+        // From B_p + H on, every partial occurrence either machine holds
+        // started after B_p, hence after both machines' last completion
+        // (tau < B_p; the speculative one's, if any, is before B_p as long as
+        // it has none in the segment yet): until one of them completes, both
+        // hold the same state, and from then on they agree.
+        const T sync_t = (T)(Bp + H);
+        const T first0 = c > 0 ? a.rec_first[((int64_t)p * kRecFirst) * a.G + s] : kEnd;
         int qi = 0;
         int32_t fcount = 0;
         T flast = tau;
@@ -501,6 +509,12 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
                 }
             }
             if (t == kEnd) break;
+            if (fcount == 0 && t >= sync_t && first0 >= t) {
+                total += c;
+                if (c > 0) tau = last;
+                synced = true;
+                break;
+            }
             if (f.step(j, t, a.flags)) {
                 ++fcount;
                 flast = t;
