@@ -140,6 +140,23 @@ def ablation(k, scale, reps):
                                                                 sched=epi.EPI_SCHED_MEASURED), reps)
     assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "measured"
     log(f"  measured-cost schedule {res['batched_measured']:.3f}s")
+    # parity: a seeded sample of every set's counts against the oracle
+    parity = "not checked"
+    try:
+        import oracle
+        import spikegen as sg_
+
+        rng = np.random.Generator(np.random.PCG64(11))
+        bad = checked = 0
+        for (s_, c_), got in zip(sets, ref):
+            idx = np.sort(rng.choice(c_["N"].size, size=min(64, c_["N"].size), replace=False))
+            want = oracle.count(s_, sg_.take_candidates(c_, idx))
+            bad += int((want != got[idx]).sum())
+            checked += idx.size
+        parity = f"{'ok' if bad == 0 else 'MISMATCH'}: {checked} sampled counts vs the oracle, {bad} differ"
+        log(f"  parity {parity}")
+    except Exception as exc:
+        log(f"oracle leg failed: {exc!r}")
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s",
@@ -152,6 +169,7 @@ def ablation(k, scale, reps):
         "cost_model": {"train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                        "train_candidates": int(sum(c["N"].size for _, c in train_sets))},
         "counts_equal_across_modes": True,
+        "parity": parity,
         "candidates": int(sum(c["N"].size for _, c in sets)), "events": int(sum(s["types"].size for s, _ in sets)),
     }
     print(json.dumps(line), flush=True)

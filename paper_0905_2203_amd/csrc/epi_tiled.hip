@@ -872,14 +872,19 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                 continue;
             }
             // learned / heuristic: blocks of similar predicted cost (sorted),
-            // heavy blocks cut into more segments, cost per item ~ uniform
+            // heavy blocks cut into more segments, cost per item ~ uniform.
+            // A block never gets fewer segments than round robin gives it:
+            // every item walks all tiles of its segment whatever its work, so
+            // a light block in one segment is one long item.
             const double cstar = std::max(total_cost / (double)target_items, 1.0);
+            const int64_t p_rr = std::max<int64_t>(1, std::min<int64_t>(
+                G >= opt.target_lanes ? 1 : (opt.target_lanes + G - 1) / G, pmax));
             int64_t b0 = 0;
             const int64_t nb = (G + W - 1) / W;
             while (b0 < nb) {
                 auto pfor = [&](int64_t b) {
                     const double bc = (double)costs[si][g.begin + b * W] * std::min<int64_t>(W, G - b * W);
-                    int64_t P = (int64_t)std::ceil(bc / cstar);
+                    int64_t P = std::max<int64_t>(p_rr, (int64_t)std::ceil(bc / cstar));
                     if (opt.segments > 0) P = opt.segments;
                     return std::max<int64_t>(1, std::min<int64_t>(P, opt.segments > 0 ? s.B : pmax));
                 };
