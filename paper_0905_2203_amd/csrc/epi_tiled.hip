@@ -908,11 +908,20 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         if (u.P > 1) rec_bytes += (size_t)u.P * u.G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst)) + 64;
     DevBuf rec;
     if ((e = rec.alloc(rec_bytes)) != hipSuccess) return e;
+    // launch classes: episode size x queue class (each with its own lane
+    // width and LDS layout, as the plain launch sizes each group)
+    constexpr int kQClasses = 5;  // Q = 1, 2, 4, 8, 16
+    constexpr int kClasses = (kMaxN + 1) * kQClasses;
+    auto cls_of = [](int N, int Q) {
+        int q = 0;
+        while ((1 << q) < Q) ++q;
+        return N * kQClasses + q;
+    };
     std::vector<CountArgs<T>> ua(units.size());
-    std::vector<std::vector<WorkItem>> items(kMaxN + 1);
-    std::vector<std::vector<float>> icost(kMaxN + 1);
-    std::vector<int> maxQ(kMaxN + 1, 1), maxK(kMaxN + 1, 1), Wn(kMaxN + 1, 256);
-    std::vector<bool> filtN(kMaxN + 1, false);
+    std::vector<std::vector<WorkItem>> items(kClasses);
+    std::vector<std::vector<float>> icost(kClasses);
+    std::vector<int> clsN(kClasses, 0), clsQ(kClasses, 1), maxK(kClasses, 1), Wn(kClasses, 256);
+    std::vector<bool> filtN(kClasses, false);
     size_t ro = 0;
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
@@ -954,56 +963,52 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
             ro += ((size_t)u.P * u.G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst)) + 64) & ~size_t(15);
         }
         ua[ui] = a;
-        maxQ[u.N] = std::max(maxQ[u.N], u.Q);
-        maxK[u.N] = std::max(maxK[u.N], (int)s.K);
-        filtN[u.N] = filtN[u.N] || u.filt;
-        for (int64_t b = 0; b < (int64_t)u.bcost.size(); ++b)
-            for (int64_t p = 0; p < u.P; ++p) {
-                items[u.N].push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
-                icost[u.N].push_back(u.bcost[b] / (float)u.P);
-            }
+        const int cl = cls_of(u.N, u.Q);
+        clsN[cl] = u.N;
+        clsQ[cl] = std::max(clsQ[cl], u.Q);
+        maxK[cl] = std::max(maxK[cl], (int)s.K);
+        filtN[cl] = filtN[cl] || u.filt;
     }
-    // lanes per workgroup per size: common to its units
-    for (int N = 1; N <= kMaxN; ++N) Wn[N] = pick_lanes<T>(N, maxQ[N], maxK[N], opt.lanes);
+    // lanes per workgroup per class: common to its units
+    for (int cl = 0; cl < kClasses; ++cl)
+        if (clsN[cl] > 0) Wn[cl] = pick_lanes<T>(clsN[cl], clsQ[cl], maxK[cl], opt.lanes);
     for (size_t ui = 0; ui < units.size(); ++ui) {
-        const int N = units[ui].N;
-        const Layout<T> L = layout<T>(N, maxQ[N], Wn[N], maxK[N], true);
-        ua[ui].Q = maxQ[N];
+        const int cl = cls_of(units[ui].N, units[ui].Q);
+        const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true);
+        ua[ui].Q = clsQ[cl];
         ua[ui].off_qse = L.off_qse;
         ua[ui].off_tbuf = L.off_tbuf;
         ua[ui].off_qh = L.off_qh;
         ua[ui].off_obuf = L.off_obuf;
         ua[ui].off_misc = L.off_misc;
     }
-    // lane blocks were cut for the unit's own width; re-cut for the common one
-    for (int N = 1; N <= kMaxN; ++N) {
-        items[N].clear();
-        icost[N].clear();
-    }
+    // work items: lane blocks of the class width x segments
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
-        const int W = Wn[u.N];
+        const int cl = cls_of(u.N, u.Q);
+        const int W = Wn[cl];
         const int64_t nb = (u.G + W - 1) / W;
         for (int64_t b = 0; b < nb; ++b) {
             const float bc = u.bcost[std::min<int64_t>((b * W) / u.W, (int64_t)u.bcost.size() - 1)];
             for (int64_t p = 0; p < u.P; ++p) {
-                items[u.N].push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
-                icost[u.N].push_back(bc / (float)u.P);
+                items[cl].push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
+                icost[cl].push_back(bc / (float)u.P);
             }
         }
     }
     int64_t n_items = 0;
-    for (int N = 1; N <= kMaxN; ++N) {
-        if (sched != EPI_SCHED_RR && !items[N].empty()) {
+    for (int cl = 0; cl < kClasses; ++cl) {
+        if (sched != EPI_SCHED_RR && !items[cl].empty()) {
             // longest processing time first
-            std::vector<int64_t> ord(items[N].size());
+            std::vector<int64_t> ord(items[cl].size());
             std::iota(ord.begin(), ord.end(), 0);
-            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return icost[N][x] > icost[N][y]; });
+            std::stable_sort(ord.begin(), ord.end(),
+                             [&](int64_t x, int64_t y) { return icost[cl][x] > icost[cl][y]; });
             std::vector<WorkItem> sorted(ord.size());
-            for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[N][ord[i]];
-            items[N] = std::move(sorted);
+            for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[cl][ord[i]];
+            items[cl] = std::move(sorted);
         }
-        n_items += (int64_t)items[N].size();
+        n_items += (int64_t)items[cl].size();
     }
     // work-log buffers (per-item wall-clock stamps live with the first set)
     for (auto &r : sets) r.c->logged = opt.worklog;
@@ -1017,43 +1022,49 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                                       hipMemcpyHostToDevice)) != hipSuccess)
         return e;
     if ((e = d_items.alloc(sizeof(WorkItem) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
-    if ((e = d_queue.alloc(sizeof(unsigned long long) * (kMaxN + 1))) != hipSuccess) return e;
-    std::vector<int64_t> ioff(kMaxN + 2, 0);
-    for (int N = 1; N <= kMaxN; ++N) {
-        if (!items[N].empty() &&
-            (e = hipMemcpy(d_items.as<WorkItem>() + ioff[N], items[N].data(), sizeof(WorkItem) * items[N].size(),
+    if ((e = d_queue.alloc(sizeof(unsigned long long) * kClasses)) != hipSuccess) return e;
+    std::vector<int64_t> ioff(kClasses + 1, 0);
+    for (int cl = 0; cl < kClasses; ++cl) {
+        if (!items[cl].empty() &&
+            (e = hipMemcpy(d_items.as<WorkItem>() + ioff[cl], items[cl].data(), sizeof(WorkItem) * items[cl].size(),
                            hipMemcpyHostToDevice)) != hipSuccess)
             return e;
-        ioff[N + 1] = ioff[N] + (int64_t)items[N].size();
+        ioff[cl + 1] = ioff[cl] + (int64_t)items[cl].size();
     }
-    // 4. one graph: clear the queues, one persistent launch per episode size,
-    //    then the reconciliation of every segmented unit
+    // 4. one graph: clear the queues, one persistent launch per class, then
+    //    the reconciliation of every segmented unit
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kMaxN + 1, 0ull);
-    for (int N = 1; N <= kMaxN && e == hipSuccess; ++N) {
-        if (items[N].empty()) continue;
-        const bool filt = filtN[N];
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kClasses, 0ull);
+    std::vector<int> corder;
+    for (int cl = 0; cl < kClasses; ++cl)
+        if (!items[cl].empty()) corder.push_back(cl);
+    for (int cl : corder) {
+        if (e != hipSuccess) break;
+        const int N = clsN[cl];
+        const bool filt = filtN[cl];
         PFn<T> fn = filt ? pick_persistent_f<T, true>(N) : pick_persistent_f<T, false>(N);
-        const Layout<T> L = layout<T>(N, maxQ[N], Wn[N], maxK[N], true);
+        const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true);
         e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total);
         if (e != hipSuccess) break;
         int per = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(fn), Wn[N], L.total);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(fn), Wn[cl], L.total);
         if (e != hipSuccess) break;
-        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)items[N].size(), (int64_t)ncu * std::max(per, 1)));
-        fn<<<(unsigned)grid, Wn[N], L.total, st>>>(d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[N],
-                                                   (int64_t)items[N].size(), ioff[N],
-                                                   reinterpret_cast<unsigned long long *>(d_queue.p) + N);
+        const int64_t grid =
+            std::max<int64_t>(1, std::min<int64_t>((int64_t)items[cl].size(), (int64_t)ncu * std::max(per, 1)));
+        fn<<<(unsigned)grid, Wn[cl], L.total, st>>>(d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[cl],
+                                                    (int64_t)items[cl].size(), ioff[cl],
+                                                    reinterpret_cast<unsigned long long *>(d_queue.p) + cl);
         e = hipGetLastError();
     }
     for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
         if (units[ui].P <= 1) continue;
         const int N = units[ui].N;
+        const int cl = cls_of(N, units[ui].Q);
         KFn<T> rf = pick_reconcile<T>(N);
         const int RW = 64;
-        const Layout<T> RL = layout<T>(N, maxQ[N], RW, maxK[N], false);
+        const Layout<T> RL = layout<T>(N, clsQ[cl], RW, maxK[cl], false);
         CountArgs<T> r = ua[ui];
         r.off_qse = RL.off_qse;
         r.off_qh = RL.off_qh;
