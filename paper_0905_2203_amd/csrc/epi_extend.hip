@@ -182,6 +182,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     // the batch's events (slot 64: a null event that no greedy keeps)
     __shared__ T ev_t[kWave + 1];
     __shared__ T ev_s[MP][kWave + 1];
+    // counting: the next leader event of the same owner (64: none), and each
+    // owner's end events per interval
+    __shared__ int32_t ev_n[kWave + 1];
+    __shared__ int32_t cnv[MODE == kCount ? MP : 1][kWave];
     // writing: each owner's first slot and entries so far, per interval
     __shared__ int64_t okey[WRITE ? MP : 1][kWave];
     __shared__ int32_t onv[WRITE ? MP : 1][kWave];
@@ -218,6 +222,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     want[lane] = 0;
     if (lane == 0) {
         ev_t[kWave] = kMin;
+        ev_n[kWave] = kWave;
 #pragma unroll
         for (int m = 0; m < MP; ++m) ev_s[m][kWave] = kMin;
     }
@@ -283,6 +288,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 okey[m][lane] = key[m];
                 onv[m][lane] = 0;
             }
+        }
+        if (MODE == kCount) {
+#pragma unroll
+            for (int m = 0; m < MP; ++m) cnv[m][lane] = 0;
         }
         __syncthreads();
         // ---- the walk over U(alpha) (this piece: the runs of entries e0..e1-1)
@@ -370,8 +379,17 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 const int ow = (int)(sl & 0xFF);
                 if (dl) atomicOr(&want[ow], 1ull << lane);
                 uint64_t vb[MP];  // delivered events that end an occurrence, per interval
+                if (MODE == kCount) {
+                    // counted by the events themselves, for the intervals
+                    // their owner counts
+                    const uint32_t dv = dl ? vm & (sl >> 8) : 0u;
 #pragma unroll
-                for (int m = 0; m < MP; ++m) vb[m] = __ballot(dl & (sv[m] != kMin));
+                    for (int m = 0; m < MP; ++m)
+                        if ((dv >> m) & 1u) atomicAdd(&cnv[m][ow], 1);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < MP; ++m) vb[m] = __ballot(dl & (sv[m] != kMin));
+                }
                 __syncthreads();
                 const uint64_t below = (1ull << lane) - 1ull;
                 const uint64_t wo = dl ? want[ow] : 0ull;  // the batch's events of the same owner
@@ -392,6 +410,9 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                             lead |= (uint32_t)((sv[m] != kMin) & (sv[m] != ev_s[m][pl])) << m;
                     }
                     lb = __ballot(dl & ((lead & (sl >> 8)) != 0));
+                    // the owner's leaders as a list in time order
+                    const uint64_t nx = wo & lb & ~((2ull << lane) - 1ull);
+                    ev_n[lane] = nx ? __builtin_ctzll(nx) : kWave;
                 }
                 if (WRITE && dl) {
                     // each event writes itself, after the owner's entries so
@@ -407,18 +428,21 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                 __syncthreads();  // every read of want and of the owners' published counts is done
                 uint64_t wm = want[lane];
                 want[lane] = 0;
+                if (MODE != kCount) {
 #pragma unroll
-                for (int m = 0; m < MP; ++m) nv[m] += __popcll(wm & vb[m]);
+                    for (int m = 0; m < MP; ++m) nv[m] += __popcll(wm & vb[m]);
+                }
                 if (WRITE) {
 #pragma unroll
                     for (int m = 0; m < MP; ++m) onv[m][lane] = nv[m];
                 }
                 if (MODE == kCount) {
                     // each owner lane runs its greedies over its leaders in
-                    // time order; lanes with none left read the null event
-                    uint64_t wl = wm & lb;
-                    if (__ballot(wl != 0)) do {  // uniform
-                        const int k = wl ? __builtin_ctzll(wl) : kWave;
+                    // time order, following the list; lanes with none left
+                    // read the null event
+                    const uint64_t wl = wm & lb;
+                    int k = wl ? __builtin_ctzll(wl) : kWave;
+                    if (__ballot(k < kWave)) do {  // uniform
                         const T yt = ev_t[k];
 #pragma unroll
                         for (int m = 0; m < MP; ++m) {
@@ -427,10 +451,14 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                             cnt[m] += g;
                             pe[m] = g ? yt : pe[m];
                         }
-                        wl &= wl - 1;
-                    } while (__ballot(wl != 0));
+                        k = ev_n[k];
+                    } while (__ballot(k < kWave));
                 }
             }
+        }
+        if (MODE == kCount) {
+#pragma unroll
+            for (int m = 0; m < MP; ++m) nv[m] = cnv[m][lane];
         }
         if (MODE == kCount || MODE == kSize) {
 #pragma unroll
