@@ -336,7 +336,11 @@ epi_status epi_costmodel_features(epi_ctx *ctx, int32_t set_id, float *X, int64_
  *     whose nodes 2..N of alpha equal nodes 1..N-1 of beta, intervals
  *     included, when the new type is not alpha's first.
  * Stops early when a level has no frequent episode.  Synchronous: returns
- * when every level is counted; *mine_id receives a handle.
+ * when every level is counted; *mine_id receives a handle.  The levels run
+ * on the context's stream, after the work queued on hip_stream so far (null:
+ * none).  Their device memory comes from a cache of the context, which
+ * keeps released blocks for reuse by later runs until epi_destroy (and gives
+ * them back to the device when an allocation would otherwise fail).
  * Errors: EPI_EINTERVAL / EPI_EOVERFLOW for a bad menu, EPI_ESIZE for a bad
  * max_size, plus those of counting. */
 epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64_t *menu_lo,

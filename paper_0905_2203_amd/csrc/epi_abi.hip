@@ -281,6 +281,7 @@ void epi_destroy(epi_ctx *ctx) {
     ctx->c.sets.clear();
     ctx->c.streams.clear();
     ctx->c.flags.reset();
+    ctx->c.cache.release();
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
     delete ctx;
 }
@@ -618,7 +619,18 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     if (s->n > 0 && (s->tmax > thi - 1 - span || s->tmin < tlo + 1 + span))
         return fail(ctx, EPI_EOVERFLOW, "stream times +- the longest span leave the timestamp type");
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
-    hipStream_t st = pick_stream(ctx, hip_stream);
+    // the levels run on the context's stream, after the work already queued
+    // on the caller's; every buffer of the run comes from the context's cache
+    hipStream_t st = ctx->c.stream;
+    if (hip_stream && (hipStream_t)hip_stream != st) {
+        hipEvent_t ev;
+        HIPTRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        hipError_t e = hipEventRecord(ev, (hipStream_t)hip_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+        (void)hipEventDestroy(ev);
+        HIPTRY(ctx, e, "ordering after the caller's stream");
+    }
+    CacheScope scope(&ctx->c.cache);
     auto mn = std::make_unique<Mine>();
     mn->stream_id = stream_id;
     mn->menu_lo.assign(menu_lo, menu_lo + n_menu);

@@ -31,37 +31,113 @@ struct TsLimits {
     static constexpr T hi() { return std::numeric_limits<T>::max(); }
 };
 
-// Owning device allocation.
+// Device blocks kept for reuse, for work that runs on one stream only: a
+// block given back while kernels queued on that stream still use it is handed
+// out again only to later work of the same stream, which runs after them.
+// Blocks are taken best fit among those at most twice the request (plus
+// 1 MiB); new ones come from hipMalloc.  Every block is freed by release(),
+// which the owner calls after synchronising the stream.
+class BlockCache {
+public:
+    BlockCache() = default;
+    BlockCache(const BlockCache &) = delete;
+    BlockCache &operator=(const BlockCache &) = delete;
+    ~BlockCache() { release(); }
+    hipError_t get(size_t b, void **p, size_t *got) {
+        b = (b + 255) & ~(size_t)255;
+        auto it = free_.lower_bound(b);
+        if (it != free_.end() && it->first <= 2 * b + ((size_t)1 << 20)) {
+            *p = it->second;
+            *got = it->first;
+            free_.erase(it);
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc(p, b);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+            // give the kept blocks back to the device (once no queued work
+            // can use them) and try once more
+            (void)hipGetLastError();
+            (void)hipDeviceSynchronize();
+            release();
+            e = hipMalloc(p, b);
+        }
+        if (e != hipSuccess) return e;
+        *got = b;
+        return hipSuccess;
+    }
+    void put(void *p, size_t bytes) { free_.emplace(bytes, p); }
+    void release() {
+        for (auto &kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+    }
+
+private:
+    std::multimap<size_t, void *> free_;
+};
+
+// While a CacheScope is alive, DevBuf::alloc of the calling thread takes its
+// blocks from the scope's cache (and gives them back to it); otherwise it
+// uses hipMalloc and hipFree.
+struct CacheScope {
+    static BlockCache *&current() {
+        static thread_local BlockCache *c = nullptr;
+        return c;
+    }
+    BlockCache *prev;
+    explicit CacheScope(BlockCache *c) : prev(current()) { current() = c; }
+    ~CacheScope() { current() = prev; }
+    CacheScope(const CacheScope &) = delete;
+    CacheScope &operator=(const CacheScope &) = delete;
+};
+
+// Owning device allocation (from the thread's cache scope, if any, which it
+// must not outlive).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    BlockCache *cache = nullptr;  // where the block goes back to (null: hipFree)
+    size_t block = 0;             // the cached block's size
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), cache(o.cache), block(o.block) {
         o.p = nullptr;
         o.bytes = 0;
+        o.cache = nullptr;
     }
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             reset();
             p = o.p;
             bytes = o.bytes;
+            cache = o.cache;
+            block = o.block;
             o.p = nullptr;
             o.bytes = 0;
+            o.cache = nullptr;
         }
         return *this;
     }
     ~DevBuf() { reset(); }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (cache) cache->put(p, block);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        cache = nullptr;
     }
     hipError_t alloc(size_t b) {
         reset();
         if (b == 0) b = 16;
-        hipError_t e = hipMalloc(&p, b);
+        hipError_t e;
+        if (BlockCache *c = CacheScope::current()) {
+            e = c->get(b, &p, &block);
+            if (e == hipSuccess) cache = c;
+        } else {
+            e = hipMalloc(&p, b);
+        }
         if (e != hipSuccess) {
             p = nullptr;
             return e;
@@ -229,6 +305,9 @@ struct Mlp {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // blocks of the mining working set (all of it runs on `stream`), kept for
+    // reuse until the context is destroyed
+    BlockCache cache;
     std::string err;
     std::map<int32_t, std::unique_ptr<Stream>> streams;
     std::map<int32_t, std::unique_ptr<CandSet>> sets;
