@@ -264,7 +264,9 @@ epi_status epi_create(int device, epi_ctx **out) {
     ctx->c.device = device;
     if ((e = hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = ctx->c.flags.alloc(sizeof(int32_t) * kNumFlags)) != hipSuccess ||
-        (e = hipMemset(ctx->c.flags.p, 0, sizeof(int32_t) * kNumFlags)) != hipSuccess) {
+        (e = hipMemset(ctx->c.flags.p, 0, sizeof(int32_t) * kNumFlags)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&ctx->c.stage, sizeof(int64_t) * kStageSlots, hipHostMallocDefault)) !=
+            hipSuccess) {
         g_create_err = hipGetErrorString(e);
         delete ctx;
         return EPI_EDEVICE;
@@ -282,6 +284,7 @@ void epi_destroy(epi_ctx *ctx) {
     ctx->c.streams.clear();
     ctx->c.flags.reset();
     ctx->c.cache.release();
+    if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
     delete ctx;
 }
@@ -633,6 +636,7 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     CacheScope scope(&ctx->c.cache);
     auto mn = std::make_unique<Mine>();
     mn->stream_id = stream_id;
+    mn->stage = ctx->c.stage;
     mn->menu_lo.assign(menu_lo, menu_lo + n_menu);
     mn->menu_hi.assign(menu_hi, menu_hi + n_menu);
     mn->threshold = threshold;

@@ -957,12 +957,15 @@ hipError_t order_by_key(const uint16_t *key, const int32_t *idx, int64_t n, int3
     if ((e = scan64(cnt.as<int32_t>(), nb * K, off.as<int64_t>(), tmp, st)) != hipSuccess) return e;
     k_key_place<<<(unsigned)nb, kBlock, lds, st>>>(key, idx, n, K, off.as<int64_t>(), order.as<int32_t>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return hipStreamSynchronize(st);  // the temporaries die here
+    // the temporaries die here: blocks of a cache scope go back for later
+    // work of this stream, others are freed after it
+    return CacheScope::current() ? hipGetLastError() : hipStreamSynchronize(st);
 }
 
 template <typename T>
 hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     hipError_t e;
+    if (!mn.stage) return hipErrorInvalidValue;
     MineLevel &P = mn.levels.back();  // level N-1
     MineLevel L;
     L.N = N;
@@ -1077,6 +1080,24 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     }
     if (m > 0 && !listed && e == hipSuccess) e = launch_walk<T, kCount>(a, nA, st);
     (void)hipEventRecord(ev1, st);
+    // the walked positions and the number of frequent episodes reach the host
+    // at one synchronisation (pinned slots 0 and 1)
+    int64_t *stage = mn.stage;
+    if (e == hipSuccess) e = hipMemcpyAsync(&stage[0], d_walked.p, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    // ---- frequent episodes, selected on the device
+    const int64_t nb = m > 0 ? (m + kSelTile - 1) / kSelTile : 0;
+    int64_t nf = 0;
+    DevBuf bcnt, boffs;
+    if (e == hipSuccess) e = bcnt.alloc(sizeof(int32_t) * std::max<int64_t>(1, nb));
+    if (e == hipSuccess) e = boffs.alloc(sizeof(int64_t) * (nb + 1));
+    const int32_t thr = (int32_t)std::max<int64_t>(INT32_MIN, std::min<int64_t>(mn.threshold, INT32_MAX));
+    if (nb > 0 && e == hipSuccess) {
+        k_sel_count<<<(unsigned)nb, kBlock, 0, st>>>(a.counts, m, thr, bcnt.as<int32_t>());
+        e = hipGetLastError();
+        if (e == hipSuccess) e = scan64(bcnt.as<int32_t>(), nb, boffs.as<int64_t>(), tmp, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&stage[1], boffs.as<int64_t>() + nb, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     float kms = 0;
     if (e == hipSuccess) (void)hipEventElapsedTime(&kms, ev0, ev1);
@@ -1084,24 +1105,8 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     (void)hipEventDestroy(ev1);
     if (e != hipSuccess) return e;
     L.kernel_ms = kms;
-    {
-        unsigned long long wk = 0;
-        if ((e = read_scalar(d_walked, 0, &wk, st)) != hipSuccess) return e;
-        L.walked = (int64_t)wk;
-    }
-    // ---- frequent episodes, selected on the device
-    const int64_t nb = m > 0 ? (m + kSelTile - 1) / kSelTile : 0;
-    int64_t nf = 0;
-    DevBuf bcnt, boffs;
-    if ((e = bcnt.alloc(sizeof(int32_t) * std::max<int64_t>(1, nb))) != hipSuccess) return e;
-    if ((e = boffs.alloc(sizeof(int64_t) * (nb + 1))) != hipSuccess) return e;
-    const int32_t thr = (int32_t)std::max<int64_t>(INT32_MIN, std::min<int64_t>(mn.threshold, INT32_MAX));
-    if (nb > 0) {
-        k_sel_count<<<(unsigned)nb, kBlock, 0, st>>>(a.counts, m, thr, bcnt.as<int32_t>());
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = scan64(bcnt.as<int32_t>(), nb, boffs.as<int64_t>(), tmp, st)) != hipSuccess) return e;
-        if ((e = read_scalar(boffs, nb, &nf, st)) != hipSuccess) return e;
-    }
+    L.walked = stage[0];
+    if (nb > 0) nf = stage[1];
     L.nf = nf;
     const size_t nfa = (size_t)std::max<int64_t>(1, nf);
     if ((e = L.d_fcand.alloc(sizeof(int64_t) * nfa)) != hipSuccess) return e;
@@ -1142,12 +1147,16 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         // chain lists)
         DevBuf tmp2, flag, jidx, job_alpha, job_f, w_order;
         if ((e = scan64(L.d_fnv.as<int32_t>(), nf, L.cbeg.as<int64_t>(), tmp2, st)) != hipSuccess) return e;
-        if ((e = read_scalar(L.cbeg, nf, &L.chain_total, st)) != hipSuccess) return e;
+        // the chain entries in all (pinned slot 2), read at the next synchronisation
+        if ((e = hipMemcpyAsync(&stage[2], L.cbeg.as<int64_t>() + nf, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                st)) != hipSuccess)
+            return e;
         if (listed) {
             k_list_begin<<<grid_of(nf), kBlock, 0, st>>>(L.d_fcand.as<int64_t>(), lst_off.as<int64_t>(), L.list_seg,
                                                          nf, L.cbeg.as<int64_t>());
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            L.chain_total = stage[2];
             L.count_ms = ms_since(t1);
             goto done;
         }
@@ -1156,8 +1165,12 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         if ((e = jidx.alloc(sizeof(int64_t) * (nf + 1))) != hipSuccess) return e;
         k_job_flags<<<grid_of(nf), kBlock, 0, st>>>(L.d_fpar.as<int32_t>(), nf, flag.as<int32_t>());
         if ((e = scan64(flag.as<int32_t>(), nf, jidx.as<int64_t>(), tmp, st)) != hipSuccess) return e;
-        int64_t nj = 0;
-        if ((e = read_scalar(jidx, nf, &nj, st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(&stage[3], jidx.as<int64_t>() + nf, sizeof(int64_t), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        L.chain_total = stage[2];
+        const int64_t nj = stage[3];
         if ((e = job_alpha.alloc(sizeof(int32_t) * nj)) != hipSuccess) return e;
         if ((e = job_f.alloc(sizeof(int64_t) * (nj + 1))) != hipSuccess) return e;
         k_job_write<<<grid_of(nf + 1), kBlock, 0, st>>>(L.d_fpar.as<int32_t>(), flag.as<int32_t>(),

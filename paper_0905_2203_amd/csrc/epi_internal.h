@@ -285,6 +285,9 @@ struct Mine {
     // level may take (larger: count and write walks)
     int64_t list_budget = 0;
     double bits_ms = 0;
+    // pinned host slots (the context's) that device scalars are copied to,
+    // several per synchronisation
+    int64_t *stage = nullptr;
 };
 
 // Cost model (epi_mlp.hip): parameters, Adam moments, gradient, activations.
@@ -308,6 +311,7 @@ struct Ctx {
     // blocks of the mining working set (all of it runs on `stream`), kept for
     // reuse until the context is destroyed
     BlockCache cache;
+    int64_t *stage = nullptr;  // pinned host slots of the mining runs (kStageSlots)
     std::string err;
     std::map<int32_t, std::unique_ptr<Stream>> streams;
     std::map<int32_t, std::unique_ptr<CandSet>> sets;
@@ -351,6 +355,7 @@ int queue_class_of(int64_t bound);
 // then count level N (>= 2) from level N-1's frequent episodes and chain lists,
 // select its frequent episodes and write their chain lists.  Menus of up to
 // kExtMaxMenu intervals.
+constexpr int kStageSlots = 8;     // pinned host slots of a mining run
 constexpr int kExtMaxMenu = 8;
 hipError_t extend_prepare(const Stream &s, Mine &mn, hipStream_t st);
 hipError_t extend_level1(const Stream &s, Mine &mn, hipStream_t st);
