@@ -816,6 +816,16 @@ __global__ __launch_bounds__(kBlock) void k_job_write(const int32_t *__restrict_
     }
 }
 
+// Length class of each job's alpha: leading zeros of its chain-list length,
+// so that ordering by the key takes the longest walks first.
+__global__ __launch_bounds__(kBlock) void k_len_key(const int32_t *__restrict__ clen, const int32_t *__restrict__ idx,
+                                                    int64_t n, uint16_t *__restrict__ key) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int32_t a = idx ? idx[j] : (int32_t)j;
+    key[j] = (uint16_t)__clz((uint32_t)clen[a] | 1u);
+}
+
 // Jobs grouped by a uint16 key (the alphas' last type): a counting sort whose
 // histogram is kept per block in LDS (kKeyItems jobs per block), so that a
 // block adds each key once; the order inside a key is arbitrary.
@@ -998,7 +1008,12 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         if ((e = read_scalar(L.d_out_off, nA, &m, st)) != hipSuccess) return e;
         // workgroups take the alphas grouped by their last type: the waves in
         // flight then walk the neighbourhoods of the same type's events
-        if ((e = order_by_key(P.d_flast.as<uint16_t>(), nullptr, nA, s.K, d_order, st)) != hipSuccess) return e;
+        {
+            DevBuf lkey;
+            if ((e = lkey.alloc(sizeof(uint16_t) * std::max<int64_t>(1, nA))) != hipSuccess) return e;
+            k_len_key<<<grid_of(nA), kBlock, 0, st>>>(P.d_fnv.as<int32_t>(), nullptr, nA, lkey.as<uint16_t>());
+            if ((e = order_by_key(lkey.as<uint16_t>(), nullptr, nA, 33, d_order, st)) != hipSuccess) return e;
+        }
     }
     L.m = m;
     WalkArgs<T> a{};
@@ -1178,9 +1193,12 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
                                                        job_f.as<int64_t>());
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (N > 2) {
-            if ((e = order_by_key(P.d_flast.as<uint16_t>(), job_alpha.as<int32_t>(), nj, s.K, w_order, st)) !=
-                hipSuccess)
-                return e;
+            // few jobs: the longest walks first, so that none is left alone at the end
+            DevBuf lkey;
+            if ((e = lkey.alloc(sizeof(uint16_t) * std::max<int64_t>(1, nj))) != hipSuccess) return e;
+            k_len_key<<<grid_of(nj), kBlock, 0, st>>>(P.d_fnv.as<int32_t>(), job_alpha.as<int32_t>(), nj,
+                                                      lkey.as<uint16_t>());
+            if ((e = order_by_key(lkey.as<uint16_t>(), nullptr, nj, 33, w_order, st)) != hipSuccess) return e;
         }
         const size_t tot = (size_t)L.chain_total;
         if ((e = L.chain.alloc(sizeof(ChainEntry<T>) * tot)) != hipSuccess) return e;
