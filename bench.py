@@ -140,23 +140,42 @@ def ablation(k, scale, reps):
                                                                 sched=epi.EPI_SCHED_MEASURED), reps)
     assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "measured"
     log(f"  measured-cost schedule {res['batched_measured']:.3f}s")
-    # parity: a seeded sample of every set's counts against the oracle
+    # parity: a seeded sample of every set's counts against the oracle, which
+    # is timed on it (all host cores)
     parity = "not checked"
+    cpu = None
     try:
         import oracle
         import spikegen as sg_
 
         rng = np.random.Generator(np.random.PCG64(11))
         bad = checked = 0
+        cores = oracle.max_threads()
+        cpu_units = cpu_s = 0.0
         for (s_, c_), got in zip(sets, ref):
             idx = np.sort(rng.choice(c_["N"].size, size=min(64, c_["N"].size), replace=False))
-            want = oracle.count(s_, sg_.take_candidates(c_, idx))
+            a = time.perf_counter()
+            want = oracle.count(s_, sg_.take_candidates(c_, idx), nthreads=cores)
+            cpu_s += time.perf_counter() - a
+            cpu_units += idx.size * s_["types"].size
             bad += int((want != got[idx]).sum())
             checked += idx.size
         parity = f"{'ok' if bad == 0 else 'MISMATCH'}: {checked} sampled counts vs the oracle, {bad} differ"
+        cpu = dict(value=cpu_units / cpu_s, unit="cand*ev/s", cores=cores, kind="oracle",
+                   sample=f"the {checked} parity candidates, {cpu_s:.2f}s")
         log(f"  parity {parity}")
     except Exception as exc:
         log(f"oracle leg failed: {exc!r}")
+    # algorithmic bytes of the state-machine engines: each candidate reads the
+    # times of its own types' events, its descriptor, and writes its count
+    alg = 0
+    for s_, c_ in sets:
+        tc = np.bincount(s_["types"], minlength=s_["K"]).astype(np.int64)
+        tsb = 8 if s_["ts_kind"] == 1 else 4
+        N_ = c_["N"].astype(np.int64)
+        ty_ = c_["types"].astype(np.int64)
+        per = np.where(np.arange(8)[None, :] < N_[:, None], tc[np.clip(ty_, 0, None)], 0).sum(axis=1)
+        alg += int(per.sum()) * tsb + int(N_.size) * ((128 if tsb == 8 else 72) + 4)
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s",
@@ -170,6 +189,9 @@ def ablation(k, scale, reps):
                        "train_candidates": int(sum(c["N"].size for _, c in train_sets))},
         "counts_equal_across_modes": True,
         "parity": parity,
+        "algorithmic_bytes": alg,
+        "algorithmic_GBps": {m: alg / t / 1e9 for m, t in res.items()},
+        "cpu_baseline": cpu,
         "candidates": int(sum(c["N"].size for _, c in sets)), "events": int(sum(s["types"].size for s, _ in sets)),
     }
     print(json.dumps(line), flush=True)
@@ -186,7 +208,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (scale reference for HBM byte counters)")
     ap.add_argument("--ablation", default="",
-                    help="comma list of workload presets (3, 4, 5): plain vs batched schedules, one JSON line each")
+                    help="comma list of workload presets (1, 3, 4, 5): plain vs batched schedules, one JSON line each")
     ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
     args = ap.parse_args()
     if args.ablation:

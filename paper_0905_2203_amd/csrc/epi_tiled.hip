@@ -28,6 +28,14 @@
 // of the speculative count is taken as is; otherwise the re-run covers the
 // whole segment.  It also stops at B_p + H if neither machine has completed
 // by then: from there on both hold the same state.
+//
+// The walk over the segments is sequential in tau, but tau is nearly always
+// the last completion the earlier segments' records give (a re-run that
+// meets the speculative run ends on the record's last completion).  So a
+// pre-pass (k_reconcile_pre, one lane per candidate and segment, all in
+// parallel) re-runs every segment from that predicted tau, and the
+// sequential walk takes the pre-pass result whenever its true tau equals the
+// prediction, re-running itself only when it does not.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -70,6 +78,12 @@ struct CountArgs {
     int32_t *rec_cnt;
     T *rec_last;
     T *rec_first;
+    // reconciliation pre-pass: each segment's true completions and last true
+    // completion when re-run from pre_tau, the last completion the records
+    // of the earlier segments give (null: no pre-pass)
+    int32_t *pre_cnt;
+    T *pre_last;
+    T *pre_tau;
     int32_t *flags;
     uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc;
     const int32_t *perm;  // lane slot -> candidate slot (scheduler order); null = identity
@@ -434,16 +448,113 @@ __device__ __forceinline__ int32_t upper_bound(const T *ts, int32_t lo, int32_t 
     return lo;
 }
 
+// Segment p of candidate lane s, given tau (the last true completion before
+// B_p): returns the segment's true completions and moves tau to the last
+// true completion up to the segment's end.  f holds the lane's machine (LDS).
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ int64_t rerun_segment(const CountArgs<T> &a, LaneFsm<T, N> &f, const int32_t (&lo_)[N],
+                                 const int32_t (&hi_)[N], T H, int p, int64_t s, T &tau) {
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kEnd = TsLimits<T>::hi();
-    const int W = blockDim.x, lane = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * W + lane;
-    if (s >= a.G) return;  // no barriers below
-    const int64_t slot = a.perm ? (int64_t)a.perm[a.begin + s] : a.begin + s;
-    LaneFsm<T, N> f;
+    const int64_t b0 = (int64_t)p * a.S;
+    const int64_t b1 = b0 + a.S < a.B ? b0 + a.S : a.B;
+    const T Bp = p == 0 ? kMin : a.tile_t0[b0];
+    const T Ep = p == a.P - 1 ? kEnd : a.tile_t0[b1];
+    const int32_t c = a.rec_cnt[(int64_t)p * a.G + s];
+    const T last = a.rec_last[(int64_t)p * a.G + s];
+    if (p == 0 || tau < (T)(Bp - H)) {
+        if (c > 0) tau = last;
+        return c;
+    }
+    // re-run from the state right after the completion at tau
+    f.e = tau;
+    f.clear_all();
+    // first event after tau of every node: the N binary searches advance in
+    // lockstep, so that each step's loads are issued together
+    int32_t cur[N], hb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        cur[k] = lo_[k];
+        hb[k] = hi_[k];
+    }
+    for (;;) {
+        bool any = false;
+        int32_t mid[N];
+        T v[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            mid[k] = cur[k] + (hb[k] - cur[k]) / 2;
+            any |= cur[k] < hb[k];
+        }
+        if (!any) break;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = cur[k] < hb[k] ? a.ts_by_type[mid[k]] : T(0);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (cur[k] < hb[k]) {
+                if (v[k] <= tau) cur[k] = mid[k] + 1;
+                else hb[k] = mid[k];
+            }
+        }
+    }
+    T head[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const T v = cur[k] < hi_[k] ? a.ts_by_type[cur[k]] : kEnd;
+        head[k] = v < Ep ? v : kEnd;
+    }
+    const int nspec = c < kRecFirst ? c : kRecFirst;
+    // From B_p + H on, every partial occurrence either machine holds
+    // started after B_p, hence after both machines' last completion
+    // (tau < B_p; the speculative one's, if any, is before B_p as long as
+    // it has none in the segment yet): until one of them completes, both
+    // hold the same state, and from then on they agree.
+    const T sync_t = (T)(Bp + H);
+    const T first0 = c > 0 ? a.rec_first[((int64_t)p * kRecFirst) * a.G + s] : kEnd;
+    int qi = 0;
+    int32_t fcount = 0;
+    T flast = tau;
+    while (true) {
+        T t = head[0];
+        int j = 0;
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            if (head[k] < t) {
+                t = head[k];
+                j = k;
+            }
+        }
+        if (t == kEnd) break;
+        if (fcount == 0 && t >= sync_t && first0 >= t) {
+            if (c > 0) tau = last;
+            return c;
+        }
+        if (f.step(j, t, a.flags)) {
+            ++fcount;
+            flast = t;
+            while (qi < nspec && a.rec_first[((int64_t)p * kRecFirst + qi) * a.G + s] < t) ++qi;
+            if (qi < nspec && a.rec_first[((int64_t)p * kRecFirst + qi) * a.G + s] == t) {
+                tau = last;
+                return fcount + (c - qi - 1);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (k == j) {
+                ++cur[k];
+                const T v = cur[k] < hi_[k] ? a.ts_by_type[cur[k]] : kEnd;
+                head[k] = v < Ep ? v : kEnd;
+            }
+        }
+    }
+    tau = flast;
+    return fcount;
+}
+
+// The lane's machine in LDS and its candidate's per-node index ranges.
+template <typename T, int N>
+__device__ __forceinline__ T reconcile_lane(const CountArgs<T> &a, unsigned char *smem, int W, int lane, int64_t slot,
+                                            LaneFsm<T, N> &f, int32_t (&lo_)[N], int32_t (&hi_)[N]) {
     f.lohi = reinterpret_cast<Pair<T> *>(smem);
     f.qse = reinterpret_cast<Pair<T> *>(smem + a.off_qse);
     f.qh = reinterpret_cast<uint32_t *>(smem + a.off_qh);
@@ -455,89 +566,59 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
     int32_t ty[N];
     T lo[L], hi[L];
     const T H = load_candidate<T, N>(a, f, slot, ty, lo, hi);
-    int32_t lo_[N], hi_[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         lo_[k] = a.type_off[ty[k]];
         hi_[k] = a.type_off[ty[k] + 1];
     }
-    T tau = kMin;
+    return H;
+}
+
+// Pre-pass: lane (s, p = blockIdx.y + 1) re-runs segment p from the last
+// completion the records of segments 0..p-1 give.
+template <typename T, int N>
+__global__ __launch_bounds__(64) void k_reconcile_pre(CountArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int W = blockDim.x, lane = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * W + lane;
+    if (s >= a.G) return;  // no barriers below
+    const int p = (int)blockIdx.y + 1;
+    const int64_t slot = a.perm ? (int64_t)a.perm[a.begin + s] : a.begin + s;
+    LaneFsm<T, N> f;
+    int32_t lo_[N], hi_[N];
+    const T H = reconcile_lane<T, N>(a, smem, W, lane, slot, f, lo_, hi_);
+    T tau = TsLimits<T>::lo();
+    for (int q = p - 1; q >= 0; --q) {
+        if (a.rec_cnt[(int64_t)q * a.G + s] > 0) {
+            tau = a.rec_last[(int64_t)q * a.G + s];
+            break;
+        }
+    }
+    const int64_t o = (int64_t)p * a.G + s;
+    a.pre_tau[o] = tau;
+    a.pre_cnt[o] = (int32_t)rerun_segment<T, N>(a, f, lo_, hi_, H, p, s, tau);
+    a.pre_last[o] = tau;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int W = blockDim.x, lane = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * W + lane;
+    if (s >= a.G) return;  // no barriers below
+    const int64_t slot = a.perm ? (int64_t)a.perm[a.begin + s] : a.begin + s;
+    LaneFsm<T, N> f;
+    int32_t lo_[N], hi_[N];
+    const T H = reconcile_lane<T, N>(a, smem, W, lane, slot, f, lo_, hi_);
+    T tau = TsLimits<T>::lo();
     int64_t total = 0;
     for (int p = 0; p < a.P; ++p) {
-        const int64_t b0 = (int64_t)p * a.S;
-        const int64_t b1 = b0 + a.S < a.B ? b0 + a.S : a.B;
-        const T Bp = p == 0 ? kMin : a.tile_t0[b0];
-        const T Ep = p == a.P - 1 ? kEnd : a.tile_t0[b1];
-        const int32_t c = a.rec_cnt[(int64_t)p * a.G + s];
-        const T last = a.rec_last[(int64_t)p * a.G + s];
-        if (p == 0 || tau < (T)(Bp - H)) {
-            total += c;
-            if (c > 0) tau = last;
-            continue;
-        }
-        // re-run from the state right after the completion at tau
-        f.e = tau;
-        f.clear_all();
-        int32_t cur[N];
-        T head[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            cur[k] = upper_bound(a.ts_by_type, lo_[k], hi_[k], tau);
-            const T v = cur[k] < hi_[k] ? a.ts_by_type[cur[k]] : kEnd;
-            head[k] = v < Ep ? v : kEnd;
-        }
-        const int nspec = c < kRecFirst ? c : kRecFirst;
-        // From B_p + H on, every partial occurrence either machine holds
-        // started after B_p, hence after both machines' last completion
-        // (tau < B_p; the speculative one's, if any, is before B_p as long as
-        // it has none in the segment yet): until one of them completes, both
-        // hold the same state, and from then on they agree.
-        const T sync_t = (T)(Bp + H);
-        const T first0 = c > 0 ? a.rec_first[((int64_t)p * kRecFirst) * a.G + s] : kEnd;
-        int qi = 0;
-        int32_t fcount = 0;
-        T flast = tau;
-        bool synced = false;
-        while (true) {
-            T t = head[0];
-            int j = 0;
-#pragma unroll
-            for (int k = 1; k < N; ++k) {
-                if (head[k] < t) {
-                    t = head[k];
-                    j = k;
-                }
-            }
-            if (t == kEnd) break;
-            if (fcount == 0 && t >= sync_t && first0 >= t) {
-                total += c;
-                if (c > 0) tau = last;
-                synced = true;
-                break;
-            }
-            if (f.step(j, t, a.flags)) {
-                ++fcount;
-                flast = t;
-                while (qi < nspec && a.rec_first[((int64_t)p * kRecFirst + qi) * a.G + s] < t) ++qi;
-                if (qi < nspec && a.rec_first[((int64_t)p * kRecFirst + qi) * a.G + s] == t) {
-                    total += fcount + (c - qi - 1);
-                    tau = last;
-                    synced = true;
-                    break;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                if (k == j) {
-                    ++cur[k];
-                    const T v = cur[k] < hi_[k] ? a.ts_by_type[cur[k]] : kEnd;
-                    head[k] = v < Ep ? v : kEnd;
-                }
-            }
-        }
-        if (!synced) {
-            total += fcount;
-            tau = flast;
+        const int64_t o = (int64_t)p * a.G + s;
+        if (p > 0 && a.pre_cnt && a.pre_tau[o] == tau) {
+            total += a.pre_cnt[o];
+            tau = a.pre_last[o];
+        } else {
+            total += rerun_segment<T, N>(a, f, lo_, hi_, H, p, s, tau);
         }
     }
     a.counts[a.orig ? a.orig[slot] : slot] = (int32_t)total;
@@ -581,7 +662,23 @@ KFn<T> pick_reconcile(int N) {
     }
 }
 
+template <typename T>
+KFn<T> pick_reconcile_pre(int N) {
+    switch (N) {
+        case 1: return k_reconcile_pre<T, 1>;
+        case 2: return k_reconcile_pre<T, 2>;
+        case 3: return k_reconcile_pre<T, 3>;
+        case 4: return k_reconcile_pre<T, 4>;
+        case 5: return k_reconcile_pre<T, 5>;
+        case 6: return k_reconcile_pre<T, 6>;
+        case 7: return k_reconcile_pre<T, 7>;
+        case 8: return k_reconcile_pre<T, 8>;
+        default: return nullptr;
+    }
+}
+
 inline uint32_t al16(size_t x) { return (uint32_t)((x + 15) & ~size_t(15)); }
+
 
 template <typename T>
 struct Layout {
@@ -633,6 +730,50 @@ hipError_t ensure_lds_attr(KFn<T> fn, uint32_t bytes) {
     if (bytes <= kLdsSoft) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)bytes);
+}
+
+constexpr int kRecLanes = 64;  // lanes per reconciliation workgroup
+
+// Bytes of the segment records of a unit of G lanes and P segments: per
+// (segment, lane) the speculative last and first completions and count, and
+// the pre-pass's assumed tau, last completion and count.
+template <typename T>
+size_t record_bytes(int64_t P, int64_t G) {
+    return (size_t)P * (size_t)G * (sizeof(T) * (3 + kRecFirst) + 2 * sizeof(int32_t));
+}
+
+template <typename T>
+void set_records(CountArgs<T> &a, unsigned char *base, int64_t P, int64_t G) {
+    const size_t PG = (size_t)P * (size_t)G;
+    a.rec_last = reinterpret_cast<T *>(base);
+    a.rec_first = a.rec_last + PG;
+    a.pre_last = a.rec_first + PG * kRecFirst;
+    a.pre_tau = a.pre_last + PG;
+    a.rec_cnt = reinterpret_cast<int32_t *>(a.pre_tau + PG);
+    a.pre_cnt = a.rec_cnt + PG;
+}
+
+// Reconciliation of a unit's segments: the pre-pass over every (lane,
+// segment > 0) in parallel, then the walk over the segments.
+template <typename T>
+hipError_t launch_reconcile(const CountArgs<T> &a, int N, const Layout<T> &RL, hipStream_t st) {
+    if (a.P < 2 || a.P > 65536 || !a.pre_cnt) return hipErrorInvalidValue;
+    CountArgs<T> r = a;
+    r.off_qse = RL.off_qse;
+    r.off_qh = RL.off_qh;
+    r.off_tbuf = RL.off_tbuf;
+    r.off_obuf = RL.off_obuf;
+    r.off_misc = RL.off_misc;
+    KFn<T> pf = pick_reconcile_pre<T>(N), rf = pick_reconcile<T>(N);
+    if (!pf || !rf) return hipErrorInvalidValue;
+    hipError_t e;
+    if ((e = ensure_lds_attr<T>(pf, RL.total)) != hipSuccess) return e;
+    if ((e = ensure_lds_attr<T>(rf, RL.total)) != hipSuccess) return e;
+    const unsigned gx = (unsigned)((r.G + kRecLanes - 1) / kRecLanes);
+    pf<<<dim3(gx, (unsigned)(r.P - 1)), kRecLanes, RL.total, st>>>(r);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    rf<<<gx, kRecLanes, RL.total, st>>>(r);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -701,15 +842,12 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.off_obuf = L.off_obuf;
         a.off_misc = L.off_misc;
         if (P > 1) {
-            const size_t need = (size_t)P * G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst));
+            const size_t need = record_bytes<T>(P, G);
             if (c.scratch.bytes < need) {
                 if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
                 if ((e = c.scratch.alloc(need)) != hipSuccess) return e;
             }
-            unsigned char *base = c.scratch.as<unsigned char>();
-            a.rec_last = reinterpret_cast<T *>(base);
-            a.rec_first = a.rec_last + (size_t)P * G;
-            a.rec_cnt = reinterpret_cast<int32_t *>(a.rec_first + (size_t)P * G * kRecFirst);
+            set_records<T>(a, c.scratch.as<unsigned char>(), P, G);
         }
         const bool filtered = c.compact && c.pred_bits && c.succ_bits;
         a.pbits = filtered ? c.pred_bits : nullptr;
@@ -721,20 +859,8 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         const dim3 grid((unsigned)((G + W - 1) / W), (unsigned)P);
         fn<<<grid, W, lds, st>>>(a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (P > 1) {
-            KFn<T> rf = pick_reconcile<T>(g.N);
-            const int RW = 64;
-            const Layout<T> RL = layout<T>(g.N, g.Q, RW, s.K, false);
-            CountArgs<T> r = a;
-            r.off_qse = RL.off_qse;
-            r.off_qh = RL.off_qh;
-            r.off_tbuf = RL.off_tbuf;
-            r.off_obuf = RL.off_obuf;
-            r.off_misc = RL.off_misc;
-            if ((e = ensure_lds_attr<T>(rf, RL.total)) != hipSuccess) return e;
-            rf<<<(unsigned)((G + RW - 1) / RW), RW, RL.total, st>>>(r);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
+        if (P > 1 && (e = launch_reconcile<T>(a, g.N, layout<T>(g.N, g.Q, kRecLanes, s.K, false), st)) != hipSuccess)
+            return e;
     }
     return hipSuccess;
 }
@@ -905,7 +1031,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     // 3. per-unit arguments (records, work log) and work items per episode size
     size_t rec_bytes = 0;
     for (const UnitH &u : units)
-        if (u.P > 1) rec_bytes += (size_t)u.P * u.G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst)) + 64;
+        if (u.P > 1) rec_bytes += record_bytes<T>(u.P, u.G) + 64;
     DevBuf rec;
     if ((e = rec.alloc(rec_bytes)) != hipSuccess) return e;
     // launch classes: episode size x queue class (each with its own lane
@@ -956,11 +1082,8 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         a.perm = perms[u.set].p ? perms[u.set].template as<int32_t>() : nullptr;
         a.work = opt.worklog ? c.work.as<int32_t>() : nullptr;
         if (u.P > 1) {
-            unsigned char *base = rec.as<unsigned char>() + ro;
-            a.rec_last = reinterpret_cast<T *>(base);
-            a.rec_first = a.rec_last + (size_t)u.P * u.G;
-            a.rec_cnt = reinterpret_cast<int32_t *>(a.rec_first + (size_t)u.P * u.G * kRecFirst);
-            ro += ((size_t)u.P * u.G * (sizeof(int32_t) + sizeof(T) * (1 + kRecFirst)) + 64) & ~size_t(15);
+            set_records<T>(a, rec.as<unsigned char>() + ro, u.P, u.G);
+            ro += (record_bytes<T>(u.P, u.G) + 64) & ~size_t(15);
         }
         ua[ui] = a;
         const int cl = cls_of(u.N, u.Q);
@@ -1062,19 +1185,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         if (units[ui].P <= 1) continue;
         const int N = units[ui].N;
         const int cl = cls_of(N, units[ui].Q);
-        KFn<T> rf = pick_reconcile<T>(N);
-        const int RW = 64;
-        const Layout<T> RL = layout<T>(N, clsQ[cl], RW, maxK[cl], false);
-        CountArgs<T> r = ua[ui];
-        r.off_qse = RL.off_qse;
-        r.off_qh = RL.off_qh;
-        r.off_tbuf = RL.off_tbuf;
-        r.off_obuf = RL.off_obuf;
-        r.off_misc = RL.off_misc;
-        e = ensure_lds_attr<T>(rf, RL.total);
-        if (e != hipSuccess) break;
-        rf<<<(unsigned)((r.G + RW - 1) / RW), RW, RL.total, st>>>(r);
-        e = hipGetLastError();
+        e = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), st);
     }
     hipError_t ec = hipStreamEndCapture(st, &graph);
     if (e == hipSuccess) e = ec;
