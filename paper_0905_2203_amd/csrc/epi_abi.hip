@@ -152,12 +152,6 @@ epi_status check_candidates(int64_t m, const uint8_t *N, const int32_t *types, c
     return EPI_OK;
 }
 
-int queue_class(int64_t b) {
-    int q = 1;
-    while (q < b) q <<= 1;
-    return q;
-}
-
 template <typename T>
 hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int32_t *types, const int64_t *lo,
                              const int64_t *hi, hipStream_t st) {
@@ -188,9 +182,13 @@ hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int
             g.Q = key[c] % 64;
             g.begin = s;
             g.end = s;
+            g.hspan = 0;
             cs.groups.push_back(g);
         }
         cs.groups.back().end = s + 1;
+        int64_t sp = 0;
+        for (int j = 0; j + 1 < N[c]; ++j) sp += hi[(int64_t)c * 7 + j];
+        cs.groups.back().hspan = std::max(cs.groups.back().hspan, sp);
     }
     hipError_t e;
     if ((e = cs.types.alloc(sizeof(int32_t) * h_types.size())) != hipSuccess) return e;

@@ -23,6 +23,10 @@
 // completion, so every ring header is rewritten in every generation; a header
 // whose generation bit differs from the lane's current one is empty.
 //
+// The machine's times are of type T: the stream's timestamps, or (int64
+// streams whose tiles are short enough) int32 offsets from the start of the
+// tile being walked, moved along with rebase() at every tile.
+//
 // LDS layout (W lanes, node slots k = 0..N-2, all lane-interleaved so that a
 // wave-wide access to one slot touches consecutive words):
 //   lohi[k*W + lane]           (lo_k, hi_k)
@@ -64,6 +68,24 @@ struct LaneFsm {
     // Empty every ring (explicitly, not through the generation bit).
     __device__ __forceinline__ void clear_all() {
         for (int k = 0; k < N - 1; ++k) qh[k * W + lane] = gen << 16;
+    }
+
+    // Relative times: move the origin d later.  Interval starts before the
+    // new origin become -1 and ends before it -2: every later query or record
+    // is at a time >= 0, for which both compare as they did (a start before
+    // it, an end before it, i.e. dead).
+    __device__ __forceinline__ void rebase(T d) {
+        for (int k = 0; k < N - 1; ++k) {
+            uint32_t hd, n;
+            load_hdr(k, hd, n);
+            for (uint32_t i = 0; i < n; ++i) {
+                Pair<T> &v = slot(k, hd);
+                const T s = v.s - d, e = v.e - d;
+                v.s = s < T(-1) ? T(-1) : s;
+                v.e = e < T(-2) ? T(-2) : e;
+                hd = next(hd);
+            }
+        }
     }
 
     // Is t inside the acceptance intervals recorded at node slot k?  On a

@@ -275,6 +275,14 @@ hipError_t build_type_index(Stream &s, hipStream_t st) {
             for (int64_t b = 0; b <= B; ++b) s.h_tile_t0[b] = t32[b];
         }
     }
+    // longest tile: from its first time to the next tile's (the last tile:
+    // to the last event), saturated
+    s.max_tile_span = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        const int64_t end = b + 1 < B ? s.h_tile_t0[b + 1] : s.tmax;
+        const uint64_t d = (uint64_t)end - (uint64_t)s.h_tile_t0[b];
+        s.max_tile_span = std::max<int64_t>(s.max_tile_span, d > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)d);
+    }
     return hipSuccess;
 }
 

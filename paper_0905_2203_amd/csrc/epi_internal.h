@@ -170,6 +170,7 @@ struct Stream {
     DevBuf tile_t0;     // T[B+1]: time of each tile's first event; [B] = type maximum
     std::vector<int32_t> h_off;  // host copy of type_off
     std::vector<int64_t> h_tile_t0;  // host copy of tile_t0 (widened)
+    int64_t max_tile_span = -1;      // longest time from a tile's first event to the next tile's (or the last event)
     size_t ts_bytes() const { return ts_kind == EPI_TS_I64 ? 8 : 4; }
 };
 
@@ -178,7 +179,17 @@ struct Group {
     int N = 0;
     int Q = 0;
     int64_t begin = 0, end = 0;  // slots [begin, end) of the grouped layout
+    int64_t hspan = -1;          // longest span (sum of upper bounds) of its episodes (-1: unknown)
 };
+
+// Ring capacity of a launch class: the smallest of 1, 2, 3, 4, 6, 8, 12, 16
+// that holds queue bound b.
+inline int queue_class(int64_t b) {
+    static constexpr int kQ[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int q : kQ)
+        if (q >= b) return q;
+    return 16;
+}
 
 struct CandSet {
     int32_t stream_id = 0;

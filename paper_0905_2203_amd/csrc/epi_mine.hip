@@ -64,6 +64,8 @@ hipError_t count_level_t(const Stream &s, const Mine &mn, MineLevel &L, const Co
     g.Q = Q;
     g.begin = 0;
     g.end = m;
+    g.hspan = 0;
+    for (int i = 0; i < nm; ++i) g.hspan = std::max<int64_t>(g.hspan, mn.menu_hi[i] * (L.N - 1));
     cs.groups.push_back(g);
     if (mn.pred_bits.p && mn.succ_bits.p && L.N > 1) {
         cs.pred_bits = mn.pred_bits.as<uint64_t>();
@@ -101,11 +103,7 @@ hipError_t count_level_t(const Stream &s, const Mine &mn, MineLevel &L, const Co
 
 }  // namespace
 
-int queue_class_of(int64_t b) {
-    int q = 1;
-    while (q < b) q <<= 1;
-    return q;
-}
+int queue_class_of(int64_t b) { return queue_class(b); }
 
 hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const CountOptions &opt, int32_t *d_flags,
                             hipStream_t st) {

@@ -41,6 +41,8 @@
 #include <numeric>
 #include <vector>
 
+#include <type_traits>
+
 #include "epi_fsm.h"
 
 namespace epi {
@@ -91,8 +93,8 @@ struct CountArgs {
     int64_t *cycles;      // work log: wall-clock start/end per work item; null = off
 };
 
-template <typename T, int N>
-__device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N> &f, int64_t slot, int32_t *ty,
+template <typename T, int N, typename R>
+__device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<R, N> &f, int64_t slot, int32_t *ty,
                                            T *lo, T *hi) {
     T H = 0;
     if (a.t16) {
@@ -115,21 +117,26 @@ __device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<T, N>
     }
 #pragma unroll
     for (int k = 0; k + 1 < N; ++k) {
-        Pair<T> v;
-        v.s = lo[k];
-        v.e = hi[k];
+        Pair<R> v;
+        v.s = (R)lo[k];
+        v.e = (R)hi[k];
         f.lohi[k * f.W + f.lane] = v;
         H += hi[k];
     }
     return H;
 }
 
-// One work item: lane block `blk` of a launch unit, time segment p.
-template <typename T, int N, bool FILT>
+// One work item: lane block `blk` of a launch unit, time segment p.  REL
+// (int64 streams whose tiles are short enough, rel_ok): the machines and the
+// staged tile hold int32 offsets from the current tile's first time, which
+// halves their LDS.
+template <typename T, int N, bool FILT, bool REL>
 __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, int p, int64_t item,
                                            unsigned char *smem) {
+    using R = std::conditional_t<REL, int32_t, T>;
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kEnd = TsLimits<T>::hi();
+    constexpr R rEnd = TsLimits<R>::hi();
     constexpr int L = N > 1 ? N - 1 : 1;
     const int W = blockDim.x, lane = threadIdx.x;
     const int64_t s = blk * W + lane;
@@ -137,13 +144,13 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
     const int64_t lslot = a.begin + (active ? s : 0);
     const int64_t slot = a.perm ? (int64_t)a.perm[lslot] : lslot;
     if (a.cycles && lane == 0) a.cycles[2 * item] = (int64_t)wall_clock64();
-    T *tbuf = reinterpret_cast<T *>(smem + a.off_tbuf);
+    R *tbuf = reinterpret_cast<R *>(smem + a.off_tbuf);
     uint16_t *obuf = reinterpret_cast<uint16_t *>(smem + a.off_obuf);
     T *misc = reinterpret_cast<T *>(smem + a.off_misc);
 
-    LaneFsm<T, N> f;
-    f.lohi = reinterpret_cast<Pair<T> *>(smem);
-    f.qse = reinterpret_cast<Pair<T> *>(smem + a.off_qse);
+    LaneFsm<R, N> f;
+    f.lohi = reinterpret_cast<Pair<R> *>(smem);
+    f.qse = reinterpret_cast<Pair<R> *>(smem + a.off_qse);
     f.qh = reinterpret_cast<uint32_t *>(smem + a.off_qh);
     f.W = W;
     f.lane = lane;
@@ -151,14 +158,17 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
     f.gen = 0;
     int32_t ty[N];
     T lo[L], hi[L];
-    const T H = load_candidate<T, N>(a, f, slot, ty, lo, hi);
+    const T H = load_candidate<T, N, R>(a, f, slot, ty, lo, hi);
+    R hiR[L];
+#pragma unroll
+    for (int k = 0; k + 1 < N; ++k) hiR[k] = (R)hi[k];
     f.clear_all();
     // vf[k] (k >= 1): no node-k event before this time can meet constraint k
     // with the intervals currently recorded at node k-1 (a lower bound on the
     // earliest interval start + 1; the type maximum when none is recorded).
-    T vf[N];
+    R vf[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) vf[k] = kEnd;
+    for (int k = 0; k < N; ++k) vf[k] = rEnd;
     // pair-existence rows of each node (filtered mode)
     int64_t prow[N], srow[N];
 #pragma unroll
@@ -175,7 +185,7 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
     const int64_t b1 = b0 + a.S < a.B ? b0 + a.S : a.B;
     const T Bp = p == 0 ? kMin : a.tile_t0[b0];
     const T Ep = p == a.P - 1 ? kEnd : a.tile_t0[b1];
-    f.e = p == 0 ? kMin : (T)(Bp - H - 1);
+    const T e0 = p == 0 ? kMin : (T)(Bp - H - 1);
 
     // first tile: the last one starting before B_p - max H of the workgroup
     int64_t bs = b0;
@@ -206,14 +216,47 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
         bs = (int64_t)misc[8];
     }
 
+    // origin of the relative times (REL): the first time of the tile walked
+    T t0b = REL ? a.tile_t0[bs] : T(0);
+    if (REL) {
+        // e0 - t0b, or -2 (before the tile) when e0 is earlier than that
+        const bool before = e0 < t0b && (uint64_t)t0b - (uint64_t)e0 > 2u;
+        f.e = before ? R(-2) : (R)(int64_t)((uint64_t)e0 - (uint64_t)t0b);
+    } else {
+        f.e = (R)e0;
+    }
     int32_t cnt = 0;
     T last = kMin;
     uint32_t w_visits = 0, w_records = 0, w_queries = 0, w_done = 0;
     for (int64_t b = bs; b < b1; ++b) {
         __syncthreads();
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.tiled + b * kTile);
-        uint4 *dst = reinterpret_cast<uint4 *>(tbuf);
-        for (int i = lane; i < (int)(kTile * sizeof(T) / 16); i += W) dst[i] = src[i];
+        R BpR, EpR;  // segment bounds in the machine's time
+        if (REL) {
+            const T nb = a.tile_t0[b];
+            const R d = (R)(nb - t0b);  // the previous tile's span (0 for the first)
+            if (d != 0) {
+                f.rebase(d);
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    if (vf[k] != rEnd) vf[k] = vf[k] - d < R(-1) ? R(-1) : (R)(vf[k] - d);
+                f.e = f.e - d < R(-2) ? R(-2) : (R)(f.e - d);
+            }
+            t0b = nb;
+            const T *src = a.tiled + b * kTile;
+            // (the last tile's padding is never read; wrapping keeps it defined)
+            for (int i = lane; i < kTile; i += W) {
+                const int64_t v = (int64_t)((uint64_t)src[i] - (uint64_t)t0b);
+                tbuf[i] = v > (int64_t)INT32_MAX ? INT32_MAX : (v < -1 ? R(-1) : (R)v);
+            }
+            BpR = Bp <= t0b ? R(-1) : (Bp - t0b >= (T)INT32_MAX ? rEnd : (R)(Bp - t0b));
+            EpR = (Ep == kEnd || Ep - t0b >= (T)INT32_MAX) ? rEnd : (R)(Ep - t0b);
+        } else {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.tiled + b * kTile);
+            uint4 *dst = reinterpret_cast<uint4 *>(tbuf);
+            for (int i = lane; i < (int)(kTile * sizeof(T) / 16); i += W) dst[i] = src[i];
+            BpR = (R)Bp;
+            EpR = (R)Ep;
+        }
         for (int i = lane; i <= a.K; i += W) obuf[i] = a.loff[b * (a.K + 1) + i];
         __syncthreads();
         if (!active) continue;
@@ -223,7 +266,7 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
         int cur[N], stop[N];
         int wi[N], we[N];
         uint64_t msk[N], nmsk[N];  // current word's bits, next word's (prefetched)
-        T head[N];
+        R head[N];
         const int64_t wbase = b * (kTile / 64);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -245,15 +288,15 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
             if (k + 1 < N) m &= a.sbits[srow[k] + wbase + w];
             return m;
         };
-        auto filt_head = [&](const int k) -> T {
+        auto filt_head = [&](const int k) -> R {
             while (msk[k] == 0 && wi[k] < we[k]) {
                 ++wi[k];
                 msk[k] = nmsk[k];
                 nmsk[k] = wi[k] < we[k] ? word_bits(k, wi[k] + 1) : 0ull;
             }
-            if (msk[k] == 0) return kEnd;
-            const T v = tbuf[(wi[k] << 6) + (int)__builtin_ctzll(msk[k])];
-            return v < Ep ? v : kEnd;
+            if (msk[k] == 0) return rEnd;
+            const R v = tbuf[(wi[k] << 6) + (int)__builtin_ctzll(msk[k])];
+            return v < EpR ? v : rEnd;
         };
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -271,13 +314,13 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
             if (FILT) {
                 head[k] = filt_head(k);
             } else {
-                const T v = cur[k] < stop[k] ? tbuf[cur[k]] : kEnd;
-                head[k] = v < Ep ? v : kEnd;
+                const R v = cur[k] < stop[k] ? tbuf[cur[k]] : rEnd;
+                head[k] = v < EpR ? v : rEnd;
             }
         }
         while (true) {
             // next event of the lane's types (any order among equal times)
-            T t = head[0];
+            R t = head[0];
             int j = 0;
 #pragma unroll
             for (int k = 1; k < N; ++k) {
@@ -286,10 +329,10 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
                     j = k;
                 }
             }
-            if (t == kEnd) break;
+            if (t == rEnd) break;
             ++w_visits;
             // per-node values of the selected node
-            T vfj = vf[0], nxt = kEnd, hij = T(0);
+            R vfj = vf[0], nxt = rEnd, hij = R(0);
 #pragma unroll
             for (int k = 1; k < N; ++k)
                 if (k == j) vfj = vf[k];
@@ -297,14 +340,14 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
             for (int k = 0; k + 1 < N; ++k) {
                 if (k == j) {
                     nxt = head[k + 1];
-                    hij = hi[k];
+                    hij = hiR[k];
                 }
             }
             // Exact rejections that need no LDS state: a start not after the
             // last completion; a query below vf; a record whose acceptance
             // interval ends before the next event of the following node
             // (only when that event is known, i.e. inside this tile).
-            const bool late_next = j + 1 < N && nxt != kEnd && nxt > (T)(t + hij);
+            const bool late_next = j + 1 < N && nxt != rEnd && nxt > (R)(t + hij);
             const bool useless = (j == 0 ? t <= f.e : t < vfj) || late_next;
             if (!useless) {
                 bool done = false;
@@ -313,12 +356,12 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
                         f.e = t;
                         done = true;
                     } else {
-                        const T ns = f.record(0, t, a.flags);
+                        const R ns = f.record(0, t, a.flags);
                         ++w_records;
-                        vf[1] = vf[1] < (T)(ns + 1) ? vf[1] : (T)(ns + 1);
+                        vf[1] = vf[1] < (R)(ns + 1) ? vf[1] : (R)(ns + 1);
                     }
                 } else {
-                    T nv;
+                    R nv;
                     ++w_queries;
                     const bool ok = f.query(j - 1, t, &nv);
                     if (!ok) {
@@ -329,21 +372,22 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
                         f.e = t;
                         f.gen ^= 1u;
 #pragma unroll
-                        for (int k = 0; k < N; ++k) vf[k] = kEnd;
+                        for (int k = 0; k < N; ++k) vf[k] = rEnd;
                         done = true;
                     } else {
-                        const T ns = f.record(j, t, a.flags);
+                        const R ns = f.record(j, t, a.flags);
                         ++w_records;
 #pragma unroll
                         for (int k = 1; k + 1 < N; ++k)
-                            if (k == j) vf[k + 1] = vf[k + 1] < (T)(ns + 1) ? vf[k + 1] : (T)(ns + 1);
+                            if (k == j) vf[k + 1] = vf[k + 1] < (R)(ns + 1) ? vf[k + 1] : (R)(ns + 1);
                     }
                 }
                 if (done) ++w_done;
-                if (done && t >= Bp) {
-                    if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = t;
+                if (done && t >= BpR) {
+                    const T ta = (T)t + t0b;  // absolute
+                    if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = ta;
                     ++cnt;
-                    last = t;
+                    last = ta;
                 }
             }
             // advance the selected node
@@ -365,8 +409,8 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
                     }
                 }
                 ++c;
-                T v = c < st ? tbuf[c] : kEnd;
-                v = v < Ep ? v : kEnd;
+                R v = c < st ? tbuf[c] : rEnd;
+                v = v < EpR ? v : rEnd;
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
                     if (k == j) {
@@ -396,10 +440,10 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
     }
 }
 
-template <typename T, int N, bool FILT>
+template <typename T, int N, bool FILT, bool REL>
 __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    count_item<T, N, FILT>(a, blockIdx.x, blockIdx.y, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, smem);
+    count_item<T, N, FILT, REL>(a, blockIdx.x, blockIdx.y, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, smem);
 }
 
 // Persistent form: every workgroup takes work items (unit, lane block,
@@ -411,7 +455,7 @@ struct WorkItem {
     int64_t blk;
 };
 
-template <typename T, int N, bool FILT>
+template <typename T, int N, bool FILT, bool REL>
 __global__ __launch_bounds__(256) void k_count_persistent(const CountArgs<T> *__restrict__ units,
                                                           const WorkItem *__restrict__ items, int64_t n_items,
                                                           int64_t item_base, unsigned long long *__restrict__ queue) {
@@ -425,12 +469,13 @@ __global__ __launch_bounds__(256) void k_count_persistent(const CountArgs<T> *__
         if (it >= n_items) break;  // uniform: every wave of the group exits
         const WorkItem w = items[it];
         const CountArgs<T> a = units[w.unit];
-        count_item<T, N, FILT>(a, w.blk, w.p, item_base + it, smem);
+        count_item<T, N, FILT, REL>(a, w.blk, w.p, item_base + it, smem);
     }
 }
 
+// p[0..n) = v, any n (one workgroup strides over it)
 __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) p[i] = v;
 }
 
 __global__ void k_zero_counts(const int32_t *__restrict__ orig, int64_t G, int32_t *__restrict__ counts) {
@@ -627,24 +672,28 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
 template <typename T>
 using KFn = void (*)(CountArgs<T>);
 
-template <typename T, bool F>
+template <typename T, bool F, bool REL>
 KFn<T> pick_count_f(int N) {
     switch (N) {
-        case 1: return k_count_tiled<T, 1, F>;
-        case 2: return k_count_tiled<T, 2, F>;
-        case 3: return k_count_tiled<T, 3, F>;
-        case 4: return k_count_tiled<T, 4, F>;
-        case 5: return k_count_tiled<T, 5, F>;
-        case 6: return k_count_tiled<T, 6, F>;
-        case 7: return k_count_tiled<T, 7, F>;
-        case 8: return k_count_tiled<T, 8, F>;
+        case 1: return k_count_tiled<T, 1, F, REL>;
+        case 2: return k_count_tiled<T, 2, F, REL>;
+        case 3: return k_count_tiled<T, 3, F, REL>;
+        case 4: return k_count_tiled<T, 4, F, REL>;
+        case 5: return k_count_tiled<T, 5, F, REL>;
+        case 6: return k_count_tiled<T, 6, F, REL>;
+        case 7: return k_count_tiled<T, 7, F, REL>;
+        case 8: return k_count_tiled<T, 8, F, REL>;
         default: return nullptr;
     }
 }
 
+// REL: the int32 relative-time machines (int64 streams only).
 template <typename T>
-KFn<T> pick_count(int N, bool filtered) {
-    return filtered ? pick_count_f<T, true>(N) : pick_count_f<T, false>(N);
+KFn<T> pick_count(int N, bool filtered, bool rel) {
+    if constexpr (sizeof(T) == 8) {
+        if (rel) return filtered ? pick_count_f<T, true, true>(N) : pick_count_f<T, false, true>(N);
+    }
+    return filtered ? pick_count_f<T, true, false>(N) : pick_count_f<T, false, false>(N);
 }
 
 template <typename T>
@@ -685,15 +734,17 @@ struct Layout {
     uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc, total;
 };
 
+// rel: the machines and the staged tile hold int32 relative times.
 template <typename T>
-Layout<T> layout(int N, int Q, int W, int K, bool tiles) {
+Layout<T> layout(int N, int Q, int W, int K, bool tiles, bool rel = false) {
     Layout<T> L;
     const size_t lv = N > 1 ? N - 1 : 0;
-    size_t o = al16(lv * W * sizeof(Pair<T>));
+    const size_t ts = rel ? sizeof(int32_t) : sizeof(T);  // machine time
+    size_t o = al16(lv * W * 2 * ts);
     L.off_qse = (uint32_t)o;
-    o += al16(lv * Q * W * sizeof(Pair<T>));
+    o += al16(lv * Q * W * 2 * ts);
     L.off_tbuf = (uint32_t)o;
-    o += tiles ? al16(kTile * sizeof(T)) : 0;
+    o += tiles ? al16(kTile * ts) : 0;
     L.off_qh = (uint32_t)o;
     o += al16(lv * W * sizeof(uint32_t));
     L.off_obuf = (uint32_t)o;
@@ -704,18 +755,29 @@ Layout<T> layout(int N, int Q, int W, int K, bool tiles) {
     return L;
 }
 
+// Whether the int32 relative-time machines can count a group of the stream:
+// an int64 stream whose longest tile plus twice the group's longest episode
+// span stays below 2^31 - 64.  Relative times lie in [-2, tile span], and the
+// machine only forms a time plus one interval bound (record, rejection test)
+// or minus a tile span (rebase), so every value then fits int32.
+template <typename T>
+bool rel_ok(const Stream &s, int64_t hspan) {
+    return sizeof(T) == 8 && s.max_tile_span >= 0 && hspan >= 0 && hspan < (int64_t(1) << 29) &&
+           s.max_tile_span < (int64_t(1) << 31) && s.max_tile_span + 2 * hspan < (int64_t(1) << 31) - 64;
+}
+
 constexpr uint32_t kLdsSoft = 64 * 1024;
 constexpr uint32_t kLdsHard = 160 * 1024;
 
 // Widest workgroup (at most max_lanes) whose LDS fits comfortably; else the
 // widest that fits at all.
 template <typename T>
-int pick_lanes(int N, int Q, int K, int max_lanes) {
+int pick_lanes(int N, int Q, int K, int max_lanes, bool rel = false) {
     int fit = 64;
     bool any = false;
     for (int W : {256, 128, 64}) {
         if (max_lanes > 0 && W > max_lanes) continue;
-        const Layout<T> L = layout<T>(N, Q, W, K, true);
+        const Layout<T> L = layout<T>(N, Q, W, K, true, rel);
         if (L.total <= kLdsSoft) return W;
         if (!any && L.total <= kLdsHard) {
             fit = W;
@@ -788,8 +850,9 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
             if ((e = hipGetLastError()) != hipSuccess) return e;
             continue;
         }
-        const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes);
-        const Layout<T> L = layout<T>(g.N, g.Q, W, s.K, true);
+        const bool rel = rel_ok<T>(s, g.hspan);
+        const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes, rel);
+        const Layout<T> L = layout<T>(g.N, g.Q, W, s.K, true, rel);
         const uint32_t lds = L.total;
         if (lds > kLdsHard) return hipErrorInvalidConfiguration;
         // segments
@@ -853,7 +916,7 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.pbits = filtered ? c.pred_bits : nullptr;
         a.sbits = filtered ? c.succ_bits : nullptr;
         a.rwords = s.B * (kTile / 64);
-        KFn<T> fn = pick_count<T>(g.N, filtered);
+        KFn<T> fn = pick_count<T>(g.N, filtered, rel);
         if (!fn) return hipErrorInvalidValue;
         if ((e = ensure_lds_attr<T>(fn, lds)) != hipSuccess) return e;
         const dim3 grid((unsigned)((G + W - 1) / W), (unsigned)P);
@@ -884,19 +947,27 @@ namespace {
 template <typename T>
 using PFn = void (*)(const CountArgs<T> *, const WorkItem *, int64_t, int64_t, unsigned long long *);
 
-template <typename T, bool F>
-PFn<T> pick_persistent_f(int N) {
+template <typename T, bool F, bool REL>
+PFn<T> pick_persistent_rf(int N) {
     switch (N) {
-        case 1: return k_count_persistent<T, 1, F>;
-        case 2: return k_count_persistent<T, 2, F>;
-        case 3: return k_count_persistent<T, 3, F>;
-        case 4: return k_count_persistent<T, 4, F>;
-        case 5: return k_count_persistent<T, 5, F>;
-        case 6: return k_count_persistent<T, 6, F>;
-        case 7: return k_count_persistent<T, 7, F>;
-        case 8: return k_count_persistent<T, 8, F>;
+        case 1: return k_count_persistent<T, 1, F, REL>;
+        case 2: return k_count_persistent<T, 2, F, REL>;
+        case 3: return k_count_persistent<T, 3, F, REL>;
+        case 4: return k_count_persistent<T, 4, F, REL>;
+        case 5: return k_count_persistent<T, 5, F, REL>;
+        case 6: return k_count_persistent<T, 6, F, REL>;
+        case 7: return k_count_persistent<T, 7, F, REL>;
+        case 8: return k_count_persistent<T, 8, F, REL>;
         default: return nullptr;
     }
+}
+
+template <typename T, bool F>
+PFn<T> pick_persistent_f(int N, bool rel) {
+    if constexpr (sizeof(T) == 8) {
+        if (rel) return pick_persistent_rf<T, F, true>(N);
+    }
+    return pick_persistent_rf<T, F, false>(N);
 }
 
 // Per-candidate predicted costs (grouped slot order) for the learned or the
@@ -949,6 +1020,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         int64_t begin, G, P, S;
         bool filt;
         std::vector<float> bcost;  // per lane block
+        bool rel = false;          // int32 relative-time machines allowed
     };
     std::vector<UnitH> units;
     std::vector<DevBuf> perms(sets.size());
@@ -983,7 +1055,8 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
             const int64_t G = g.end - g.begin;
             if (G <= 0) continue;
             const bool filt = c.compact && c.pred_bits && c.succ_bits;
-            const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes);
+            const bool rel = rel_ok<T>(s, g.hspan);
+            const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes, rel);
             const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
             if (costs[si].empty()) {
                 // round robin: submission order, segments as in plain mode
@@ -993,6 +1066,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                 const int64_t S = (s.B + P - 1) / P;
                 P = (s.B + S - 1) / S;
                 UnitH u{(int)si, g.N, g.Q, W, g.begin, G, P, S, filt, {}};
+                u.rel = rel;
                 u.bcost.assign((G + W - 1) / W, 1.f);
                 units.push_back(std::move(u));
                 continue;
@@ -1021,6 +1095,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                 const int64_t P = (s.B + S - 1) / S;
                 UnitH u{(int)si, g.N, g.Q, W, g.begin + b0 * W, std::min<int64_t>(G - b0 * W, (b1 - b0) * W), P, S,
                         filt, {}};
+                u.rel = rel;
                 for (int64_t b = b0; b < b1; ++b)
                     u.bcost.push_back(costs[si][g.begin + b * W] * (float)std::min<int64_t>(W, G - b * W));
                 units.push_back(std::move(u));
@@ -1034,20 +1109,22 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         if (u.P > 1) rec_bytes += record_bytes<T>(u.P, u.G) + 64;
     DevBuf rec;
     if ((e = rec.alloc(rec_bytes)) != hipSuccess) return e;
-    // launch classes: episode size x queue class (each with its own lane
-    // width and LDS layout, as the plain launch sizes each group)
-    constexpr int kQClasses = 5;  // Q = 1, 2, 4, 8, 16
-    constexpr int kClasses = (kMaxN + 1) * kQClasses;
-    auto cls_of = [](int N, int Q) {
+    // launch classes: episode size x queue class x machine time type (each
+    // with its own lane width and LDS layout, as the plain launch sizes each
+    // group)
+    constexpr int kQClasses = 8;  // Q = 1, 2, 3, 4, 6, 8, 12, 16
+    constexpr int kClasses = (kMaxN + 1) * kQClasses * 2;
+    auto cls_of = [](int N, int Q, bool rel) {
+        static constexpr int kQ[kQClasses] = {1, 2, 3, 4, 6, 8, 12, 16};
         int q = 0;
-        while ((1 << q) < Q) ++q;
-        return N * kQClasses + q;
+        while (q + 1 < kQClasses && kQ[q] < Q) ++q;
+        return (N * kQClasses + q) * 2 + (rel ? 1 : 0);
     };
     std::vector<CountArgs<T>> ua(units.size());
     std::vector<std::vector<WorkItem>> items(kClasses);
     std::vector<std::vector<float>> icost(kClasses);
     std::vector<int> clsN(kClasses, 0), clsQ(kClasses, 1), maxK(kClasses, 1), Wn(kClasses, 256);
-    std::vector<bool> filtN(kClasses, false);
+    std::vector<bool> filtN(kClasses, false), relN(kClasses, false);
     size_t ro = 0;
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
@@ -1086,18 +1163,19 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
             ro += (record_bytes<T>(u.P, u.G) + 64) & ~size_t(15);
         }
         ua[ui] = a;
-        const int cl = cls_of(u.N, u.Q);
+        const int cl = cls_of(u.N, u.Q, u.rel);
         clsN[cl] = u.N;
+        relN[cl] = u.rel;
         clsQ[cl] = std::max(clsQ[cl], u.Q);
         maxK[cl] = std::max(maxK[cl], (int)s.K);
         filtN[cl] = filtN[cl] || u.filt;
     }
     // lanes per workgroup per class: common to its units
     for (int cl = 0; cl < kClasses; ++cl)
-        if (clsN[cl] > 0) Wn[cl] = pick_lanes<T>(clsN[cl], clsQ[cl], maxK[cl], opt.lanes);
+        if (clsN[cl] > 0) Wn[cl] = pick_lanes<T>(clsN[cl], clsQ[cl], maxK[cl], opt.lanes, relN[cl]);
     for (size_t ui = 0; ui < units.size(); ++ui) {
-        const int cl = cls_of(units[ui].N, units[ui].Q);
-        const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true);
+        const int cl = cls_of(units[ui].N, units[ui].Q, units[ui].rel);
+        const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
         ua[ui].Q = clsQ[cl];
         ua[ui].off_qse = L.off_qse;
         ua[ui].off_tbuf = L.off_tbuf;
@@ -1108,7 +1186,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     // work items: lane blocks of the class width x segments
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
-        const int cl = cls_of(u.N, u.Q);
+        const int cl = cls_of(u.N, u.Q, u.rel);
         const int W = Wn[cl];
         const int64_t nb = (u.G + W - 1) / W;
         for (int64_t b = 0; b < nb; ++b) {
@@ -1159,7 +1237,8 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kClasses, 0ull);
+    static_assert(kClasses <= 65536, "queue counters");
+    k_fill_u64<<<1, 256, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kClasses, 0ull);
     std::vector<int> corder;
     for (int cl = 0; cl < kClasses; ++cl)
         if (!items[cl].empty()) corder.push_back(cl);
@@ -1167,8 +1246,8 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         if (e != hipSuccess) break;
         const int N = clsN[cl];
         const bool filt = filtN[cl];
-        PFn<T> fn = filt ? pick_persistent_f<T, true>(N) : pick_persistent_f<T, false>(N);
-        const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true);
+        PFn<T> fn = filt ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
+        const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
         e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total);
         if (e != hipSuccess) break;
         int per = 0;
@@ -1184,7 +1263,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
         if (units[ui].P <= 1) continue;
         const int N = units[ui].N;
-        const int cl = cls_of(N, units[ui].Q);
+        const int cl = cls_of(N, units[ui].Q, units[ui].rel);
         e = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), st);
     }
     hipError_t ec = hipStreamEndCapture(st, &graph);
