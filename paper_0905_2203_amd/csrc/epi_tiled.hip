@@ -787,6 +787,36 @@ int pick_lanes(int N, int Q, int K, int max_lanes, bool rel = false) {
     return fit;
 }
 
+// Lane width of a launch of kernel fn: the one (of 256, 128, 64, at most
+// max_lanes) whose workgroups keep the most waves resident on a CU, as the
+// runtime counts them (LDS and registers); ties go to the wider one, whose
+// waves share one staged tile.  Falls back to pick_lanes.
+template <typename T>
+int pick_lanes_fn(const void *fn, int N, int Q, int K, int max_lanes, bool rel) {
+    int best = 0, bestW = 0;
+    for (int W : {256, 128, 64}) {
+        if (max_lanes > 0 && W > max_lanes) continue;
+        const Layout<T> L = layout<T>(N, Q, W, K, true, rel);
+        if (L.total > kLdsHard) continue;
+        if (L.total > kLdsSoft &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, W, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        const int waves = per * (W / 64);
+        if (waves > best) {
+            best = waves;
+            bestW = W;
+        }
+    }
+    return best > 0 ? bestW : pick_lanes<T>(N, Q, K, max_lanes, rel);
+}
+
 template <typename T>
 hipError_t ensure_lds_attr(KFn<T> fn, uint32_t bytes) {
     if (bytes <= kLdsSoft) return hipSuccess;
@@ -851,7 +881,10 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
             continue;
         }
         const bool rel = rel_ok<T>(s, g.hspan);
-        const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes, rel);
+        const bool filtered = c.compact && c.pred_bits && c.succ_bits;
+        KFn<T> fn = pick_count<T>(g.N, filtered, rel);
+        if (!fn) return hipErrorInvalidValue;
+        const int W = pick_lanes_fn<T>(reinterpret_cast<const void *>(fn), g.N, g.Q, s.K, opt.lanes, rel);
         const Layout<T> L = layout<T>(g.N, g.Q, W, s.K, true, rel);
         const uint32_t lds = L.total;
         if (lds > kLdsHard) return hipErrorInvalidConfiguration;
@@ -912,12 +945,9 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
             }
             set_records<T>(a, c.scratch.as<unsigned char>(), P, G);
         }
-        const bool filtered = c.compact && c.pred_bits && c.succ_bits;
         a.pbits = filtered ? c.pred_bits : nullptr;
         a.sbits = filtered ? c.succ_bits : nullptr;
         a.rwords = s.B * (kTile / 64);
-        KFn<T> fn = pick_count<T>(g.N, filtered, rel);
-        if (!fn) return hipErrorInvalidValue;
         if ((e = ensure_lds_attr<T>(fn, lds)) != hipSuccess) return e;
         const dim3 grid((unsigned)((G + W - 1) / W), (unsigned)P);
         fn<<<grid, W, lds, st>>>(a);
@@ -1056,7 +1086,9 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
             if (G <= 0) continue;
             const bool filt = c.compact && c.pred_bits && c.succ_bits;
             const bool rel = rel_ok<T>(s, g.hspan);
-            const int W = pick_lanes<T>(g.N, g.Q, s.K, opt.lanes, rel);
+            const PFn<T> pfn = filt ? pick_persistent_f<T, true>(g.N, rel) : pick_persistent_f<T, false>(g.N, rel);
+            if (!pfn) return hipErrorInvalidValue;
+            const int W = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), g.N, g.Q, s.K, opt.lanes, rel);
             const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
             if (costs[si].empty()) {
                 // round robin: submission order, segments as in plain mode
@@ -1172,7 +1204,13 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     }
     // lanes per workgroup per class: common to its units
     for (int cl = 0; cl < kClasses; ++cl)
-        if (clsN[cl] > 0) Wn[cl] = pick_lanes<T>(clsN[cl], clsQ[cl], maxK[cl], opt.lanes, relN[cl]);
+        if (clsN[cl] > 0) {
+            const PFn<T> pfn = filtN[cl] ? pick_persistent_f<T, true>(clsN[cl], relN[cl])
+                                         : pick_persistent_f<T, false>(clsN[cl], relN[cl]);
+            if (!pfn) return hipErrorInvalidValue;
+            Wn[cl] = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), clsN[cl], clsQ[cl], maxK[cl], opt.lanes,
+                                      relN[cl]);
+        }
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const int cl = cls_of(units[ui].N, units[ui].Q, units[ui].rel);
         const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
