@@ -41,10 +41,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel_name):
-    """HBM bytes per launch of ``kernel_name`` from the committed rocprofv3
-    counter summary, or None when the summary is for another kernel or the
-    kernel sources changed since the counters were taken."""
+def profiled(kernel_name, key, field):
+    """A per-launch figure of ``kernel_name`` (line ``key`` of the committed
+    rocprofv3 counter summary), or None when the summary is for another
+    kernel or the kernel sources changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", PROFILE)
@@ -52,13 +52,19 @@ def profiled_traffic(kernel_name):
     try:
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
         for line in open(path):
-            if line.startswith("traffic_bytes_per_launch:"):
+            if line.startswith(key + ":"):
                 rec = json.loads(line.split(":", 1)[1])
                 if rec["kernel"] == kernel_name and rec["source_hash"] == h:
-                    return int(rec["bytes"])
+                    return rec[field]
     except OSError:
         pass
     return None
+
+
+def profiled_traffic(kernel_name):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)."""
+    v = profiled(kernel_name, "traffic_bytes_per_launch", "bytes")
+    return None if v is None else int(v)
 
 
 def _timed(ctx, fn, reps):
@@ -373,6 +379,9 @@ def main():
             "frac": achieved_gbs / PEAK_HBM_GBS,
             "traffic": traffic,
             "algorithmic_bytes": alg,
+            # the walk's own limit: wave-level VALU instructions x 4 cycles over
+            # 1024 SIMDs x 2.4 GHz x the launch time (SQ counters, same profile)
+            "valu_issue_frac": profiled(kname, "valu_issue_per_launch", "frac"),
         },
         "cpu_baseline": cpu,
         "parity": parity,
