@@ -49,7 +49,7 @@ enum {
     EPI_ETYPE = -3,     /* event or episode type outside [0, K)                  */
     EPI_EINTERVAL = -4, /* an interval violates 0 <= lo < hi                     */
     EPI_ESIZE = -5,     /* episode size outside 1..8, or n / K / m out of range  */
-    EPI_EREPEAT = -6,   /* a type occurs twice in one episode                    */
+    EPI_EREPEAT = -6,   /* a type occurs twice in one episode (unless allowed)   */
     EPI_EOVERFLOW = -7, /* times +- the episode span leave the timestamp type    */
     EPI_ENOMEM = -8,    /* device or host allocation failed                      */
     EPI_EDEVICE = -9,   /* HIP runtime error or a device-side check failed       */
@@ -94,7 +94,8 @@ epi_status epi_validate_stream(const int32_t *types, const void *times, int64_t 
                                int32_t K);
 
 /* Check m candidate episodes (Def. 2, Sec. II-C):
- *   N[c] in 1..8; types[c*8 + j] in [0, K) and distinct for j < N[c];
+ *   N[c] in 1..8; types[c*8 + j] in [0, K) and distinct for j < N[c]
+ *   (epi_submit_candidates admits repeats under EPI_OPT_ALLOW_REPEATS);
  *   0 <= lo[c*7 + j] < hi[c*7 + j] for j < N[c]-1; the span sum_j hi
  *   fits the timestamp type.  Slots beyond N[c] are ignored. */
 epi_status epi_validate_candidates(int64_t m, const uint8_t *N, const int32_t *types,
@@ -206,9 +207,19 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
  *                         fit; else one walk per parent counts it and a
  *                         second writes its chain lists (0 = always the
  *                         latter)
- * EPI_EINVAL for an unknown option or value.  Counts never depend on them. */
+ *   EPI_OPT_ALLOW_REPEATS 0 (default) / 1: epi_submit_candidates accepts
+ *                         episodes in which a type occurs at several nodes
+ *                         (Def. 2 does not exclude them; e.g. A -> B -> A).
+ *                         An occurrence still takes one event per node with
+ *                         strictly increasing times (every lower bound is
+ *                         >= 0 and strict), so one event never fills two
+ *                         nodes of an occurrence; the state machines take
+ *                         each event at every node of its type.
+ * EPI_EINVAL for an unknown option or value.  Counts never depend on the
+ * engine options (EPI_OPT_ALLOW_REPEATS only widens what is accepted). */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
-       EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8 };
+       EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8,
+       EPI_OPT_ALLOW_REPEATS = 9 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Autotune the batched engine for these sets and schedule: time every

@@ -8,7 +8,9 @@
  *
  * Definitions (Sec. II-C of the paper):
  *   - event stream: (E_i, t_i), i = 1..n, with t_i <= t_{i+1}           (Def. 1)
- *   - serial episode alpha = (A_1 .. A_N) of distinct event types         (Def. 2)
+ *   - serial episode alpha = (A_1 .. A_N) of event types                  (Def. 2)
+ *     (a type may occur at several nodes; an occurrence's times strictly
+ *     increase, so one event never fills two nodes of an occurrence)
  *   - inter-event constraint j: lo_j < t(A_{j+1}) - t(A_j) <= hi_j        (Sec. II-C)
  *   - an occurrence is a tuple of events, one per node, meeting every
  *     constraint; its span is [start, end] = [t(A_1), t(A_N)]
@@ -206,7 +208,9 @@ static int64_t count_fsm(const int32_t *types, const int64_t *t, int64_t n, int 
                     }
                 }
             }
-            break; /* types within an episode are distinct */
+            /* a type at several nodes: the event is taken at each of them,
+             * last node first (a record at time t never admits a query at
+             * the same t, so the order does not change the result) */
         }
     }
     for (int k = 0; k < ORACLE_MAXN; k++) free(s[k].v);

@@ -95,8 +95,9 @@ int64_t span_of(int N, const int64_t *hi) {
     return s;
 }
 
+// repeats: accept a type at several nodes of an episode (EPI_OPT_ALLOW_REPEATS)
 epi_status check_candidates(int64_t m, const uint8_t *N, const int32_t *types, const int64_t *lo,
-                            const int64_t *hi, int32_t K, int ts_kind, std::string *msg) {
+                            const int64_t *hi, int32_t K, int ts_kind, std::string *msg, bool repeats = false) {
     if (ts_kind != EPI_TS_I32 && ts_kind != EPI_TS_I64) {
         if (msg) *msg = "ts_kind must be EPI_TS_I32 or EPI_TS_I64";
         return EPI_EINVAL;
@@ -125,7 +126,7 @@ epi_status check_candidates(int64_t m, const uint8_t *N, const int32_t *types, c
                 say("type outside [0, K)");
                 return EPI_ETYPE;
             }
-            for (int k = 0; k < j; ++k)
+            for (int k = 0; k < j && !repeats; ++k)
                 if (ty[k] == ty[j]) {
                     say("repeated event type");
                     return EPI_EREPEAT;
@@ -431,7 +432,7 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
     Stream *s = find_stream(ctx, stream_id);
     if (!s) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
     std::string msg;
-    epi_status v = check_candidates(m, N, types, lo, hi, s->K, s->ts_kind, &msg);
+    epi_status v = check_candidates(m, N, types, lo, hi, s->K, s->ts_kind, &msg, ctx->c.opt.allow_repeats);
     if (v != EPI_OK) return fail(ctx, v, "%s", msg.c_str());
     // times +- span must stay strictly inside the timestamp type
     const int64_t tlo = s->ts_kind == EPI_TS_I64 ? INT64_MIN : INT32_MIN;
@@ -570,6 +571,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
         case EPI_OPT_MINE_LIST_BYTES:
             if (value < 0) return fail(ctx, EPI_EINVAL, "list bytes must be >= 0");
             ctx->c.opt.mine_list_bytes = value;
+            return EPI_OK;
+        case EPI_OPT_ALLOW_REPEATS:
+            if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "allow-repeats must be 0 or 1");
+            ctx->c.opt.allow_repeats = value != 0;
             return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);

@@ -232,6 +232,7 @@ struct CountOptions {
     int64_t target_items = 0;      // batched mode: work items aimed at (0: 8 per compute unit)
     int64_t pair_filter_max_bytes = int64_t(1) << 30;
     int64_t mine_list_bytes = int64_t(8) << 30;  // extension engine: list-path budget per level
+    bool allow_repeats = false;    // epi_submit_candidates accepts a type at several nodes
 };
 
 // One level of a level-wise discovery run: candidates of size N in

@@ -59,6 +59,7 @@ EPI_OPT_MINE_ENGINE = 5
 EPI_OPT_WORKLOG = 6
 EPI_OPT_TARGET_ITEMS = 7
 EPI_OPT_MINE_LIST_BYTES = 8
+EPI_OPT_ALLOW_REPEATS = 9
 
 
 class EpiError(RuntimeError):

@@ -96,6 +96,31 @@ def test_bruteforce_tiny_streams(seed):
             assert got_f[i] == want, (ep, lo, hi)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_bruteforce_repeated_types(seed):
+    """Episodes with a type at several nodes (drawn with replacement from 2-3
+    types): definition by enumeration == both oracle formulations."""
+    rng = np.random.Generator(np.random.PCG64(500 + seed))
+    for _ in range(40):
+        K = int(rng.integers(2, 4))
+        s = sg.tiny_stream(rng, int(rng.integers(1, 25)), K, 30)
+        eps = []
+        for _ in range(6):
+            n = int(rng.integers(2, 5))
+            ty = [int(x) for x in rng.integers(0, K, size=n)]
+            lo = [int(rng.integers(0, 6)) for _ in range(n - 1)]
+            hi = [a + int(rng.integers(1, 8)) for a in lo]
+            eps.append((ty, lo, hi))
+        c = sg.candidates_from_list(eps)
+        got_d = oracle.count(s, c, "decomp")
+        got_f = oracle.count(s, c, "fsm")
+        for i, (ty, lo, hi) in enumerate(eps):
+            spans = brute.occurrences(s["types"], s["times"], ty, lo, hi)
+            want = brute.max_nonoverlapped_dp(spans)
+            assert got_d[i] == want, (ty, lo, hi)
+            assert got_f[i] == want, (ty, lo, hi)
+
+
 def test_bruteforce_dense_ties():
     """Streams where most events share timestamps (times in 0..6)."""
     for s, c in _tiny_cases(7, 200, 16, 3, 6, 3, 4):
