@@ -57,7 +57,7 @@ enum {
 };
 
 enum { EPI_TS_I32 = 0, EPI_TS_I64 = 1 };
-enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1 };
+enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1, EPI_MODE_INCREMENTAL = 2 };
 enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1, EPI_SCHED_HEURISTIC = 2, EPI_SCHED_MEASURED = 3 };
 
 #define EPI_MAX_N 8 /* largest episode size */
@@ -154,9 +154,12 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  *                     in submission order (asynchronous);
  *   EPI_MODE_BATCHED  all sets (possibly on different streams of one
  *                     timestamp kind) in one captured graph: one persistent
- *                     kernel per episode size pulls (set, lane block,
- *                     segment) work items from a device queue, then the
- *                     segmented ones are reconciled (returns when done).
+ *                     kernel per launch class (episode size, ring class,
+ *                     machine time type) pulls (set, lane block, segment)
+ *                     work items from a device queue, then the segmented
+ *                     ones are reconciled (returns when done).
+ *   EPI_MODE_INCREMENTAL  after epi_append_stream: only the appended
+ *                     events are counted (see epi_append_stream).
  * sched (batched mode): EPI_SCHED_RR keeps submission order;
  * EPI_SCHED_LEARNED orders each class's episodes by the cost model's
  * predicted work (see epi_costmodel_train; without a trained model it falls
@@ -169,6 +172,27 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  * The counts never depend on mode or sched. */
 epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched,
                      void *hip_stream);
+
+/* Streaming (the streaming direction of the paper's Future Work section,
+ * here exact): append n events to a loaded stream.  Same checks as
+ * epi_load_stream, and the first appended time must not precede the
+ * stream's last one (EPI_EUNSORTED).  The per-type index is rebuilt;
+ * synchronous (the device is idle when it returns).  Sets on the stream keep
+ * their counts, which then cover the events before the append, until they
+ * are counted again: fully (EPI_MODE_PLAIN / EPI_MODE_BATCHED) or
+ * incrementally (EPI_MODE_INCREMENTAL).
+ *
+ * EPI_MODE_INCREMENTAL in epi_count: a set never counted is counted fully
+ * (as EPI_MODE_PLAIN); a set counted before one or more appends only adds
+ * the occurrences completed by the appended events.  Each episode keeps its
+ * last completion tau from every count, and its machine resumes from the
+ * state right after max(tau, B - H - 1) (B = the first appended time, H =
+ * the episode's longest span): an occurrence ending at or after B starts at
+ * or after B - H, so nothing before that point can still complete (the
+ * reasoning of the segment reconciliation).  The counts equal a full count
+ * of the whole stream.  Sets from level-wise discovery cannot be counted
+ * this way (EPI_EINVAL). */
+epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *types, const void *times, int64_t n);
 
 /* Engine options (per context), used by tests and by tuning:
  *   EPI_OPT_SEGMENTS      0 = automatic (default); k >= 1 = cut the stream

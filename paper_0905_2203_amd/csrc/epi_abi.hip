@@ -197,6 +197,7 @@ hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int
     if ((e = cs.hi.alloc(sizeof(T) * h_hi.size())) != hipSuccess) return e;
     if ((e = cs.orig.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
     if ((e = cs.counts.alloc(sizeof(int32_t) * m)) != hipSuccess) return e;
+    if ((e = cs.tau.alloc(sizeof(T) * m)) != hipSuccess) return e;
     if (m > 0) {
         if ((e = hipMemcpyAsync(cs.types.p, h_types.data(), sizeof(int32_t) * h_types.size(), hipMemcpyHostToDevice,
                                 st)) != hipSuccess)
@@ -469,7 +470,8 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id) {
 epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched, void *hip_stream) {
     if (!ctx) return EPI_EINVAL;
     if (k < 0 || (k > 0 && !set_ids)) return fail(ctx, EPI_EINVAL, "bad set list");
-    if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED) return fail(ctx, EPI_EINVAL, "unknown mode %d", mode);
+    if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED && mode != EPI_MODE_INCREMENTAL)
+        return fail(ctx, EPI_EINVAL, "unknown mode %d", mode);
     if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED && sched != EPI_SCHED_HEURISTIC &&
         sched != EPI_SCHED_MEASURED)
         return fail(ctx, EPI_EINVAL, "unknown sched %d", sched);
@@ -482,6 +484,37 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
     }
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
     hipStream_t st = pick_stream(ctx, hip_stream);
+    if (mode == EPI_MODE_INCREMENTAL) {
+        // sets never counted: a full count; sets counted before an append:
+        // only the occurrences the appended events complete
+        for (int32_t i = 0; i < k; ++i) {
+            CandSet *cs = find_set(ctx, set_ids[i]);
+            if (cs->compact) return fail(ctx, EPI_EINVAL, "set %d cannot be counted incrementally", set_ids[i]);
+        }
+        for (int32_t i = 0; i < k; ++i) {
+            CandSet *cs = find_set(ctx, set_ids[i]);
+            Stream *s = find_stream(ctx, cs->stream_id);
+            cs->logged = false;
+            if (!cs->counted || cs->counted_n < 0) {
+                HIPTRY(ctx, launch_count(*s, *cs, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "launching the count");
+            } else if (cs->counted_n < s->n && cs->m > 0) {
+                int64_t B = 0;
+                if (s->ts_kind == EPI_TS_I64) {
+                    HIPTRY(ctx, hipMemcpy(&B, s->times.as<int64_t>() + cs->counted_n, 8, hipMemcpyDeviceToHost),
+                           "reading times");
+                } else {
+                    int32_t b32 = 0;
+                    HIPTRY(ctx, hipMemcpy(&b32, s->times.as<int32_t>() + cs->counted_n, 4, hipMemcpyDeviceToHost),
+                           "reading times");
+                    B = b32;
+                }
+                HIPTRY(ctx, launch_count_append(*s, *cs, B, ctx->c.flags.as<int32_t>(), st), "counting appended events");
+            }
+            cs->counted = true;
+            cs->counted_n = s->n;
+        }
+        return EPI_OK;
+    }
     // measured costs: the logged work, per grouped slot, taken before the log
     // is reset (kept for later counts that log nothing)
     if (mode == EPI_MODE_BATCHED && sched == EPI_SCHED_MEASURED) {
@@ -524,7 +557,10 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
         }
         HIPTRY(ctx, launch_count_batched(refs, sched, ctx->c.opt, ctx->c.mlp, ctx->c.flags.as<int32_t>(), st),
                "batched count");
-        for (auto &r : refs) r.c->counted = true;
+        for (auto &r : refs) {
+            r.c->counted = true;
+            r.c->counted_n = r.s->n;
+        }
         return EPI_OK;
     }
     for (int32_t i = 0; i < k; ++i) {
@@ -532,7 +568,45 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
         Stream *s = find_stream(ctx, cs->stream_id);
         HIPTRY(ctx, launch_count(*s, *cs, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "launching the count");
         cs->counted = true;
+        cs->counted_n = s->n;
     }
+    return EPI_OK;
+}
+
+epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *types, const void *times, int64_t n) {
+    if (!ctx) return EPI_EINVAL;
+    Stream *s = find_stream(ctx, stream_id);
+    if (!s) return fail(ctx, EPI_ESTATE, "unknown stream id %d", stream_id);
+    std::string msg;
+    epi_status v = check_stream(types, times, n, s->ts_kind, s->K, &msg);
+    if (v != EPI_OK) return fail(ctx, v, "%s", msg.c_str());
+    if (n == 0) return EPI_OK;
+    if (s->n + n >= (int64_t(1) << 31)) return fail(ctx, EPI_ESIZE, "the stream would reach 2^31 events");
+    const bool i64 = s->ts_kind == EPI_TS_I64;
+    const int64_t first = i64 ? ((const int64_t *)times)[0] : ((const int32_t *)times)[0];
+    const int64_t last = i64 ? ((const int64_t *)times)[n - 1] : ((const int32_t *)times)[n - 1];
+    if (s->n > 0 && first < s->tmax)
+        return fail(ctx, EPI_EUNSORTED, "appended times must not precede the stream's last time");
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    // the work queued on the stream's arrays ends before they are replaced
+    HIPTRY(ctx, hipDeviceSynchronize(), "sync");
+    const size_t tb = s->ts_bytes();
+    DevBuf ty, tm;
+    HIPTRY(ctx, ty.alloc(sizeof(int32_t) * (size_t)(s->n + n)), "allocating stream types");
+    HIPTRY(ctx, tm.alloc(tb * (size_t)(s->n + n)), "allocating stream times");
+    if (s->n > 0) {
+        HIPTRY(ctx, hipMemcpy(ty.p, s->types.p, sizeof(int32_t) * s->n, hipMemcpyDeviceToDevice), "copying types");
+        HIPTRY(ctx, hipMemcpy(tm.p, s->times.p, tb * s->n, hipMemcpyDeviceToDevice), "copying times");
+    }
+    HIPTRY(ctx, hipMemcpy(ty.as<int32_t>() + s->n, types, sizeof(int32_t) * n, hipMemcpyHostToDevice), "copying types");
+    HIPTRY(ctx, hipMemcpy(tm.as<unsigned char>() + tb * s->n, times, tb * n, hipMemcpyHostToDevice), "copying times");
+    s->types = std::move(ty);
+    s->times = std::move(tm);
+    if (s->n == 0) s->tmin = first;
+    s->tmax = last;
+    s->n += n;
+    HIPTRY(ctx, build_type_index(*s, ctx->c.stream), "building the per-type index");
+    HIPTRY(ctx, hipStreamSynchronize(ctx->c.stream), "sync");
     return EPI_OK;
 }
 

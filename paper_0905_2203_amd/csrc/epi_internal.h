@@ -200,6 +200,8 @@ struct CandSet {
     DevBuf lo, hi;  // T [7][m]
     DevBuf orig;    // int32 [m]
     DevBuf counts;  // int32 [m], submission order
+    DevBuf tau;     // T [m], submission order: each episode's last completion (type minimum: none)
+    int64_t counted_n = -1;  // stream events covered by the counts (-1: never counted)
     DevBuf scratch; // per-segment speculative records of the last count
     DevBuf work;    // work log: int32 [m][kWork] (submission order) when enabled
     DevBuf cycles;  // work log: int64 [items][2] wall-clock start/end of the last count
@@ -346,6 +348,9 @@ hipError_t build_type_index(Stream &s, hipStream_t st);
 hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
                                   int32_t K, int32_t *d_flags, hipStream_t st);
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st);
+// Add to set c's counts the occurrences completed by the stream's events
+// after the first c.counted_n (B = the first of their times).
+hipError_t launch_count_append(const Stream &s, CandSet &c, int64_t B, int32_t *d_flags, hipStream_t st);
 // Batched count of several candidate sets (possibly on different streams) in
 // one graph launch of persistent kernels, one per episode size.  sched:
 // EPI_SCHED_RR (submission order), EPI_SCHED_LEARNED (the cost model's

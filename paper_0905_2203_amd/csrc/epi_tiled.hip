@@ -86,6 +86,9 @@ struct CountArgs {
     int32_t *pre_cnt;
     T *pre_last;
     T *pre_tau;
+    // each candidate's last completion (submission order; the type minimum
+    // for none), kept for counting appended events (null: not kept)
+    T *tau;
     int32_t *flags;
     uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc;
     const int32_t *perm;  // lane slot -> candidate slot (scheduler order); null = identity
@@ -434,6 +437,7 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
     }
     if (a.P == 1) {
         a.counts[o] = cnt;
+        if (a.tau) a.tau[o] = last;
     } else {
         a.rec_cnt[(int64_t)p * a.G + s] = cnt;
         a.rec_last[(int64_t)p * a.G + s] = last;
@@ -478,9 +482,14 @@ __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
     for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) p[i] = v;
 }
 
-__global__ void k_zero_counts(const int32_t *__restrict__ orig, int64_t G, int32_t *__restrict__ counts) {
+template <typename T>
+__global__ void k_zero_counts(const int32_t *__restrict__ orig, int64_t G, int32_t *__restrict__ counts,
+                              T *__restrict__ tau) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < G) counts[orig ? orig[i] : i] = 0;
+    if (i < G) {
+        counts[orig ? orig[i] : i] = 0;
+        if (tau) tau[orig ? orig[i] : i] = TsLimits<T>::lo();
+    }
 }
 
 // first index in [lo, hi) with ts[index] > x
@@ -491,6 +500,40 @@ __device__ __forceinline__ int32_t upper_bound(const T *ts, int32_t lo, int32_t 
         if (ts[mid] <= x) lo = mid + 1; else hi = mid;
     }
     return lo;
+}
+
+// First index after time x in each node's range [lo_k, hi_k) of the per-type
+// index: the N binary searches advance in lockstep, so that each step's
+// loads are issued together.
+template <typename T, int N>
+__device__ __forceinline__ void first_after(const T *ts, const int32_t (&lo_)[N], const int32_t (&hi_)[N], T x,
+                                            int32_t (&cur)[N]) {
+    int32_t hb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        cur[k] = lo_[k];
+        hb[k] = hi_[k];
+    }
+    for (;;) {
+        bool any = false;
+        int32_t mid[N];
+        T v[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            mid[k] = cur[k] + (hb[k] - cur[k]) / 2;
+            any |= cur[k] < hb[k];
+        }
+        if (!any) break;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = cur[k] < hb[k] ? ts[mid[k]] : T(0);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (cur[k] < hb[k]) {
+                if (v[k] <= x) cur[k] = mid[k] + 1;
+                else hb[k] = mid[k];
+            }
+        }
+    }
 }
 
 // Segment p of candidate lane s, given tau (the last true completion before
@@ -514,34 +557,9 @@ __device__ int64_t rerun_segment(const CountArgs<T> &a, LaneFsm<T, N> &f, const 
     // re-run from the state right after the completion at tau
     f.e = tau;
     f.clear_all();
-    // first event after tau of every node: the N binary searches advance in
-    // lockstep, so that each step's loads are issued together
-    int32_t cur[N], hb[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        cur[k] = lo_[k];
-        hb[k] = hi_[k];
-    }
-    for (;;) {
-        bool any = false;
-        int32_t mid[N];
-        T v[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            mid[k] = cur[k] + (hb[k] - cur[k]) / 2;
-            any |= cur[k] < hb[k];
-        }
-        if (!any) break;
-#pragma unroll
-        for (int k = 0; k < N; ++k) v[k] = cur[k] < hb[k] ? a.ts_by_type[mid[k]] : T(0);
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            if (cur[k] < hb[k]) {
-                if (v[k] <= tau) cur[k] = mid[k] + 1;
-                else hb[k] = mid[k];
-            }
-        }
-    }
+    // first event after tau of every node
+    int32_t cur[N];
+    first_after<T, N>(a.ts_by_type, lo_, hi_, tau, cur);
     T head[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -666,11 +684,90 @@ __global__ __launch_bounds__(256) void k_reconcile(CountArgs<T> a) {
             total += rerun_segment<T, N>(a, f, lo_, hi_, H, p, s, tau);
         }
     }
-    a.counts[a.orig ? a.orig[slot] : slot] = (int32_t)total;
+    const int64_t o = a.orig ? a.orig[slot] : slot;
+    a.counts[o] = (int32_t)total;
+    if (a.tau) a.tau[o] = tau;
+}
+
+// Appended events (streaming).  A set counted up to the stream's first n0
+// events holds, per candidate, its count and last completion tau.  After an
+// append (first new time B) the machine resumes from the state right after
+// max(tau, B - H - 1): every occurrence ending at or after B starts at or
+// after B - H, so the earlier partial occurrences cannot complete any more
+// when tau < B - H, and none completes in [B - H, B) (tau is the last
+// completion before B); when tau >= B - H, the machine re-runs from tau over
+// the events after it, which reproduces its true state.  Either way every
+// completion it finds is at or after B and is added to the count.
+template <typename T, int N>
+__global__ __launch_bounds__(64) void k_count_append(CountArgs<T> a, T B) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr T kEnd = TsLimits<T>::hi();
+    const int W = blockDim.x, lane = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * W + lane;
+    if (s >= a.G) return;  // no barriers below
+    const int64_t slot = a.begin + s;
+    LaneFsm<T, N> f;
+    int32_t lo_[N], hi_[N];
+    const T H = reconcile_lane<T, N>(a, smem, W, lane, slot, f, lo_, hi_);
+    const int64_t o = a.orig ? a.orig[slot] : slot;
+    const T tau = a.tau[o];
+    const T from = tau > (T)(B - H - 1) ? tau : (T)(B - H - 1);
+    f.e = from;
+    f.clear_all();
+    int32_t cur[N];
+    first_after<T, N>(a.ts_by_type, lo_, hi_, from, cur);
+    T head[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) head[k] = cur[k] < hi_[k] ? a.ts_by_type[cur[k]] : kEnd;
+    int32_t add = 0;
+    T last = tau;
+    while (true) {
+        T t = head[0];
+        int j = 0;
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            if (head[k] < t) {
+                t = head[k];
+                j = k;
+            }
+        }
+        if (t == kEnd) break;
+        if (f.step(j, t, a.flags)) {
+            ++add;
+            last = t;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (k == j) {
+                ++cur[k];
+                head[k] = cur[k] < hi_[k] ? a.ts_by_type[cur[k]] : kEnd;
+            }
+        }
+    }
+    a.counts[o] += add;
+    a.tau[o] = last;
 }
 
 template <typename T>
 using KFn = void (*)(CountArgs<T>);
+
+template <typename T>
+using AFn = void (*)(CountArgs<T>, T);
+
+template <typename T>
+AFn<T> pick_append(int N) {
+    switch (N) {
+        case 1: return k_count_append<T, 1>;
+        case 2: return k_count_append<T, 2>;
+        case 3: return k_count_append<T, 3>;
+        case 4: return k_count_append<T, 4>;
+        case 5: return k_count_append<T, 5>;
+        case 6: return k_count_append<T, 6>;
+        case 7: return k_count_append<T, 7>;
+        case 8: return k_count_append<T, 8>;
+        default: return nullptr;
+    }
+}
 
 template <typename T, bool F, bool REL>
 KFn<T> pick_count_f(int N) {
@@ -875,8 +972,9 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         const int64_t G = g.end - g.begin;
         if (G <= 0) continue;
         if (s.n == 0) {  // no events: every count is zero
-            k_zero_counts<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(
-                c.compact ? nullptr : c.orig.as<int32_t>() + g.begin, G, c.counts.as<int32_t>() + (c.compact ? g.begin : 0));
+            k_zero_counts<T><<<(unsigned)((G + 255) / 256), 256, 0, st>>>(
+                c.compact ? nullptr : c.orig.as<int32_t>() + g.begin, G, c.counts.as<int32_t>() + (c.compact ? g.begin : 0),
+                !c.compact && c.tau.p ? c.tau.as<T>() : nullptr);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             continue;
         }
@@ -928,6 +1026,7 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.S = S;
         a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
         a.counts = c.counts.as<int32_t>();
+        a.tau = !c.compact && c.tau.p ? c.tau.as<T>() : nullptr;
         a.flags = d_flags;
         a.perm = nullptr;
         a.work = opt.worklog && c.work.p ? c.work.as<int32_t>() : nullptr;
@@ -958,7 +1057,52 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
     return hipSuccess;
 }
 
+// The events of the stream appended since set c was counted (B: the first
+// appended time): one lane per candidate resumes its machine (k_count_append).
+template <typename T>
+hipError_t count_append_t(const Stream &s, CandSet &c, int64_t B, int32_t *d_flags, hipStream_t st) {
+    hipError_t e;
+    if (c.compact || !c.tau.p) return hipErrorInvalidValue;
+    for (const Group &g : c.groups) {
+        const int64_t G = g.end - g.begin;
+        if (G <= 0) continue;
+        AFn<T> fn = pick_append<T>(g.N);
+        if (!fn) return hipErrorInvalidValue;
+        const Layout<T> L = layout<T>(g.N, g.Q, kRecLanes, s.K, false);
+        CountArgs<T> a{};
+        a.ts_by_type = s.ts_by_type.as<T>();
+        a.type_off = s.type_off.as<int32_t>();
+        a.K = s.K;
+        a.ctypes = c.types.as<int32_t>();
+        a.clo = c.lo.as<T>();
+        a.chi = c.hi.as<T>();
+        a.m = c.m;
+        a.begin = g.begin;
+        a.G = G;
+        a.Q = g.Q;
+        a.P = 1;
+        a.orig = c.orig.as<int32_t>();
+        a.counts = c.counts.as<int32_t>();
+        a.tau = c.tau.as<T>();
+        a.flags = d_flags;
+        a.off_qse = L.off_qse;
+        a.off_qh = L.off_qh;
+        a.off_tbuf = L.off_tbuf;
+        a.off_obuf = L.off_obuf;
+        a.off_misc = L.off_misc;
+        if ((e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total)) != hipSuccess) return e;
+        fn<<<(unsigned)((G + kRecLanes - 1) / kRecLanes), kRecLanes, L.total, st>>>(a, (T)B);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t launch_count_append(const Stream &s, CandSet &c, int64_t B, int32_t *d_flags, hipStream_t st) {
+    if (s.ts_kind == EPI_TS_I64) return count_append_t<int64_t>(s, c, B, d_flags, st);
+    return count_append_t<int32_t>(s, c, B, d_flags, st);
+}
 
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st) {
     if (s.ts_kind == EPI_TS_I64) return count_t<int64_t>(s, c, opt, d_flags, st);
@@ -1187,6 +1331,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         a.S = u.S;
         a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
         a.counts = c.counts.as<int32_t>();
+        a.tau = !c.compact && c.tau.p ? c.tau.template as<T>() : nullptr;
         a.flags = d_flags;
         a.perm = perms[u.set].p ? perms[u.set].template as<int32_t>() : nullptr;
         a.work = opt.worklog ? c.work.as<int32_t>() : nullptr;

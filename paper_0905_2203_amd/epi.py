@@ -33,6 +33,7 @@ EPI_TS_I32 = 0
 EPI_TS_I64 = 1
 EPI_MODE_PLAIN = 0
 EPI_MODE_BATCHED = 1
+EPI_MODE_INCREMENTAL = 2
 EPI_SCHED_RR = 0
 EPI_SCHED_LEARNED = 1
 EPI_SCHED_HEURISTIC = 2
@@ -42,7 +43,7 @@ EXPORTS = [
     "epi_create", "epi_destroy", "epi_last_error", "epi_status_string",
     "epi_validate_stream", "epi_validate_candidates",
     "epi_load_stream", "epi_load_stream_device", "epi_stream_info", "epi_read_type_index",
-    "epi_release_stream", "epi_submit_candidates", "epi_release_set",
+    "epi_release_stream", "epi_append_stream", "epi_submit_candidates", "epi_release_set",
     "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device",
     "epi_mine", "epi_mine_levels", "epi_mine_level_info", "epi_mine_read", "epi_mine_read_at",
     "epi_mine_level_bytes", "epi_mine_release",
@@ -99,6 +100,7 @@ def lib():
             "epi_stream_info": ([P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(INT)], I32),
             "epi_read_type_index": ([P, I32, P, P], I32),
             "epi_release_stream": ([P, I32], I32),
+            "epi_append_stream": ([P, I32, P, P, I64], I32),
             "epi_submit_candidates": ([P, I32, I64, P, P, P, P, ctypes.POINTER(I32)], I32),
             "epi_release_set": ([P, I32], I32),
             "epi_count": ([P, P, I32, INT, INT, P], I32),
@@ -225,6 +227,12 @@ class Context:
         self._check(lib().epi_load_stream(self.h, _ptr(types), _ptr(times), types.size, _ts_kind(times),
                                           int(K), ctypes.byref(sid)))
         return sid.value
+
+    def epi_append_stream(self, sid: int, types: np.ndarray, times: np.ndarray):
+        """Append events (times not before the stream's last) to stream sid."""
+        types = np.ascontiguousarray(types, np.int32)
+        times = np.ascontiguousarray(times)
+        self._check(lib().epi_append_stream(self.h, int(sid), _ptr(types), _ptr(times), types.size))
 
     def epi_load_stream_device(self, d_types, d_times, K: int, hip_stream=None) -> int:
         """d_types / d_times: contiguous torch tensors on the device."""
