@@ -115,7 +115,7 @@ epi_status epi_load_stream(epi_ctx *ctx, const int32_t *types, const void *times
 /* Same, from device buffers (int32 types, int32/int64 times) enqueued on
  * `hip_stream` (hipStream_t; null = the context's stream).  The inputs are
  * validated on the device; a violation is reported as EPI_EUNSORTED or
- * EPI_ETYPE by this call (it synchronises once to read the verdict). */
+ * EPI_ETYPE by this call (it synchronises once to read the result). */
 epi_status epi_load_stream_device(epi_ctx *ctx, const int32_t *d_types, const void *d_times,
                                   int64_t n, int ts_kind, int32_t K, void *hip_stream,
                                   int32_t *stream_id);
