@@ -231,6 +231,15 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
  *                         fit; else one walk per parent counts it and a
  *                         second writes its chain lists (0 = always the
  *                         latter)
+ *   EPI_OPT_MINE_LIST_ALPHAS  level-wise discovery, extension engine: levels
+ *                         with fewer frequent parent episodes than this
+ *                         (default 65536) take the list path when it fits;
+ *                         the others count with one walk per parent, and
+ *                         write their chain lists with walks cut into pieces
+ *                         (a size walk, then a list walk, over the frequent
+ *                         extensions) when the parents with frequent
+ *                         extensions are few and the list budget is not 0,
+ *                         else with one walk per such parent
  *   EPI_OPT_ALLOW_REPEATS 0 (default) / 1: epi_submit_candidates accepts
  *                         episodes in which a type occurs at several nodes
  *                         (Def. 2 does not exclude them; e.g. A -> B -> A).
@@ -243,7 +252,7 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
  * engine options (EPI_OPT_ALLOW_REPEATS only widens what is accepted). */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
        EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8,
-       EPI_OPT_ALLOW_REPEATS = 9 };
+       EPI_OPT_ALLOW_REPEATS = 9, EPI_OPT_MINE_LIST_ALPHAS = 10 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Autotune the batched engine for these sets and schedule: time every

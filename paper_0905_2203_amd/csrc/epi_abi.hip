@@ -646,6 +646,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
             if (value < 0) return fail(ctx, EPI_EINVAL, "list bytes must be >= 0");
             ctx->c.opt.mine_list_bytes = value;
             return EPI_OK;
+        case EPI_OPT_MINE_LIST_ALPHAS:
+            if (value < 0) return fail(ctx, EPI_EINVAL, "list alphas must be >= 0");
+            ctx->c.opt.mine_list_alphas = value;
+            return EPI_OK;
         case EPI_OPT_ALLOW_REPEATS:
             if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "allow-repeats must be 0 or 1");
             ctx->c.opt.allow_repeats = value != 0;
@@ -721,6 +725,7 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     // menus go to the state-machine engine
     mn->engine = n_menu <= kExtMaxMenu ? ctx->c.opt.mine_engine : 0;
     mn->list_budget = ctx->c.opt.mine_list_bytes;
+    mn->list_alphas = ctx->c.opt.mine_list_alphas;
     if (mn->engine == 1) {
         // extension engine: each level extends the previous level's chain lists
         auto tb = std::chrono::steady_clock::now();

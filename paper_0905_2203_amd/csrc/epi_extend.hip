@@ -55,10 +55,16 @@ double ms_since(Clock::time_point t0) { return std::chrono::duration<double, std
 
 constexpr int kWave = 64;
 constexpr uint16_t kNoSlot = 0;  // owner-slot entry of a type no lane counts (no intervals)
-// List path: taken for levels with fewer alphas than kListAlphas, whose walks
-// are cut into pieces so that about kListJobs workgroups run.
-constexpr int64_t kListAlphas = 65536;
+// List path: taken for levels with fewer alphas than Mine::list_alphas, whose
+// walks are cut into pieces so that about kListJobs workgroups run.  Chain
+// lists of levels with fewer write jobs than kWritePieced are written by
+// walks cut into pieces likewise (a size walk and a list walk over the
+// frequent extensions, about kWriteJobs workgroups each), so that no long
+// walk runs alone; with more jobs one walk per job keeps the GPU busy and
+// costs half the work.
 constexpr int64_t kListJobs = 65536;
+constexpr int64_t kWritePieced = 32768;
+constexpr int64_t kWriteJobs = 262144;
 
 // One entry of a chain list: an end event of an episode (time, stream
 // position) and the latest start of an occurrence ending there.
@@ -129,8 +135,14 @@ __device__ __forceinline__ T read_lane(T v, int l) {
 
 // Walk kinds: count (greedy counts and end-event counts per candidate),
 // write (chain lists of the frequent episodes), size (end events per
-// candidate and piece), list (end events of every candidate, per piece).
-enum WalkMode { kCount = 0, kWrite = 1, kSize = 2, kList = 3 };
+// candidate and piece), list (end events of every candidate, per piece), and
+// size and list over the frequent extensions only (chain lists written by
+// pieces).
+enum WalkMode { kCount = 0, kWrite = 1, kSize = 2, kList = 3, kWSize = 4, kWList = 5 };
+
+// walks over a write job's frequent extensions
+template <int MODE>
+constexpr bool kFreqJob = MODE == kWrite || MODE == kWSize || MODE == kWList;
 
 // Extension r of a job: its new type B, interval id and key (count and size:
 // the candidate's index; write: the first slot of its chain list).  Within a
@@ -138,11 +150,11 @@ enum WalkMode { kCount = 0, kWrite = 1, kSize = 2, kList = 3 };
 template <typename T, int MODE>
 __device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int64_t alpha, int64_t r, int32_t &B,
                                           int &iv, int64_t &key) {
-    if (MODE == kWrite) {
+    if (kFreqJob<MODE>) {
         const int64_t f = a.job_f[job] + r;
         B = a.w_type[f];
         iv = a.w_iv[f];
-        key = a.w_off[f];
+        key = MODE == kWrite ? a.w_off[f] : f;
     } else if (a.level2) {
         const int64_t bi0 = r / a.M;
         iv = (int)(r - bi0 * a.M);
@@ -160,7 +172,7 @@ __device__ __forceinline__ void extension(const WalkArgs<T> &a, int64_t job, int
 
 template <typename T, int MODE>
 __device__ __forceinline__ int64_t n_extensions(const WalkArgs<T> &a, int64_t job, int64_t alpha) {
-    if (MODE == kWrite) return a.job_f[job + 1] - a.job_f[job];
+    if (kFreqJob<MODE>) return a.job_f[job + 1] - a.job_f[job];
     if (a.level2) return (int64_t)(a.nf1 - 1) * a.M;
     return a.out_off[alpha + 1] - a.out_off[alpha];
 }
@@ -171,7 +183,7 @@ __device__ __forceinline__ int64_t n_extensions(const WalkArgs<T> &a, int64_t jo
 // states idle.
 template <typename T, int MP, int MODE>
 __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
-    constexpr bool WRITE = MODE == kWrite || MODE == kList;
+    constexpr bool WRITE = MODE == kWrite || MODE == kList || MODE == kWList;
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kMax = TsLimits<T>::hi();
     constexpr bool kExact = MP <= 4;
@@ -243,8 +255,8 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
             int64_t key = -1;
             if (in) {
                 extension<T, MODE>(a, job, alpha, r, B, iv, key);
-                if (MODE == kSize) key = key * a.nseg + seg;
-                if (MODE == kList) key = a.lst_off[key * a.nseg + seg];
+                if (MODE == kSize || MODE == kWSize) key = key * a.nseg + seg;
+                if (MODE == kList || MODE == kWList) key = a.lst_off[key * a.nseg + seg];
             }
             int32_t pB = __shfl_up(B, 1, kWave);
             if (lane == 0) pB = prevB;
@@ -460,7 +472,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
 #pragma unroll
             for (int m = 0; m < MP; ++m) nv[m] = cnv[m][lane];
         }
-        if (MODE == kCount || MODE == kSize) {
+        if (MODE == kCount || MODE == kSize || MODE == kWSize) {
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
                 if (own[m]) {
@@ -483,11 +495,12 @@ bool walk_args_complete(const WalkArgs<T> &a) {
     ok = ok && a.chain;
     if (a.level2) ok = ok && a.f1 && a.type_off && a.nf1 >= 2;
     else ok = ok && a.cbeg && a.clen;
-    if (MODE == kWrite) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv && a.w_off && a.wchain;
+    if (kFreqJob<MODE>) ok = ok && a.job_alpha && a.job_f && a.w_type && a.w_iv;
     else ok = ok && (a.level2 || (a.out_off && a.rlo && a.xlo && a.xhi && a.flast && a.fliv));
+    if (MODE == kWrite) ok = ok && a.w_off && a.wchain;
     if (MODE == kCount) ok = ok && a.counts && a.nvalid;
-    if (MODE == kSize) ok = ok && a.nvalid;
-    if (MODE == kList) ok = ok && a.lst_off && a.wchain;
+    if (MODE == kSize || MODE == kWSize) ok = ok && a.nvalid;
+    if (MODE == kList || MODE == kWList) ok = ok && a.lst_off && a.wchain;
     if (MODE == kWrite || MODE == kCount) ok = ok && a.nseg == 1;
     return ok;
 }
@@ -1065,7 +1078,7 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
     // candidate's end events are listed (list path), when they fit the budget.
     bool listed = false;
     DevBuf lst_off;
-    if (m > 0 && nA < kListAlphas) {
+    if (m > 0 && nA < mn.list_alphas) {
         const int32_t nseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (kListJobs + nA - 1) / nA));
         if ((e = lst_off.alloc(sizeof(int64_t) * (m * nseg + 1))) != hipSuccess) return e;
         DevBuf nvseg;
@@ -1209,7 +1222,25 @@ hipError_t level_t(const Stream &s, Mine &mn, int N, hipStream_t st) {
         a.w_iv = L.d_fliv.as<uint8_t>();
         a.w_off = L.cbeg.as<int64_t>();
         a.wchain = L.chain.as<ChainEntry<T>>();
-        if ((e = launch_walk<T, kWrite>(a, nj, st)) != hipSuccess) return e;
+        DevBuf wseg, woff;
+        if (mn.list_budget > 0 && nj < kWritePieced) {
+            // few write jobs: walks cut into pieces; the end events of each
+            // (frequent episode, piece), scanned in that order, give every
+            // piece its offset in the chain lists (the same layout)
+            const int32_t nseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (kWriteJobs + nj - 1) / nj));
+            if ((e = wseg.alloc(sizeof(int32_t) * (size_t)nf * nseg)) != hipSuccess) return e;
+            if ((e = woff.alloc(sizeof(int64_t) * ((size_t)nf * nseg + 1))) != hipSuccess) return e;
+            a.nseg = nseg;
+            a.nvalid = wseg.as<int32_t>();
+            a.walked = nullptr;
+            if ((e = launch_walk<T, kWSize>(a, nj * nseg, st)) != hipSuccess) return e;
+            if ((e = scan64(wseg.as<int32_t>(), nf * nseg, woff.as<int64_t>(), tmp, st)) != hipSuccess) return e;
+            a.lst_off = woff.as<int64_t>();
+            if ((e = launch_walk<T, kWList>(a, nj * nseg, st)) != hipSuccess) return e;
+        } else {
+            a.nseg = 1;
+            if ((e = launch_walk<T, kWrite>(a, nj, st)) != hipSuccess) return e;
+        }
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;  // the job buffers die here
     } else {
         if ((e = hipMemsetAsync(L.cbeg.p, 0, sizeof(int64_t), st)) != hipSuccess) return e;

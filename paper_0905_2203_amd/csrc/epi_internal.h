@@ -235,6 +235,7 @@ struct CountOptions {
     int64_t pair_filter_max_bytes = int64_t(1) << 30;
     int64_t mine_list_bytes = int64_t(8) << 30;  // extension engine: list-path budget per level
     bool allow_repeats = false;    // epi_submit_candidates accepts a type at several nodes
+    int64_t mine_list_alphas = 65536;  // extension engine: list path below this many parent episodes
 };
 
 // One level of a level-wise discovery run: candidates of size N in
@@ -298,6 +299,7 @@ struct Mine {
     // list path: device bytes the end-event lists of every candidate of a
     // level may take (larger: count and write walks)
     int64_t list_budget = 0;
+    int64_t list_alphas = 65536;  // levels with fewer alphas than this take the list path
     double bits_ms = 0;
     // pinned host slots (the context's) that device scalars are copied to,
     // several per synchronisation

@@ -61,6 +61,7 @@ EPI_OPT_WORKLOG = 6
 EPI_OPT_TARGET_ITEMS = 7
 EPI_OPT_MINE_LIST_BYTES = 8
 EPI_OPT_ALLOW_REPEATS = 9
+EPI_OPT_MINE_LIST_ALPHAS = 10
 
 
 class EpiError(RuntimeError):

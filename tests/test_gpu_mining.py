@@ -61,27 +61,36 @@ def compare_mining(ctx, name, s, menu, max_size, theta):
     return ref
 
 
-@pytest.mark.parametrize("list_bytes", [8 << 30, 0], ids=["lists", "walks"])
-def test_more_extension_types_than_lanes(ctx, list_bytes):
+@pytest.mark.parametrize("list_bytes,list_alphas", [(8 << 30, 65536), (0, 65536), (8 << 30, 0)],
+                         ids=["lists", "walks", "pieced_writes"])
+def test_more_extension_types_than_lanes(ctx, list_bytes, list_alphas):
     # 80 types: an episode has up to 79 (level 2) or 77 (level 3) extension
-    # types, more than the 64 lanes of one walk round; every level both from
-    # the end-event lists (walks cut into pieces) and by count and write walks
+    # types, more than the 64 lanes of one walk round; every level from the
+    # end-event lists (walks cut into pieces), by count walks and one write
+    # walk per parent, and by count walks and chain lists written in pieces
     rng = np.random.Generator(np.random.PCG64(31))
     s = sg.poisson_stream(rng, K=80, rate_hz=6.0, dur_s=60.0, ts_kind=0, unit_per_ms=1000, cascades=[4],
                           cascade_trigger_hz=[5.0])
     ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_BYTES, list_bytes)
+    ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_ALPHAS, list_alphas)
     try:
         ref = compare_mining(ctx, "K80", s, [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS], 4, 17)
     finally:
         ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_BYTES, 8 << 30)
+        ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_ALPHAS, 65536)
     assert len(ref[1]["frequent"]) > 0 and len(ref[2]["frequent"]) > 0
 
 
-def test_int64_nanoseconds(ctx):
+@pytest.mark.parametrize("list_alphas", [65536, 0], ids=["lists", "pieced_writes"])
+def test_int64_nanoseconds(ctx, list_alphas):
     rng = np.random.Generator(np.random.PCG64(32))
     s = sg.poisson_stream(rng, K=12, rate_hz=15.0, dur_s=60.0, ts_kind=1, unit_per_ms=1_000_000, cascades=[4],
                           cascade_trigger_hz=[5.0])
-    compare_mining(ctx, "int64", s, [(a * 1_000_000, b * 1_000_000) for a, b in sg.MENU_MINING_MS], 5, 40)
+    ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_ALPHAS, list_alphas)
+    try:
+        compare_mining(ctx, "int64", s, [(a * 1_000_000, b * 1_000_000) for a, b in sg.MENU_MINING_MS], 5, 40)
+    finally:
+        ctx.epi_set_option(epi.EPI_OPT_MINE_LIST_ALPHAS, 65536)
 
 
 def test_menu_of_six_overlapping_intervals(ctx):
