@@ -123,3 +123,38 @@ def test_negative_threshold_every_candidate_frequent(ctx):
     s = sg.poisson_stream(rng, K=5, rate_hz=4.0, dur_s=20.0, ts_kind=0, unit_per_ms=1000)
     ref = compare_mining(ctx, "theta-1", s, [(0, 5000), (5000, 20000)], 4, -1)
     assert any(v == 0 for v in ref[-1]["counts"].values())
+
+
+def test_runs_of_different_sizes_share_the_context_cache(ctx):
+    # the context keeps the blocks of each run for the next: runs of growing
+    # and shrinking size, two mines alive at once and released out of order,
+    # one run ordered after a caller's stream; every one equals the oracle
+    import torch
+
+    rng = np.random.Generator(np.random.PCG64(37))
+    small = sg.poisson_stream(rng, K=6, rate_hz=10.0, dur_s=30.0, ts_kind=0, unit_per_ms=1000)
+    big = sg.poisson_stream(rng, K=16, rate_hz=12.0, dur_s=60.0, ts_kind=0, unit_per_ms=1000, cascades=[4],
+                            cascade_trigger_hz=[5.0])
+    menu = [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS]
+    runs = [(small, 3, 10), (big, 4, 30), (small, 4, 5)]
+    mids, sids, refs = [], [], []
+    side = torch.cuda.Stream()
+    for i, (s, size, theta) in enumerate(runs):
+        say(f"run {i}: n={s['types'].size} K={s['K']} size {size} theta {theta}")
+        refs.append(apriori.mine(s, menu, size, theta))
+        sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
+        hs = side.cuda_stream if i == 2 else None
+        mids.append(ctx.epi_mine(sid, menu, size, theta, hip_stream=hs))
+        sids.append(sid)
+    for i in (1, 0, 2):  # out of order
+        mid, ref = mids[i], refs[i]
+        assert ctx.epi_mine_levels(mid) == len(ref)
+        for L in range(1, len(ref) + 1):
+            c, counts = ctx.epi_mine_read(mid, L)
+            got = {_key(c, j): int(counts[j]) for j in range(c["N"].size)}
+            want = {(ty, tuple(menu[v][0] for v in iv), tuple(menu[v][1] for v in iv)): cnt
+                    for (ty, iv), cnt in ref[L - 1]["counts"].items()}
+            assert got == want, f"run {i} level {L}"
+        ctx.epi_mine_release(mid)
+    for sid in sids:
+        ctx.epi_release_stream(sid)
