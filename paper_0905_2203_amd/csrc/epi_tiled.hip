@@ -1419,14 +1419,52 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     //    the reconciliation of every segmented unit
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-    static_assert(kClasses <= 65536, "queue counters");
-    k_fill_u64<<<1, 256, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kClasses, 0ull);
     std::vector<int> corder;
     for (int cl = 0; cl < kClasses; ++cl)
         if (!items[cl].empty()) corder.push_back(cl);
+    // the classes' persistent launches are independent: they run as parallel
+    // branches of the graph, on up to kBranches streams, the costliest classes
+    // first and each on the least loaded branch (their tails overlap)
+    constexpr int kBranches = 4;
+    const int nb = std::max(1, std::min<int>(kBranches, (int)corder.size()));
+    std::vector<double> ccost(kClasses, 0.0);
+    for (int cl : corder) {
+        for (float x : icost[cl]) ccost[cl] += x;
+        if (sched == EPI_SCHED_RR) ccost[cl] = (double)items[cl].size();
+    }
+    std::stable_sort(corder.begin(), corder.end(), [&](int x, int y) { return ccost[x] > ccost[y]; });
+    std::vector<hipStream_t> br(nb, nullptr);
+    std::vector<hipEvent_t> joined(nb, nullptr);
+    hipEvent_t fork = nullptr;
+    auto cleanup = [&]() {
+        for (auto &x : joined)
+            if (x) (void)hipEventDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto &x : br)
+            if (x) (void)hipStreamDestroy(x);
+    };
+    for (int i = 0; i < nb && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&joined[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        cleanup();
+        return e;
+    }
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        cleanup();
+        return e;
+    }
+    static_assert(kClasses <= 65536, "queue counters");
+    k_fill_u64<<<1, 256, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kClasses, 0ull);
+    e = hipEventRecord(fork, st);
+    for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], fork, 0);
+    std::vector<double> load(nb, 0.0);
     for (int cl : corder) {
         if (e != hipSuccess) break;
+        const int bi = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[bi] += ccost[cl];
         const int N = clsN[cl];
         const bool filt = filtN[cl];
         PFn<T> fn = filt ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
@@ -1438,10 +1476,17 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         if (e != hipSuccess) break;
         const int64_t grid =
             std::max<int64_t>(1, std::min<int64_t>((int64_t)items[cl].size(), (int64_t)ncu * std::max(per, 1)));
-        fn<<<(unsigned)grid, Wn[cl], L.total, st>>>(d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[cl],
-                                                    (int64_t)items[cl].size(), ioff[cl],
-                                                    reinterpret_cast<unsigned long long *>(d_queue.p) + cl);
+        fn<<<(unsigned)grid, Wn[cl], L.total, br[bi]>>>(d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[cl],
+                                                        (int64_t)items[cl].size(), ioff[cl],
+                                                        reinterpret_cast<unsigned long long *>(d_queue.p) + cl);
         e = hipGetLastError();
+    }
+    // every branch joins back before the reconciliation (also after an
+    // error, so that the capture ends cleanly)
+    for (int i = 0; i < nb; ++i) {
+        hipError_t ej = hipEventRecord(joined[i], br[i]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(st, joined[i], 0);
+        if (e == hipSuccess) e = ej;
     }
     for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
         if (units[ui].P <= 1) continue;
@@ -1456,6 +1501,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // the descriptors die here
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    cleanup();
     for (auto &r : sets) r.c->n_items = n_items;
     return e;
 }
