@@ -204,6 +204,66 @@ def ablation(k, scale, reps):
     ctx.close()
 
 
+def tracking_sweep(scale, reps, m_per_len=16):
+    """Episode-length sweep (the runtime-vs-length experiment of Sec. V-C,
+    on synthetic data): a few long episodes over a long stream, counted by
+    per-event tracking (EPI_MODE_TRACKING) and by the one-lane-per-episode
+    engine with automatic segments (EPI_MODE_PLAIN).  Stream: 64 types,
+    Poisson background at 40 Hz per type over 3600 s (about 9.2M events),
+    int64 nanoseconds, plus two planted 8-node cascades at 4 Hz whose gaps
+    lie in (0,5], (5,10] or (10,20] ms.  Per length N = 2..8: the planted
+    cascades' N-node prefixes and random N-node episodes over those
+    intervals, m_per_len in all.  Counts of both modes are checked against
+    the oracle; one JSON line per length."""
+    import spikegen as sg
+    from paper_0905_2203_amd import epi
+
+    rng = np.random.Generator(np.random.PCG64(911))
+    unit = 1_000_000
+    dur = 3600.0 * scale
+    s = sg.poisson_stream(rng, K=64, rate_hz=40.0, dur_s=dur, ts_kind=1, unit_per_ms=unit, cascades=[8, 8],
+                          cascade_trigger_hz=[4.0, 4.0])
+    n = int(s["types"].size)
+    log(f"tracking sweep: n={n}")
+    ctx = epi.Context(0)
+    sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
+    menu = [(a * unit, b * unit) for a, b in sg.MENU_MINING_MS]
+    try:
+        import oracle
+    except ImportError:
+        oracle = None
+    for N in range(2, 9):
+        eps = []
+        for p in s["planted"]:
+            eps.append(([int(x) for x in p["types"][:N]], [int(x) for x in p["lo"][: N - 1]],
+                        [int(x) for x in p["hi"][: N - 1]]))
+        while len(eps) < m_per_len:
+            iv = [menu[int(rng.integers(len(menu)))] for _ in range(N - 1)]
+            eps.append((rng.permutation(64)[:N].tolist(), [a for a, _ in iv], [b for _, b in iv]))
+        c = sg.candidates_from_list(eps)
+        cid = ctx.epi_submit_candidates(sid, c)
+        t_track = _timed(ctx, lambda: ctx.epi_count([cid], mode=epi.EPI_MODE_TRACKING), reps)
+        got_t = ctx.epi_read_counts(cid, len(eps))
+        t_plain = _timed(ctx, lambda: ctx.epi_count([cid], mode=epi.EPI_MODE_PLAIN), reps)
+        got_p = ctx.epi_read_counts(cid, len(eps))
+        parity = "not checked"
+        if oracle is not None:
+            want = oracle.count(s, c)
+            bad = int((want != got_t).sum() + (want != got_p).sum())
+            parity = f"{'ok' if bad == 0 else 'MISMATCH'}: {len(eps)} episodes, both modes, {bad} differ"
+        ctx.epi_release_set(cid)
+        line = {
+            "metric": "tracking_sweep", "episode_size": N, "episodes": len(eps), "events": n,
+            "tracking_ms": round(1e3 * t_track, 3), "plain_ms": round(1e3 * t_plain, 3),
+            "tracking_cand_ev_per_s": len(eps) * n / t_track, "plain_cand_ev_per_s": len(eps) * n / t_plain,
+            "tracking_vs_plain": round(t_plain / t_track, 3), "planted_counts": [int(x) for x in got_t[:2]],
+            "parity": parity, "dtype": "int64", "data": "synthetic",
+        }
+        print(json.dumps(line), flush=True)
+    ctx.epi_release_stream(sid)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,7 +276,12 @@ def main():
     ap.add_argument("--ablation", default="",
                     help="comma list of workload presets (1, 3, 4, 5): plain vs batched schedules, one JSON line each")
     ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
+    ap.add_argument("--tracking-sweep", action="store_true",
+                    help="episode-length sweep: per-event tracking vs the plain engine, one JSON line per length")
     args = ap.parse_args()
+    if args.tracking_sweep:
+        tracking_sweep(args.abl_scale, max(1, args.steps))
+        return
     if args.ablation:
         for k in [int(x) for x in args.ablation.split(",") if x]:
             ablation(k, args.abl_scale, max(1, args.steps))

@@ -57,7 +57,7 @@ enum {
 };
 
 enum { EPI_TS_I32 = 0, EPI_TS_I64 = 1 };
-enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1, EPI_MODE_INCREMENTAL = 2 };
+enum { EPI_MODE_PLAIN = 0, EPI_MODE_BATCHED = 1, EPI_MODE_INCREMENTAL = 2, EPI_MODE_TRACKING = 3 };
 enum { EPI_SCHED_RR = 0, EPI_SCHED_LEARNED = 1, EPI_SCHED_HEURISTIC = 2, EPI_SCHED_MEASURED = 3 };
 
 #define EPI_MAX_N 8 /* largest episode size */
@@ -160,6 +160,19 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  *                     ones are reconciled (returns when done).
  *   EPI_MODE_INCREMENTAL  after epi_append_stream: only the appended
  *                     events are counted (see epi_append_stream).
+ *   EPI_MODE_TRACKING parallel over events instead of episodes, for a few
+ *                     long episodes over a long stream (Parallel Local
+ *                     Tracking, Sec. IV-C, then the greedy of Alg. 1,
+ *                     Sec. IV-A): node by node, every event of the node's
+ *                     type finds by binary search the latest start of a
+ *                     chain ending at it, the events with a chain are
+ *                     compacted in time order (Sec. IV-D/E), and the count
+ *                     is the greedy over the (latest start, end) intervals,
+ *                     ranked by pointer jumping.  Working memory about
+ *                     4*ts + 24 bytes per event of an episode's most
+ *                     frequent type, in groups of at most 2 GiB; no work
+ *                     log; returns when done.  Sets of level-wise discovery
+ *                     are rejected (EPI_EINVAL).
  * sched (batched mode): EPI_SCHED_RR keeps submission order;
  * EPI_SCHED_LEARNED orders each class's episodes by the cost model's
  * predicted work (see epi_costmodel_train; without a trained model it falls

@@ -453,6 +453,10 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
     hipError_t e = s->ts_kind == EPI_TS_I64 ? upload_candidates<int64_t>(*cs, m, N, types, lo, hi, ctx->c.stream)
                                             : upload_candidates<int32_t>(*cs, m, N, types, lo, hi, ctx->c.stream);
     if (e != hipSuccess) return hipfail(ctx, e, "uploading candidates");
+    cs->h_N.assign(N, N + m);
+    cs->h_types.assign(types, types + m * kMaxN);
+    cs->h_lo.assign(lo, lo + m * (kMaxN - 1));
+    cs->h_hi.assign(hi, hi + m * (kMaxN - 1));
     const int32_t id = ctx->c.next_id++;
     ctx->c.sets[id] = std::move(cs);
     *set_id = id;
@@ -470,7 +474,8 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id) {
 epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, int sched, void *hip_stream) {
     if (!ctx) return EPI_EINVAL;
     if (k < 0 || (k > 0 && !set_ids)) return fail(ctx, EPI_EINVAL, "bad set list");
-    if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED && mode != EPI_MODE_INCREMENTAL)
+    if (mode != EPI_MODE_PLAIN && mode != EPI_MODE_BATCHED && mode != EPI_MODE_INCREMENTAL &&
+        mode != EPI_MODE_TRACKING)
         return fail(ctx, EPI_EINVAL, "unknown mode %d", mode);
     if (sched != EPI_SCHED_RR && sched != EPI_SCHED_LEARNED && sched != EPI_SCHED_HEURISTIC &&
         sched != EPI_SCHED_MEASURED)
@@ -510,6 +515,20 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
                 }
                 HIPTRY(ctx, launch_count_append(*s, *cs, B, ctx->c.flags.as<int32_t>(), st), "counting appended events");
             }
+            cs->counted = true;
+            cs->counted_n = s->n;
+        }
+        return EPI_OK;
+    }
+    if (mode == EPI_MODE_TRACKING) {
+        for (int32_t i = 0; i < k; ++i)
+            if (find_set(ctx, set_ids[i])->compact)
+                return fail(ctx, EPI_EINVAL, "set %d cannot be counted by tracking", set_ids[i]);
+        for (int32_t i = 0; i < k; ++i) {
+            CandSet *cs = find_set(ctx, set_ids[i]);
+            Stream *s = find_stream(ctx, cs->stream_id);
+            cs->logged = false;
+            HIPTRY(ctx, launch_count_tracking(*s, *cs, st), "counting by tracking");
             cs->counted = true;
             cs->counted_n = s->n;
         }

@@ -221,6 +221,12 @@ struct CandSet {
     const uint64_t *succ_bits = nullptr;
     std::vector<Group> groups;
     bool counted = false;
+    // host copy of the candidates (submission order; not for the compact
+    // layout): sizes [m], types [m][8], lo and hi [m][7]
+    std::vector<uint8_t> h_N;
+    std::vector<int32_t> h_types;
+    std::vector<int64_t> h_lo, h_hi;
+    DevBuf track_work, track_desc;  // working set of the tracking engine, kept for the next count
 };
 
 // Launch options (epi_set_option).
@@ -350,6 +356,9 @@ hipError_t build_type_index(Stream &s, hipStream_t st);
 hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
                                   int32_t K, int32_t *d_flags, hipStream_t st);
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st);
+// Count set c by per-event tracking of each episode's nodes and the greedy
+// over the latest-start intervals (epi_track.hip); returns when done.
+hipError_t launch_count_tracking(const Stream &s, CandSet &c, hipStream_t st);
 // Add to set c's counts the occurrences completed by the stream's events
 // after the first c.counted_n (B = the first of their times).
 hipError_t launch_count_append(const Stream &s, CandSet &c, int64_t B, int32_t *d_flags, hipStream_t st);

@@ -1,0 +1,369 @@
+// Counting by Parallel Local Tracking (Sec. IV-C) followed by the greedy of
+// Alg. 1 (Sec. IV-A): the engine for a few long episodes over a long stream,
+// where one lane per episode would leave most of the GPU idle.  It is
+// parallel over the events of each node's type instead of over episodes.
+//
+// For an episode alpha, the chain events of node k are the events x of type
+// alpha[k] that end an occurrence of alpha[1..k]; each carries the latest
+// start L_k(x) of such an occurrence.  Keeping only the latest start per end
+// event is exact for the greedy (Sec. IV-A: the non-overlapped subset is
+// taken in order of end times, and of two occurrences with one end the later
+// start dominates) and keeps every list no longer than its type's events.
+// L_1(x) = t_x.  Along the chain events of a node, in time order, L is
+// non-decreasing, so the predecessor with the latest start is the latest
+// chain event y of node k-1 with lo < t_x - t_y <= hi: one binary search per
+// event, which is the backward tracking of Alg. 2 with the search replacing
+// the scan.  The events with a chain are compacted in time order by a
+// count / scan / write pass (the order-preserving compaction of Sec. IV-D/E).
+// The count is Alg. 1 over the intervals (L_N(x), t_x) in time order: after
+// keeping x the next kept interval is the first with L > t_x, a binary search
+// over the non-decreasing L; the kept intervals form the successor chain of
+// the first interval, whose length and last element pointer jumping finds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "epi_internal.h"
+
+namespace epi {
+namespace {
+
+constexpr int kTB = 256;               // threads per block of the per-event kernels
+constexpr int kTPer = 8;               // events per thread
+constexpr int kTChunk = kTB * kTPer;   // events per block
+constexpr int kTWaves = kTB / 64;
+constexpr int kScanT = 1024;           // threads of the per-episode scan
+constexpr int kMaxJobs = 65535;        // episodes per launch (grid y)
+constexpr size_t kChunkBytes = size_t(2) << 30;  // working set of one group of episodes
+
+template <typename T>
+struct TrackJob {
+    const T *pt;         // chain events of node k-1: times (non-decreasing)
+    const T *pL;         // and their latest starts (non-decreasing)
+    const int32_t *pn;   // how many (on the device; null: pn_host)
+    int32_t pn_host;
+    int32_t ne;          // events of node k's type
+    const T *et;         // their times, in order
+    T lo, hi;            // constraint (lo, hi] from node k-1 to node k
+    T *ot, *oL;          // chain events of node k (written in time order)
+    int32_t *on;         // how many (written by the scan)
+    int32_t *blk;        // per-block counts, then offsets: max(1, ceil(ne / kTChunk)) entries
+};
+
+template <typename T>
+struct GreedyJob {
+    const T *t, *L;      // intervals (L_N(x), t_x) in time order
+    const int32_t *pn;   // how many (device; null: pn_host)
+    int32_t pn_host;
+    int32_t bound;       // capacity of the arrays below
+    int32_t *nx[2], *d[2], *last[2];
+    int32_t slot;        // submission index of the episode
+};
+
+__device__ __forceinline__ int32_t n_blocks(int32_t ne) { return max(1, (ne + kTChunk - 1) / kTChunk); }
+
+// Latest start of a chain of the previous nodes ending at an event at time t
+// of node k; false if none.
+template <typename T>
+__device__ __forceinline__ bool track_event(const TrackJob<T> &j, int32_t np, T t, T *L) {
+    const T lim = t - j.lo;  // the predecessor lies strictly before t - lo ...
+    int32_t a = 0, b = np;
+    while (a < b) {
+        const int32_t mid = a + (b - a) / 2;
+        if (j.pt[mid] < lim) a = mid + 1;
+        else b = mid;
+    }
+    if (a == 0) return false;
+    if (j.pt[a - 1] < t - j.hi) return false;  // ... and at or after t - hi
+    *L = j.pL[a - 1];
+    return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_count(const TrackJob<T> *__restrict__ jobs) {
+    const TrackJob<T> j = jobs[blockIdx.y];
+    if ((int32_t)blockIdx.x >= n_blocks(j.ne)) return;
+    const int32_t np = j.pn ? *j.pn : j.pn_host;
+    __shared__ int32_t tot;
+    if (threadIdx.x == 0) tot = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTChunk;
+    int32_t c = 0;
+    for (int r = 0; r < kTPer; ++r) {
+        const int64_t i = base + r * kTB + threadIdx.x;
+        T L;
+        if (i < j.ne && track_event(j, np, j.et[i], &L)) ++c;
+    }
+    atomicAdd(&tot, c);
+    __syncthreads();
+    if (threadIdx.x == 0) j.blk[blockIdx.x] = tot;
+}
+
+// Exclusive scan of one episode's block counts (one workgroup per episode);
+// the total is the node's number of chain events.
+template <typename T>
+__global__ __launch_bounds__(kScanT) void k_track_scan(const TrackJob<T> *__restrict__ jobs) {
+    const TrackJob<T> j = jobs[blockIdx.y];
+    const int32_t nb = n_blocks(j.ne);
+    __shared__ int32_t wsum[kScanT / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t carry = 0;
+    for (int32_t b0 = 0; b0 < nb; b0 += kScanT) {
+        const int32_t b = b0 + (int32_t)threadIdx.x;
+        const int32_t v = b < nb ? j.blk[b] : 0;
+        int32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        int32_t woff = 0, total = 0;
+        for (int q = 0; q < kScanT / 64; ++q) {
+            const int32_t s = wsum[q];
+            if (q < w) woff += s;
+            total += s;
+        }
+        if (b < nb) j.blk[b] = carry + woff + x - v;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *j.on = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_write(const TrackJob<T> *__restrict__ jobs) {
+    const TrackJob<T> j = jobs[blockIdx.y];
+    if ((int32_t)blockIdx.x >= n_blocks(j.ne)) return;
+    const int32_t np = j.pn ? *j.pn : j.pn_host;
+    __shared__ int32_t wc[kTWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t pos = j.blk[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kTChunk;
+    for (int r = 0; r < kTPer; ++r) {
+        const int64_t i = base + r * kTB + threadIdx.x;
+        T t = 0, L = 0;
+        bool ok = false;
+        if (i < j.ne) {
+            t = j.et[i];
+            ok = track_event(j, np, t, &L);
+        }
+        const uint64_t bal = __ballot(ok);
+        const int32_t below = __popcll(bal & ((uint64_t(1) << lane) - 1));
+        if (lane == 0) wc[w] = __popcll(bal);
+        __syncthreads();
+        int32_t woff = 0, total = 0;
+        for (int q = 0; q < kTWaves; ++q) {
+            if (q < w) woff += wc[q];
+            total += wc[q];
+        }
+        if (ok) {
+            j.ot[pos + woff + below] = t;
+            j.oL[pos + woff + below] = L;
+        }
+        pos += total;
+        __syncthreads();
+    }
+}
+
+// Successor of every interval under the greedy: the first later interval
+// whose start is after its end (the end of the list if none).
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_next(const GreedyJob<T> *__restrict__ jobs) {
+    const GreedyJob<T> j = jobs[blockIdx.y];
+    const int32_t n = j.pn ? *j.pn : j.pn_host;
+    const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
+    if (i >= n) return;
+    const T ti = j.t[i];
+    int32_t a = (int32_t)i + 1, b = n;
+    while (a < b) {
+        const int32_t mid = a + (b - a) / 2;
+        if (j.L[mid] <= ti) a = mid + 1;
+        else b = mid;
+    }
+    j.nx[0][i] = a;
+    j.d[0][i] = 1;
+    j.last[0][i] = (int32_t)i;
+}
+
+// One pointer-jumping round: every interval's (covered count, last covered
+// interval, next uncovered interval) over twice the distance.
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_jump(const GreedyJob<T> *__restrict__ jobs, int r) {
+    const GreedyJob<T> j = jobs[blockIdx.y];
+    const int32_t n = j.pn ? *j.pn : j.pn_host;
+    const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
+    if (i >= n) return;
+    const int src = r & 1, dst = src ^ 1;
+    const int32_t k = j.nx[src][i];
+    if (k < n) {
+        j.d[dst][i] = j.d[src][i] + j.d[src][k];
+        j.last[dst][i] = j.last[src][k];
+        j.nx[dst][i] = j.nx[src][k];
+    } else {
+        j.d[dst][i] = j.d[src][i];
+        j.last[dst][i] = j.last[src][i];
+        j.nx[dst][i] = k;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_final(const GreedyJob<T> *__restrict__ jobs, int32_t njobs, int R,
+                                                     int32_t *__restrict__ counts, T *__restrict__ tau) {
+    const int32_t q = blockIdx.x * kTB + threadIdx.x;
+    if (q >= njobs) return;
+    const GreedyJob<T> j = jobs[q];
+    const int32_t n = j.pn ? *j.pn : j.pn_host;
+    const int r = R & 1;
+    counts[j.slot] = n > 0 ? j.d[r][0] : 0;
+    if (tau) tau[j.slot] = n > 0 ? j.t[j.last[r][0]] : TsLimits<T>::lo();
+}
+
+size_t round_up(size_t b) { return (b + 255) & ~size_t(255); }
+
+template <typename T>
+hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
+    const int64_t m = c.m;
+    if (m == 0) return hipSuccess;
+    auto nt = [&](int32_t E) -> int32_t { return s.h_off[E + 1] - s.h_off[E]; };
+    auto job_bytes = [&](int64_t q) -> size_t {
+        const int N = c.h_N[q];
+        const int32_t *ty = c.h_types.data() + q * kMaxN;
+        size_t maxl = 0, nbm = 1;
+        for (int k = 1; k < N; ++k) {
+            maxl = std::max<size_t>(maxl, (size_t)nt(ty[k]));
+            nbm = std::max<size_t>(nbm, ((size_t)nt(ty[k]) + kTChunk - 1) / kTChunk);
+        }
+        const size_t nN = std::max<size_t>(1, (size_t)nt(ty[N - 1]));
+        return 4 * round_up(sizeof(T) * std::max<size_t>(maxl, 1)) + 6 * round_up(4 * nN) + round_up(4 * nbm) +
+               round_up(4 * kMaxN);
+    };
+    const T *tsb = s.ts_by_type.as<T>();
+    hipError_t e;
+    for (int64_t q0 = 0; q0 < m;) {
+        // a group of episodes whose working set fits the budget (at least one)
+        int64_t q1 = q0;
+        size_t total = 0;
+        while (q1 < m && q1 - q0 < kMaxJobs) {
+            const size_t b = job_bytes(q1);
+            if (q1 > q0 && total + b > kChunkBytes) break;
+            total += b;
+            ++q1;
+        }
+        DevBuf &work = c.track_work;
+        if (work.bytes < total && (e = work.alloc(total)) != hipSuccess) return e;
+        std::vector<std::vector<TrackJob<T>>> lv(kMaxN + 1);
+        std::vector<GreedyJob<T>> gj;
+        int32_t max_bound = 1;
+        char *p = work.as<char>();
+        for (int64_t q = q0; q < q1; ++q) {
+            const int N = c.h_N[q];
+            const int32_t *ty = c.h_types.data() + q * kMaxN;
+            size_t maxl = 0, nbm = 1;
+            for (int k = 1; k < N; ++k) {
+                maxl = std::max<size_t>(maxl, (size_t)nt(ty[k]));
+                nbm = std::max<size_t>(nbm, ((size_t)nt(ty[k]) + kTChunk - 1) / kTChunk);
+            }
+            const size_t nN = std::max<size_t>(1, (size_t)nt(ty[N - 1]));
+            const size_t lb = round_up(sizeof(T) * std::max<size_t>(maxl, 1));
+            T *buf[2][2] = {{(T *)p, (T *)(p + lb)}, {(T *)(p + 2 * lb), (T *)(p + 3 * lb)}};
+            p += 4 * lb;
+            int32_t *ga[6];
+            for (int a = 0; a < 6; ++a) {
+                ga[a] = (int32_t *)p;
+                p += round_up(4 * nN);
+            }
+            int32_t *blk = (int32_t *)p;
+            p += round_up(4 * nbm);
+            int32_t *on = (int32_t *)p;
+            p += round_up(4 * kMaxN);
+            // node 1: the type's events, each its own start
+            const T *pt = tsb + s.h_off[ty[0]], *pL = pt;
+            const int32_t *pn = nullptr;
+            int32_t pn_host = nt(ty[0]);
+            for (int k = 1; k < N; ++k) {
+                TrackJob<T> j;
+                j.pt = pt;
+                j.pL = pL;
+                j.pn = pn;
+                j.pn_host = pn_host;
+                j.ne = nt(ty[k]);
+                j.et = tsb + s.h_off[ty[k]];
+                j.lo = (T)c.h_lo[q * (kMaxN - 1) + k - 1];
+                j.hi = (T)c.h_hi[q * (kMaxN - 1) + k - 1];
+                j.ot = buf[k & 1][0];
+                j.oL = buf[k & 1][1];
+                j.on = on + k;
+                j.blk = blk;
+                lv[k].push_back(j);
+                pt = j.ot;
+                pL = j.oL;
+                pn = j.on;
+            }
+            GreedyJob<T> g;
+            g.t = pt;
+            g.L = pL;
+            g.pn = pn;
+            g.pn_host = pn_host;
+            g.bound = (int32_t)nN;
+            for (int a = 0; a < 2; ++a) {
+                g.nx[a] = ga[a];
+                g.d[a] = ga[2 + a];
+                g.last[a] = ga[4 + a];
+            }
+            g.slot = (int32_t)q;
+            gj.push_back(g);
+            max_bound = std::max<int32_t>(max_bound, g.bound);
+        }
+        // descriptors: the levels' jobs, then the greedy's
+        size_t db = 0;
+        std::vector<size_t> loff(kMaxN + 1, 0);
+        for (int k = 1; k < kMaxN; ++k) {
+            loff[k] = db;
+            db += round_up(sizeof(TrackJob<T>) * lv[k].size());
+        }
+        const size_t goff = db;
+        db += round_up(sizeof(GreedyJob<T>) * gj.size());
+        std::vector<char> hd(db);
+        for (int k = 1; k < kMaxN; ++k)
+            if (!lv[k].empty()) std::copy_n((const char *)lv[k].data(), sizeof(TrackJob<T>) * lv[k].size(), &hd[loff[k]]);
+        std::copy_n((const char *)gj.data(), sizeof(GreedyJob<T>) * gj.size(), &hd[goff]);
+        DevBuf &desc = c.track_desc;
+        if (desc.bytes < db && (e = desc.alloc(db)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(desc.p, hd.data(), db, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+        for (int k = 1; k < kMaxN; ++k) {
+            if (lv[k].empty()) continue;
+            int32_t gx = 1;
+            for (const auto &j : lv[k]) gx = std::max<int32_t>(gx, (j.ne + kTChunk - 1) / kTChunk);
+            const auto *dj = (const TrackJob<T> *)(desc.as<char>() + loff[k]);
+            const dim3 grid((unsigned)gx, (unsigned)lv[k].size());
+            k_track_count<T><<<grid, kTB, 0, st>>>(dj);
+            k_track_scan<T><<<dim3(1, (unsigned)lv[k].size()), kScanT, 0, st>>>(dj);
+            k_track_write<T><<<grid, kTB, 0, st>>>(dj);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const auto *dg = (const GreedyJob<T> *)(desc.as<char>() + goff);
+        const dim3 ggrid((unsigned)((max_bound + kTB - 1) / kTB), (unsigned)gj.size());
+        k_track_next<T><<<ggrid, kTB, 0, st>>>(dg);
+        int R = 0;
+        while ((int64_t(1) << R) < max_bound) ++R;
+        for (int r = 0; r < R; ++r) k_track_jump<T><<<ggrid, kTB, 0, st>>>(dg, r);
+        k_track_final<T><<<(unsigned)((gj.size() + kTB - 1) / kTB), kTB, 0, st>>>(
+            dg, (int32_t)gj.size(), R, c.counts.as<int32_t>(), c.tau.p ? c.tau.as<T>() : nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // the host descriptors die here, and the next group reuses the working set
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        q0 = q1;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_count_tracking(const Stream &s, CandSet &c, hipStream_t st) {
+    if (c.compact || (int64_t)c.h_N.size() != c.m) return hipErrorInvalidValue;
+    return s.ts_kind == EPI_TS_I64 ? count_tracking_t<int64_t>(s, c, st) : count_tracking_t<int32_t>(s, c, st);
+}
+
+}  // namespace epi

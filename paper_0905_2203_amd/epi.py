@@ -34,6 +34,7 @@ EPI_TS_I64 = 1
 EPI_MODE_PLAIN = 0
 EPI_MODE_BATCHED = 1
 EPI_MODE_INCREMENTAL = 2
+EPI_MODE_TRACKING = 3
 EPI_SCHED_RR = 0
 EPI_SCHED_LEARNED = 1
 EPI_SCHED_HEURISTIC = 2
