@@ -30,10 +30,12 @@ namespace epi {
 namespace {
 
 constexpr int kTB = 256;               // threads per block of the per-event kernels
-constexpr int kTPer = 8;               // events per thread
+constexpr int kTPer = 4;               // events per thread
 constexpr int kTChunk = kTB * kTPer;   // events per block
 constexpr int kTWaves = kTB / 64;
 constexpr int kScanT = 1024;           // threads of the per-episode scan
+constexpr int kStage = 2048;           // chain events of node k-1 staged in LDS per block
+constexpr int kJPer = 4;               // intervals per thread of a pointer-jumping round
 constexpr int kMaxJobs = 65535;        // episodes per launch (grid y)
 constexpr size_t kChunkBytes = size_t(2) << 30;  // working set of one group of episodes
 
@@ -46,9 +48,16 @@ struct TrackJob {
     int32_t ne;          // events of node k's type
     const T *et;         // their times, in order
     T lo, hi;            // constraint (lo, hi] from node k-1 to node k
+    T *tl;               // per event of node k: its latest start, or the type minimum (no chain)
     T *ot, *oL;          // chain events of node k (written in time order)
     int32_t *on;         // how many (written by the scan)
     int32_t *blk;        // per-block counts, then offsets: max(1, ceil(ne / kTChunk)) entries
+};
+
+// (next uncovered interval, intervals covered, last covered interval) of the
+// pointer jumping
+struct Hop {
+    int32_t nx, d, last, pad;
 };
 
 template <typename T>
@@ -57,43 +66,88 @@ struct GreedyJob {
     const int32_t *pn;   // how many (device; null: pn_host)
     int32_t pn_host;
     int32_t bound;       // capacity of the arrays below
-    int32_t *nx[2], *d[2], *last[2];
+    Hop *h[2];
     int32_t slot;        // submission index of the episode
 };
 
 __device__ __forceinline__ int32_t n_blocks(int32_t ne) { return max(1, (ne + kTChunk - 1) / kTChunk); }
 
-// Latest start of a chain of the previous nodes ending at an event at time t
-// of node k; false if none.
+// first index in [a, b) of ts with ts[index] >= x (b if none)
 template <typename T>
-__device__ __forceinline__ bool track_event(const TrackJob<T> &j, int32_t np, T t, T *L) {
-    const T lim = t - j.lo;  // the predecessor lies strictly before t - lo ...
-    int32_t a = 0, b = np;
+__device__ __forceinline__ int32_t lower_idx(const T *ts, int32_t a, int32_t b, T x) {
     while (a < b) {
         const int32_t mid = a + (b - a) / 2;
-        if (j.pt[mid] < lim) a = mid + 1;
+        if (ts[mid] < x) a = mid + 1;
         else b = mid;
     }
-    if (a == 0) return false;
-    if (j.pt[a - 1] < t - j.hi) return false;  // ... and at or after t - hi
-    *L = j.pL[a - 1];
-    return true;
+    return a;
 }
 
+// The same by one wave: 64 probes per step, so a few dependent loads instead
+// of one per halving (the value is uniform across the wave).
 template <typename T>
-__global__ __launch_bounds__(kTB) void k_track_count(const TrackJob<T> *__restrict__ jobs) {
+__device__ __forceinline__ int32_t lower_idx_wave(const T *ts, int32_t a, int32_t b, T x) {
+    const int lane = threadIdx.x & 63;
+    while (b - a > 64) {
+        const int32_t step = (b - a + 63) / 64;
+        const int64_t p = (int64_t)a + (int64_t)lane * step;
+        const int cnt = __popcll(__ballot(p < b && ts[p] < x));
+        if (cnt == 0) return a;
+        // the first index at or above x lies in (a + (cnt-1) step, a + cnt step]
+        const int64_t na = (int64_t)a + (int64_t)(cnt - 1) * step + 1;
+        const int64_t nb = (int64_t)a + (int64_t)cnt * step;
+        a = (int32_t)na;
+        b = (int32_t)min<int64_t>(nb, b);
+    }
+    return a + __popcll(__ballot(a + lane < b && ts[a + lane] < x));
+}
+
+// Backward tracking of one block of node k's events: each finds the latest
+// chain event y of node k-1 with t - hi <= t_y < t - lo and takes its latest
+// start.  The chain events any event of the block can reach (from the block's
+// first time - lo back by one entry to its last time - lo) are staged in LDS
+// when they fit, else searched in place.  Writes every event's latest start
+// (tl) and the block's number of chain events.
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_search(const TrackJob<T> *__restrict__ jobs) {
     const TrackJob<T> j = jobs[blockIdx.y];
     if ((int32_t)blockIdx.x >= n_blocks(j.ne)) return;
     const int32_t np = j.pn ? *j.pn : j.pn_host;
-    __shared__ int32_t tot;
+    __shared__ T st[kStage], sL[kStage];
+    __shared__ int32_t rng[2], tot;
+    const int64_t base = (int64_t)blockIdx.x * kTChunk;
+    const int64_t end = min<int64_t>(base + kTChunk, j.ne);
+    if (threadIdx.x < 128) {  // waves 0 and 1: the range of the first and of the last event
+        const int w = threadIdx.x >> 6;
+        int32_t a = 0;
+        if (base < end) a = lower_idx_wave(j.pt, 0, np, (w == 0 ? j.et[base] : j.et[end - 1]) - j.lo);
+        if ((threadIdx.x & 63) == 0) rng[w] = a;
+    }
     if (threadIdx.x == 0) tot = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTChunk;
+    const int32_t s0 = max(rng[0] - 1, 0), len = rng[1] - s0;
+    const bool staged = len <= kStage;
+    if (staged)
+        for (int32_t q = threadIdx.x; q < len; q += kTB) {
+            st[q] = j.pt[s0 + q];
+            sL[q] = j.pL[s0 + q];
+        }
+    __syncthreads();
     int32_t c = 0;
     for (int r = 0; r < kTPer; ++r) {
         const int64_t i = base + r * kTB + threadIdx.x;
-        T L;
-        if (i < j.ne && track_event(j, np, j.et[i], &L)) ++c;
+        if (i >= end) break;
+        const T t = j.et[i];
+        T L = TsLimits<T>::lo();
+        if (staged) {
+            const int32_t a = lower_idx(st, 0, len, t - j.lo);
+            if (a > 0 && st[a - 1] >= t - j.hi) L = sL[a - 1];
+        } else {
+            const int32_t a = lower_idx(j.pt, 0, np, t - j.lo);
+            if (a > 0 && j.pt[a - 1] >= t - j.hi) L = j.pL[a - 1];
+        }
+        j.tl[i] = L;
+        c += L != TsLimits<T>::lo();
     }
     atomicAdd(&tot, c);
     __syncthreads();
@@ -132,23 +186,23 @@ __global__ __launch_bounds__(kScanT) void k_track_scan(const TrackJob<T> *__rest
     if (threadIdx.x == 0) *j.on = carry;
 }
 
+// Order-preserving compaction of the events with a chain.
 template <typename T>
 __global__ __launch_bounds__(kTB) void k_track_write(const TrackJob<T> *__restrict__ jobs) {
     const TrackJob<T> j = jobs[blockIdx.y];
     if ((int32_t)blockIdx.x >= n_blocks(j.ne)) return;
-    const int32_t np = j.pn ? *j.pn : j.pn_host;
     __shared__ int32_t wc[kTWaves];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int32_t pos = j.blk[blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * kTChunk;
     for (int r = 0; r < kTPer; ++r) {
         const int64_t i = base + r * kTB + threadIdx.x;
-        T t = 0, L = 0;
-        bool ok = false;
+        T t = 0, L = TsLimits<T>::lo();
         if (i < j.ne) {
             t = j.et[i];
-            ok = track_event(j, np, t, &L);
+            L = j.tl[i];
         }
+        const bool ok = L != TsLimits<T>::lo();
         const uint64_t bal = __ballot(ok);
         const int32_t below = __popcll(bal & ((uint64_t(1) << lane) - 1));
         if (lane == 0) wc[w] = __popcll(bal);
@@ -182,30 +236,33 @@ __global__ __launch_bounds__(kTB) void k_track_next(const GreedyJob<T> *__restri
         if (j.L[mid] <= ti) a = mid + 1;
         else b = mid;
     }
-    j.nx[0][i] = a;
-    j.d[0][i] = 1;
-    j.last[0][i] = (int32_t)i;
+    j.h[0][i] = Hop{a, 1, (int32_t)i, 0};
 }
 
-// One pointer-jumping round: every interval's (covered count, last covered
-// interval, next uncovered interval) over twice the distance.
+// One pointer-jumping round: every interval's (next uncovered interval,
+// covered count, last covered interval) over twice the distance.
+// Each thread takes kJPer intervals, so that their loads are in flight together.
 template <typename T>
 __global__ __launch_bounds__(kTB) void k_track_jump(const GreedyJob<T> *__restrict__ jobs, int r) {
     const GreedyJob<T> j = jobs[blockIdx.y];
     const int32_t n = j.pn ? *j.pn : j.pn_host;
-    const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
-    if (i >= n) return;
-    const int src = r & 1, dst = src ^ 1;
-    const int32_t k = j.nx[src][i];
-    if (k < n) {
-        j.d[dst][i] = j.d[src][i] + j.d[src][k];
-        j.last[dst][i] = j.last[src][k];
-        j.nx[dst][i] = j.nx[src][k];
-    } else {
-        j.d[dst][i] = j.d[src][i];
-        j.last[dst][i] = j.last[src][i];
-        j.nx[dst][i] = k;
-    }
+    const int64_t i0 = (int64_t)blockIdx.x * kTB * kJPer + threadIdx.x;
+    if (i0 >= n) return;
+    const Hop *src = j.h[r & 1];
+    Hop *dst = j.h[(r & 1) ^ 1];
+    Hop x[kJPer];
+#pragma unroll
+    for (int q = 0; q < kJPer; ++q)
+        if (i0 + q * kTB < n) x[q] = src[i0 + q * kTB];
+#pragma unroll
+    for (int q = 0; q < kJPer; ++q)
+        if (i0 + q * kTB < n && x[q].nx < n) {
+            const Hop y = src[x[q].nx];
+            x[q] = Hop{y.nx, x[q].d + y.d, y.last, 0};
+        }
+#pragma unroll
+    for (int q = 0; q < kJPer; ++q)
+        if (i0 + q * kTB < n) dst[i0 + q * kTB] = x[q];
 }
 
 template <typename T>
@@ -215,9 +272,9 @@ __global__ __launch_bounds__(kTB) void k_track_final(const GreedyJob<T> *__restr
     if (q >= njobs) return;
     const GreedyJob<T> j = jobs[q];
     const int32_t n = j.pn ? *j.pn : j.pn_host;
-    const int r = R & 1;
-    counts[j.slot] = n > 0 ? j.d[r][0] : 0;
-    if (tau) tau[j.slot] = n > 0 ? j.t[j.last[r][0]] : TsLimits<T>::lo();
+    const Hop h0 = n > 0 ? j.h[R & 1][0] : Hop{0, 0, 0, 0};
+    counts[j.slot] = n > 0 ? h0.d : 0;
+    if (tau) tau[j.slot] = n > 0 ? j.t[h0.last] : TsLimits<T>::lo();
 }
 
 size_t round_up(size_t b) { return (b + 255) & ~size_t(255); }
@@ -236,8 +293,8 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
             nbm = std::max<size_t>(nbm, ((size_t)nt(ty[k]) + kTChunk - 1) / kTChunk);
         }
         const size_t nN = std::max<size_t>(1, (size_t)nt(ty[N - 1]));
-        return 4 * round_up(sizeof(T) * std::max<size_t>(maxl, 1)) + 6 * round_up(4 * nN) + round_up(4 * nbm) +
-               round_up(4 * kMaxN);
+        return 5 * round_up(sizeof(T) * std::max<size_t>(maxl, 1)) + 2 * round_up(sizeof(Hop) * nN) +
+               round_up(4 * nbm) + round_up(4 * kMaxN);
     };
     const T *tsb = s.ts_by_type.as<T>();
     hipError_t e;
@@ -268,11 +325,12 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
             const size_t nN = std::max<size_t>(1, (size_t)nt(ty[N - 1]));
             const size_t lb = round_up(sizeof(T) * std::max<size_t>(maxl, 1));
             T *buf[2][2] = {{(T *)p, (T *)(p + lb)}, {(T *)(p + 2 * lb), (T *)(p + 3 * lb)}};
-            p += 4 * lb;
-            int32_t *ga[6];
-            for (int a = 0; a < 6; ++a) {
-                ga[a] = (int32_t *)p;
-                p += round_up(4 * nN);
+            T *tl = (T *)(p + 4 * lb);
+            p += 5 * lb;
+            Hop *ga[2];
+            for (int a = 0; a < 2; ++a) {
+                ga[a] = (Hop *)p;
+                p += round_up(sizeof(Hop) * nN);
             }
             int32_t *blk = (int32_t *)p;
             p += round_up(4 * nbm);
@@ -292,6 +350,7 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
                 j.et = tsb + s.h_off[ty[k]];
                 j.lo = (T)c.h_lo[q * (kMaxN - 1) + k - 1];
                 j.hi = (T)c.h_hi[q * (kMaxN - 1) + k - 1];
+                j.tl = tl;
                 j.ot = buf[k & 1][0];
                 j.oL = buf[k & 1][1];
                 j.on = on + k;
@@ -307,11 +366,8 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
             g.pn = pn;
             g.pn_host = pn_host;
             g.bound = (int32_t)nN;
-            for (int a = 0; a < 2; ++a) {
-                g.nx[a] = ga[a];
-                g.d[a] = ga[2 + a];
-                g.last[a] = ga[4 + a];
-            }
+            g.h[0] = ga[0];
+            g.h[1] = ga[1];
             g.slot = (int32_t)q;
             gj.push_back(g);
             max_bound = std::max<int32_t>(max_bound, g.bound);
@@ -338,7 +394,7 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
             for (const auto &j : lv[k]) gx = std::max<int32_t>(gx, (j.ne + kTChunk - 1) / kTChunk);
             const auto *dj = (const TrackJob<T> *)(desc.as<char>() + loff[k]);
             const dim3 grid((unsigned)gx, (unsigned)lv[k].size());
-            k_track_count<T><<<grid, kTB, 0, st>>>(dj);
+            k_track_search<T><<<grid, kTB, 0, st>>>(dj);
             k_track_scan<T><<<dim3(1, (unsigned)lv[k].size()), kScanT, 0, st>>>(dj);
             k_track_write<T><<<grid, kTB, 0, st>>>(dj);
             if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -348,7 +404,8 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
         k_track_next<T><<<ggrid, kTB, 0, st>>>(dg);
         int R = 0;
         while ((int64_t(1) << R) < max_bound) ++R;
-        for (int r = 0; r < R; ++r) k_track_jump<T><<<ggrid, kTB, 0, st>>>(dg, r);
+        const dim3 jgrid((unsigned)((max_bound + kTB * kJPer - 1) / (kTB * kJPer)), (unsigned)gj.size());
+        for (int r = 0; r < R; ++r) k_track_jump<T><<<jgrid, kTB, 0, st>>>(dg, r);
         k_track_final<T><<<(unsigned)((gj.size() + kTB - 1) / kTB), kTB, 0, st>>>(
             dg, (int32_t)gj.size(), R, c.counts.as<int32_t>(), c.tau.p ? c.tau.as<T>() : nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
