@@ -30,6 +30,8 @@ namespace epi {
 namespace {
 
 constexpr int kTB = 256;               // threads per block of the per-event kernels
+constexpr int kTBLog = 8;
+static_assert((1 << kTBLog) == kTB, "kTBLog");
 constexpr int kTPer = 4;               // events per thread
 constexpr int kTChunk = kTB * kTPer;   // events per block
 constexpr int kTWaves = kTB / 64;
@@ -222,21 +224,53 @@ __global__ __launch_bounds__(kTB) void k_track_write(const TrackJob<T> *__restri
 }
 
 // Successor of every interval under the greedy: the first later interval
-// whose start is after its end (the end of the list if none).
+// whose start is after its end (the end of the list if none).  Each block of
+// kTB intervals then follows its successors inside the block by pointer
+// jumping in LDS, so every record leaves the block: (first successor at or
+// after the block's end, intervals covered, last covered).  The chain from any
+// interval then takes at most one record per block.
 template <typename T>
 __global__ __launch_bounds__(kTB) void k_track_next(const GreedyJob<T> *__restrict__ jobs) {
     const GreedyJob<T> j = jobs[blockIdx.y];
     const int32_t n = j.pn ? *j.pn : j.pn_host;
-    const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
-    if (i >= n) return;
-    const T ti = j.t[i];
-    int32_t a = (int32_t)i + 1, b = n;
-    while (a < b) {
-        const int32_t mid = a + (b - a) / 2;
-        if (j.L[mid] <= ti) a = mid + 1;
-        else b = mid;
+    const int64_t b0 = (int64_t)blockIdx.x * kTB;
+    if (b0 >= n) return;  // the whole block
+    const int t = threadIdx.x;
+    const int64_t i = b0 + t;
+    const int32_t bend = (int32_t)min<int64_t>(b0 + kTB, n);
+    __shared__ int32_t snx[2][kTB], sd[2][kTB], sl[2][kTB];
+    int32_t nx = n, d = 0, last = 0;
+    if (i < n) {
+        const T ti = j.t[i];
+        int32_t a = (int32_t)i + 1, b = n;
+        while (a < b) {
+            const int32_t mid = a + (b - a) / 2;
+            if (j.L[mid] <= ti) a = mid + 1;
+            else b = mid;
+        }
+        nx = a;
+        d = 1;
+        last = (int32_t)i;
     }
-    j.h[0][i] = Hop{a, 1, (int32_t)i, 0};
+    snx[0][t] = nx;
+    sd[0][t] = d;
+    sl[0][t] = last;
+    __syncthreads();
+    for (int r = 0; r < kTBLog; ++r) {
+        const int src = r & 1;
+        int32_t x = snx[src][t], dd = sd[src][t], ll = sl[src][t];
+        if (i < n && x < bend) {  // a successor inside the block (x > i >= b0)
+            const int k = x - (int32_t)b0;
+            dd += sd[src][k];
+            ll = sl[src][k];
+            x = snx[src][k];
+        }
+        snx[src ^ 1][t] = x;
+        sd[src ^ 1][t] = dd;
+        sl[src ^ 1][t] = ll;
+        __syncthreads();
+    }
+    if (i < n) j.h[0][i] = Hop{snx[kTBLog & 1][t], sd[kTBLog & 1][t], sl[kTBLog & 1][t], 0};
 }
 
 // One pointer-jumping round: every interval's (next uncovered interval,
@@ -402,8 +436,10 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
         const auto *dg = (const GreedyJob<T> *)(desc.as<char>() + goff);
         const dim3 ggrid((unsigned)((max_bound + kTB - 1) / kTB), (unsigned)gj.size());
         k_track_next<T><<<ggrid, kTB, 0, st>>>(dg);
+        // records leave their block of kTB intervals: at most one per block on any chain
+        const int64_t max_blocks = (max_bound + kTB - 1) / kTB;
         int R = 0;
-        while ((int64_t(1) << R) < max_bound) ++R;
+        while ((int64_t(1) << R) < max_blocks) ++R;
         const dim3 jgrid((unsigned)((max_bound + kTB * kJPer - 1) / (kTB * kJPer)), (unsigned)gj.size());
         for (int r = 0; r < R; ++r) k_track_jump<T><<<jgrid, kTB, 0, st>>>(dg, r);
         k_track_final<T><<<(unsigned)((gj.size() + kTB - 1) / kTB), kTB, 0, st>>>(
