@@ -26,7 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "episode_oracle.c")
 
-METHODS = {"decomp": 0, "fsm": 1}
+METHODS = {"decomp": 0, "fsm": 1, "fsm_stream": 2}
 
 
 def build(force: bool = True) -> str:

@@ -89,3 +89,35 @@ def count(types, times, ep, lo, hi, method="dp"):
     if method == "exhaustive":
         return max_nonoverlapped_exhaustive(spans)
     return max_nonoverlapped_dp(spans)
+
+
+def occurrences_positions(types, times, ep, lo, hi):
+    """All occurrences as (first event index, last event index) spans."""
+    n = len(types)
+    N = len(ep)
+    out = []
+
+    def rec(k, prev_idx, first):
+        for i in range(n):
+            if types[i] != ep[k]:
+                continue
+            if k > 0:
+                d = int(times[i]) - int(times[prev_idx])
+                if not (lo[k - 1] < d <= hi[k - 1]):
+                    continue
+            f = i if k == 0 else first
+            if k == N - 1:
+                out.append((f, i))
+            else:
+                rec(k + 1, i, f)
+
+    rec(0, -1, 0)
+    return out
+
+
+def count_stream_order(types, times, ep, lo, hi):
+    """Frequency with overlap decided in stream order (the reset of the state
+    machine of Sec. III-A taken literally): two occurrences are non-overlapped
+    iff one's last event comes before the other's first event in the stream.
+    The same interval-scheduling DP, over stream positions."""
+    return max_nonoverlapped_dp(occurrences_positions(types, times, ep, lo, hi))

@@ -33,6 +33,14 @@
  *     last completion, which makes the state machine compute exactly the
  *     greedy of Alg. 1 under the time-based overlap test.
  *
+ *   ORACLE_FSM_STREAM -- the same state machine with the reset of the
+ *     listing of Sec. III-A taken in stream order: after a completion, any
+ *     event that comes later in the stream may start an occurrence (a start
+ *     is admitted iff its stream position is after the last completion's),
+ *     so two occurrences are non-overlapped iff one's last event precedes
+ *     the other's first event in the stream.  It equals ORACLE_FSM on streams
+ *     without equal timestamps and differs only at ties.
+ *
  * Readings adopted where the paper is silent or inconsistent:
  *   - previous end starts at minus infinity (Alg. 1 writes 0);
  *   - completion is tested at the last node N (the commented listing tests
@@ -52,6 +60,7 @@
 
 #define ORACLE_DECOMP 0
 #define ORACLE_FSM 1
+#define ORACLE_FSM_STREAM 2
 #define ORACLE_MAXN 8
 #define NONE INT64_MIN
 
@@ -168,20 +177,21 @@ static void tl_push(tlist *l, int64_t x) {
 }
 
 static int64_t count_fsm(const int32_t *types, const int64_t *t, int64_t n, int N,
-                         const int32_t *ep, const int64_t *lo, const int64_t *hi) {
+                         const int32_t *ep, const int64_t *lo, const int64_t *hi, int stream_order) {
     tlist s[ORACLE_MAXN];
     memset(s, 0, sizeof(s));
-    int64_t count = 0, e = NONE;
+    int64_t count = 0, e = NONE, pe = -1; /* time and stream position of the last completion */
     for (int64_t i = 0; i < n; i++) {
         int32_t E = types[i];
         /* nodes are scanned from the last to the first, as in Sec. III-A */
         for (int j = N - 1; j >= 0; j--) {
             if (E != ep[j]) continue;
             if (j == 0) {
-                if (t[i] > e) {
+                if (stream_order ? i > pe : t[i] > e) {
                     if (N == 1) {
                         count++;
                         e = t[i];
+                        pe = i;
                     } else {
                         tl_push(&s[0], t[i]);
                     }
@@ -202,6 +212,7 @@ static int64_t count_fsm(const int32_t *types, const int64_t *t, int64_t n, int 
                     if (j == N - 1) {
                         count++;
                         e = t[i];
+                        pe = i;
                         for (int k = 0; k < N; k++) s[k].head = s[k].len = 0;
                     } else {
                         tl_push(&s[j], t[i]);
@@ -242,8 +253,8 @@ int oracle_count_batch(const int32_t *types, const int64_t *times, int64_t n, in
         const int32_t *ep = cand_types + c * ORACLE_MAXN;
         const int64_t *lo = cand_lo + c * (ORACLE_MAXN - 1);
         const int64_t *hi = cand_hi + c * (ORACLE_MAXN - 1);
-        if (method == ORACLE_FSM)
-            out_counts[c] = count_fsm(types, times, n, cand_N[c], ep, lo, hi);
+        if (method == ORACLE_FSM || method == ORACLE_FSM_STREAM)
+            out_counts[c] = count_fsm(types, times, n, cand_N[c], ep, lo, hi, method == ORACLE_FSM_STREAM);
         else
             out_counts[c] = count_decomp(times, &ix, cand_N[c], ep, lo, hi);
     }

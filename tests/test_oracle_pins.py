@@ -348,3 +348,68 @@ def test_levelwise_recovers_planted_cascades():
         ty = tuple(int(x) for x in remap[p["types"]])
         iv = tuple(menu.index((int(a), int(b))) for a, b in zip(p["lo"], p["hi"]))
         assert (ty, iv) in levels[len(ty) - 1]["frequent"]
+
+
+# ---- stream-order overlap (the listing's reset of Sec. III-A taken in stream order) ----
+
+def _golden(name_prefix):
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+    items = d["cases"] if isinstance(d, dict) and "cases" in d else d
+    items = items if isinstance(items, list) else list(items.values())
+    return [x for x in items if x["name"].startswith(name_prefix)]
+
+
+def _golden_case(x):
+    ev = np.array(x["events"], dtype=np.int64).reshape(-1, 2)
+    s = dict(types=ev[:, 0].astype(np.int32), times=ev[:, 1], K=int(ev[:, 0].max()) + 1 if ev.size else 1, ts_kind=1)
+    c = sg.candidates_from_list([(x["episode"], x["lo"], x["hi"])])
+    return s, c
+
+
+def test_stream_order_worked_examples():
+    """Hand-derived from the state machine of Sec. III-A with its reset in
+    stream order.  W3: (A,0),(B,5) completes at the second event; (A,5) comes
+    later in the stream, so it starts again and (B,10) (gap 5 <= 5) completes:
+    2 (time semantics: 1).  W6: every event of a one-node episode is an
+    occurrence: 3 (time semantics: 2 distinct timestamps)."""
+    for prefix, want in (("W3 ", 2), ("W6 ", 3)):
+        (x,) = _golden(prefix)
+        s, c = _golden_case(x)
+        assert oracle.count(s, c, "fsm_stream")[0] == want
+        assert oracle.count(s, c, "fsm")[0] == x["count"]
+        assert brute.count_stream_order(s["types"], s["times"], x["episode"], x["lo"], x["hi"]) == want
+
+
+def test_stream_order_equals_time_semantics_without_ties():
+    """With every timestamp distinct, stream order is time order."""
+    rng = np.random.Generator(np.random.PCG64(610))
+    for _ in range(30):
+        n = int(rng.integers(1, 400))
+        times = np.sort(rng.choice(10 * n + 10, size=n, replace=False)).astype(np.int64)
+        K = int(rng.integers(2, 6))
+        s = dict(types=rng.integers(0, K, size=n).astype(np.int32), times=times, K=K, ts_kind=1)
+        c = sg.tiny_candidates(rng, 20, K, 4, 30)
+        assert np.array_equal(oracle.count(s, c, "fsm_stream"), oracle.count(s, c, "decomp"))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_stream_order_bruteforce_with_ties(seed):
+    """Dense ties and repeated types: the stream-order state machine equals
+    the maximum number of occurrences that pairwise do not share stream
+    positions in overlapping order (enumeration + interval-scheduling DP over
+    positions)."""
+    rng = np.random.Generator(np.random.PCG64(620 + seed))
+    for _ in range(40):
+        K = int(rng.integers(2, 4))
+        s = sg.tiny_stream(rng, int(rng.integers(1, 22)), K, 8)
+        eps = []
+        for _ in range(6):
+            n = int(rng.integers(1, 5))
+            ty = [int(x) for x in rng.integers(0, K, size=n)]
+            lo = [int(rng.integers(0, 3)) for _ in range(n - 1)]
+            hi = [a + int(rng.integers(1, 5)) for a in lo]
+            eps.append((ty, lo, hi))
+        c = sg.candidates_from_list(eps)
+        got = oracle.count(s, c, "fsm_stream")
+        for i, (ty, lo, hi) in enumerate(eps):
+            assert got[i] == brute.count_stream_order(s["types"], s["times"], ty, lo, hi), (ty, lo, hi)
