@@ -261,11 +261,24 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
  *                         >= 0 and strict), so one event never fills two
  *                         nodes of an occurrence; the state machines take
  *                         each event at every node of its type.
+ *   EPI_OPT_STREAM_ORDER  0 (default) / 1: candidate sets submitted while
+ *                         it is 1 decide overlap in stream order, the reset
+ *                         of the serial state machine of Sec. III-A taken
+ *                         literally: after a completion, any event later in
+ *                         the stream may start an occurrence, so two
+ *                         occurrences are non-overlapped iff one's last
+ *                         event precedes the other's first event in the
+ *                         stream (a one-node episode counts every event of
+ *                         its type).  Equal to the default (time) semantics
+ *                         on streams without equal timestamps.  Such sets
+ *                         are counted by EPI_MODE_TRACKING only (other
+ *                         modes: EPI_EINVAL).
  * EPI_EINVAL for an unknown option or value.  Counts never depend on the
- * engine options (EPI_OPT_ALLOW_REPEATS only widens what is accepted). */
+ * engine options (EPI_OPT_ALLOW_REPEATS only widens what is accepted;
+ * EPI_OPT_STREAM_ORDER selects the other overlap semantics). */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
        EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8,
-       EPI_OPT_ALLOW_REPEATS = 9, EPI_OPT_MINE_LIST_ALPHAS = 10 };
+       EPI_OPT_ALLOW_REPEATS = 9, EPI_OPT_MINE_LIST_ALPHAS = 10, EPI_OPT_STREAM_ORDER = 11 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Autotune the batched engine for these sets and schedule: time every

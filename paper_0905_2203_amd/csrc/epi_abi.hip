@@ -453,6 +453,7 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
     hipError_t e = s->ts_kind == EPI_TS_I64 ? upload_candidates<int64_t>(*cs, m, N, types, lo, hi, ctx->c.stream)
                                             : upload_candidates<int32_t>(*cs, m, N, types, lo, hi, ctx->c.stream);
     if (e != hipSuccess) return hipfail(ctx, e, "uploading candidates");
+    cs->stream_order = ctx->c.opt.stream_order;
     cs->h_N.assign(N, N + m);
     cs->h_types.assign(types, types + m * kMaxN);
     cs->h_lo.assign(lo, lo + m * (kMaxN - 1));
@@ -483,6 +484,9 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
     for (int32_t i = 0; i < k; ++i) {
         CandSet *cs = find_set(ctx, set_ids[i]);
         if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+        if (cs->stream_order && mode != EPI_MODE_TRACKING)
+            return fail(ctx, EPI_EINVAL, "set %d decides overlap in stream order: count it with EPI_MODE_TRACKING",
+                        set_ids[i]);
         if (mode == EPI_MODE_BATCHED && sched == EPI_SCHED_MEASURED && !(cs->counted && cs->logged) &&
             (int64_t)cs->measured.size() != cs->m)
             return fail(ctx, EPI_ESTATE, "set %d has no work log to schedule by", set_ids[i]);
@@ -672,6 +676,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
         case EPI_OPT_ALLOW_REPEATS:
             if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "allow-repeats must be 0 or 1");
             ctx->c.opt.allow_repeats = value != 0;
+            return EPI_OK;
+        case EPI_OPT_STREAM_ORDER:
+            if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "stream order must be 0 or 1");
+            ctx->c.opt.stream_order = value != 0;
             return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);

@@ -227,6 +227,7 @@ struct CandSet {
     std::vector<int32_t> h_types;
     std::vector<int64_t> h_lo, h_hi;
     DevBuf track_work, track_desc;  // working set of the tracking engine, kept for the next count
+    bool stream_order = false;      // overlap decided in stream order (counted by the tracking engine only)
 };
 
 // Launch options (epi_set_option).
@@ -242,6 +243,7 @@ struct CountOptions {
     int64_t mine_list_bytes = int64_t(8) << 30;  // extension engine: list-path budget per level
     bool allow_repeats = false;    // epi_submit_candidates accepts a type at several nodes
     int64_t mine_list_alphas = 65536;  // extension engine: list path below this many parent episodes
+    bool stream_order = false;     // sets submitted now decide overlap in stream order
 };
 
 // One level of a level-wise discovery run: candidates of size N in

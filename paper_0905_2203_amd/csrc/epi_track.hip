@@ -50,8 +50,10 @@ struct TrackJob {
     int32_t ne;          // events of node k's type
     const T *et;         // their times, in order
     T lo, hi;            // constraint (lo, hi] from node k-1 to node k
+    const int32_t *ep;   // stream positions of node k's events (stream-order overlap), else null
     T *tl;               // per event of node k: its latest start, or the type minimum (no chain)
     T *ot, *oL;          // chain events of node k (written in time order)
+    T *oK;               // and their stream positions (stream-order overlap), else null
     int32_t *on;         // how many (written by the scan)
     int32_t *blk;        // per-block counts, then offsets: max(1, ceil(ne / kTChunk)) entries
 };
@@ -65,6 +67,8 @@ struct Hop {
 template <typename T>
 struct GreedyJob {
     const T *t, *L;      // intervals (L_N(x), t_x) in time order
+    const T *key;        // the ends compared with the starts: t, or stream positions (then L holds
+                         // the first events' stream positions)
     const int32_t *pn;   // how many (device; null: pn_host)
     int32_t pn_host;
     int32_t bound;       // capacity of the arrays below
@@ -217,6 +221,7 @@ __global__ __launch_bounds__(kTB) void k_track_write(const TrackJob<T> *__restri
         if (ok) {
             j.ot[pos + woff + below] = t;
             j.oL[pos + woff + below] = L;
+            if (j.oK) j.oK[pos + woff + below] = (T)j.ep[i];
         }
         pos += total;
         __syncthreads();
@@ -241,11 +246,11 @@ __global__ __launch_bounds__(kTB) void k_track_next(const GreedyJob<T> *__restri
     __shared__ int32_t snx[2][kTB], sd[2][kTB], sl[2][kTB];
     int32_t nx = n, d = 0, last = 0;
     if (i < n) {
-        const T ti = j.t[i];
+        const T ki = j.key[i];
         int32_t a = (int32_t)i + 1, b = n;
         while (a < b) {
             const int32_t mid = a + (b - a) / 2;
-            if (j.L[mid] <= ti) a = mid + 1;
+            if (j.L[mid] <= ki) a = mid + 1;
             else b = mid;
         }
         nx = a;
@@ -311,6 +316,13 @@ __global__ __launch_bounds__(kTB) void k_track_final(const GreedyJob<T> *__restr
     if (tau) tau[j.slot] = n > 0 ? j.t[h0.last] : TsLimits<T>::lo();
 }
 
+// stream positions of a type's events, widened to the time type
+template <typename T>
+__global__ __launch_bounds__(kTB) void k_track_pos(const int32_t *__restrict__ pos, int32_t n, T *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
+    if (i < n) out[i] = (T)pos[i];
+}
+
 size_t round_up(size_t b) { return (b + 255) & ~size_t(255); }
 
 template <typename T>
@@ -318,16 +330,18 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
     const int64_t m = c.m;
     if (m == 0) return hipSuccess;
     auto nt = [&](int32_t E) -> int32_t { return s.h_off[E + 1] - s.h_off[E]; };
+    const bool so = c.stream_order;
+    const int nbuf = so ? 8 : 5;  // (t, L) x 2 and tl; with stream order also K x 2 and node 1's positions
     auto job_bytes = [&](int64_t q) -> size_t {
         const int N = c.h_N[q];
         const int32_t *ty = c.h_types.data() + q * kMaxN;
-        size_t maxl = 0, nbm = 1;
+        size_t maxl = so ? (size_t)nt(ty[0]) : 0, nbm = 1;
         for (int k = 1; k < N; ++k) {
             maxl = std::max<size_t>(maxl, (size_t)nt(ty[k]));
             nbm = std::max<size_t>(nbm, ((size_t)nt(ty[k]) + kTChunk - 1) / kTChunk);
         }
         const size_t nN = std::max<size_t>(1, (size_t)nt(ty[N - 1]));
-        return 5 * round_up(sizeof(T) * std::max<size_t>(maxl, 1)) + 2 * round_up(sizeof(Hop) * nN) +
+        return nbuf * round_up(sizeof(T) * std::max<size_t>(maxl, 1)) + 2 * round_up(sizeof(Hop) * nN) +
                round_up(4 * nbm) + round_up(4 * kMaxN);
     };
     const T *tsb = s.ts_by_type.as<T>();
@@ -351,7 +365,7 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
         for (int64_t q = q0; q < q1; ++q) {
             const int N = c.h_N[q];
             const int32_t *ty = c.h_types.data() + q * kMaxN;
-            size_t maxl = 0, nbm = 1;
+            size_t maxl = so ? (size_t)nt(ty[0]) : 0, nbm = 1;
             for (int k = 1; k < N; ++k) {
                 maxl = std::max<size_t>(maxl, (size_t)nt(ty[k]));
                 nbm = std::max<size_t>(nbm, ((size_t)nt(ty[k]) + kTChunk - 1) / kTChunk);
@@ -360,7 +374,9 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
             const size_t lb = round_up(sizeof(T) * std::max<size_t>(maxl, 1));
             T *buf[2][2] = {{(T *)p, (T *)(p + lb)}, {(T *)(p + 2 * lb), (T *)(p + 3 * lb)}};
             T *tl = (T *)(p + 4 * lb);
-            p += 5 * lb;
+            T *kb[2] = {so ? (T *)(p + 5 * lb) : nullptr, so ? (T *)(p + 6 * lb) : nullptr};
+            T *l1 = so ? (T *)(p + 7 * lb) : nullptr;
+            p += nbuf * lb;
             Hop *ga[2];
             for (int a = 0; a < 2; ++a) {
                 ga[a] = (Hop *)p;
@@ -370,8 +386,14 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
             p += round_up(4 * nbm);
             int32_t *on = (int32_t *)p;
             p += round_up(4 * kMaxN);
-            // node 1: the type's events, each its own start
-            const T *pt = tsb + s.h_off[ty[0]], *pL = pt;
+            // node 1: the type's events, each its own start (its time, or its stream position)
+            const T *pt = tsb + s.h_off[ty[0]], *pL = pt, *pK = pt;
+            if (so) {
+                if (nt(ty[0]) > 0)
+                    k_track_pos<T><<<(unsigned)((nt(ty[0]) + kTB - 1) / kTB), kTB, 0, st>>>(
+                        s.pos_by_type.as<int32_t>() + s.h_off[ty[0]], nt(ty[0]), l1);
+                pL = pK = l1;
+            }
             const int32_t *pn = nullptr;
             int32_t pn_host = nt(ty[0]);
             for (int k = 1; k < N; ++k) {
@@ -384,7 +406,9 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
                 j.et = tsb + s.h_off[ty[k]];
                 j.lo = (T)c.h_lo[q * (kMaxN - 1) + k - 1];
                 j.hi = (T)c.h_hi[q * (kMaxN - 1) + k - 1];
+                j.ep = so ? s.pos_by_type.as<int32_t>() + s.h_off[ty[k]] : nullptr;
                 j.tl = tl;
+                j.oK = kb[k & 1];
                 j.ot = buf[k & 1][0];
                 j.oL = buf[k & 1][1];
                 j.on = on + k;
@@ -392,11 +416,13 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
                 lv[k].push_back(j);
                 pt = j.ot;
                 pL = j.oL;
+                pK = so ? j.oK : j.ot;
                 pn = j.on;
             }
             GreedyJob<T> g;
             g.t = pt;
             g.L = pL;
+            g.key = pK;
             g.pn = pn;
             g.pn_host = pn_host;
             g.bound = (int32_t)nN;

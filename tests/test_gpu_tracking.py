@@ -4,8 +4,9 @@ bit-exact against the oracle: long planted episodes and all their prefixes,
 random episodes of sizes 1 to 8, a type with no events, equal-time events,
 int32 and int64 streams, repeated types, a type with over two million events
 (more than 1024 compaction blocks and 22 pointer-jumping rounds), an empty
-set, and incremental counting after appends that resumes from the tracking
-count's last completions."""
+set, incremental counting after appends that resumes from the tracking
+count's last completions, and stream-order overlap (EPI_OPT_STREAM_ORDER)
+against the oracle's stream-order state machine."""
 import numpy as np
 import pytest
 
@@ -164,6 +165,44 @@ def test_tracking_then_incremental(ctx):
         ctx.epi_append_stream(sid, s["types"][cut:], s["times"][cut:])
         ctx.epi_count([cid], mode=epi.EPI_MODE_INCREMENTAL)
         assert np.array_equal(ctx.epi_read_counts(cid, c["N"].size), oracle.count(s, c))
+    finally:
+        ctx.epi_release_set(cid)
+        ctx.epi_release_stream(sid)
+
+
+@pytest.mark.parametrize("ts_kind", [0, 1], ids=["int32_us", "int64_ns"])
+def test_tracking_stream_order(ctx, ts_kind):
+    # dense equal times (a 2 ms grid), so that stream-order and time overlap
+    # differ; one-node episodes, long planted ones, repeated types
+    unit = 1000 if ts_kind == 0 else 1_000_000
+    rng = np.random.Generator(np.random.PCG64(87 + ts_kind))
+    s = sg.poisson_stream(rng, K=12, rate_hz=40.0, dur_s=40.0, ts_kind=ts_kind, unit_per_ms=unit, cascades=[6],
+                          cascade_trigger_hz=[6.0])
+    s["times"] = np.ascontiguousarray(s["times"] // (2 * unit) * (2 * unit), dtype=s["times"].dtype)
+    eps = _planted_family(s) + _random_long(rng, 60, 12, unit)
+    eps += [([a, b], [0], [2 * unit]) for a in range(4) for b in range(4)]  # includes a == b
+    eps += [([0, 1, 0], [0, 0], [4 * unit, 4 * unit]), ([2, 2, 2], [0, 0], [2 * unit, 6 * unit])]
+    c = sg.candidates_from_list(eps)
+    want = oracle.count(s, c, "fsm_stream")
+    timewise = oracle.count(s, c, "decomp")
+    say(f"{ts_kind=}: n={s['types'].size}, {c['N'].size} candidates, {(want != timewise).sum()} differ by semantics")
+    assert (want != timewise).sum() > 10
+    sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
+    ctx.epi_set_option(epi.EPI_OPT_ALLOW_REPEATS, 1)
+    ctx.epi_set_option(epi.EPI_OPT_STREAM_ORDER, 1)
+    try:
+        cid = ctx.epi_submit_candidates(sid, c)
+    finally:
+        ctx.epi_set_option(epi.EPI_OPT_STREAM_ORDER, 0)
+        ctx.epi_set_option(epi.EPI_OPT_ALLOW_REPEATS, 0)
+    try:
+        ctx.epi_count([cid], mode=epi.EPI_MODE_TRACKING)
+        got = ctx.epi_read_counts(cid, c["N"].size)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, f"{bad.size} differ, e.g. #{bad[0]} {eps[bad[0]]}: got {got[bad[0]]} want {want[bad[0]]}"
+        with pytest.raises(epi.EpiError) as err:  # the state-machine engines decide overlap on times
+            ctx.epi_count([cid], mode=epi.EPI_MODE_PLAIN)
+        assert err.value.code == epi.EPI_EINVAL
     finally:
         ctx.epi_release_set(cid)
         ctx.epi_release_stream(sid)

@@ -23,7 +23,10 @@ MUTANTS = [
      "if (t[pprev[mid]] <= tx - hi[k - 1]) a = mid + 1;"),
     ("decomp earliest start", "if (prev[y] != NONE && prev[y] > best) best = prev[y];",
      "if (prev[y] != NONE && (best == NONE || prev[y] < best)) best = prev[y];"),
-    ("fsm admits ties", "if (t[i] > e) {", "if (t[i] >= e) {"),
+    ("fsm admits ties", "stream_order ? i > pe : t[i] > e", "stream_order ? i > pe : t[i] >= e"),
+    ("stream order admits the completing event", "stream_order ? i > pe : t[i] > e",
+     "stream_order ? i >= pe : t[i] > e"),
+    ("stream order keeps time admission", "stream_order ? i > pe : t[i] > e", "t[i] > e"),
     ("fsm lower bound inclusive", "if (lo[j - 1] < d && d <= hi[j - 1]) {", "if (lo[j - 1] <= d && d <= hi[j - 1]) {"),
     ("fsm completion one node early", "if (j == N - 1) {", "if (j == N - 2) {"),
     ("fsm prune inclusive", "pl->v[pl->head] < t[i] - hi[j - 1]", "pl->v[pl->head] <= t[i] - hi[j - 1]"),
@@ -64,7 +67,29 @@ def _count_with(L, s, c, method):
     return out
 
 
+def _stream_pins_detect(L):
+    # tiny streams with dense ties and episodes with repeated types, against
+    # the enumeration over stream positions
+    rng = np.random.Generator(np.random.PCG64(6))
+    for _ in range(150):
+        s = sg.tiny_stream(rng, int(rng.integers(2, 20)), 3, 8)
+        eps = []
+        for _ in range(6):
+            n = int(rng.integers(1, 4))
+            ty = [int(x) for x in rng.integers(0, 3, size=n)]
+            lo = [int(rng.integers(0, 3)) for _ in range(n - 1)]
+            eps.append((ty, lo, [a + int(rng.integers(1, 5)) for a in lo]))
+        c = sg.candidates_from_list(eps)
+        got = _count_with(L, s, c, "fsm_stream")
+        for i, (ty, lo, hi) in enumerate(eps):
+            if got[i] != brute.count_stream_order(s["types"], s["times"], ty, lo, hi):
+                return True
+    return False
+
+
 def _pins_detect(L, method):
+    if method == "fsm_stream":
+        return _stream_pins_detect(L)
     rng = np.random.Generator(np.random.PCG64(5))
     for _ in range(150):
         s = sg.tiny_stream(rng, int(rng.integers(2, 24)), 4, 30)
@@ -85,5 +110,5 @@ def test_pins_catch_planted_mistake(tmp_path, mut):
         pytest.skip("gcc missing")
     name, old, new = mut
     L = _build_mutant(tmp_path, name, old, new)
-    method = "fsm" if name.startswith("fsm") else "decomp"
+    method = "fsm_stream" if name.startswith("stream") else "fsm" if name.startswith("fsm") else "decomp"
     assert _pins_detect(L, method), f"mutant {name!r} survived the brute-force pins"
