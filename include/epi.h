@@ -169,10 +169,12 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  *                     compacted in time order (Sec. IV-D/E), and the count
  *                     is the greedy over the (latest start, end) intervals,
  *                     ranked by pointer jumping.  Working memory about
- *                     4*ts + 24 bytes per event of an episode's most
- *                     frequent type, in groups of at most 2 GiB; no work
- *                     log; returns when done.  Sets of level-wise discovery
- *                     are rejected (EPI_EINVAL).
+ *                     5*ts + 32 bytes (8*ts + 32 under
+ *                     EPI_OPT_STREAM_ORDER) per event of an episode's most
+ *                     frequent type, in groups of at most 2 GiB, kept with
+ *                     the set for its next count; no work log; returns when
+ *                     done.  The only mode for sets submitted under
+ *                     EPI_OPT_STREAM_ORDER.
  * sched (batched mode): EPI_SCHED_RR keeps submission order;
  * EPI_SCHED_LEARNED orders each class's episodes by the cost model's
  * predicted work (see epi_costmodel_train; without a trained model it falls
