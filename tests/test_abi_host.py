@@ -123,3 +123,17 @@ def test_context_without_gpu_fails_loudly():
     with pytest.raises(epi.EpiError) as ei:
         epi.Context(0)
     assert ei.value.code == epi.EPI_EDEVICE
+
+
+def test_binding_constants_match_the_header():
+    """Every mode, option, schedule, timestamp-kind and status constant the
+    header declares has the same value in the binding."""
+    from paper_0905_2203_amd import epi as binding
+
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "epi.h")).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"\b(EPI_[A-Z0-9_]+)\s*=\s*(-?\d+)", hdr))
+    assert any(k.startswith("EPI_OPT_") for k in consts) and "EPI_MODE_TRACKING" in consts
+    missing = [k for k in consts if not hasattr(binding, k)]
+    assert not missing, missing
+    wrong = {k: (v, getattr(binding, k)) for k, v in consts.items() if getattr(binding, k) != v}
+    assert not wrong, wrong
