@@ -14,11 +14,18 @@
 // chain event y of node k-1 with lo < t_x - t_y <= hi: one binary search per
 // event, which is the backward tracking of Alg. 2 with the search replacing
 // the scan.  The events with a chain are compacted in time order by a
-// count / scan / write pass (the order-preserving compaction of Sec. IV-D/E).
-// The count is Alg. 1 over the intervals (L_N(x), t_x) in time order: after
-// keeping x the next kept interval is the first with L > t_x, a binary search
-// over the non-decreasing L; the kept intervals form the successor chain of
-// the first interval, whose length and last element pointer jumping finds.
+// search (which counts) / scan / write pass (the order-preserving compaction
+// of Sec. IV-D/E).  The count is Alg. 1 over the intervals (L_N(x), t_x) in
+// time order: after keeping x the next kept interval is the first with
+// L > t_x, a binary search over the non-decreasing L; the kept intervals form
+// the successor chain of the first interval, whose length and last element
+// pointer jumping finds (first inside blocks of intervals in LDS, then across
+// blocks).
+//
+// Under stream-order overlap the starts L and the ends compared with them are
+// stream positions instead of times (the predecessor windows stay in time);
+// along a node's chain events in (time, position) order the latest start
+// position is still non-decreasing, so nothing else changes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
