@@ -10,9 +10,11 @@ never imports it and shares no code with it.
 * ``brute``: tiny-input enumeration of every constrained occurrence followed by
   an exhaustive / dynamic-programming maximum non-overlapped subset.
 * ``apriori``: the level-wise discovery procedure of Sec. II-C on top of
-  ``count``.
-* ``segmented``: exact segment-parallel counting with boundary-state
-  reconciliation, re-derived independently of the engine.
+  ``count`` (tuples for small runs, arrays for levels of 1e8 candidates).
+* ``segmented``: segment-parallel counting with an exact joining rule for the
+  segments (the segment idea of Sec. III-B), pure Python, pinned against the
+  unsegmented count.
+* ``mlp``: the scheduler's cost model in FP64 (forward, back-propagation, Adam).
 """
 from __future__ import annotations
 

@@ -438,13 +438,13 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
     // times +- span must stay strictly inside the timestamp type
     const int64_t tlo = s->ts_kind == EPI_TS_I64 ? INT64_MIN : INT32_MIN;
     const int64_t thi = s->ts_kind == EPI_TS_I64 ? INT64_MAX : INT32_MAX;
-    if (s->n > 0) {
-        for (int64_t c = 0; c < m; ++c) {
-            const int64_t sp = span_of(N[c], hi + c * 7);
-            if (s->tmax > thi - 1 - sp || s->tmin < tlo + 1 + sp)
-                return fail(ctx, EPI_EOVERFLOW, "candidate %lld: stream times +- its span leave the timestamp type",
-                            (long long)c);
-        }
+    int64_t max_span = 0;
+    for (int64_t c = 0; c < m; ++c) {
+        const int64_t sp = span_of(N[c], hi + c * 7);
+        max_span = std::max(max_span, sp);
+        if (s->n > 0 && (s->tmax > thi - 1 - sp || s->tmin < tlo + 1 + sp))
+            return fail(ctx, EPI_EOVERFLOW, "candidate %lld: stream times +- its span leave the timestamp type",
+                        (long long)c);
     }
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
     auto cs = std::make_unique<CandSet>();
@@ -454,6 +454,7 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
                                             : upload_candidates<int32_t>(*cs, m, N, types, lo, hi, ctx->c.stream);
     if (e != hipSuccess) return hipfail(ctx, e, "uploading candidates");
     cs->stream_order = ctx->c.opt.stream_order;
+    cs->max_span = max_span;
     cs->h_N.assign(N, N + m);
     cs->h_types.assign(types, types + m * kMaxN);
     cs->h_lo.assign(lo, lo + m * (kMaxN - 1));
@@ -610,6 +611,23 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
     const int64_t last = i64 ? ((const int64_t *)times)[n - 1] : ((const int32_t *)times)[n - 1];
     if (s->n > 0 && first < s->tmax)
         return fail(ctx, EPI_EUNSORTED, "appended times must not precede the stream's last time");
+    // the stream's times +- the span of every set and mining run on it must
+    // stay strictly inside the timestamp type after the append, as at
+    // submission (the state machines form t + hi, the tracking engine t - hi)
+    {
+        const int64_t tlo = i64 ? INT64_MIN : INT32_MIN;
+        const int64_t thi = i64 ? INT64_MAX : INT32_MAX;
+        const int64_t nmin = s->n > 0 ? s->tmin : first;
+        auto fits = [&](int64_t sp) { return !(last > thi - 1 - sp || nmin < tlo + 1 + sp); };
+        for (auto &kv : ctx->c.sets)
+            if (kv.second->stream_id == stream_id && !fits(kv.second->max_span))
+                return fail(ctx, EPI_EOVERFLOW, "set %d: appended times +- its longest span leave the timestamp type",
+                            kv.first);
+        for (auto &kv : ctx->c.mines)
+            if (kv.second->stream_id == stream_id && !fits(kv.second->max_span))
+                return fail(ctx, EPI_EOVERFLOW,
+                            "mining run %d: appended times +- its longest span leave the timestamp type", kv.first);
+    }
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
     // the work queued on the stream's arrays ends before they are replaced
     HIPTRY(ctx, hipDeviceSynchronize(), "sync");
@@ -744,6 +762,7 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     CacheScope scope(&ctx->c.cache);
     auto mn = std::make_unique<Mine>();
     mn->stream_id = stream_id;
+    mn->max_span = span;
     mn->stage = ctx->c.stage;
     mn->menu_lo.assign(menu_lo, menu_lo + n_menu);
     mn->menu_hi.assign(menu_hi, menu_hi + n_menu);

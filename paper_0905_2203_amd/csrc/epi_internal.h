@@ -228,6 +228,7 @@ struct CandSet {
     std::vector<int64_t> h_lo, h_hi;
     DevBuf track_work, track_desc;  // working set of the tracking engine, kept for the next count
     bool stream_order = false;      // overlap decided in stream order (counted by the tracking engine only)
+    int64_t max_span = 0;           // longest span (sum of upper bounds) of its episodes
 };
 
 // Launch options (epi_set_option).
@@ -295,6 +296,7 @@ struct MineLevel {
 struct Mine {
     int engine = 1;  // 1: extension engine (default), 0: state-machine engine
     int32_t stream_id = 0;
+    int64_t max_span = 0;  // longest span of any episode the run may count (longest menu end x (sizes - 1))
     std::vector<int64_t> menu_lo, menu_hi;
     int64_t threshold = 0;
     std::vector<MineLevel> levels;

@@ -470,7 +470,10 @@ __global__ __launch_bounds__(256) void k_count_persistent(const CountArgs<T> *__
         __syncthreads();
         const int64_t it = next;
         __syncthreads();
-        if (it >= n_items) break;  // uniform: every wave of the group exits
+        // uniform: every wave of the group exits; unsigned, so that a counter
+        // that was not cleared (any value) ends the loop instead of indexing
+        // items[] out of range
+        if ((uint64_t)it >= (uint64_t)n_items) break;
         const WorkItem w = items[it];
         const CountArgs<T> a = units[w.unit];
         count_item<T, N, FILT, REL>(a, w.blk, w.p, item_base + it, smem);

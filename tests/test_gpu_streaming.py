@@ -110,3 +110,34 @@ def test_bad_appends_change_nothing(ctx):
     finally:
         ctx.epi_release_set(cid)
         ctx.epi_release_stream(sid)
+
+
+def test_append_beyond_the_span_headroom_is_rejected(ctx):
+    """An int32 stream appended to near INT32_MAX: times + the longest span of
+    a set (or of a mining run) on the stream would leave the type, so the
+    append is refused (EPI_EOVERFLOW) and the stream and counts are unchanged;
+    an append that keeps the headroom is accepted.  Sets submitted while the
+    stream was empty are checked too."""
+    imax = np.iinfo(np.int32).max
+    span = 30_000  # 3 nodes, (0, 10000] and (5000, 20000]
+    c = sg.candidates_from_list([([0, 1, 2], [0, 5000], [10_000, 20_000]), ([1, 2], [0], [5000])])
+    m = c["N"].size
+    sid = ctx.epi_load_stream(np.zeros(0, np.int32), np.zeros(0, np.int32), 3)
+    cid = ctx.epi_submit_candidates(sid, c)  # on the empty stream: nothing to check yet
+    try:
+        ok_t = np.array([imax - 1 - span - 20, imax - 1 - span - 10, imax - 1 - span], np.int32)
+        ctx.epi_append_stream(sid, np.array([0, 1, 2], np.int32), ok_t)
+        ctx.epi_count([cid], mode=epi.EPI_MODE_PLAIN)
+        before = ctx.epi_read_counts(cid, m)
+        say(f"append near INT32_MAX accepted up to {int(ok_t[-1])}")
+        with pytest.raises(epi.EpiError) as err:
+            ctx.epi_append_stream(sid, np.array([2], np.int32), np.array([imax - span], np.int32))
+        assert err.value.code == epi.EPI_EOVERFLOW
+        assert ctx.epi_stream_info(sid)[0] == 3
+        ctx.epi_count([cid], mode=epi.EPI_MODE_INCREMENTAL)
+        assert np.array_equal(ctx.epi_read_counts(cid, m), before)
+        s_now = dict(types=np.array([0, 1, 2], np.int32), times=ok_t, K=3, ts_kind=0)
+        assert np.array_equal(before, oracle.count(s_now, c))
+    finally:
+        ctx.epi_release_set(cid)
+        ctx.epi_release_stream(sid)

@@ -413,3 +413,25 @@ def test_stream_order_bruteforce_with_ties(seed):
         got = oracle.count(s, c, "fsm_stream")
         for i, (ty, lo, hi) in enumerate(eps):
             assert got[i] == brute.count_stream_order(s["types"], s["times"], ty, lo, hi), (ty, lo, hi)
+
+
+def test_array_levelwise_equals_tuple_levelwise():
+    """The array form of the level-wise procedure (used for levels of 1e8
+    candidates) generates the same candidates, in the same order, with the same
+    counts and frequent sets as the tuple form."""
+    from oracle import apriori
+
+    rng = np.random.Generator(np.random.PCG64(41))
+    s = sg.poisson_stream(rng, K=12, rate_hz=15.0, dur_s=60.0, ts_kind=0, unit_per_ms=1000, cascades=[4],
+                          cascade_trigger_hz=[5.0])
+    menu = [(a * 1000, b * 1000) for a, b in sg.MENU_MINING_MS]
+    ref = apriori.mine(s, menu, 5, 20)
+    arr = apriori.mine_arrays(s, menu, 5, 20, chunk=777)
+    assert len(ref) == len(arr) == 5
+    for L, (r, a) in enumerate(zip(ref, arr), start=1):
+        eps = [(tuple(int(x) for x in a["types"][i]), tuple(int(x) for x in a["ivs"][i]))
+               for i in range(a["counts"].size)]
+        assert {ep: int(c) for ep, c in zip(eps, a["counts"])} == r["counts"]
+        assert {ep for ep, f in zip(eps, a["frequent"]) if f} == r["frequent"]
+        if L >= 3:
+            assert eps == apriori.join(sorted(ref[L - 2]["frequent"]))
