@@ -115,19 +115,15 @@ static int64_t count_decomp(const int64_t *t, const type_index *ix, int N, const
         const int64_t *pk = ix->pos + ix->off[ep[k]];
         int64_t nk = ix->off[ep[k] + 1] - ix->off[ep[k]];
         int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nk > 0 ? nk : 1));
+        int64_t a = 0; /* first y with t_y >= tx - hi; tx only grows, so a only moves forward */
         for (int64_t x = 0; x < nk; x++) {
             int64_t tx = t[pk[x]];
-            /* first y with t_y >= tx - hi (binary search over the sorted list) */
-            int64_t a = 0, b = nprev;
-            while (a < b) {
-                int64_t mid = a + (b - a) / 2;
-                if (t[pprev[mid]] < tx - hi[k - 1]) a = mid + 1; else b = mid;
-            }
+            while (a < nprev && t[pprev[a]] < tx - hi[k - 1]) a++;
             int64_t best = NONE;
             for (int64_t y = a; y < nprev; y++) {
                 int64_t d = tx - t[pprev[y]];
                 if (d <= lo[k - 1]) break;          /* t_y too recent: later y are too */
-                if (d > hi[k - 1]) continue;        /* cannot happen after the search */
+                if (d > hi[k - 1]) continue;        /* cannot happen: a starts the window */
                 if (prev[y] != NONE && prev[y] > best) best = prev[y];
             }
             cur[x] = best;

@@ -19,8 +19,8 @@ MUTANTS = [
     ("alg1 non-strict", "if (prev_e < prev[x]) {", "if (prev_e <= prev[x]) {"),
     ("alg1 keeps start", "prev_e = t[pprev[x]];", "prev_e = prev[x];"),
     ("decomp lower bound inclusive", "if (d <= lo[k - 1]) break;", "if (d < lo[k - 1]) break;"),
-    ("decomp upper bound exclusive", "if (t[pprev[mid]] < tx - hi[k - 1]) a = mid + 1;",
-     "if (t[pprev[mid]] <= tx - hi[k - 1]) a = mid + 1;"),
+    ("decomp upper bound exclusive", "while (a < nprev && t[pprev[a]] < tx - hi[k - 1]) a++;",
+     "while (a < nprev && t[pprev[a]] <= tx - hi[k - 1]) a++;"),
     ("decomp earliest start", "if (prev[y] != NONE && prev[y] > best) best = prev[y];",
      "if (prev[y] != NONE && (best == NONE || prev[y] < best)) best = prev[y];"),
     ("fsm admits ties", "stream_order ? i > pe : t[i] > e", "stream_order ? i > pe : t[i] >= e"),
