@@ -88,14 +88,23 @@ class MultisetDigest:
         return {"rows": self.rows, "count_sum": self.count_sum, "h1": f"{self.s1:016x}", "h2": f"{self.s2:016x}"}
 
 
+def _need(path):
+    if not os.path.exists(path):
+        import pytest
+
+        pytest.skip(f"expected values {os.path.basename(path)} not written yet (tests/golden/make_full_parity.py)")
+
+
 def load_counts(name):
     """Expected counts of a full-size workload: (meta dict, {key: int32 array})."""
     path = os.path.join(GOLDEN, name)
+    _need(path)
     z = np.load(path, allow_pickle=False)
     meta = json.loads(str(z["meta"]))
     return meta, {k: z[k] for k in z.files if k != "meta"}
 
 
 def load_json(name):
+    _need(os.path.join(GOLDEN, name))
     with open(os.path.join(GOLDEN, name)) as f:
         return json.load(f)
