@@ -81,7 +81,7 @@ def _timed(ctx, fn, reps):
     return float(np.median(out))
 
 
-def ablation(k, scale, reps):
+def ablation(k, scale, reps, lane_engine=1):
     """Plain engine vs the batched persistent engine under round-robin, the
     event-count heuristic and the learned cost model, on workload preset k.
     Every mode's counts are checked equal; one JSON line per preset."""
@@ -89,6 +89,7 @@ def ablation(k, scale, reps):
     from paper_0905_2203_amd import epi
 
     ctx = epi.Context(0)
+    ctx.epi_set_option(epi.EPI_OPT_LANE_ENGINE, lane_engine)
     if k == 3:
         sets = []
         for r in range(16):
@@ -184,7 +185,7 @@ def ablation(k, scale, reps):
         alg += int(per.sum()) * tsb + int(N_.size) * ((128 if tsb == 8 else 72) + 4)
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
-        "ablation_preset": k, "scale": scale, "unit": "cand*ev/s",
+        "ablation_preset": k, "scale": scale, "unit": "cand*ev/s", "lane_engine": lane_engine,
         "value": {m: units / t for m, t in res.items()},
         "seconds": res,
         "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
@@ -276,6 +277,8 @@ def main():
     ap.add_argument("--ablation", default="",
                     help="comma list of workload presets (1, 3, 4, 5): plain vs batched schedules, one JSON line each")
     ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
+    ap.add_argument("--lane-engine", type=int, default=1,
+                    help="ablation: 1 = register-indexed lane machines where they apply, 0 = LDS-ring machines")
     ap.add_argument("--tracking-sweep", action="store_true",
                     help="episode-length sweep: per-event tracking vs the plain engine, one JSON line per length")
     args = ap.parse_args()
@@ -284,7 +287,7 @@ def main():
         return
     if args.ablation:
         for k in [int(x) for x in args.ablation.split(",") if x]:
-            ablation(k, args.abl_scale, max(1, args.steps))
+            ablation(k, args.abl_scale, max(1, args.steps), args.lane_engine)
         return
     if args.calibrate_copy:
         import torch

@@ -275,12 +275,20 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
  *                         on streams without equal timestamps.  Such sets
  *                         are counted by EPI_MODE_TRACKING only (other
  *                         modes: EPI_EINVAL).
+ *   EPI_OPT_LANE_ENGINE   1 (default) / 0: the state machines keep their
+ *                         bookkeeping in registers and, per node, a ring of
+ *                         exactly that interval's bound in LDS (lane
+ *                         machines), wherever the stream's tiles allow int32
+ *                         times relative to the tile; 0 = every group on the
+ *                         machines with all their state in LDS (each ring as
+ *                         deep as the episode's deepest)
  * EPI_EINVAL for an unknown option or value.  Counts never depend on the
  * engine options (EPI_OPT_ALLOW_REPEATS only widens what is accepted;
  * EPI_OPT_STREAM_ORDER selects the other overlap semantics). */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
        EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8,
-       EPI_OPT_ALLOW_REPEATS = 9, EPI_OPT_MINE_LIST_ALPHAS = 10, EPI_OPT_STREAM_ORDER = 11 };
+       EPI_OPT_ALLOW_REPEATS = 9, EPI_OPT_MINE_LIST_ALPHAS = 10, EPI_OPT_STREAM_ORDER = 11,
+       EPI_OPT_LANE_ENGINE = 12 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Autotune the batched engine for these sets and schedule: time every

@@ -9,7 +9,7 @@
 #include <cstring>
 #include <numeric>
 
-#include "epi_internal.h"
+#include "epi_count.h"
 
 using namespace epi;
 
@@ -138,11 +138,6 @@ epi_status check_candidates(int64_t m, const uint8_t *N, const int32_t *types, c
                 say("interval must satisfy 0 <= lo < hi");
                 return EPI_EINTERVAL;
             }
-            if (queue_bound(l[j], h[j]) > kMaxQueue) {
-                say("interval (lo, hi] too narrow for its offset: 1 + hi/(hi-lo+1) exceeds the supported queue depth " +
-                    std::to_string(kMaxQueue));
-                return EPI_EINTERVAL;
-            }
         }
         const int64_t sp = span_of(n, h);
         if (sp < 0 || sp >= tmax) {
@@ -153,16 +148,27 @@ epi_status check_candidates(int64_t m, const uint8_t *N, const int32_t *types, c
     return EPI_OK;
 }
 
+// An episode with an interval whose ring bound exceeds kLaneMaxQ is "deep":
+// the state machines do not take it; the per-event tracking engine, which
+// keeps no rings, counts it in every mode.
+bool is_deep(int N, const int64_t *lo, const int64_t *hi) {
+    for (int j = 0; j + 1 < N; ++j)
+        if (queue_bound(lo[j], hi[j]) > kLaneMaxQ) return true;
+    return false;
+}
+
 template <typename T>
 hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int32_t *types, const int64_t *lo,
                              const int64_t *hi, hipStream_t st) {
-    // launch class of each candidate: (N, queue capacity)
+    // launch class of each candidate: (N, ring entries class); deep ones last
+    constexpr int kDeepKey = 1 << 20;
     std::vector<int> key(m);
     for (int64_t c = 0; c < m; ++c) {
-        int Q = 1;
-        for (int j = 0; j + 1 < N[c]; ++j)
-            Q = std::max<int>(Q, queue_class(queue_bound(lo[c * 7 + j], hi[c * 7 + j])));
-        key[c] = N[c] * 64 + Q;
+        if (is_deep(N[c], lo + c * 7, hi + c * 7)) {
+            key[c] = kDeepKey;
+            continue;
+        }
+        key[c] = N[c] * 64 + cap_class_index(std::max(1, lane_ring_entries(N[c], lo + c * 7, hi + c * 7)));
     }
     std::vector<int32_t> order(m);
     std::iota(order.begin(), order.end(), 0);
@@ -177,19 +183,26 @@ hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int
             h_lo[(size_t)j * m + s] = j + 1 < N[c] ? (T)lo[(int64_t)c * 7 + j] : T(0);
             h_hi[(size_t)j * m + s] = j + 1 < N[c] ? (T)hi[(int64_t)c * 7 + j] : T(0);
         }
-        if (cs.groups.empty() || key[c] != cs.groups.back().N * 64 + cs.groups.back().Q) {
+        if (key[c] == kDeepKey) continue;  // no group: the tracking engine counts it
+        if (cs.groups.empty() || s == 0 || key[c] != key[order[s - 1]]) {
             Group g;
             g.N = N[c];
-            g.Q = key[c] % 64;
+            g.Q = 1;
+            g.C = 0;
             g.begin = s;
             g.end = s;
             g.hspan = 0;
             cs.groups.push_back(g);
         }
-        cs.groups.back().end = s + 1;
+        Group &g = cs.groups.back();
+        g.end = s + 1;
         int64_t sp = 0;
-        for (int j = 0; j + 1 < N[c]; ++j) sp += hi[(int64_t)c * 7 + j];
-        cs.groups.back().hspan = std::max(cs.groups.back().hspan, sp);
+        for (int j = 0; j + 1 < N[c]; ++j) {
+            sp += hi[(int64_t)c * 7 + j];
+            g.Q = std::max<int>(g.Q, queue_class(queue_bound(lo[(int64_t)c * 7 + j], hi[(int64_t)c * 7 + j])));
+        }
+        g.hspan = std::max(g.hspan, sp);
+        g.C = std::max(g.C, lane_ring_entries(N[c], lo + (int64_t)c * 7, hi + (int64_t)c * 7));
     }
     hipError_t e;
     if ((e = cs.types.alloc(sizeof(int32_t) * h_types.size())) != hipSuccess) return e;
@@ -455,6 +468,30 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
     if (e != hipSuccess) return hipfail(ctx, e, "uploading candidates");
     cs->stream_order = ctx->c.opt.stream_order;
     cs->max_span = max_span;
+    {
+        // deep episodes: a sub-set counted by the tracking engine
+        std::vector<int32_t> didx;
+        for (int64_t c = 0; c < m; ++c)
+            if (is_deep(N[c], lo + c * 7, hi + c * 7)) didx.push_back((int32_t)c);
+        if (!didx.empty()) {
+            auto d = std::make_unique<CandSet>();
+            const int64_t md = (int64_t)didx.size();
+            d->stream_id = stream_id;
+            d->m = md;
+            for (int32_t c : didx) {
+                d->h_N.push_back(N[c]);
+                d->h_types.insert(d->h_types.end(), types + (int64_t)c * kMaxN, types + (int64_t)(c + 1) * kMaxN);
+                d->h_lo.insert(d->h_lo.end(), lo + (int64_t)c * (kMaxN - 1), lo + (int64_t)(c + 1) * (kMaxN - 1));
+                d->h_hi.insert(d->h_hi.end(), hi + (int64_t)c * (kMaxN - 1), hi + (int64_t)(c + 1) * (kMaxN - 1));
+            }
+            HIPTRY(ctx, d->counts.alloc(sizeof(int32_t) * md), "deep episodes");
+            HIPTRY(ctx, d->tau.alloc(s->ts_bytes() * md), "deep episodes");
+            HIPTRY(ctx, cs->deep_idx.alloc(sizeof(int32_t) * md), "deep episodes");
+            HIPTRY(ctx, hipMemcpy(cs->deep_idx.p, didx.data(), sizeof(int32_t) * md, hipMemcpyHostToDevice),
+                   "deep episodes");
+            cs->deep = std::move(d);
+        }
+    }
     cs->h_N.assign(N, N + m);
     cs->h_types.assign(types, types + m * kMaxN);
     cs->h_lo.assign(lo, lo + m * (kMaxN - 1));
@@ -507,6 +544,7 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
             cs->logged = false;
             if (!cs->counted || cs->counted_n < 0) {
                 HIPTRY(ctx, launch_count(*s, *cs, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "launching the count");
+                HIPTRY(ctx, count_deep_subset(*s, *cs, st), "counting deep episodes");
             } else if (cs->counted_n < s->n && cs->m > 0) {
                 int64_t B = 0;
                 if (s->ts_kind == EPI_TS_I64) {
@@ -519,6 +557,8 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
                     B = b32;
                 }
                 HIPTRY(ctx, launch_count_append(*s, *cs, B, ctx->c.flags.as<int32_t>(), st), "counting appended events");
+                // deep episodes: counted again over the whole stream
+                HIPTRY(ctx, count_deep_subset(*s, *cs, st), "counting deep episodes");
             }
             cs->counted = true;
             cs->counted_n = s->n;
@@ -582,6 +622,7 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
         HIPTRY(ctx, launch_count_batched(refs, sched, ctx->c.opt, ctx->c.mlp, ctx->c.flags.as<int32_t>(), st),
                "batched count");
         for (auto &r : refs) {
+            HIPTRY(ctx, count_deep_subset(*r.s, *r.c, st), "counting deep episodes");
             r.c->counted = true;
             r.c->counted_n = r.s->n;
         }
@@ -591,6 +632,7 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
         CandSet *cs = find_set(ctx, set_ids[i]);
         Stream *s = find_stream(ctx, cs->stream_id);
         HIPTRY(ctx, launch_count(*s, *cs, ctx->c.opt, ctx->c.flags.as<int32_t>(), st), "launching the count");
+        HIPTRY(ctx, count_deep_subset(*s, *cs, st), "counting deep episodes");
         cs->counted = true;
         cs->counted_n = s->n;
     }
@@ -699,6 +741,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
             if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "stream order must be 0 or 1");
             ctx->c.opt.stream_order = value != 0;
             return EPI_OK;
+        case EPI_OPT_LANE_ENGINE:
+            if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "lane engine must be 0 or 1");
+            ctx->c.opt.lane_engine = value != 0;
+            return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);
     }
@@ -737,8 +783,10 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
     for (int i = 0; i < n_menu; ++i) {
         if (!(0 <= menu_lo[i] && menu_lo[i] < menu_hi[i]))
             return fail(ctx, EPI_EINTERVAL, "menu interval %d must satisfy 0 <= lo < hi", i);
-        if (queue_bound(menu_lo[i], menu_hi[i]) > kMaxQueue)
-            return fail(ctx, EPI_EINTERVAL, "menu interval %d exceeds the supported queue depth", i);
+        // the extension engine keeps no rings; the state-machine engine (menus
+        // of more than kExtMaxMenu intervals, or chosen) holds kMaxQueue
+        if (queue_bound(menu_lo[i], menu_hi[i]) > kMaxQueue && (n_menu > kExtMaxMenu || ctx->c.opt.mine_engine == 0))
+            return fail(ctx, EPI_EINTERVAL, "menu interval %d exceeds the state-machine engine's ring depth", i);
         hmax = std::max(hmax, menu_hi[i]);
     }
     const int64_t tlo = s->ts_kind == EPI_TS_I64 ? INT64_MIN : INT32_MIN;
@@ -792,7 +840,7 @@ epi_status epi_mine(epi_ctx *ctx, int32_t stream_id, int32_t n_menu, const int64
         }
     } else {
         // pair-existence bitmaps of the menu (skipped when they would be too big)
-        const double bits_bytes = 2.0 * 8.0 * n_menu * (double)s->K * (double)s->B * (kTile / 64);
+        const double bits_bytes = 2.0 * 8.0 * n_menu * (double)s->K * (double)s->B * (s->T / 64);
         if (ctx->c.opt.pair_filter && max_size > 1 && s->n > 0 &&
             bits_bytes <= (double)ctx->c.opt.pair_filter_max_bytes) {
             auto tb = std::chrono::steady_clock::now();

@@ -1,0 +1,103 @@
+// Arguments of the state-machine counting kernels (shared by the LDS-ring
+// machines of epi_tiled.hip and the register-indexed machines of
+// epi_lane.hip) and the interface of the latter.
+#pragma once
+
+#include "epi_fsm.h"
+
+namespace epi {
+
+constexpr int kRecFirst = 4;  // speculative completion times recorded per segment
+
+template <typename T>
+struct CountArgs {
+    const T *tiled;
+    const uint16_t *loff;
+    const T *tile_t0;
+    const T *ts_by_type;
+    const int32_t *type_off;
+    int64_t B;
+    int32_t K;
+    const int32_t *ctypes;
+    const T *clo;
+    const T *chi;
+    const uint16_t *t16;  // compact layout (when non-null): types
+    const uint8_t *iv;    //   interval ids into menu
+    const T *menu;        //   (lo, hi) pairs
+    const uint64_t *pbits;  // pair-existence bitmaps (filtered mode)
+    const uint64_t *sbits;
+    int64_t rwords;         // words per bitmap row (B * T / 64)
+    int32_t tile;           // events per tile of the stream
+    int64_t m;
+    int64_t begin;  // first slot of the group
+    int64_t G;      // group size
+    int32_t Q;
+    int32_t P;
+    int64_t S;  // tiles per segment
+    const int32_t *orig;
+    int32_t *counts;
+    int32_t *rec_cnt;
+    T *rec_last;
+    T *rec_first;
+    // reconciliation pre-pass: each segment's true completions and last true
+    // completion when re-run from pre_tau, the last completion the records
+    // of the earlier segments give (null: no pre-pass)
+    int32_t *pre_cnt;
+    T *pre_last;
+    T *pre_tau;
+    // each candidate's last completion (submission order; the type minimum
+    // for none), kept for counting appended events (null: not kept)
+    T *tau;
+    int32_t *flags;
+    uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc;
+    int32_t C;            // epi_lane.hip: ring entries per lane (off_qse: the rings)
+    const int32_t *perm;  // lane slot -> candidate slot (scheduler order); null = identity
+    int32_t *work;        // work log: kWork counters per candidate (submission order); null = off
+    int64_t *cycles;      // work log: wall-clock start/end per work item; null = off
+};
+
+// Persistent form: one work item = (unit, lane block, segment).
+struct WorkItem {
+    int32_t unit;
+    int32_t p;
+    int64_t blk;
+};
+
+// ---- register-indexed lane machines (epi_lane.hip) --------------------------
+// A group of episodes can be counted by them when the stream's tiles are
+// short enough for int32 relative times (lane_rel_ok) and every interval's
+// ring bound is at most kLaneMaxQ.  pk: relative times fit 28 bits, so
+// (time, node) pack into one 31-bit key.
+constexpr int kLaneMaxQ = 15;
+
+inline bool lane_rel_ok(int64_t max_tile_span, int64_t hspan) {
+    return max_tile_span >= 0 && hspan >= 0 && hspan < (int64_t(1) << 29) && max_tile_span < (int64_t(1) << 30) &&
+           max_tile_span + 2 * hspan < (int64_t(1) << 31) - 64;
+}
+inline bool lane_pk_ok(int64_t max_tile_span) { return max_tile_span >= 0 && max_tile_span < (int64_t(1) << 28); }
+
+// Ring entries of an episode: sum over its intervals of the ring bound.
+inline int lane_ring_entries(int N, const int64_t *lo, const int64_t *hi) {
+    int c = 0;
+    for (int j = 0; j + 1 < N; ++j) c += (int)(1 + hi[j] / (hi[j] - lo[j] + 1));
+    return c;
+}
+
+struct LaneLayout {
+    uint32_t off_ring, off_tbuf, off_obuf, off_misc, total;
+};
+LaneLayout lane_layout(int C, int W, int K, int tile);
+
+// Kernel symbols (for attributes and occupancy) and launches.
+template <typename T>
+const void *lane_tiled_fn(int N, bool pk);
+template <typename T>
+const void *lane_persistent_fn(int N, bool pk);
+template <typename T>
+hipError_t lane_launch_tiled(const CountArgs<T> &a, int N, bool pk, dim3 grid, int W, uint32_t lds, hipStream_t st);
+template <typename T>
+hipError_t lane_launch_persistent(int N, bool pk, unsigned grid, int W, uint32_t lds, hipStream_t st,
+                                  const CountArgs<T> *units, const WorkItem *items, int64_t n_items, int64_t item_base,
+                                  unsigned long long *queue);
+
+}  // namespace epi

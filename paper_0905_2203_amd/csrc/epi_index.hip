@@ -12,10 +12,11 @@
 //                 from a wave-wide compare loop, so the scatter is stable.
 //                 It writes the per-type index (times, and the stream
 //                 position of every entry) and a tile-major copy in
-//                 which each chunk of kTile stream positions (a "tile") holds
+//                 which each chunk of T stream positions (a "tile") holds
 //                 its own events grouped by type, with per-tile uint16
 //                 offsets, so that a workgroup can stage a time window of
 //                 every type list with one contiguous, coalesced copy.
+#include <algorithm>
 #include <vector>
 
 #include "epi_internal.h"
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kWave) void k_scatter(const int32_t *__restrict__ t
                                                    const int32_t *__restrict__ cnt, const int32_t *__restrict__ base,
                                                    T *__restrict__ out, int32_t *__restrict__ pos_out,
                                                    T *__restrict__ tiled,
-                                                   uint16_t *__restrict__ loff, T *__restrict__ tile_t0) {
+                                                   uint16_t *__restrict__ loff, T *__restrict__ tile_t0,
+                                                   int32_t TT) {
     __shared__ int32_t rank[kMaxK];   // next rank of each type inside this tile
     __shared__ int32_t start[kMaxK];  // tile-local start of each type group
     __shared__ int32_t wsum[kWave];
@@ -77,8 +79,8 @@ __global__ __launch_bounds__(kWave) void k_scatter(const int32_t *__restrict__ t
         }
     }
     if (lane == kWave - 1) loff[b * (K + 1) + K] = (uint16_t)(x);
-    const int64_t beg = b * kTile;
-    const int64_t end = beg + kTile < n ? beg + kTile : n;
+    const int64_t beg = b * TT;
+    const int64_t end = beg + TT < n ? beg + TT : n;
     if (lane == 0) {
         tile_t0[b] = times[beg];
         if (b == B - 1) tile_t0[B] = TsLimits<T>::hi();
@@ -188,6 +190,13 @@ __global__ void k_offsets(const int32_t *__restrict__ base, int32_t K, int64_t B
     if (k == K) off[K] = (int32_t)n;
 }
 
+// g[i] = times[min(i * step, n - 1)], i < ng
+template <typename T>
+__global__ void k_sample_times(const T *__restrict__ times, int64_t n, int64_t step, int64_t ng, T *__restrict__ g) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ng) g[i] = times[i * step < n ? i * step : n - 1];
+}
+
 template <typename T>
 __global__ void k_validate(const int32_t *__restrict__ types, const T *__restrict__ times, int64_t n, int32_t K,
                            int32_t *__restrict__ flags) {
@@ -214,16 +223,71 @@ hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, i
     return hipGetLastError();
 }
 
+namespace {
+
+// Longest tile of T events (T a multiple of kMinTile): from its first time
+// to the next tile's first time, the last tile to the stream's last time;
+// g holds the times at every kMinTile-th position (and the last one).
+int64_t longest_tile(const std::vector<int64_t> &g, int64_t n, int T) {
+    const int64_t per = T / kMinTile, B = (n + T - 1) / T;
+    uint64_t best = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        const int64_t i1 = (b + 1) * per;
+        const int64_t end = b + 1 < B ? g[i1] : g.back();
+        best = std::max<uint64_t>(best, (uint64_t)end - (uint64_t)g[b * per]);
+    }
+    return best > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)best;
+}
+
+// Events per tile of a stream (Stream::T).
+hipError_t pick_tile(Stream &s, hipStream_t st) {
+    s.T = kTile;
+    if (s.n <= kMinTile) return hipSuccess;
+    const int64_t ng = (s.n + kMinTile - 1) / kMinTile + 1;
+    DevBuf d;
+    hipError_t e;
+    if ((e = d.alloc(sizeof(int64_t) * ng)) != hipSuccess) return e;
+    std::vector<int64_t> g(ng);
+    const unsigned blocks = (unsigned)((ng + 255) / 256);
+    if (s.ts_kind == EPI_TS_I64) {
+        k_sample_times<int64_t><<<blocks, 256, 0, st>>>(s.times.as<int64_t>(), s.n, kMinTile, ng, d.as<int64_t>());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(g.data(), d.p, 8 * ng, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    } else {
+        std::vector<int32_t> g32(ng);
+        k_sample_times<int32_t><<<blocks, 256, 0, st>>>(s.times.as<int32_t>(), s.n, kMinTile, ng, d.as<int32_t>());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(g32.data(), d.p, 4 * ng, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        for (int64_t i = 0; i < ng; ++i) g[i] = g32[i];
+    }
+    // the last sample is the last time (index n - 1)
+    for (int64_t bound : {int64_t(1) << 28, int64_t(1) << 30}) {
+        for (int T = kTile; T >= kMinTile; T /= 2) {
+            if (longest_tile(g, s.n, T) < bound) {
+                s.T = T;
+                return hipSuccess;
+            }
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 hipError_t build_type_index(Stream &s, hipStream_t st) {
     hipError_t e;
     const int64_t n = s.n;
     const int32_t K = s.K;
-    const int64_t B = n > 0 ? (n + kTile - 1) / kTile : 0;
+    if ((e = pick_tile(s, st)) != hipSuccess) return e;
+    const int TT = s.T;
+    const int64_t B = n > 0 ? (n + TT - 1) / TT : 0;
     s.B = B;
     if ((e = s.type_off.alloc(sizeof(int32_t) * (K + 1))) != hipSuccess) return e;
     if ((e = s.ts_by_type.alloc(s.ts_bytes() * (size_t)n)) != hipSuccess) return e;
     if ((e = s.pos_by_type.alloc(sizeof(int32_t) * (size_t)n)) != hipSuccess) return e;
-    if ((e = s.tiled_ts.alloc(s.ts_bytes() * (size_t)B * kTile)) != hipSuccess) return e;
+    if ((e = s.tiled_ts.alloc(s.ts_bytes() * (size_t)B * TT)) != hipSuccess) return e;
     if ((e = s.tile_loff.alloc(sizeof(uint16_t) * (size_t)B * (K + 1))) != hipSuccess) return e;
     if ((e = s.tile_t0.alloc(s.ts_bytes() * (size_t)(B + 1))) != hipSuccess) return e;
     const int64_t Bc = B > 0 ? B : 1;
@@ -234,7 +298,7 @@ hipError_t build_type_index(Stream &s, hipStream_t st) {
     if ((e = base.alloc(sizeof(int32_t) * len)) != hipSuccess) return e;
     if ((e = sums.alloc(sizeof(int32_t) * nb)) != hipSuccess) return e;
     if (n > 0) {
-        k_hist<<<B, kWave, 0, st>>>(s.types.as<int32_t>(), n, K, kTile, B, cnt.as<int32_t>());
+        k_hist<<<B, kWave, 0, st>>>(s.types.as<int32_t>(), n, K, TT, B, cnt.as<int32_t>());
     } else {
         if ((e = hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * len, st)) != hipSuccess) return e;
     }
@@ -248,13 +312,13 @@ hipError_t build_type_index(Stream &s, hipStream_t st) {
                                                     cnt.as<int32_t>(), base.as<int32_t>(),
                                                     s.ts_by_type.as<int64_t>(), s.pos_by_type.as<int32_t>(),
                                                     s.tiled_ts.as<int64_t>(),
-                                                    s.tile_loff.as<uint16_t>(), s.tile_t0.as<int64_t>());
+                                                    s.tile_loff.as<uint16_t>(), s.tile_t0.as<int64_t>(), TT);
         else
             k_scatter<int32_t><<<B, kWave, 0, st>>>(s.types.as<int32_t>(), s.times.as<int32_t>(), n, K, B,
                                                     cnt.as<int32_t>(), base.as<int32_t>(),
                                                     s.ts_by_type.as<int32_t>(), s.pos_by_type.as<int32_t>(),
                                                     s.tiled_ts.as<int32_t>(),
-                                                    s.tile_loff.as<uint16_t>(), s.tile_t0.as<int32_t>());
+                                                    s.tile_loff.as<uint16_t>(), s.tile_t0.as<int32_t>(), TT);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the temporaries are freed when this returns: wait for the kernels first

@@ -17,7 +17,8 @@ namespace epi {
 constexpr int kMaxN = EPI_MAX_N;
 constexpr int kMaxK = 4096;        // LDS histogram bound of the index build
 constexpr int kMaxQueue = 16;      // deepest merged-interval ring (LDS) per node
-constexpr int kTile = 2048;        // events per stream tile
+constexpr int kTile = 2048;        // largest number of events per stream tile (the stream picks its own, Stream::T)
+constexpr int kMinTile = 256;      // smallest tile a stream may pick
 constexpr int kMlpHidden = 64;     // hidden units of the cost model
 constexpr int kFeatures = 24;      // cost-model features per candidate
 constexpr int kWork = 5;           // work-log counters per candidate
@@ -162,10 +163,14 @@ struct Stream {
     DevBuf ts_by_type;  // T[n], grouped by type, each group in time order
     DevBuf pos_by_type; // int32[n], stream position of each ts_by_type entry
     // Tile-major copy of the index: tile b holds stream positions
-    // [b*kTile, (b+1)*kTile); inside a tile the events are grouped by type
-    // (each group in time order) starting at tile_loff[b*(K+1) + type].
+    // [b*T, (b+1)*T); inside a tile the events are grouped by type (each
+    // group in time order) starting at tile_loff[b*(K+1) + type].  T is the
+    // largest of 2048, 1024, 512, 256 whose tiles span less than 2^28 time
+    // units (relative times of a tile then leave 3 bits for a node index in
+    // a 31-bit key), else the largest spanning less than 2^30, else 2048.
+    int T = kTile;      // events per tile
     int64_t B = 0;      // number of tiles
-    DevBuf tiled_ts;    // T[B*kTile] (the last tile is padded)
+    DevBuf tiled_ts;    // T[B*T] (the last tile is padded)
     DevBuf tile_loff;   // uint16[B*(K+1)]
     DevBuf tile_t0;     // T[B+1]: time of each tile's first event; [B] = type maximum
     std::vector<int32_t> h_off;  // host copy of type_off
@@ -177,10 +182,27 @@ struct Stream {
 // Candidates of one launch class: same episode size N and queue capacity Q.
 struct Group {
     int N = 0;
-    int Q = 0;
+    int Q = 0;                   // ring capacity class of the deepest interval (LDS-ring machines)
+    int C = 0;                   // most ring entries of one episode: sum of its intervals' bounds (lane machines)
     int64_t begin = 0, end = 0;  // slots [begin, end) of the grouped layout
     int64_t hspan = -1;          // longest span (sum of upper bounds) of its episodes (-1: unknown)
 };
+
+// Launch classes of the register-indexed lane machines: an episode's ring
+// entries (the sum of its intervals' bounds) rounded up to one of these.
+constexpr int kCapClasses = 23;
+inline int cap_class_index(int c) {
+    static constexpr int kC[kCapClasses] = {1,  2,  3,  4,  5,  6,  7,  8,  10, 12, 14, 16,
+                                            20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 112};
+    for (int i = 0; i < kCapClasses; ++i)
+        if (kC[i] >= c) return i;
+    return kCapClasses - 1;
+}
+inline int cap_class_value(int i) {
+    static constexpr int kC[kCapClasses] = {1,  2,  3,  4,  5,  6,  7,  8,  10, 12, 14, 16,
+                                            20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 112};
+    return kC[i < 0 ? 0 : (i >= kCapClasses ? kCapClasses - 1 : i)];
+}
 
 // Ring capacity of a launch class: the smallest of 1, 2, 3, 4, 6, 8, 12, 16
 // that holds queue bound b.
@@ -216,7 +238,7 @@ struct CandSet {
     // Optional pair-existence bitmaps of the menu (compact layout only; not
     // owned): bit (i, x, pos) of pred_bits says the event at tiled position
     // pos has an event of type x at a gap in menu interval i before it;
-    // succ_bits the same after it.  Rows of B*kTile bits.
+    // succ_bits the same after it.  Rows of B*T bits (T: the stream's tile).
     const uint64_t *pred_bits = nullptr;
     const uint64_t *succ_bits = nullptr;
     std::vector<Group> groups;
@@ -229,6 +251,12 @@ struct CandSet {
     DevBuf track_work, track_desc;  // working set of the tracking engine, kept for the next count
     bool stream_order = false;      // overlap decided in stream order (counted by the tracking engine only)
     int64_t max_span = 0;           // longest span (sum of upper bounds) of its episodes
+    // Episodes with an interval deeper than the state machines' rings
+    // (bound > kLaneMaxQ) sit in the last slots of the grouped layout, in no
+    // group; the tracking engine counts them as this sub-set, whose counts
+    // and last completions are then scattered to deep_idx (submission indices).
+    std::unique_ptr<CandSet> deep;
+    DevBuf deep_idx;  // int32 [deep->m]
 };
 
 // Launch options (epi_set_option).
@@ -245,6 +273,7 @@ struct CountOptions {
     bool allow_repeats = false;    // epi_submit_candidates accepts a type at several nodes
     int64_t mine_list_alphas = 65536;  // extension engine: list path below this many parent episodes
     bool stream_order = false;     // sets submitted now decide overlap in stream order
+    bool lane_engine = true;       // state machines: register-indexed lane machines where they apply
 };
 
 // One level of a level-wise discovery run: candidates of size N in
@@ -363,6 +392,9 @@ hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, in
 // Count set c by per-event tracking of each episode's nodes and the greedy
 // over the latest-start intervals (epi_track.hip); returns when done.
 hipError_t launch_count_tracking(const Stream &s, CandSet &c, hipStream_t st);
+// Count set c's deep episodes (CandSet::deep) by tracking and scatter their
+// counts and last completions into c's; returns when done (no-op without).
+hipError_t count_deep_subset(const Stream &s, CandSet &c, hipStream_t st);
 // Add to set c's counts the occurrences completed by the stream's events
 // after the first c.counted_n (B = the first of their times).
 hipError_t launch_count_append(const Stream &s, CandSet &c, int64_t B, int32_t *d_flags, hipStream_t st);

@@ -16,7 +16,7 @@
 #include <numeric>
 #include <thread>
 
-#include "epi_internal.h"
+#include "epi_count.h"
 
 namespace epi {
 
@@ -40,10 +40,12 @@ hipError_t count_level_t(const Stream &s, const Mine &mn, MineLevel &L, const Co
     const int nm = (int)mn.menu_lo.size();
     std::vector<T> menu(2 * nm);
     int Q = 1;
+    int64_t qmax = 1;
     for (int i = 0; i < nm; ++i) {
         menu[2 * i] = (T)mn.menu_lo[i];
         menu[2 * i + 1] = (T)mn.menu_hi[i];
         if (L.N > 1) Q = std::max(Q, queue_class_of(queue_bound(mn.menu_lo[i], mn.menu_hi[i])));
+        qmax = std::max(qmax, queue_bound(mn.menu_lo[i], mn.menu_hi[i]));
     }
     if ((e = cs.t16.alloc(sizeof(uint16_t) * L.types.size())) != hipSuccess) return e;
     if ((e = cs.iv.alloc(L.iv.size())) != hipSuccess) return e;
@@ -62,6 +64,8 @@ hipError_t count_level_t(const Stream &s, const Mine &mn, MineLevel &L, const Co
     Group g;
     g.N = L.N;
     g.Q = Q;
+    // lane machines: every interval's ring as deep as the menu's deepest
+    g.C = qmax <= kLaneMaxQ ? (int)qmax * (L.N - 1) : 0;
     g.begin = 0;
     g.end = m;
     g.hspan = 0;

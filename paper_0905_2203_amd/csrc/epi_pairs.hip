@@ -48,16 +48,16 @@ __global__ __launch_bounds__(256) void k_pair_bits(const T *__restrict__ tiled, 
                                                    int64_t B, int32_t K, const T *__restrict__ ts,
                                                    const int32_t *__restrict__ type_off, const T *__restrict__ menu,
                                                    int32_t M, uint64_t *__restrict__ pbits,
-                                                   uint64_t *__restrict__ sbits) {
+                                                   uint64_t *__restrict__ sbits, int32_t TT) {
     const int lane = threadIdx.x & 63;
-    const int64_t words = B * (kTile / 64);
+    const int64_t words = B * (TT / 64);
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;  // uniform per wave
     if (w >= words) return;
     const int x = blockIdx.y;
-    const int64_t b = w / (kTile / 64);
-    const int pos = (int)(w % (kTile / 64)) * 64 + lane;
+    const int64_t b = w / (TT / 64);
+    const int pos = (int)(w % (TT / 64)) * 64 + lane;
     const bool valid = pos < loff[b * (K + 1) + K];
-    const T t = valid ? tiled[b * kTile + pos] : T(0);
+    const T t = valid ? tiled[b * TT + pos] : T(0);
     const int32_t xlo = type_off[x], xhi = type_off[x + 1];
     for (int i = 0; i < M; ++i) {
         const T lo = menu[2 * i], hi = menu[2 * i + 1];
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_pair_bits(const T *__restrict__ tiled, 
 
 hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st) {
     const int M = (int)mn.menu_lo.size();
-    const int64_t words = s.B * (kTile / 64);
+    const int64_t words = s.B * (s.T / 64);
     const size_t bytes = sizeof(uint64_t) * (size_t)M * s.K * words;
     hipError_t e;
     if ((e = mn.pred_bits.alloc(bytes)) != hipSuccess) return e;
@@ -102,7 +102,7 @@ hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st) {
         k_pair_bits<int64_t><<<grid, 64 * wpb, 0, st>>>(s.tiled_ts.as<int64_t>(), s.tile_loff.as<uint16_t>(), s.B, s.K,
                                                        s.ts_by_type.as<int64_t>(), s.type_off.as<int32_t>(),
                                                        menu.as<int64_t>(), M, mn.pred_bits.as<uint64_t>(),
-                                                       mn.succ_bits.as<uint64_t>());
+                                                       mn.succ_bits.as<uint64_t>(), s.T);
     } else {
         std::vector<int32_t> h32(2 * M);
         for (int i = 0; i < 2 * M; ++i) h32[i] = (int32_t)h[i];
@@ -112,7 +112,7 @@ hipError_t build_pair_bits(const Stream &s, Mine &mn, hipStream_t st) {
         k_pair_bits<int32_t><<<grid, 64 * wpb, 0, st>>>(s.tiled_ts.as<int32_t>(), s.tile_loff.as<uint16_t>(), s.B, s.K,
                                                        s.ts_by_type.as<int32_t>(), s.type_off.as<int32_t>(),
                                                        menu.as<int32_t>(), M, mn.pred_bits.as<uint64_t>(),
-                                                       mn.succ_bits.as<uint64_t>());
+                                                       mn.succ_bits.as<uint64_t>(), s.T);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipStreamSynchronize(st);  // the menu buffer dies here

@@ -1,7 +1,7 @@
 // Tiled counting engine and exact segment reconciliation.
 //
 // k_count_tiled: a workgroup holds W candidate episodes of one size N (one
-// lane each) and walks a range of stream tiles.  Each tile (kTile stream
+// lane each) and walks a range of stream tiles.  Each tile (T stream
 // positions, grouped by type) is copied into LDS with coalesced 16-byte
 // loads and shared by all W lanes; a lane merges, in time order, the tile's
 // events of its own N types only (the per-tile type offsets give each
@@ -43,58 +43,11 @@
 
 #include <type_traits>
 
-#include "epi_fsm.h"
+#include "epi_count.h"
 
 namespace epi {
 
 namespace {
-
-constexpr int kRecFirst = 4;  // speculative completion times recorded per segment
-
-template <typename T>
-struct CountArgs {
-    const T *tiled;
-    const uint16_t *loff;
-    const T *tile_t0;
-    const T *ts_by_type;
-    const int32_t *type_off;
-    int64_t B;
-    int32_t K;
-    const int32_t *ctypes;
-    const T *clo;
-    const T *chi;
-    const uint16_t *t16;  // compact layout (when non-null): types
-    const uint8_t *iv;    //   interval ids into menu
-    const T *menu;        //   (lo, hi) pairs
-    const uint64_t *pbits;  // pair-existence bitmaps (filtered mode)
-    const uint64_t *sbits;
-    int64_t rwords;         // words per bitmap row (B * kTile / 64)
-    int64_t m;
-    int64_t begin;  // first slot of the group
-    int64_t G;      // group size
-    int32_t Q;
-    int32_t P;
-    int64_t S;  // tiles per segment
-    const int32_t *orig;
-    int32_t *counts;
-    int32_t *rec_cnt;
-    T *rec_last;
-    T *rec_first;
-    // reconciliation pre-pass: each segment's true completions and last true
-    // completion when re-run from pre_tau, the last completion the records
-    // of the earlier segments give (null: no pre-pass)
-    int32_t *pre_cnt;
-    T *pre_last;
-    T *pre_tau;
-    // each candidate's last completion (submission order; the type minimum
-    // for none), kept for counting appended events (null: not kept)
-    T *tau;
-    int32_t *flags;
-    uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc;
-    const int32_t *perm;  // lane slot -> candidate slot (scheduler order); null = identity
-    int32_t *work;        // work log: kWork counters per candidate (submission order); null = off
-    int64_t *cycles;      // work log: wall-clock start/end per work item; null = off
-};
 
 template <typename T, int N, typename R>
 __device__ __forceinline__ T load_candidate(const CountArgs<T> &a, LaneFsm<R, N> &f, int64_t slot, int32_t *ty,
@@ -245,18 +198,18 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
                 f.e = f.e - d < R(-2) ? R(-2) : (R)(f.e - d);
             }
             t0b = nb;
-            const T *src = a.tiled + b * kTile;
+            const T *src = a.tiled + b * a.tile;
             // (the last tile's padding is never read; wrapping keeps it defined)
-            for (int i = lane; i < kTile; i += W) {
+            for (int i = lane; i < a.tile; i += W) {
                 const int64_t v = (int64_t)((uint64_t)src[i] - (uint64_t)t0b);
                 tbuf[i] = v > (int64_t)INT32_MAX ? INT32_MAX : (v < -1 ? R(-1) : (R)v);
             }
             BpR = Bp <= t0b ? R(-1) : (Bp - t0b >= (T)INT32_MAX ? rEnd : (R)(Bp - t0b));
             EpR = (Ep == kEnd || Ep - t0b >= (T)INT32_MAX) ? rEnd : (R)(Ep - t0b);
         } else {
-            const uint4 *src = reinterpret_cast<const uint4 *>(a.tiled + b * kTile);
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.tiled + b * a.tile);
             uint4 *dst = reinterpret_cast<uint4 *>(tbuf);
-            for (int i = lane; i < (int)(kTile * sizeof(T) / 16); i += W) dst[i] = src[i];
+            for (int i = lane; i < (int)(a.tile * sizeof(T) / 16); i += W) dst[i] = src[i];
             BpR = (R)Bp;
             EpR = (R)Ep;
         }
@@ -270,7 +223,7 @@ __device__ __forceinline__ void count_item(const CountArgs<T> &a, int64_t blk, i
         int wi[N], we[N];
         uint64_t msk[N], nmsk[N];  // current word's bits, next word's (prefetched)
         R head[N];
-        const int64_t wbase = b * (kTile / 64);
+        const int64_t wbase = b * (a.tile / 64);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             cur[k] = obuf[ty[k]];
@@ -453,11 +406,6 @@ __global__ __launch_bounds__(256) void k_count_tiled(CountArgs<T> a) {
 // Persistent form: every workgroup takes work items (unit, lane block,
 // segment) from a device queue until it is empty.  Units may belong to
 // different streams and candidate sets; they share the LDS layout.
-struct WorkItem {
-    int32_t unit;
-    int32_t p;
-    int64_t blk;
-};
 
 template <typename T, int N, bool FILT, bool REL>
 __global__ __launch_bounds__(256) void k_count_persistent(const CountArgs<T> *__restrict__ units,
@@ -834,9 +782,10 @@ struct Layout {
     uint32_t off_qse, off_tbuf, off_qh, off_obuf, off_misc, total;
 };
 
-// rel: the machines and the staged tile hold int32 relative times.
+// rel: the machines and the staged tile hold int32 relative times; tile:
+// events per tile of the stream(s).
 template <typename T>
-Layout<T> layout(int N, int Q, int W, int K, bool tiles, bool rel = false) {
+Layout<T> layout(int N, int Q, int W, int K, bool tiles, bool rel = false, int tile = kTile) {
     Layout<T> L;
     const size_t lv = N > 1 ? N - 1 : 0;
     const size_t ts = rel ? sizeof(int32_t) : sizeof(T);  // machine time
@@ -844,7 +793,7 @@ Layout<T> layout(int N, int Q, int W, int K, bool tiles, bool rel = false) {
     L.off_qse = (uint32_t)o;
     o += al16(lv * Q * W * 2 * ts);
     L.off_tbuf = (uint32_t)o;
-    o += tiles ? al16(kTile * ts) : 0;
+    o += tiles ? al16((size_t)tile * ts) : 0;
     L.off_qh = (uint32_t)o;
     o += al16(lv * W * sizeof(uint32_t));
     L.off_obuf = (uint32_t)o;
@@ -968,6 +917,47 @@ hipError_t launch_reconcile(const CountArgs<T> &a, int N, const Layout<T> &RL, h
     return hipGetLastError();
 }
 
+// Lane width of a launch of the lane-machine kernel fn with ring entries C:
+// the one (of 256, 128, 64, at most max_lanes) whose workgroups keep the most
+// waves resident on a CU; ties go to the wider one.
+int lane_pick_width(const void *fn, int C, int K, int tile, int max_lanes) {
+    int best = 0, bestW = 64;
+    for (int W : {256, 128, 64}) {
+        if (max_lanes > 0 && W > max_lanes) continue;
+        const LaneLayout L = lane_layout(C, W, K, tile);
+        if (L.total > kLdsHard) continue;
+        if (L.total > kLdsSoft &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, W, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        const int waves = per * (W / 64);
+        if (waves > best) {
+            best = waves;
+            bestW = W;
+        }
+    }
+    return bestW;
+}
+
+hipError_t lane_lds_attr(const void *fn, uint32_t bytes) {
+    if (bytes <= kLdsSoft) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Whether the register-indexed lane machines count group g of stream s.
+template <typename T>
+bool lane_group_ok(const Stream &s, const CandSet &c, const Group &g, const CountOptions &opt) {
+    const bool filtered = c.compact && c.pred_bits && c.succ_bits;
+    return opt.lane_engine && !filtered && (g.N == 1 || (g.C > 0 && g.C <= cap_class_value(kCapClasses - 1))) &&
+           lane_rel_ok(s.max_tile_span, g.hspan);
+}
+
 template <typename T>
 hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st) {
     hipError_t e;
@@ -981,13 +971,19 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
             if ((e = hipGetLastError()) != hipSuccess) return e;
             continue;
         }
-        const bool rel = rel_ok<T>(s, g.hspan);
+        const bool lane = lane_group_ok<T>(s, c, g, opt);
+        const bool pk = lane && lane_pk_ok(s.max_tile_span);
+        const bool rel = !lane && rel_ok<T>(s, g.hspan);
         const bool filtered = c.compact && c.pred_bits && c.succ_bits;
-        KFn<T> fn = pick_count<T>(g.N, filtered, rel);
-        if (!fn) return hipErrorInvalidValue;
-        const int W = pick_lanes_fn<T>(reinterpret_cast<const void *>(fn), g.N, g.Q, s.K, opt.lanes, rel);
+        KFn<T> fn = lane ? nullptr : pick_count<T>(g.N, filtered, rel);
+        const void *lfn = lane ? lane_tiled_fn<T>(g.N, pk) : nullptr;
+        if (!fn && !lfn) return hipErrorInvalidValue;
+        const int C = std::max(1, g.C);
+        const int W = lane ? lane_pick_width(lfn, C, s.K, s.T, opt.lanes)
+                           : pick_lanes_fn<T>(reinterpret_cast<const void *>(fn), g.N, g.Q, s.K, opt.lanes, rel);
         const Layout<T> L = layout<T>(g.N, g.Q, W, s.K, true, rel);
-        const uint32_t lds = L.total;
+        const LaneLayout LL = lane_layout(C, W, s.K, s.T);
+        const uint32_t lds = lane ? LL.total : L.total;
         if (lds > kLdsHard) return hipErrorInvalidConfiguration;
         // segments
         int64_t P = 1;
@@ -1025,6 +1021,7 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.begin = g.begin;
         a.G = G;
         a.Q = g.Q;
+        a.C = C;
         a.P = (int32_t)P;
         a.S = S;
         a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
@@ -1034,11 +1031,19 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.perm = nullptr;
         a.work = opt.worklog && c.work.p ? c.work.as<int32_t>() : nullptr;
         a.cycles = nullptr;
-        a.off_qse = L.off_qse;
-        a.off_tbuf = L.off_tbuf;
-        a.off_qh = L.off_qh;
-        a.off_obuf = L.off_obuf;
-        a.off_misc = L.off_misc;
+        if (lane) {
+            a.off_qse = LL.off_ring;
+            a.off_tbuf = LL.off_tbuf;
+            a.off_qh = 0;
+            a.off_obuf = LL.off_obuf;
+            a.off_misc = LL.off_misc;
+        } else {
+            a.off_qse = L.off_qse;
+            a.off_tbuf = L.off_tbuf;
+            a.off_qh = L.off_qh;
+            a.off_obuf = L.off_obuf;
+            a.off_misc = L.off_misc;
+        }
         if (P > 1) {
             const size_t need = record_bytes<T>(P, G);
             if (c.scratch.bytes < need) {
@@ -1049,11 +1054,17 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         }
         a.pbits = filtered ? c.pred_bits : nullptr;
         a.sbits = filtered ? c.succ_bits : nullptr;
-        a.rwords = s.B * (kTile / 64);
-        if ((e = ensure_lds_attr<T>(fn, lds)) != hipSuccess) return e;
+        a.rwords = s.B * (s.T / 64);
+        a.tile = s.T;
         const dim3 grid((unsigned)((G + W - 1) / W), (unsigned)P);
-        fn<<<grid, W, lds, st>>>(a);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (lane) {
+            if ((e = lane_lds_attr(lfn, lds)) != hipSuccess) return e;
+            if ((e = lane_launch_tiled<T>(a, g.N, pk, grid, W, lds, st)) != hipSuccess) return e;
+        } else {
+            if ((e = ensure_lds_attr<T>(fn, lds)) != hipSuccess) return e;
+            fn<<<grid, W, lds, st>>>(a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         if (P > 1 && (e = launch_reconcile<T>(a, g.N, layout<T>(g.N, g.Q, kRecLanes, s.K, false), st)) != hipSuccess)
             return e;
     }
@@ -1198,6 +1209,9 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         bool filt;
         std::vector<float> bcost;  // per lane block
         bool rel = false;          // int32 relative-time machines allowed
+        bool lane = false;         // register-indexed lane machines
+        bool pk = false;           //   with packed (time, node) keys
+        int C = 0;                 //   ring entries per lane
     };
     std::vector<UnitH> units;
     std::vector<DevBuf> perms(sets.size());
@@ -1232,10 +1246,19 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
             const int64_t G = g.end - g.begin;
             if (G <= 0) continue;
             const bool filt = c.compact && c.pred_bits && c.succ_bits;
-            const bool rel = rel_ok<T>(s, g.hspan);
-            const PFn<T> pfn = filt ? pick_persistent_f<T, true>(g.N, rel) : pick_persistent_f<T, false>(g.N, rel);
-            if (!pfn) return hipErrorInvalidValue;
-            const int W = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), g.N, g.Q, s.K, opt.lanes, rel);
+            const bool lane = lane_group_ok<T>(s, c, g, opt);
+            const bool pk = lane && lane_pk_ok(s.max_tile_span);
+            const bool rel = !lane && rel_ok<T>(s, g.hspan);
+            const int C = std::max(1, g.C);
+            int W;
+            if (lane) {
+                W = lane_pick_width(lane_persistent_fn<T>(g.N, pk), C, s.K, s.T, opt.lanes);
+            } else {
+                const PFn<T> pfn =
+                    filt ? pick_persistent_f<T, true>(g.N, rel) : pick_persistent_f<T, false>(g.N, rel);
+                if (!pfn) return hipErrorInvalidValue;
+                W = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), g.N, g.Q, s.K, opt.lanes, rel);
+            }
             const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
             if (costs[si].empty()) {
                 // round robin: submission order, segments as in plain mode
@@ -1246,6 +1269,9 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                 P = (s.B + S - 1) / S;
                 UnitH u{(int)si, g.N, g.Q, W, g.begin, G, P, S, filt, {}};
                 u.rel = rel;
+                u.lane = lane;
+                u.pk = pk;
+                u.C = C;
                 u.bcost.assign((G + W - 1) / W, 1.f);
                 units.push_back(std::move(u));
                 continue;
@@ -1275,6 +1301,9 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                 UnitH u{(int)si, g.N, g.Q, W, g.begin + b0 * W, std::min<int64_t>(G - b0 * W, (b1 - b0) * W), P, S,
                         filt, {}};
                 u.rel = rel;
+                u.lane = lane;
+                u.pk = pk;
+                u.C = C;
                 for (int64_t b = b0; b < b1; ++b)
                     u.bcost.push_back(costs[si][g.begin + b * W] * (float)std::min<int64_t>(W, G - b * W));
                 units.push_back(std::move(u));
@@ -1291,19 +1320,24 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     // launch classes: episode size x queue class x machine time type (each
     // with its own lane width and LDS layout, as the plain launch sizes each
     // group)
+    // (the LDS-ring machines: episode size x queue class x machine time type;
+    // the lane machines: episode size x ring-entries class x key form)
     constexpr int kQClasses = 8;  // Q = 1, 2, 3, 4, 6, 8, 12, 16
-    constexpr int kClasses = (kMaxN + 1) * kQClasses * 2;
-    auto cls_of = [](int N, int Q, bool rel) {
+    constexpr int kRingClasses = (kMaxN + 1) * kQClasses * 2;
+    constexpr int kClasses = kRingClasses + (kMaxN + 1) * kCapClasses * 2;
+    auto cls_of = [](const UnitH &u) {
+        if (u.lane) return kRingClasses + (u.N * kCapClasses + cap_class_index(u.C)) * 2 + (u.pk ? 1 : 0);
         static constexpr int kQ[kQClasses] = {1, 2, 3, 4, 6, 8, 12, 16};
         int q = 0;
-        while (q + 1 < kQClasses && kQ[q] < Q) ++q;
-        return (N * kQClasses + q) * 2 + (rel ? 1 : 0);
+        while (q + 1 < kQClasses && kQ[q] < u.Q) ++q;
+        return (u.N * kQClasses + q) * 2 + (u.rel ? 1 : 0);
     };
     std::vector<CountArgs<T>> ua(units.size());
     std::vector<std::vector<WorkItem>> items(kClasses);
     std::vector<std::vector<float>> icost(kClasses);
-    std::vector<int> clsN(kClasses, 0), clsQ(kClasses, 1), maxK(kClasses, 1), Wn(kClasses, 256);
-    std::vector<bool> filtN(kClasses, false), relN(kClasses, false);
+    std::vector<int> clsN(kClasses, 0), clsQ(kClasses, 1), clsC(kClasses, 1), maxK(kClasses, 1), maxT(kClasses, 64),
+        Wn(kClasses, 256);
+    std::vector<bool> filtN(kClasses, false), relN(kClasses, false), laneN(kClasses, false), pkN(kClasses, false);
     size_t ro = 0;
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
@@ -1325,7 +1359,8 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         a.menu = c.compact ? c.menu.as<T>() : nullptr;
         a.pbits = u.filt ? c.pred_bits : nullptr;
         a.sbits = u.filt ? c.succ_bits : nullptr;
-        a.rwords = s.B * (kTile / 64);
+        a.rwords = s.B * (s.T / 64);
+        a.tile = s.T;
         a.m = c.m;
         a.begin = u.begin;
         a.G = u.G;
@@ -1343,16 +1378,25 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
             ro += (record_bytes<T>(u.P, u.G) + 64) & ~size_t(15);
         }
         ua[ui] = a;
-        const int cl = cls_of(u.N, u.Q, u.rel);
+        const int cl = cls_of(u);
         clsN[cl] = u.N;
         relN[cl] = u.rel;
+        laneN[cl] = u.lane;
+        pkN[cl] = u.pk;
         clsQ[cl] = std::max(clsQ[cl], u.Q);
+        clsC[cl] = std::max(clsC[cl], u.C);
         maxK[cl] = std::max(maxK[cl], (int)s.K);
+        maxT[cl] = std::max(maxT[cl], s.T);
         filtN[cl] = filtN[cl] || u.filt;
     }
     // lanes per workgroup per class: common to its units
     for (int cl = 0; cl < kClasses; ++cl)
         if (clsN[cl] > 0) {
+            if (laneN[cl]) {
+                Wn[cl] = lane_pick_width(lane_persistent_fn<T>(clsN[cl], pkN[cl]), clsC[cl], maxK[cl], maxT[cl],
+                                         opt.lanes);
+                continue;
+            }
             const PFn<T> pfn = filtN[cl] ? pick_persistent_f<T, true>(clsN[cl], relN[cl])
                                          : pick_persistent_f<T, false>(clsN[cl], relN[cl]);
             if (!pfn) return hipErrorInvalidValue;
@@ -1360,9 +1404,19 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
                                       relN[cl]);
         }
     for (size_t ui = 0; ui < units.size(); ++ui) {
-        const int cl = cls_of(units[ui].N, units[ui].Q, units[ui].rel);
-        const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
+        const int cl = cls_of(units[ui]);
         ua[ui].Q = clsQ[cl];
+        ua[ui].C = clsC[cl];
+        if (laneN[cl]) {
+            const LaneLayout L = lane_layout(clsC[cl], Wn[cl], maxK[cl], maxT[cl]);
+            ua[ui].off_qse = L.off_ring;
+            ua[ui].off_tbuf = L.off_tbuf;
+            ua[ui].off_qh = 0;
+            ua[ui].off_obuf = L.off_obuf;
+            ua[ui].off_misc = L.off_misc;
+            continue;
+        }
+        const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
         ua[ui].off_qse = L.off_qse;
         ua[ui].off_tbuf = L.off_tbuf;
         ua[ui].off_qh = L.off_qh;
@@ -1372,7 +1426,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     // work items: lane blocks of the class width x segments
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
-        const int cl = cls_of(u.N, u.Q, u.rel);
+        const int cl = cls_of(u);
         const int W = Wn[cl];
         const int64_t nb = (u.G + W - 1) / W;
         for (int64_t b = 0; b < nb; ++b) {
@@ -1470,11 +1524,24 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         load[bi] += ccost[cl];
         const int N = clsN[cl];
         const bool filt = filtN[cl];
+        int per = 0;
+        if (laneN[cl]) {
+            const void *lfn = lane_persistent_fn<T>(N, pkN[cl]);
+            const LaneLayout L = lane_layout(clsC[cl], Wn[cl], maxK[cl], maxT[cl]);
+            if ((e = lane_lds_attr(lfn, L.total)) != hipSuccess) break;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, lfn, Wn[cl], L.total)) != hipSuccess) break;
+            const int64_t grid =
+                std::max<int64_t>(1, std::min<int64_t>((int64_t)items[cl].size(), (int64_t)ncu * std::max(per, 1)));
+            e = lane_launch_persistent<T>(N, pkN[cl], (unsigned)grid, Wn[cl], L.total, br[bi],
+                                          d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[cl],
+                                          (int64_t)items[cl].size(), ioff[cl],
+                                          reinterpret_cast<unsigned long long *>(d_queue.p) + cl);
+            continue;
+        }
         PFn<T> fn = filt ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
         const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
         e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total);
         if (e != hipSuccess) break;
-        int per = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(fn), Wn[cl], L.total);
         if (e != hipSuccess) break;
         const int64_t grid =
@@ -1494,7 +1561,7 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
     for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
         if (units[ui].P <= 1) continue;
         const int N = units[ui].N;
-        const int cl = cls_of(N, units[ui].Q, units[ui].rel);
+        const int cl = cls_of(units[ui]);
         e = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), st);
     }
     hipError_t ec = hipStreamEndCapture(st, &graph);

@@ -485,7 +485,34 @@ hipError_t count_tracking_t(const Stream &s, CandSet &c, hipStream_t st) {
     return hipSuccess;
 }
 
+template <typename T>
+__global__ void k_scatter_deep(int64_t md, const int32_t *__restrict__ idx, const int32_t *__restrict__ dc,
+                               const T *__restrict__ dtau, int32_t *__restrict__ counts, T *__restrict__ tau) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= md) return;
+    counts[idx[i]] = dc[i];
+    if (tau) tau[idx[i]] = dtau[i];
+}
+
 }  // namespace
+
+hipError_t count_deep_subset(const Stream &s, CandSet &c, hipStream_t st) {
+    if (!c.deep || c.deep->m == 0) return hipSuccess;
+    CandSet &d = *c.deep;
+    hipError_t e = launch_count_tracking(s, d, st);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((d.m + 255) / 256);
+    if (s.ts_kind == EPI_TS_I64)
+        k_scatter_deep<int64_t><<<blocks, 256, 0, st>>>(d.m, c.deep_idx.as<int32_t>(), d.counts.as<int32_t>(),
+                                                       d.tau.as<int64_t>(), c.counts.as<int32_t>(),
+                                                       c.tau.p ? c.tau.as<int64_t>() : nullptr);
+    else
+        k_scatter_deep<int32_t><<<blocks, 256, 0, st>>>(d.m, c.deep_idx.as<int32_t>(), d.counts.as<int32_t>(),
+                                                       d.tau.as<int32_t>(), c.counts.as<int32_t>(),
+                                                       c.tau.p ? c.tau.as<int32_t>() : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
 
 hipError_t launch_count_tracking(const Stream &s, CandSet &c, hipStream_t st) {
     if (c.compact || (int64_t)c.h_N.size() != c.m) return hipErrorInvalidValue;

@@ -64,6 +64,7 @@ EPI_OPT_MINE_LIST_BYTES = 8
 EPI_OPT_ALLOW_REPEATS = 9
 EPI_OPT_MINE_LIST_ALPHAS = 10
 EPI_OPT_STREAM_ORDER = 11
+EPI_OPT_LANE_ENGINE = 12
 
 
 class EpiError(RuntimeError):

@@ -101,11 +101,16 @@ def test_validate_candidate_size_and_overflow():
     assert epi.epi_validate_candidates(sg.empty_candidates(0), 32, 0) == epi.EPI_OK
 
 
-def test_validate_candidate_queue_depth_limit():
-    # 1 + hi/(hi-lo+1) = 1 + 100/2 = 51 intervals could be live at once
-    assert epi.epi_validate_candidates(_one([0, 1], [99], [100]), 32, 0) == epi.EPI_EINTERVAL
-    # the deepest interval of the random-candidate menu: (20, 25] ms -> bound 5
+def test_validate_accepts_every_legal_interval():
+    # Sec. II-C admits any 0 <= lo < hi: a narrow interval far from its node,
+    # 1 + hi/(hi-lo+1) = 1 + 100/2 = 51 live acceptance intervals, is legal
+    # (the state machines leave such episodes to the per-event tracking engine)
+    assert epi.epi_validate_candidates(_one([0, 1], [99], [100]), 32, 0) == epi.EPI_OK
+    assert epi.epi_validate_candidates(_one([0, 1], [95_000_000], [100_000_000]), 32, 1) == epi.EPI_OK
     assert epi.epi_validate_candidates(_one([0, 1], [20_000_000], [25_000_000]), 32, 1) == epi.EPI_OK
+    # still refused: lo < 0, lo >= hi
+    assert epi.epi_validate_candidates(_one([0, 1], [-1], [5]), 32, 0) == epi.EPI_EINTERVAL
+    assert epi.epi_validate_candidates(_one([0, 1], [5], [5]), 32, 0) == epi.EPI_EINTERVAL
 
 
 def test_generated_workloads_validate():
