@@ -1,18 +1,22 @@
-"""Benchmark: level-wise discovery of frequent serial episodes on one MI355X.
+"""Benchmark of exact serial-episode counting on one MI355X.
 
-Workload (the mining preset): 64 event types, independent 20 Hz Poisson
-spike trains over 300 s with int32 microsecond times, plus 4 planted cascades
-of 4-6 types whose gaps are drawn from {(0,5], (5,10], (10,20]} ms, fired at
-2-8 Hz; candidates are generated level by level from size 1 up to size 6
-over that interval menu, and an episode is frequent when its count is
-greater than 100.
+Default (the headline line): the Large workload -- 256 event types, 50M
+events over 3600 s with int64 nanosecond times (Poisson background plus 32
+planted cascades of 3-8 types), 200k candidate episodes of sizes 2-8 (every
+sub-episode of the planted cascades, the rest random over the interval menu
+{0,5,10,20} ms offset x {5,10,20} ms width).  One step = one exact count of
+all 200k candidates over the whole stream, inputs resident in HBM: the batched
+engine (segment-parallel lane machines in persistent launches, one kept
+hipGraph) ordered by the learned cost model (features -> MLP -> device sort ->
+longest-first work items, all inside the graph).  The plain engine, round
+robin and the event-count heuristic are timed beside it on the same inputs.
 
-One step = validate the device-resident stream and build its per-type index,
-then every level: generate candidates, count them on the GPU (one counting
-launch per level), read the counts back and keep the frequent ones.
+Metric: candidate-episode x events counted per second = m * n / step time.
 
-Metric: candidate-episode x events counted per second = sum over levels of
-(candidates of the level x events of the stream) / step time.
+Other lines: ``--mining`` (level-wise discovery of the mining preset),
+``--ablation`` (presets 1, 3, 4, 5: plain vs batched schedules),
+``--tracking-sweep`` (episode-length sweep of the per-event tracking
+engine), ``--calibrate-copy`` (a 1 GiB device copy for the byte counters).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this engine runs on
 one GPU.
@@ -31,8 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # vector-ALU lane operations per second (T)
 PROFILE = "k_ext_walk_mining.md"
 KERNEL_SOURCES = ("epi_extend.hip",)
+LARGE_PROFILE = "k_lane_persistent_large.md"
+LARGE_SOURCES = ("epi_lane.hip", "epi_tiled.hip", "epi_sched.hip", "epi_sort.hip", "epi_count.h")
 THRESHOLD = 100
 MAX_SIZE = 6
 
@@ -41,16 +48,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def profiled(kernel_name, key, field):
+def source_hash(sources):
+    import hashlib
+
+    srcs = [os.path.join(ROOT, "paper_0905_2203_amd", "csrc", f) for f in sources]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
+
+
+def profiled(kernel_name, key, field, profile=PROFILE, sources=KERNEL_SOURCES):
     """A per-launch figure of ``kernel_name`` (line ``key`` of the committed
     rocprofv3 counter summary), or None when the summary is for another
     kernel or the kernel sources changed since the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", PROFILE)
-    srcs = [os.path.join(ROOT, "paper_0905_2203_amd", "csrc", f) for f in KERNEL_SOURCES]
+    path = os.path.join(ROOT, "profiles", profile)
     try:
-        h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
+        h = source_hash(sources)
         for line in open(path):
             if line.startswith(key + ":"):
                 rec = json.loads(line.split(":", 1)[1])
@@ -81,7 +92,7 @@ def _timed(ctx, fn, reps):
     return float(np.median(out))
 
 
-def ablation(k, scale, reps, lane_engine=1):
+def ablation(k, scale, reps, lane_engine=1, ring_classes=0):
     """Plain engine vs the batched persistent engine under round-robin, the
     event-count heuristic and the learned cost model, on workload preset k.
     Every mode's counts are checked equal; one JSON line per preset."""
@@ -90,6 +101,7 @@ def ablation(k, scale, reps, lane_engine=1):
 
     ctx = epi.Context(0)
     ctx.epi_set_option(epi.EPI_OPT_LANE_ENGINE, lane_engine)
+    ctx.epi_set_option(epi.EPI_OPT_RING_CLASSES, ring_classes)
     if k == 3:
         sets = []
         for r in range(16):
@@ -186,6 +198,7 @@ def ablation(k, scale, reps, lane_engine=1):
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s", "lane_engine": lane_engine,
+        "ring_classes": ring_classes,
         "value": {m: units / t for m, t in res.items()},
         "seconds": res,
         "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
@@ -265,13 +278,201 @@ def tracking_sweep(scale, reps, m_per_len=16):
     ctx.close()
 
 
+def alg_bytes(s, c):
+    """Bytes the counting method must read and write for candidate set c on
+    stream s: each candidate reads the times of its own types' events, its
+    descriptor (128 B with int64 times, 72 B with int32) and writes a 4-B count."""
+    tc = np.bincount(s["types"], minlength=s["K"]).astype(np.int64)
+    tsb = 8 if s["ts_kind"] == 1 else 4
+    N = c["N"].astype(np.int64)
+    ty = c["types"].astype(np.int64)
+    per = np.where(np.arange(8)[None, :] < N[:, None], tc[np.clip(ty, 0, None)], 0).sum(axis=1)
+    return int(per.sum()) * tsb + int(N.size) * ((128 if tsb == 8 else 72) + 4)
+
+
+def large_bench(args):
+    """The headline line: the Large workload, batched + learned schedule."""
+    import torch
+
+    import spikegen as sg
+    from paper_0905_2203_amd import epi
+
+    t0 = time.time()
+    s = sg.config_stream(5, scale=args.scale)
+    c = sg.config_candidates(5, s, scale=args.scale)
+    train = sg.random_candidates(sg.rng_for(5, offset=100), max(int(50_000 * args.scale), 64), s["K"], 2, 8,
+                                 s["unit_per_ms"])
+    n, m = int(s["types"].size), int(c["N"].size)
+    log(f"large workload: n={n} K={s['K']} m={m} generated in {time.time() - t0:.1f}s")
+    torch.cuda.init()
+    # every count and every timing event on one stream of our own (default
+    # priority): the events bracket exactly the work the counts queue
+    stream = torch.cuda.Stream()
+    hs = stream.cuda_stream
+    d_types = torch.from_numpy(s["types"]).cuda()
+    d_times = torch.from_numpy(s["times"]).cuda()
+    torch.cuda.synchronize()
+    assert hs != 0, "the count stream must not be the null stream"
+    ctx = epi.Context(0)
+    if args.ring_classes >= 0:
+        ctx.epi_set_option(epi.EPI_OPT_RING_CLASSES, args.ring_classes)
+    sid = ctx.epi_load_stream_device(d_types, d_times, s["K"], hip_stream=hs)
+    cid = ctx.epi_submit_candidates(sid, c)
+    ctx.epi_sync()
+
+    # the cost model: trained once on the work log of a disjoint candidate set
+    # (each episode's own work: no segments)
+    a = time.perf_counter()
+    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)
+    tid = ctx.epi_submit_candidates(sid, train)
+    ctx.epi_count([tid], mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
+    losses = ctx.epi_costmodel_train([tid], epochs=40, seed=7)
+    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
+    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+    ctx.epi_release_set(tid)
+    train_s = time.perf_counter() - a
+    log(f"cost model trained in {train_s:.1f}s (loss {losses[0]:.3f} -> {losses[-1]:.3f})")
+
+    legs = {"batched_learned": (epi.EPI_MODE_BATCHED, epi.EPI_SCHED_LEARNED),
+            "plain": (epi.EPI_MODE_PLAIN, epi.EPI_SCHED_RR),
+            "batched_rr": (epi.EPI_MODE_BATCHED, epi.EPI_SCHED_RR),
+            "batched_heuristic": (epi.EPI_MODE_BATCHED, epi.EPI_SCHED_HEURISTIC)}
+
+    def run(mode, sched, steps, warmup, name):
+        for w in range(warmup):
+            ctx.epi_count([cid], mode=mode, sched=sched, hip_stream=hs)
+            ctx.epi_sync()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record(stream)
+            ctx.epi_count([cid], mode=mode, sched=sched, hip_stream=hs)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ctx.epi_sync()
+        wall = time.perf_counter() - a
+        ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        log(f"  {name}: {np.mean(ms):.1f} ms per count (events), {1e3 * wall / steps:.1f} ms wall")
+        return float(np.mean(ms)), wall
+
+    res, counts = {}, {}
+    # the headline leg: exactly K timed steps after W warm-up steps
+    res["batched_learned"], wall_learned = run(*legs["batched_learned"], args.steps, args.warmup, "batched_learned")
+    counts["batched_learned"] = ctx.epi_read_counts(cid, m)
+    stats = ctx.epi_batched_stats()
+    reps = max(1, min(3, args.steps))
+    for name in ("plain", "batched_rr", "batched_heuristic"):
+        res[name], _ = run(*legs[name], reps, 1, name)
+        counts[name] = ctx.epi_read_counts(cid, m)
+    equal = all(np.array_equal(counts[k], counts["batched_learned"]) for k in counts)
+
+    # parity: every count against the oracle-written expected counts of this
+    # workload, else a seeded sample against the oracle
+    parity = "not checked"
+    got = counts["batched_learned"]
+    try:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from fullsize import cand_fingerprint, stream_fingerprint
+
+        path = os.path.join(ROOT, "tests", "golden", "full_cfg5.npz")
+        if args.scale == 1.0 and os.path.exists(path):
+            z = np.load(path, allow_pickle=False)
+            meta = json.loads(str(z["meta"]))
+            if meta["stream"] == stream_fingerprint(s) and meta["candidates"] == cand_fingerprint(c):
+                bad = int((z["counts"] != got).sum())
+                parity = (f"{'ok' if bad == 0 and equal else 'MISMATCH'}: all {m} counts vs the oracle's "
+                          f"(tests/golden/full_cfg5.npz), {bad} differ; modes agree: {equal}")
+    except Exception as exc:
+        log(f"golden check failed: {exc!r}")
+    cpu = None
+    if not args.no_cpu:
+        try:
+            import oracle
+
+            k = min(args.cpu_sample, m)
+            idx = np.unique(np.linspace(0, m - 1, k).astype(np.int64))
+            cores = oracle.max_threads()
+            a = time.perf_counter()
+            want = oracle.count(s, sg.take_candidates(c, idx), nthreads=cores)
+            el = time.perf_counter() - a
+            bad = int((want != got[idx]).sum())
+            if parity == "not checked":
+                parity = f"{'ok' if bad == 0 and equal else 'MISMATCH'}: {idx.size} sampled counts vs the oracle, {bad} differ"
+            cpu = dict(value=idx.size * n / el, unit="cand*ev/s", cores=cores, kind="oracle",
+                       sample=f"{idx.size} of the {m} candidates (evenly spaced), all {n} events, "
+                              f"decomposition oracle in {el:.1f}s")
+        except Exception as exc:
+            log(f"oracle leg failed: {exc!r}")
+
+    alg = alg_bytes(s, c)
+    t_step = res["batched_learned"] / 1e3
+    achieved = alg / t_step / 1e9
+    kname = "batched count graph (k_lane_persistent per launch class on parallel branches, scheduler, reconcile)"
+    traffic = profiled("batched_learned_graph", "traffic_bytes_per_launch", "bytes", LARGE_PROFILE, LARGE_SOURCES)
+    ctx.epi_release_set(cid)
+    ctx.epi_release_stream(sid)
+    ctx.close()
+    value = m * n / t_step
+    line = {
+        "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
+        "value": value,
+        "unit": "cand*ev/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["batched_learned"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "Large: 256 types, 50M events over 3600 s, int64 ns, Poisson background + 32 planted "
+                        "cascades (3-8 types); 200k candidates of sizes 2-8; batched persistent graph, "
+                        "segment-parallel lane machines, learned cost-model schedule",
+            "scale": args.scale, "events": n, "candidates": m,
+            "mode": "batched + learned schedule",
+        },
+        "modes": {k: {"ms_per_count": v, "cand_ev_per_s": m * n / (v / 1e3)} for k, v in res.items()},
+        "learned_vs_plain": res["plain"] / res["batched_learned"],
+        "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
+        "learned_vs_heuristic": res["batched_heuristic"] / res["batched_learned"],
+        "wall_ms_per_step": 1e3 * wall_learned / args.steps,
+        "graph": {"plans_built": stats["built"], "replays": stats["replays"]},
+        "cost_model": {"train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                       "train_candidates": int(train["N"].size)},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kname,
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes": alg,
+            "per_unit": "per candidate: sum over its nodes of the node type's events x 8 B + 128 B descriptor "
+                        "+ 4 B count; one launch = one count of all candidates",
+        },
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=200_000, help="level-3 candidates timed on the CPU")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="candidates timed on the CPU (default: 384 of the Large workload; 200k level-3 "
+                         "candidates with --mining)")
+    ap.add_argument("--scale", type=float, default=1.0, help="size scale of the Large workload")
+    ap.add_argument("--mining", action="store_true", help="level-wise discovery of the mining preset")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (scale reference for HBM byte counters)")
     ap.add_argument("--ablation", default="",
@@ -279,6 +480,9 @@ def main():
     ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
     ap.add_argument("--lane-engine", type=int, default=1,
                     help="ablation: 1 = register-indexed lane machines where they apply, 0 = LDS-ring machines")
+    ap.add_argument("--ring-classes", type=int, default=-1,
+                    help="batched launch groups per episode size: 0 submission groups, 1 one, 2 three "
+                         "(default: the engine default for the Large line, 0 for --ablation)")
     ap.add_argument("--tracking-sweep", action="store_true",
                     help="episode-length sweep: per-event tracking vs the plain engine, one JSON line per length")
     args = ap.parse_args()
@@ -287,7 +491,7 @@ def main():
         return
     if args.ablation:
         for k in [int(x) for x in args.ablation.split(",") if x]:
-            ablation(k, args.abl_scale, max(1, args.steps), args.lane_engine)
+            ablation(k, args.abl_scale, max(1, args.steps), args.lane_engine, max(0, args.ring_classes))
         return
     if args.calibrate_copy:
         import torch
@@ -303,7 +507,18 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.mining:
+        if args.cpu_sample <= 0:
+            args.cpu_sample = 200_000
+        mining_bench(args)
+        return
+    if args.cpu_sample <= 0:
+        args.cpu_sample = 384
+    large_bench(args)
 
+
+def mining_bench(args):
+    """Level-wise discovery of the mining preset, one JSON line."""
     import torch
 
     import spikegen as sg
@@ -374,6 +589,7 @@ def main():
     mp = len(menu) if len(menu) <= 4 else 8
     kname = f"k_ext_walk<int, {mp}, 0>" if dom >= 2 else "k_level1<int>"
     traffic = profiled_traffic(kname)
+    valu_frac = profiled(kname, "valu_issue_per_launch", "frac")
 
     # parity spot check (outside the timed region): sampled counts vs the oracle
     parity = "not checked"
@@ -438,18 +654,25 @@ def main():
             "mode": "plain",
             "level_ms": {"generate": gen_ms, "count_incl_transfers": cnt_ms, "kernels": kern_ms},
         },
+        # the walk is bound by vector-ALU issue, not by HBM: VALU issue share
+        # = wave-level VALU instructions x 4 cycles over 1024 SIMDs x 2.4 GHz
+        # x the launch time (SQ counters of the committed profile); the peak
+        # is 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": f"{kname} (level {dom}, {cand_per_level[dom - 1]} candidates)",
-            "achieved": achieved_gbs,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": achieved_gbs / PEAK_HBM_GBS,
+            "achieved": None if valu_frac is None else valu_frac * PEAK_VALU_TOPS,
+            "peak": PEAK_VALU_TOPS,
+            "unit": "T lane-ops/s (VALU)",
+            "frac": valu_frac,
             "traffic": traffic,
-            "algorithmic_bytes": alg,
-            # the walk's own limit: wave-level VALU instructions x 4 cycles over
-            # 1024 SIMDs x 2.4 GHz x the launch time (SQ counters, same profile)
-            "valu_issue_frac": profiled(kname, "valu_issue_per_launch", "frac"),
+            # bytes the walk must read (walked stream positions x (type + time)
+            # + chain entries), over the kernel time: the walk shares one
+            # stream walk among all extensions of a parent, so this is not the
+            # per-candidate byte count of the state machines
+            "walked_bytes": alg,
+            "walked_GBps": achieved_gbs,
+            "walked_frac_of_hbm_peak": achieved_gbs / PEAK_HBM_GBS,
         },
         "cpu_baseline": cpu,
         "parity": parity,

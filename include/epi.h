@@ -282,13 +282,23 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
  *                         times relative to the tile; 0 = every group on the
  *                         machines with all their state in LDS (each ring as
  *                         deep as the episode's deepest)
+ *   EPI_OPT_RING_CLASSES  batched mode: how episodes of one size form launch
+ *                         groups (each group's episodes are ordered by cost
+ *                         and cut into lane blocks, and its interval rings
+ *                         take the group's largest): 0 (default) = the
+ *                         submission groups (size x ring-entries class of
+ *                         1, 2, ... 112 entries), 1 = one group per size,
+ *                         2 = three per size (ring entries per interval on
+ *                         average <= 2, <= 3, more); fewer groups let the
+ *                         cost order pack lanes of closer work into a wave
+ *                         at a larger LDS footprint
  * EPI_EINVAL for an unknown option or value.  Counts never depend on the
  * engine options (EPI_OPT_ALLOW_REPEATS only widens what is accepted;
  * EPI_OPT_STREAM_ORDER selects the other overlap semantics). */
 enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OPT_PAIR_FILTER = 4,
        EPI_OPT_MINE_ENGINE = 5, EPI_OPT_WORKLOG = 6, EPI_OPT_TARGET_ITEMS = 7, EPI_OPT_MINE_LIST_BYTES = 8,
        EPI_OPT_ALLOW_REPEATS = 9, EPI_OPT_MINE_LIST_ALPHAS = 10, EPI_OPT_STREAM_ORDER = 11,
-       EPI_OPT_LANE_ENGINE = 12 };
+       EPI_OPT_LANE_ENGINE = 12, EPI_OPT_RING_CLASSES = 13 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Autotune the batched engine for these sets and schedule: time every
@@ -320,6 +330,24 @@ epi_status epi_read_worklog(epi_ctx *ctx, int32_t set_id, int32_t *work, int64_t
  * of the last batched count that included this set (cycles[n_items][2]);
  * with cycles = null only *n_out receives the number of items. */
 epi_status epi_read_item_cycles(epi_ctx *ctx, int32_t set_id, int64_t *cycles, int64_t n_items, int64_t *n_out);
+
+/* Batched plans of the context: *plans_built = plans captured and
+ * instantiated so far, *replays = batched counts that launched a kept plan
+ * again (no capture, no instantiation, no host scheduling), *plans_kept =
+ * plans held now (at most 8, least recently used dropped first).  A plan is
+ * kept per (set list, schedule, options, cost model); releasing a set drops
+ * the plans that count it, appending to or releasing a stream drops all.
+ * Any pointer may be null. */
+epi_status epi_batched_stats(epi_ctx *ctx, int64_t *plans_built, int64_t *replays, int64_t *plans_kept);
+
+/* The lane order of the set's last batched count (while its plan is kept;
+ * EPI_ESTATE otherwise): order[i] = submission index of the episode counted
+ * in lane slot i, block[i] = the workgroup-sized lane block of slot i (blocks
+ * numbered per set; lanes 64 at a time form the waves of a block; -1: the
+ * slot is counted by the tracking engine).  Blocks the scheduler ordered by
+ * cost hold episodes of similar predicted work, the divergence of Sec. V-C
+ * that the schedule attacks.  order and block are host arrays of m. */
+epi_status epi_read_schedule(epi_ctx *ctx, int32_t set_id, int32_t *order, int32_t *block, int64_t m);
 
 /* Device pointer to a set's counts (int32[m], submission order), valid until
  * the set is released; contents are defined once the count's stream work is
@@ -367,13 +395,15 @@ epi_status epi_mlp_train(epi_ctx *ctx, const float *X, const float *t, int64_t B
 /* Train the cost model on sets counted with the work log on (best without
  * time segments, EPI_OPT_SEGMENTS = 1, so each episode's logged work is its
  * own): features x of each episode -> t = log1p(events visited + records +
- * queries).  Features and target are standardised on the training set
+ * queries) - x[23], the correction of log work relative to the log of the
+ * summed event counts of the episode's types (feature 23, the event-count
+ * heuristic).  Features and target are standardised on the training set
  * (x' = (x - x_mu) * x_isd with x_isd = 1 / standard deviation, 0 for a
  * constant feature; t' = (t - y_mu) / y_sd), shuffled once, and a fresh model
  * seeded by `seed` is trained on (x', t') for `epochs` passes of Adam
  * (lr 3e-3, mini-batches of 512); losses[epochs] (may be null) receives the
  * epoch losses in standardised units (1 = the target's variance).  The
- * cost model's prediction is then y_sd * net(x') + y_mu. */
+ * cost model's prediction of log1p(work) is then x[23] + y_sd * net(x') + y_mu. */
 epi_status epi_costmodel_train(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int32_t epochs, uint64_t seed,
                                float *losses);
 
@@ -383,7 +413,7 @@ epi_status epi_costmodel_scaling(epi_ctx *ctx, float *x_mu, float *x_isd, float 
 
 /* Save the cost model (parameters and standardisation) to a file / load it
  * into the context (replacing any model; Adam state cleared).  The file is
- * binary: "EPICM001", int32 F, int64 n_params, float params[n_params],
+ * binary: "EPICR001", int32 F, int64 n_params, float params[n_params],
  * float x_mu[F], float x_isd[F], float y_mu, float y_sd, host byte order.
  * EPI_ESTATE when saving without a model; EPI_EINVAL for a path that cannot
  * be opened or a file that is not exactly this layout. */

@@ -292,6 +292,7 @@ void epi_destroy(epi_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->c.device);
     (void)hipDeviceSynchronize();
+    ctx->c.batch.clear();
     ctx->c.mines.clear();
     ctx->c.sets.clear();
     ctx->c.streams.clear();
@@ -435,6 +436,7 @@ epi_status epi_release_stream(epi_ctx *ctx, int32_t stream_id) {
     for (auto &kv : ctx->c.sets)
         if (kv.second->stream_id == stream_id)
             return fail(ctx, EPI_ESTATE, "stream %d still has candidate set %d", stream_id, kv.first);
+    ctx->c.batch.evict_all();
     (void)hipDeviceSynchronize();
     ctx->c.streams.erase(stream_id);
     return EPI_OK;
@@ -505,6 +507,7 @@ epi_status epi_submit_candidates(epi_ctx *ctx, int32_t stream_id, int64_t m, con
 epi_status epi_release_set(epi_ctx *ctx, int32_t set_id) {
     if (!ctx) return EPI_EINVAL;
     if (!find_set(ctx, set_id)) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    ctx->c.batch.evict_set(set_id);
     (void)hipDeviceSynchronize();
     ctx->c.sets.erase(set_id);
     return EPI_OK;
@@ -526,7 +529,7 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
             return fail(ctx, EPI_EINVAL, "set %d decides overlap in stream order: count it with EPI_MODE_TRACKING",
                         set_ids[i]);
         if (mode == EPI_MODE_BATCHED && sched == EPI_SCHED_MEASURED && !(cs->counted && cs->logged) &&
-            (int64_t)cs->measured.size() != cs->m)
+            !cs->has_measured)
             return fail(ctx, EPI_ESTATE, "set %d has no work log to schedule by", set_ids[i]);
     }
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
@@ -585,17 +588,10 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
         for (int32_t i = 0; i < k; ++i) {
             CandSet *cs = find_set(ctx, set_ids[i]);
             if (!(cs->counted && cs->logged)) continue;
-            std::vector<int32_t> w((size_t)cs->m * kWork), orig(cs->m);
-            if (cs->m > 0) {
-                HIPTRY(ctx, hipStreamSynchronize(st), "sync");
-                HIPTRY(ctx, hipMemcpy(w.data(), cs->work.p, sizeof(int32_t) * w.size(), hipMemcpyDeviceToHost), "copy");
-                HIPTRY(ctx, hipMemcpy(orig.data(), cs->orig.p, sizeof(int32_t) * cs->m, hipMemcpyDeviceToHost), "copy");
-            }
-            cs->measured.resize(cs->m);
-            for (int64_t j = 0; j < cs->m; ++j) {
-                const int32_t *x = w.data() + (int64_t)orig[j] * kWork;
-                cs->measured[j] = (float)x[0] + (float)x[1] + (float)x[2];
-            }
+            if (cs->dmeasured.bytes < sizeof(float) * (size_t)std::max<int64_t>(cs->m, 1))
+                HIPTRY(ctx, cs->dmeasured.alloc(sizeof(float) * std::max<int64_t>(cs->m, 1)), "measured costs");
+            HIPTRY(ctx, measured_costs(*cs, st), "measured costs");
+            cs->has_measured = true;
         }
     }
     // work log: cleared before the count
@@ -610,6 +606,7 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
     }
     if (mode == EPI_MODE_BATCHED) {
         std::vector<BatchRef> refs;
+        std::vector<int32_t> ids(set_ids, set_ids + k);
         int kind = -1;
         for (int32_t i = 0; i < k; ++i) {
             CandSet *cs = find_set(ctx, set_ids[i]);
@@ -619,7 +616,9 @@ epi_status epi_count(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int mode, 
             kind = s->ts_kind;
             refs.push_back(BatchRef{s, cs});
         }
-        HIPTRY(ctx, launch_count_batched(refs, sched, ctx->c.opt, ctx->c.mlp, ctx->c.flags.as<int32_t>(), st),
+        HIPTRY(ctx,
+               launch_count_batched(refs, ids, sched, ctx->c.opt, ctx->c.mlp, ctx->c.batch, ctx->c.flags.as<int32_t>(),
+                                    st),
                "batched count");
         for (auto &r : refs) {
             HIPTRY(ctx, count_deep_subset(*r.s, *r.c, st), "counting deep episodes");
@@ -671,8 +670,10 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
                             "mining run %d: appended times +- its longest span leave the timestamp type", kv.first);
     }
     HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
-    // the work queued on the stream's arrays ends before they are replaced
+    // the work queued on the stream's arrays ends before they are replaced;
+    // batched plans over the old arrays are dropped
     HIPTRY(ctx, hipDeviceSynchronize(), "sync");
+    ctx->c.batch.evict_all();
     const size_t tb = s->ts_bytes();
     DevBuf ty, tm;
     HIPTRY(ctx, ty.alloc(sizeof(int32_t) * (size_t)(s->n + n)), "allocating stream types");
@@ -744,6 +745,10 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value) {
         case EPI_OPT_LANE_ENGINE:
             if (value != 0 && value != 1) return fail(ctx, EPI_EINVAL, "lane engine must be 0 or 1");
             ctx->c.opt.lane_engine = value != 0;
+            return EPI_OK;
+        case EPI_OPT_RING_CLASSES:
+            if (value < 0 || value > 2) return fail(ctx, EPI_EINVAL, "ring classes must be 0, 1 or 2");
+            ctx->c.opt.ring_classes = (int)value;
             return EPI_OK;
         default:
             return fail(ctx, EPI_EINVAL, "unknown option %d", option);
@@ -1174,14 +1179,16 @@ epi_status epi_read_item_cycles(epi_ctx *ctx, int32_t set_id, int64_t *cycles, i
     if (!ctx) return EPI_EINVAL;
     CandSet *cs = find_set(ctx, set_id);
     if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
-    if (n_out) *n_out = cs->cycles.p ? cs->n_items : 0;
+    const BatchPlan *pl = cs->cycles_plan ? ctx->c.batch.find_id(cs->cycles_plan) : nullptr;
+    const bool have = pl && pl->cycles.p;
+    if (n_out) *n_out = have ? pl->n_items : 0;
     if (!cycles) return EPI_OK;
-    if (!cs->cycles.p || n_items != cs->n_items)
+    if (!have || n_items != pl->n_items)
         return fail(ctx, EPI_EINVAL, "the last batched count of set %d stamped %lld items", set_id,
-                    (long long)(cs->cycles.p ? cs->n_items : 0));
+                    (long long)(have ? pl->n_items : 0));
     epi_status f = epi_sync(ctx);
     if (f != EPI_OK) return f;
-    HIPTRY(ctx, hipMemcpy(cycles, cs->cycles.p, sizeof(int64_t) * 2 * n_items, hipMemcpyDeviceToHost), "copy");
+    HIPTRY(ctx, hipMemcpy(cycles, pl->cycles.p, sizeof(int64_t) * 2 * n_items, hipMemcpyDeviceToHost), "copy");
     return EPI_OK;
 }
 
@@ -1200,9 +1207,12 @@ epi_status epi_costmodel_train(epi_ctx *ctx, const int32_t *set_ids, int32_t k, 
         v = epi_read_worklog(ctx, set_ids[i], w.data(), cs->m);
         if (v != EPI_OK) return v;
         X.insert(X.end(), Xi.begin(), Xi.end());
-        // target: log1p of the lane's work (events visited + state-machine operations)
+        // target: log1p of the lane's work (events visited + state-machine
+        // operations) less the base feature, log1p of the summed event counts
+        // of the episode's types (the network learns the correction to it)
         for (int64_t c = 0; c < cs->m; ++c)
-            t.push_back(std::log1p((float)w[c * kWork + 0] + (float)w[c * kWork + 1] + (float)w[c * kWork + 2]));
+            t.push_back(std::log1p((float)w[c * kWork + 0] + (float)w[c * kWork + 1] + (float)w[c * kWork + 2]) -
+                        Xi[c * kFeatures + kBaseFeature]);
     }
     const int64_t B = (int64_t)t.size();
     // shuffle once (SplitMix64-driven Fisher-Yates) so mini-batches mix sets
@@ -1270,7 +1280,7 @@ epi_status epi_costmodel_scaling(epi_ctx *ctx, float *x_mu, float *x_isd, float 
 }
 
 namespace {
-constexpr char kModelMagic[8] = {'E', 'P', 'I', 'C', 'M', '0', '0', '1'};
+constexpr char kModelMagic[8] = {'E', 'P', 'I', 'C', 'R', '0', '0', '1'};
 }
 
 epi_status epi_costmodel_save(epi_ctx *ctx, const char *path) {
@@ -1463,6 +1473,49 @@ epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sch
     if (chosen) {
         chosen[0] = lanes;
         chosen[1] = per_cu;
+    }
+    return EPI_OK;
+}
+
+epi_status epi_batched_stats(epi_ctx *ctx, int64_t *plans_built, int64_t *replays, int64_t *plans_kept) {
+    if (!ctx) return EPI_EINVAL;
+    if (plans_built) *plans_built = ctx->c.batch.built;
+    if (replays) *replays = ctx->c.batch.replays;
+    if (plans_kept) *plans_kept = (int64_t)ctx->c.batch.plans.size();
+    return EPI_OK;
+}
+
+epi_status epi_read_schedule(epi_ctx *ctx, int32_t set_id, int32_t *order, int32_t *block, int64_t m) {
+    if (!ctx) return EPI_EINVAL;
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (m != cs->m || (m > 0 && (!order || !block)))
+        return fail(ctx, EPI_EINVAL, "set %d holds %lld candidates", set_id, (long long)cs->m);
+    const BatchPlan *pl = cs->last_plan ? ctx->c.batch.find_id(cs->last_plan) : nullptr;
+    if (!pl) return fail(ctx, EPI_ESTATE, "set %d has no kept batched schedule", set_id);
+    int si = -1;
+    for (size_t i = 0; i < pl->set_ids.size(); ++i)
+        if (pl->set_ids[i] == set_id) si = (int)i;
+    if (si < 0) return fail(ctx, EPI_ESTATE, "set %d has no kept batched schedule", set_id);
+    epi_status f = epi_sync(ctx);
+    if (f != EPI_OK) return f;
+    if (m == 0) return EPI_OK;
+    std::vector<int32_t> orig(m), perm(m);
+    HIPTRY(ctx, hipMemcpy(orig.data(), cs->orig.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "copy");
+    if (pl->perm)
+        HIPTRY(ctx, hipMemcpy(perm.data(), pl->perm + pl->soff[si], sizeof(int32_t) * m, hipMemcpyDeviceToHost),
+               "copy");
+    else
+        std::iota(perm.begin(), perm.end(), 0);
+    for (int64_t i = 0; i < m; ++i) {
+        order[i] = orig[perm[i]];
+        block[i] = -1;
+    }
+    int32_t nb = 0;
+    for (const auto &u : pl->uview) {
+        if (u.set != si) continue;
+        for (int64_t i = 0; i < u.G; ++i) block[u.begin + i] = nb + (int32_t)(i / u.W);
+        nb += (int32_t)((u.G + u.W - 1) / u.W);
     }
     return EPI_OK;
 }

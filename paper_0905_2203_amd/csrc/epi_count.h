@@ -63,6 +63,47 @@ struct WorkItem {
     int64_t blk;
 };
 
+// ---- device scheduler of the batched count (epi_sched.hip) -------------------
+// One set of a batched count, as the scheduler kernels see it.
+struct SchedSet {
+    const int32_t *type_off;  // the stream's per-type offsets [K+1]
+    const int32_t *ctypes;    // grouped types [8][m]
+    const void *clo, *chi;    // grouped bounds [7][m] (the stream's time type)
+    const float *measured;    // logged work per grouped slot (null: none)
+    int64_t m;
+    int64_t off;              // the set's first slot in the count's global slot order
+};
+// One launch group (set, episode size) of the global slot order.
+struct SchedGroup {
+    int32_t set;
+    int32_t N;
+};
+// One unit of the batched count: its first global slot, size, the lane width
+// of its launch class, its segments and the rank of its launch class.
+struct SchedUnit {
+    int64_t gbase;
+    int64_t G;
+    int32_t W;
+    int32_t P;
+    int32_t cls;
+    int32_t pad;
+};
+// Cost of every global slot into y: the cost model's log-work prediction
+// (EPI_SCHED_LEARNED; X: feature scratch [M][kFeatures]), the summed event
+// counts of the types (EPI_SCHED_HEURISTIC) or the logged work (EPI_SCHED_MEASURED).
+hipError_t sched_costs(int ts_kind, int sched, const SchedSet *sets, const SchedGroup *groups, const int32_t *gid,
+                       int64_t M, Mlp &mlp, float *X, float *y, hipStream_t st);
+// Sort keys (group, descending cost) and values (local slot) of every global slot.
+hipError_t sched_keys(const SchedSet *sets, const SchedGroup *groups, const int32_t *gid, int64_t M, const float *y,
+                      bool log_cost, uint64_t *key, int32_t *val, hipStream_t st);
+// Sort keys (class rank, descending cost) and values (index) of the work items
+// tmpl, from the candidates' sorted keys skey.
+hipError_t sched_item_keys(const WorkItem *tmpl, int64_t n, const SchedUnit *units, const uint64_t *skey,
+                           uint64_t *key, int32_t *val, hipStream_t st);
+hipError_t sched_gather_items(const WorkItem *tmpl, const int32_t *idx, int64_t n, WorkItem *out, hipStream_t st);
+// c.dmeasured = each grouped slot's logged work (visits + records + queries).
+hipError_t measured_costs(const CandSet &c, hipStream_t st);
+
 // ---- register-indexed lane machines (epi_lane.hip) --------------------------
 // A group of episodes can be counted by them when the stream's tiles are
 // short enough for int32 relative times (lane_rel_ok) and every interval's

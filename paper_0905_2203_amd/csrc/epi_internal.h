@@ -21,6 +21,7 @@ constexpr int kTile = 2048;        // largest number of events per stream tile (
 constexpr int kMinTile = 256;      // smallest tile a stream may pick
 constexpr int kMlpHidden = 64;     // hidden units of the cost model
 constexpr int kFeatures = 24;      // cost-model features per candidate
+constexpr int kBaseFeature = 23;   // the cost model predicts log work as this feature + the network's correction
 constexpr int kWork = 5;           // work-log counters per candidate
 
 // Device error flags (int32 each), set by kernels with atomicOr / atomicAdd.
@@ -226,10 +227,12 @@ struct CandSet {
     int64_t counted_n = -1;  // stream events covered by the counts (-1: never counted)
     DevBuf scratch; // per-segment speculative records of the last count
     DevBuf work;    // work log: int32 [m][kWork] (submission order) when enabled
-    DevBuf cycles;  // work log: int64 [items][2] wall-clock start/end of the last count
     int64_t n_items = 0;  // work items of the last count
     bool logged = false;  // the last count recorded a work log
-    std::vector<float> measured;  // EPI_SCHED_MEASURED: logged work per grouped slot, taken before the count
+    DevBuf dmeasured;             // EPI_SCHED_MEASURED: logged work per grouped slot (float [m]), taken before a count resets the log
+    bool has_measured = false;
+    uint64_t cycles_plan = 0;     // batched plan whose per-item times the work log of the last count keeps (0: none)
+    uint64_t last_plan = 0;       // batched plan of the last batched count that included the set (0: none)
     // Compact layout (level-wise mining): one episode size, types uint16
     // [N][m], interval ids uint8 [N-1][m] into a menu of (lo, hi) pairs
     // (T[2*n_menu]); slots are in submission order (orig unused).
@@ -274,6 +277,7 @@ struct CountOptions {
     int64_t mine_list_alphas = 65536;  // extension engine: list path below this many parent episodes
     bool stream_order = false;     // sets submitted now decide overlap in stream order
     bool lane_engine = true;       // state machines: register-indexed lane machines where they apply
+    int ring_classes = 0;          // batched mode: 0 submission groups, 1 one group per size, 2 three per size
 };
 
 // One level of a level-wise discovery run: candidates of size N in
@@ -360,6 +364,65 @@ struct Mlp {
     bool ready() const { return p.p != nullptr; }
 };
 
+// A batched count, planned once and kept as an instantiated graph: the
+// scheduler kernels (costs, device sorts, item order), the queue clear, the
+// persistent launches (parallel branches) and the reconciliation.  A later
+// count of the same sets, schedule and options replays it.
+struct BatchPlan {
+    std::vector<int64_t> key;      // identity (sets, streams, buffers, options, schedule, model)
+    std::vector<int32_t> set_ids;
+    uint64_t id = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevBuf units, tmpl, items, queue, rec, cycles;
+    DevBuf ssets, sgroups, gid, sunits, X, y, k0, k1, v0, v1, ik0, ik1, iv0, iv1, hist;
+    int64_t n_items = 0;
+    int64_t launches = 0;
+    // the schedule, for reading back: each set's first global slot, the
+    // permutation buffer (null: submission order within each group) and the
+    // units' (set, first slot, size, lane width)
+    std::vector<int64_t> soff;
+    const int32_t *perm = nullptr;
+    struct UnitView {
+        int set;
+        int64_t begin, G;
+        int W;
+    };
+    std::vector<UnitView> uview;
+    BatchPlan() = default;
+    BatchPlan(const BatchPlan &) = delete;
+    BatchPlan &operator=(const BatchPlan &) = delete;
+    ~BatchPlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// The context's batched plans (most recently used last) and the branch
+// streams and events the plans' graphs were captured with (created once).
+struct BatchCache {
+    static constexpr size_t kMaxPlans = 8;
+    static constexpr int kBranches = 4;
+    std::vector<std::unique_ptr<BatchPlan>> plans;
+    hipStream_t br[kBranches] = {};
+    hipEvent_t joined[kBranches] = {};
+    hipEvent_t fork = nullptr;
+    uint64_t next_id = 1;
+    int64_t built = 0;     // plans captured and instantiated
+    int64_t replays = 0;   // graph launches of a kept plan
+    BatchCache() = default;
+    BatchCache(const BatchCache &) = delete;
+    BatchCache &operator=(const BatchCache &) = delete;
+    ~BatchCache() { clear(); }
+    hipError_t branches();
+    BatchPlan *find(const std::vector<int64_t> &key);
+    BatchPlan *find_id(uint64_t id);
+    // plans are dropped only after the device is idle (their graphs may run)
+    void evict_set(int32_t id);
+    void evict_all();
+    void clear();
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -375,6 +438,7 @@ struct Ctx {
     DevBuf flags;  // int32[kNumFlags]
     CountOptions opt;
     Mlp mlp;
+    BatchCache batch;
 };
 
 // Queue capacity bound of one constraint (lo, hi]: at most
@@ -388,7 +452,15 @@ inline int64_t queue_bound(int64_t lo, int64_t hi) {
 hipError_t build_type_index(Stream &s, hipStream_t st);
 hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, int64_t n, int ts_kind,
                                   int32_t K, int32_t *d_flags, hipStream_t st);
-hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st);
+// ext_scratch (optional): device memory of ext_bytes for the segment records,
+// used instead of the set's own (then nothing is allocated and nothing waits
+// on the host; hipErrorOutOfMemory if a group's records do not fit).
+hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st,
+                        unsigned char *ext_scratch = nullptr, size_t ext_bytes = 0);
+// Segments of a plain count of a group of G episodes on stream s (and the
+// tiles per segment, *S_out), and the bytes of its segment records.
+int64_t plain_segments(const Stream &s, int64_t G, const CountOptions &opt, int64_t *S_out);
+size_t plain_record_bytes(const Stream &s, int64_t P, int64_t G);
 // Count set c by per-event tracking of each episode's nodes and the greedy
 // over the latest-start intervals (epi_track.hip); returns when done.
 hipError_t launch_count_tracking(const Stream &s, CandSet &c, hipStream_t st);
@@ -408,8 +480,11 @@ struct BatchRef {
     const Stream *s;
     CandSet *c;
 };
-hipError_t launch_count_batched(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp,
-                                int32_t *d_flags, hipStream_t st);
+// ids: the sets' ids (plan identity).  Returns after queuing the graph on st
+// (asynchronous).
+hipError_t launch_count_batched(std::vector<BatchRef> &sets, const std::vector<int32_t> &ids, int sched,
+                                const CountOptions &opt, Mlp &mlp, BatchCache &cache, int32_t *d_flags,
+                                hipStream_t st);
 // Count every candidate of one mining level on the device (compact layout);
 // fills L.counts and the timing fields.
 hipError_t count_mine_level(const Stream &s, const Mine &mn, MineLevel &L, const CountOptions &opt, int32_t *d_flags,

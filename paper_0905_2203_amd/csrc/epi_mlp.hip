@@ -14,8 +14,9 @@
 // k_mlp_reduce: one thread per parameter; sums its gradient over the batch in
 //   a fixed order (deterministic), e.g. dL/dW2[a][j] = sum_i h1[i][a] dz2[i][j].
 // k_mlp_adam:   one thread per parameter; Adam step k.
-// k_standardize, k_affine: the cost model's input and output scaling around
-//   the network, (x - mu) * isd per feature and y * sd + mu.
+// k_standardize, k_affine_base: the cost model's input and output scaling
+//   around the network, (x - mu) * isd per feature and y * sd + mu, plus the
+//   raw base feature (the network predicts the correction to it).
 #include <cmath>
 #include <vector>
 
@@ -133,9 +134,19 @@ __global__ void k_standardize(float *__restrict__ X, int64_t n, int F, const flo
     X[q] = (X[q] - norm[f]) * norm[F + f];
 }
 
-__global__ void k_affine(float *__restrict__ y, int64_t n, float sd, float mu) {
+// y = y * sd + mu + x_base, where x_base is the raw value of input feature
+// `base` of the sample (recovered from the standardised Xs: x = x' / isd + mu;
+// a constant feature, isd = 0, is its mean); base < 0: no base term.
+__global__ void k_affine_base(float *__restrict__ y, int64_t n, float sd, float mu, const float *__restrict__ Xs,
+                              int F, const float *__restrict__ norm, int base) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) y[q] = fmaf(y[q], sd, mu);
+    if (q >= n) return;
+    float b = 0.f;
+    if (base >= 0) {
+        const float isd = norm[F + base], m = norm[base];
+        b = isd > 0.f ? Xs[q * F + base] / isd + m : m;
+    }
+    y[q] = fmaf(y[q], sd, mu) + b;
 }
 
 }  // namespace
@@ -161,7 +172,9 @@ hipError_t costmodel_predict_device(Mlp &net, float *dX, int64_t B, float *dy, h
     hipError_t e;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mlp_forward_device(net, dX, B, dy, st)) != hipSuccess) return e;
-    k_affine<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(dy, B, net.y_sd, net.y_mu);
+    k_affine_base<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(dy, B, net.y_sd, net.y_mu, dX, net.F,
+                                                                net.norm.as<float>(),
+                                                                net.F > kBaseFeature ? kBaseFeature : -1);
     return hipGetLastError();
 }
 

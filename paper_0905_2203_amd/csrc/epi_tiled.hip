@@ -41,9 +41,11 @@
 #include <numeric>
 #include <vector>
 
+#include <cstring>
 #include <type_traits>
 
 #include "epi_count.h"
+#include "epi_sort.h"
 
 namespace epi {
 
@@ -959,7 +961,8 @@ bool lane_group_ok(const Stream &s, const CandSet &c, const Group &g, const Coun
 }
 
 template <typename T>
-hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st) {
+hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st,
+                   unsigned char *ext_scratch, size_t ext_bytes) {
     hipError_t e;
     for (const Group &g : c.groups) {
         const int64_t G = g.end - g.begin;
@@ -985,23 +988,8 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         const LaneLayout LL = lane_layout(C, W, s.K, s.T);
         const uint32_t lds = lane ? LL.total : L.total;
         if (lds > kLdsHard) return hipErrorInvalidConfiguration;
-        // segments
-        int64_t P = 1;
-        if (opt.segments > 0) {
-            P = opt.segments;
-        } else if (opt.segments == 0) {
-            const int64_t target = opt.target_lanes;
-            P = G >= target ? 1 : (target + G - 1) / G;
-        }
-        // at most one segment per 4 tiles (the look-back before each segment
-        // start is re-read), and within the grid's y limit
-        const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
-        if (opt.segments == 0 && P > pmax) P = pmax;
-        if (P > s.B) P = s.B;
-        if (P > 65535) P = 65535;
-        if (P < 1) P = 1;
-        const int64_t S = (s.B + P - 1) / P;
-        P = (s.B + S - 1) / S;
+        int64_t S = 1;
+        int64_t P = plain_segments(s, G, opt, &S);
 
         CountArgs<T> a{};
         a.tiled = s.tiled_ts.as<T>();
@@ -1046,11 +1034,18 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         }
         if (P > 1) {
             const size_t need = record_bytes<T>(P, G);
-            if (c.scratch.bytes < need) {
-                if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-                if ((e = c.scratch.alloc(need)) != hipSuccess) return e;
+            if (ext_scratch) {
+                // the caller's scratch (no allocation); groups run one after
+                // another on st, so each reuses it from the start
+                if (need > ext_bytes) return hipErrorOutOfMemory;
+                set_records<T>(a, ext_scratch, P, G);
+            } else {
+                if (c.scratch.bytes < need) {
+                    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+                    if ((e = c.scratch.alloc(need)) != hipSuccess) return e;
+                }
+                set_records<T>(a, c.scratch.as<unsigned char>(), P, G);
             }
-            set_records<T>(a, c.scratch.as<unsigned char>(), P, G);
         }
         a.pbits = filtered ? c.pred_bits : nullptr;
         a.sbits = filtered ? c.succ_bits : nullptr;
@@ -1118,9 +1113,36 @@ hipError_t launch_count_append(const Stream &s, CandSet &c, int64_t B, int32_t *
     return count_append_t<int32_t>(s, c, B, d_flags, st);
 }
 
-hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st) {
-    if (s.ts_kind == EPI_TS_I64) return count_t<int64_t>(s, c, opt, d_flags, st);
-    return count_t<int32_t>(s, c, opt, d_flags, st);
+hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st,
+                        unsigned char *ext_scratch, size_t ext_bytes) {
+    if (s.ts_kind == EPI_TS_I64) return count_t<int64_t>(s, c, opt, d_flags, st, ext_scratch, ext_bytes);
+    return count_t<int32_t>(s, c, opt, d_flags, st, ext_scratch, ext_bytes);
+}
+
+int64_t plain_segments(const Stream &s, int64_t G, const CountOptions &opt, int64_t *S_out) {
+    int64_t P = 1;
+    if (opt.segments > 0) {
+        P = opt.segments;
+    } else if (opt.segments == 0) {
+        const int64_t target = opt.target_lanes;
+        P = G >= target ? 1 : (target + G - 1) / G;
+    }
+    // at most one segment per 4 tiles (the look-back before each segment
+    // start is re-read), and within the grid's y limit
+    const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
+    if (opt.segments == 0 && P > pmax) P = pmax;
+    if (P > s.B) P = s.B;
+    if (P > 65535) P = 65535;
+    if (P < 1) P = 1;
+    const int64_t S = (std::max<int64_t>(s.B, 1) + P - 1) / P;
+    P = (s.B + S - 1) / S;
+    if (P < 1) P = 1;
+    if (S_out) *S_out = S;
+    return P;
+}
+
+size_t plain_record_bytes(const Stream &s, int64_t P, int64_t G) {
+    return P > 1 ? (s.ts_kind == EPI_TS_I64 ? record_bytes<int64_t>(P, G) : record_bytes<int32_t>(P, G)) : 0;
 }
 
 }  // namespace epi
@@ -1158,170 +1180,196 @@ PFn<T> pick_persistent_f(int N, bool rel) {
     return pick_persistent_rf<T, F, false>(N);
 }
 
-// Per-candidate predicted costs (grouped slot order) for the learned or the
-// heuristic schedule; empty when the schedule is round robin.
-hipError_t predicted_costs(const Stream &s, const CandSet &c, int sched, Mlp &mlp, hipStream_t st,
-                           std::vector<float> &cost) {
-    cost.clear();
-    if (sched == EPI_SCHED_RR || c.m == 0) return hipSuccess;
-    if (sched == EPI_SCHED_LEARNED && !(mlp.ready() && mlp.F == kFeatures)) return hipSuccess;  // fallback: RR
-    if (sched == EPI_SCHED_MEASURED) {
-        if ((int64_t)c.measured.size() == c.m) cost = c.measured;
-        return hipSuccess;
-    }
-    hipError_t e;
-    DevBuf dX;
-    if ((e = dX.alloc(sizeof(float) * c.m * kFeatures)) != hipSuccess) return e;
-    if ((e = candidate_features(s, c, dX.as<float>(), st)) != hipSuccess) return e;
-    cost.assign(c.m, 0.f);
+// Identity of a batched plan: everything its graph bakes in (buffers, sizes,
+// launch groups, options, schedule and, for the learned schedule, the model's
+// buffers and output scaling).
+std::vector<int64_t> plan_key(const std::vector<BatchRef> &sets, const std::vector<int32_t> &ids, int sched,
+                              const CountOptions &opt, const Mlp &mlp, const int32_t *d_flags) {
+    std::vector<int64_t> k;
+    auto P = [&](const void *p) { k.push_back((int64_t)(intptr_t)p); };
+    k.push_back(sched);
+    k.push_back(opt.segments);
+    k.push_back(opt.lanes);
+    k.push_back(opt.target_lanes);
+    k.push_back(opt.worklog);
+    k.push_back(opt.lane_engine);
+    k.push_back(opt.ring_classes);
+    P(d_flags);
     if (sched == EPI_SCHED_LEARNED) {
-        DevBuf dy;
-        if ((e = dy.alloc(sizeof(float) * c.m)) != hipSuccess) return e;
-        if ((e = costmodel_predict_device(mlp, dX.as<float>(), c.m, dy.as<float>(), st)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(cost.data(), dy.p, sizeof(float) * c.m, hipMemcpyDeviceToHost, st)) != hipSuccess)
-            return e;
-        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-        for (float &x : cost) x = std::exp(std::min(x, 60.f));  // the model predicts log1p(work)
-    } else {
-        std::vector<float> X((size_t)c.m * kFeatures);
-        if ((e = hipMemcpy(X.data(), dX.p, sizeof(float) * X.size(), hipMemcpyDeviceToHost)) != hipSuccess) return e;
-        for (int64_t i = 0; i < c.m; ++i) {
-            double v = 0;
-            for (int k = 0; k < 8; ++k) v += std::expm1((double)X[i * kFeatures + k]);
-            cost[i] = (float)v;
+        k.push_back(mlp.ready() ? mlp.F : -1);
+        P(mlp.p.p);
+        P(mlp.norm.p);
+        uint32_t a, b;
+        std::memcpy(&a, &mlp.y_mu, 4);
+        std::memcpy(&b, &mlp.y_sd, 4);
+        k.push_back(((int64_t)a << 32) | b);
+    }
+    for (size_t i = 0; i < sets.size(); ++i) {
+        const Stream &s = *sets[i].s;
+        const CandSet &c = *sets[i].c;
+        k.push_back(ids[i]);
+        P(&s);
+        k.push_back(s.n);
+        k.push_back(s.K);
+        k.push_back(s.B);
+        k.push_back(s.T);
+        k.push_back(s.max_tile_span);
+        P(s.tiled_ts.p);
+        P(s.tile_loff.p);
+        P(s.tile_t0.p);
+        P(s.type_off.p);
+        P(s.ts_by_type.p);
+        P(&c);
+        k.push_back(c.m);
+        k.push_back(c.compact);
+        P(c.types.p);
+        P(c.lo.p);
+        P(c.hi.p);
+        P(c.orig.p);
+        P(c.counts.p);
+        P(c.tau.p);
+        P(c.work.p);
+        P(c.dmeasured.p);
+        P(c.t16.p);
+        P(c.iv.p);
+        P(c.menu.p);
+        P(c.pred_bits);
+        P(c.succ_bits);
+        k.push_back((int64_t)c.groups.size());
+        for (const Group &g : c.groups) {
+            k.push_back(g.N);
+            k.push_back(g.Q);
+            k.push_back(g.C);
+            k.push_back(g.begin);
+            k.push_back(g.end);
+            k.push_back(g.hspan);
         }
     }
-    return hipSuccess;
+    return k;
 }
 
+// Plan a batched count: launch units (set, episode size group) with their
+// segment counts, launch classes with their lane widths and LDS layouts, the
+// work-item template (class-major), the device tables of the scheduler, and
+// one captured graph: [costs -> candidate sort -> item keys -> item sort ->
+// item gather] (costed schedules only), clear of the queue counters,
+// persistent launches (parallel branches), reconciliation.
 template <typename T>
-hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp, int32_t *d_flags,
-                     hipStream_t st) {
+hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp, int32_t *d_flags,
+                  BatchCache &cache, BatchPlan &plan, hipStream_t st) {
     hipError_t e;
     int dev = 0, ncu = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    const int64_t target_items = opt.target_items > 0 ? opt.target_items : (int64_t)ncu * 8;
+    if ((e = cache.branches()) != hipSuccess) return e;
 
+    // the schedule: round robin without costs, for compact (level-wise) sets
+    // and for the learned schedule without a model
+    bool costed = sched != EPI_SCHED_RR;
+    if (sched == EPI_SCHED_LEARNED && !(mlp.ready() && mlp.F == kFeatures)) costed = false;
+    for (auto &r : sets)
+        if (r.c->compact) costed = false;
+    if (sched == EPI_SCHED_MEASURED)
+        for (auto &r : sets)
+            if (!r.c->has_measured) costed = false;
+
+    // launch groups: the submission groups (episode size x ring entries
+    // class), adjacent ones of one size merged per EPI_OPT_RING_CLASSES
+    // (fewer, larger groups: the cost order spans more episodes, so each
+    // wave's lanes are closer in work; the rings take the group's largest)
+    std::vector<std::vector<Group>> mg(sets.size());
+    for (size_t si = 0; si < sets.size(); ++si) {
+        auto bucket = [&](const Group &g) {
+            const int L = std::max(1, g.N - 1);
+            if (opt.ring_classes == 1) return 0;
+            if (opt.ring_classes == 2) return g.C <= 2 * L ? 0 : (g.C <= 3 * L ? 1 : 2);
+            return cap_class_index(std::max(1, g.C));
+        };
+        for (const Group &g : sets[si].c->groups) {
+            if (g.end <= g.begin) continue;
+            if (!mg[si].empty()) {
+                Group &b = mg[si].back();
+                if (b.N == g.N && b.end == g.begin && bucket(b) == bucket(g) && opt.ring_classes != 0) {
+                    b.end = g.end;
+                    b.Q = std::max(b.Q, g.Q);
+                    b.C = std::max(b.C, g.C);
+                    b.hspan = std::max(b.hspan, g.hspan);
+                    continue;
+                }
+            }
+            mg[si].push_back(g);
+        }
+    }
+
+    // global slot order: the sets back to back; launch groups numbered in
+    // that order (each set's deep tail, counted elsewhere, is a group too)
+    std::vector<int64_t> soff(sets.size() + 1, 0);
+    for (size_t si = 0; si < sets.size(); ++si) soff[si + 1] = soff[si] + sets[si].c->m;
+    const int64_t M = soff.back();
+    std::vector<SchedGroup> sgroups;
+    std::vector<int32_t> gid(costed ? M : 0);
+    std::vector<SchedSet> ssets(sets.size());
+    for (size_t si = 0; si < sets.size(); ++si) {
+        const Stream &s = *sets[si].s;
+        const CandSet &c = *sets[si].c;
+        ssets[si] = SchedSet{s.type_off.as<int32_t>(), c.types.as<int32_t>(), c.lo.p, c.hi.p,
+                             c.has_measured ? c.dmeasured.as<float>() : nullptr, c.m, soff[si]};
+        if (!costed) continue;
+        int64_t end = 0;
+        for (const Group &g : mg[si]) {
+            for (int64_t i = g.begin; i < g.end; ++i) gid[soff[si] + i] = (int32_t)sgroups.size();
+            sgroups.push_back(SchedGroup{(int32_t)si, g.N});
+            end = std::max(end, g.end);
+        }
+        if (end < c.m) {
+            for (int64_t i = end; i < c.m; ++i) gid[soff[si] + i] = (int32_t)sgroups.size();
+            sgroups.push_back(SchedGroup{(int32_t)si, 1});
+        }
+    }
+
+    // 1. launch units: one per (set, group), segments as in plain mode
     struct UnitH {
         int set, N, Q, W;
         int64_t begin, G, P, S;
-        bool filt;
-        std::vector<float> bcost;  // per lane block
-        bool rel = false;          // int32 relative-time machines allowed
-        bool lane = false;         // register-indexed lane machines
-        bool pk = false;           //   with packed (time, node) keys
-        int C = 0;                 //   ring entries per lane
+        bool filt, rel, lane, pk;
+        int C;
     };
     std::vector<UnitH> units;
-    std::vector<DevBuf> perms(sets.size());
-    std::vector<std::vector<float>> costs(sets.size());
-    // 1. costs and schedule order per set
-    double total_cost = 0;
+    std::vector<std::pair<size_t, Group>> empty_groups;  // groups of sets on streams without events
     for (size_t si = 0; si < sets.size(); ++si) {
         const Stream &s = *sets[si].s;
         CandSet &c = *sets[si].c;
-        if ((e = predicted_costs(s, c, sched, mlp, st, costs[si])) != hipSuccess) return e;
-        if (!costs[si].empty()) {
-            std::vector<int32_t> perm(c.m);
-            std::iota(perm.begin(), perm.end(), 0);
-            for (const Group &g : c.groups)
-                std::stable_sort(perm.begin() + g.begin, perm.begin() + g.end,
-                                 [&](int32_t x, int32_t y) { return costs[si][x] > costs[si][y]; });
-            if ((e = perms[si].alloc(sizeof(int32_t) * c.m)) != hipSuccess) return e;
-            if ((e = hipMemcpy(perms[si].p, perm.data(), sizeof(int32_t) * c.m, hipMemcpyHostToDevice)) != hipSuccess)
-                return e;
-            std::vector<float> sorted(c.m);
-            for (int64_t i = 0; i < c.m; ++i) sorted[i] = costs[si][perm[i]];
-            costs[si] = std::move(sorted);
-            for (float x : costs[si]) total_cost += x;
-        }
-    }
-    // 2. launch units: lane blocks with the same segment count
-    for (size_t si = 0; si < sets.size(); ++si) {
-        const Stream &s = *sets[si].s;
-        CandSet &c = *sets[si].c;
-        if (s.n == 0) continue;
-        for (const Group &g : c.groups) {
+        for (const Group &g : mg[si]) {
             const int64_t G = g.end - g.begin;
             if (G <= 0) continue;
-            const bool filt = c.compact && c.pred_bits && c.succ_bits;
-            const bool lane = lane_group_ok<T>(s, c, g, opt);
-            const bool pk = lane && lane_pk_ok(s.max_tile_span);
-            const bool rel = !lane && rel_ok<T>(s, g.hspan);
-            const int C = std::max(1, g.C);
-            int W;
-            if (lane) {
-                W = lane_pick_width(lane_persistent_fn<T>(g.N, pk), C, s.K, s.T, opt.lanes);
-            } else {
-                const PFn<T> pfn =
-                    filt ? pick_persistent_f<T, true>(g.N, rel) : pick_persistent_f<T, false>(g.N, rel);
-                if (!pfn) return hipErrorInvalidValue;
-                W = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), g.N, g.Q, s.K, opt.lanes, rel);
-            }
-            const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
-            if (costs[si].empty()) {
-                // round robin: submission order, segments as in plain mode
-                int64_t P = G >= opt.target_lanes ? 1 : (opt.target_lanes + G - 1) / G;
-                if (opt.segments > 0) P = opt.segments;
-                P = std::max<int64_t>(1, std::min<int64_t>(P, opt.segments > 0 ? s.B : pmax));
-                const int64_t S = (s.B + P - 1) / P;
-                P = (s.B + S - 1) / S;
-                UnitH u{(int)si, g.N, g.Q, W, g.begin, G, P, S, filt, {}};
-                u.rel = rel;
-                u.lane = lane;
-                u.pk = pk;
-                u.C = C;
-                u.bcost.assign((G + W - 1) / W, 1.f);
-                units.push_back(std::move(u));
+            if (s.n == 0) {
+                empty_groups.emplace_back(si, g);
                 continue;
             }
-            // learned / heuristic: blocks of similar predicted cost (sorted),
-            // heavy blocks cut into more segments, cost per item ~ uniform.
-            // A block never gets fewer segments than round robin gives it:
-            // every item walks all tiles of its segment whatever its work, so
-            // a light block in one segment is one long item.
-            const double cstar = std::max(total_cost / (double)target_items, 1.0);
-            const int64_t p_rr = std::max<int64_t>(1, std::min<int64_t>(
-                G >= opt.target_lanes ? 1 : (opt.target_lanes + G - 1) / G, pmax));
-            int64_t b0 = 0;
-            const int64_t nb = (G + W - 1) / W;
-            while (b0 < nb) {
-                auto pfor = [&](int64_t b) {
-                    const double bc = (double)costs[si][g.begin + b * W] * std::min<int64_t>(W, G - b * W);
-                    int64_t P = std::max<int64_t>(p_rr, (int64_t)std::ceil(bc / cstar));
-                    if (opt.segments > 0) P = opt.segments;
-                    return std::max<int64_t>(1, std::min<int64_t>(P, opt.segments > 0 ? s.B : pmax));
-                };
-                const int64_t P0 = pfor(b0);
-                int64_t b1 = b0 + 1;
-                while (b1 < nb && pfor(b1) == P0) ++b1;
-                const int64_t S = (s.B + P0 - 1) / P0;
-                const int64_t P = (s.B + S - 1) / S;
-                UnitH u{(int)si, g.N, g.Q, W, g.begin + b0 * W, std::min<int64_t>(G - b0 * W, (b1 - b0) * W), P, S,
-                        filt, {}};
-                u.rel = rel;
-                u.lane = lane;
-                u.pk = pk;
-                u.C = C;
-                for (int64_t b = b0; b < b1; ++b)
-                    u.bcost.push_back(costs[si][g.begin + b * W] * (float)std::min<int64_t>(W, G - b * W));
-                units.push_back(std::move(u));
-                b0 = b1;
-            }
+            UnitH u{};
+            u.set = (int)si;
+            u.N = g.N;
+            u.Q = g.Q;
+            u.begin = g.begin;
+            u.G = G;
+            u.filt = c.compact && c.pred_bits && c.succ_bits;
+            u.lane = lane_group_ok<T>(s, c, g, opt);
+            u.pk = u.lane && lane_pk_ok(s.max_tile_span);
+            u.rel = !u.lane && rel_ok<T>(s, g.hspan);
+            u.C = std::max(1, g.C);
+            const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(s.B / 4, 65535));
+            int64_t P = G >= opt.target_lanes ? 1 : (opt.target_lanes + G - 1) / G;
+            if (opt.segments > 0) P = opt.segments;
+            P = std::max<int64_t>(1, std::min<int64_t>(P, opt.segments > 0 ? s.B : pmax));
+            P = std::min<int64_t>(P, 65535);
+            u.S = (s.B + P - 1) / P;
+            u.P = (s.B + u.S - 1) / u.S;
+            units.push_back(u);
         }
     }
-    // 3. per-unit arguments (records, work log) and work items per episode size
-    size_t rec_bytes = 0;
-    for (const UnitH &u : units)
-        if (u.P > 1) rec_bytes += record_bytes<T>(u.P, u.G) + 64;
-    DevBuf rec;
-    if ((e = rec.alloc(rec_bytes)) != hipSuccess) return e;
-    // launch classes: episode size x queue class x machine time type (each
-    // with its own lane width and LDS layout, as the plain launch sizes each
-    // group)
-    // (the LDS-ring machines: episode size x queue class x machine time type;
-    // the lane machines: episode size x ring-entries class x key form)
+    // 2. launch classes: the LDS-ring machines by (episode size, queue class,
+    // time type); the lane machines by (episode size, ring-entries class,
+    // key form); each with one lane width and LDS layout for its units
     constexpr int kQClasses = 8;  // Q = 1, 2, 3, 4, 6, 8, 12, 16
     constexpr int kRingClasses = (kMaxN + 1) * kQClasses * 2;
     constexpr int kClasses = kRingClasses + (kMaxN + 1) * kCapClasses * 2;
@@ -1332,17 +1380,74 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         while (q + 1 < kQClasses && kQ[q] < u.Q) ++q;
         return (u.N * kQClasses + q) * 2 + (u.rel ? 1 : 0);
     };
-    std::vector<CountArgs<T>> ua(units.size());
-    std::vector<std::vector<WorkItem>> items(kClasses);
-    std::vector<std::vector<float>> icost(kClasses);
     std::vector<int> clsN(kClasses, 0), clsQ(kClasses, 1), clsC(kClasses, 1), maxK(kClasses, 1), maxT(kClasses, 64),
         Wn(kClasses, 256);
     std::vector<bool> filtN(kClasses, false), relN(kClasses, false), laneN(kClasses, false), pkN(kClasses, false);
+    for (const UnitH &u : units) {
+        const Stream &s = *sets[u.set].s;
+        const int cl = cls_of(u);
+        clsN[cl] = u.N;
+        relN[cl] = u.rel;
+        laneN[cl] = u.lane;
+        pkN[cl] = u.pk;
+        clsQ[cl] = std::max(clsQ[cl], u.Q);
+        clsC[cl] = std::max(clsC[cl], u.C);
+        maxK[cl] = std::max(maxK[cl], (int)s.K);
+        maxT[cl] = std::max(maxT[cl], s.T);
+        filtN[cl] = filtN[cl] || u.filt;
+    }
+    std::vector<int> crank(kClasses, -1), corder;
+    for (int cl = 0; cl < kClasses; ++cl) {
+        if (clsN[cl] <= 0) continue;
+        crank[cl] = (int)corder.size();
+        corder.push_back(cl);
+        if (laneN[cl]) {
+            Wn[cl] = lane_pick_width(lane_persistent_fn<T>(clsN[cl], pkN[cl]), clsC[cl], maxK[cl], maxT[cl], opt.lanes);
+            continue;
+        }
+        const PFn<T> pfn = filtN[cl] ? pick_persistent_f<T, true>(clsN[cl], relN[cl])
+                                     : pick_persistent_f<T, false>(clsN[cl], relN[cl]);
+        if (!pfn) return hipErrorInvalidValue;
+        Wn[cl] = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), clsN[cl], clsQ[cl], maxK[cl], opt.lanes,
+                                  relN[cl]);
+    }
+
+    // 3. the candidate sort's passes (decided now: the permutation's buffer
+    // is the one the last pass writes)
+    int gpass = 1;
+    while (gpass < 4 && ((int64_t)sgroups.size() >> (8 * gpass)) > 0) ++gpass;
+    std::vector<int> cshift = {0, 8, 16, 24};
+    for (int i = 0; i < gpass; ++i) cshift.push_back(32 + 8 * i);
+    int ipass = 1;
+    while (ipass < 4 && ((int64_t)corder.size() >> (8 * ipass)) > 0) ++ipass;
+    std::vector<int> ishift = {0, 8, 16, 24};
+    for (int i = 0; i < ipass; ++i) ishift.push_back(32 + 8 * i);
+    if (costed && M > 0) {
+        if ((e = plan.k0.alloc(sizeof(uint64_t) * M)) != hipSuccess) return e;
+        if ((e = plan.k1.alloc(sizeof(uint64_t) * M)) != hipSuccess) return e;
+        if ((e = plan.v0.alloc(sizeof(int32_t) * M)) != hipSuccess) return e;
+        if ((e = plan.v1.alloc(sizeof(int32_t) * M)) != hipSuccess) return e;
+        if ((e = plan.y.alloc(sizeof(float) * M)) != hipSuccess) return e;
+        if (sched == EPI_SCHED_LEARNED && (e = plan.X.alloc(sizeof(float) * M * kFeatures)) != hipSuccess) return e;
+    }
+    const bool perm_second = (cshift.size() % 2) == 1;
+    const int32_t *perm_base = !(costed && M > 0) ? nullptr : (perm_second ? plan.v1.as<int32_t>() : plan.v0.as<int32_t>());
+    const uint64_t *skey_base =
+        !(costed && M > 0) ? nullptr : (perm_second ? plan.k1.as<uint64_t>() : plan.k0.as<uint64_t>());
+
+    // 4. per-unit arguments, records and the work-item template (class-major)
+    size_t rec_bytes = 0;
+    for (const UnitH &u : units)
+        if (u.P > 1) rec_bytes += record_bytes<T>(u.P, u.G) + 64;
+    if ((e = plan.rec.alloc(rec_bytes)) != hipSuccess) return e;
+    std::vector<CountArgs<T>> ua(units.size());
+    std::vector<SchedUnit> su(units.size());
     size_t ro = 0;
     for (size_t ui = 0; ui < units.size(); ++ui) {
         const UnitH &u = units[ui];
         const Stream &s = *sets[u.set].s;
         CandSet &c = *sets[u.set].c;
+        const int cl = cls_of(u);
         CountArgs<T> a{};
         a.tiled = s.tiled_ts.as<T>();
         a.loff = s.tile_loff.as<uint16_t>();
@@ -1364,198 +1469,190 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         a.m = c.m;
         a.begin = u.begin;
         a.G = u.G;
-        a.Q = u.Q;
+        a.Q = clsQ[cl];
+        a.C = clsC[cl];
         a.P = (int32_t)u.P;
         a.S = u.S;
         a.orig = c.compact ? nullptr : c.orig.as<int32_t>();
         a.counts = c.counts.as<int32_t>();
         a.tau = !c.compact && c.tau.p ? c.tau.template as<T>() : nullptr;
         a.flags = d_flags;
-        a.perm = perms[u.set].p ? perms[u.set].template as<int32_t>() : nullptr;
+        a.perm = perm_base ? perm_base + soff[u.set] : nullptr;
         a.work = opt.worklog ? c.work.as<int32_t>() : nullptr;
         if (u.P > 1) {
-            set_records<T>(a, rec.as<unsigned char>() + ro, u.P, u.G);
+            set_records<T>(a, plan.rec.as<unsigned char>() + ro, u.P, u.G);
             ro += (record_bytes<T>(u.P, u.G) + 64) & ~size_t(15);
         }
-        ua[ui] = a;
-        const int cl = cls_of(u);
-        clsN[cl] = u.N;
-        relN[cl] = u.rel;
-        laneN[cl] = u.lane;
-        pkN[cl] = u.pk;
-        clsQ[cl] = std::max(clsQ[cl], u.Q);
-        clsC[cl] = std::max(clsC[cl], u.C);
-        maxK[cl] = std::max(maxK[cl], (int)s.K);
-        maxT[cl] = std::max(maxT[cl], s.T);
-        filtN[cl] = filtN[cl] || u.filt;
-    }
-    // lanes per workgroup per class: common to its units
-    for (int cl = 0; cl < kClasses; ++cl)
-        if (clsN[cl] > 0) {
-            if (laneN[cl]) {
-                Wn[cl] = lane_pick_width(lane_persistent_fn<T>(clsN[cl], pkN[cl]), clsC[cl], maxK[cl], maxT[cl],
-                                         opt.lanes);
-                continue;
-            }
-            const PFn<T> pfn = filtN[cl] ? pick_persistent_f<T, true>(clsN[cl], relN[cl])
-                                         : pick_persistent_f<T, false>(clsN[cl], relN[cl]);
-            if (!pfn) return hipErrorInvalidValue;
-            Wn[cl] = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), clsN[cl], clsQ[cl], maxK[cl], opt.lanes,
-                                      relN[cl]);
-        }
-    for (size_t ui = 0; ui < units.size(); ++ui) {
-        const int cl = cls_of(units[ui]);
-        ua[ui].Q = clsQ[cl];
-        ua[ui].C = clsC[cl];
         if (laneN[cl]) {
             const LaneLayout L = lane_layout(clsC[cl], Wn[cl], maxK[cl], maxT[cl]);
-            ua[ui].off_qse = L.off_ring;
-            ua[ui].off_tbuf = L.off_tbuf;
-            ua[ui].off_qh = 0;
-            ua[ui].off_obuf = L.off_obuf;
-            ua[ui].off_misc = L.off_misc;
-            continue;
+            a.off_qse = L.off_ring;
+            a.off_tbuf = L.off_tbuf;
+            a.off_qh = 0;
+            a.off_obuf = L.off_obuf;
+            a.off_misc = L.off_misc;
+        } else {
+            const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
+            a.off_qse = L.off_qse;
+            a.off_tbuf = L.off_tbuf;
+            a.off_qh = L.off_qh;
+            a.off_obuf = L.off_obuf;
+            a.off_misc = L.off_misc;
         }
-        const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
-        ua[ui].off_qse = L.off_qse;
-        ua[ui].off_tbuf = L.off_tbuf;
-        ua[ui].off_qh = L.off_qh;
-        ua[ui].off_obuf = L.off_obuf;
-        ua[ui].off_misc = L.off_misc;
+        ua[ui] = a;
+        su[ui] = SchedUnit{soff[u.set] + u.begin, u.G, Wn[cl], (int32_t)u.P, crank[cl], 0};
     }
-    // work items: lane blocks of the class width x segments
-    for (size_t ui = 0; ui < units.size(); ++ui) {
-        const UnitH &u = units[ui];
-        const int cl = cls_of(u);
-        const int W = Wn[cl];
-        const int64_t nb = (u.G + W - 1) / W;
-        for (int64_t b = 0; b < nb; ++b) {
-            const float bc = u.bcost[std::min<int64_t>((b * W) / u.W, (int64_t)u.bcost.size() - 1)];
-            for (int64_t p = 0; p < u.P; ++p) {
-                items[cl].push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
-                icost[cl].push_back(bc / (float)u.P);
+    std::vector<WorkItem> tmpl;
+    std::vector<int64_t> ioff(kClasses + 1, 0);
+    std::vector<double> ccost(kClasses, 0.0);  // items per class (the branch balance)
+    for (int cl = 0; cl < kClasses; ++cl) {
+        ioff[cl] = (int64_t)tmpl.size();
+        for (size_t ui = 0; ui < units.size(); ++ui) {
+            const UnitH &u = units[ui];
+            if (cls_of(u) != cl) continue;
+            const int64_t nb = (u.G + Wn[cl] - 1) / Wn[cl];
+            for (int64_t b = 0; b < nb; ++b) {
+                const auto &s = *sets[u.set].s;
+                // a lane block's items cost about its lanes' visits: weight the
+                // branch balance by the stream's events per segment
+                ccost[cl] += (double)std::min<int64_t>(Wn[cl], u.G - b * Wn[cl]) * (double)s.n / 64.0;
+                for (int64_t p = 0; p < u.P; ++p) tmpl.push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
             }
         }
     }
-    int64_t n_items = 0;
-    for (int cl = 0; cl < kClasses; ++cl) {
-        if (sched != EPI_SCHED_RR && !items[cl].empty()) {
-            // longest processing time first
-            std::vector<int64_t> ord(items[cl].size());
-            std::iota(ord.begin(), ord.end(), 0);
-            std::stable_sort(ord.begin(), ord.end(),
-                             [&](int64_t x, int64_t y) { return icost[cl][x] > icost[cl][y]; });
-            std::vector<WorkItem> sorted(ord.size());
-            for (size_t i = 0; i < ord.size(); ++i) sorted[i] = items[cl][ord[i]];
-            items[cl] = std::move(sorted);
-        }
-        n_items += (int64_t)items[cl].size();
-    }
-    // work-log buffers (per-item wall-clock stamps live with the first set)
-    for (auto &r : sets) r.c->logged = opt.worklog;
+    ioff[kClasses] = (int64_t)tmpl.size();
+    const int64_t n_items = (int64_t)tmpl.size();
+    plan.n_items = n_items;
+    plan.soff = soff;
+    plan.perm = perm_base;
+    for (const UnitH &u : units) plan.uview.push_back(BatchPlan::UnitView{u.set, u.begin, u.G, Wn[cls_of(u)]});
     if (opt.worklog) {
-        if ((e = sets[0].c->cycles.alloc(sizeof(int64_t) * 2 * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
-        for (auto &a : ua) a.cycles = sets[0].c->cycles.as<int64_t>();
+        if ((e = plan.cycles.alloc(sizeof(int64_t) * 2 * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+        for (auto &a : ua) a.cycles = plan.cycles.as<int64_t>();
     }
-    DevBuf d_units, d_items, d_queue;
-    if ((e = d_units.alloc(sizeof(CountArgs<T>) * std::max<size_t>(1, ua.size()))) != hipSuccess) return e;
-    if (!ua.empty() && (e = hipMemcpy(d_units.p, ua.data(), sizeof(CountArgs<T>) * ua.size(),
-                                      hipMemcpyHostToDevice)) != hipSuccess)
-        return e;
-    if ((e = d_items.alloc(sizeof(WorkItem) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
-    if ((e = d_queue.alloc(sizeof(unsigned long long) * kClasses)) != hipSuccess) return e;
-    std::vector<int64_t> ioff(kClasses + 1, 0);
-    for (int cl = 0; cl < kClasses; ++cl) {
-        if (!items[cl].empty() &&
-            (e = hipMemcpy(d_items.as<WorkItem>() + ioff[cl], items[cl].data(), sizeof(WorkItem) * items[cl].size(),
-                           hipMemcpyHostToDevice)) != hipSuccess)
-            return e;
-        ioff[cl + 1] = ioff[cl] + (int64_t)items[cl].size();
-    }
-    // 4. one graph: clear the queues, one persistent launch per class, then
-    //    the reconciliation of every segmented unit
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<int> corder;
-    for (int cl = 0; cl < kClasses; ++cl)
-        if (!items[cl].empty()) corder.push_back(cl);
-    // the classes' persistent launches are independent: they run as parallel
-    // branches of the graph, on up to kBranches streams, the costliest classes
-    // first and each on the least loaded branch (their tails overlap)
-    constexpr int kBranches = 4;
-    const int nb = std::max(1, std::min<int>(kBranches, (int)corder.size()));
-    std::vector<double> ccost(kClasses, 0.0);
-    for (int cl : corder) {
-        for (float x : icost[cl]) ccost[cl] += x;
-        if (sched == EPI_SCHED_RR) ccost[cl] = (double)items[cl].size();
-    }
-    std::stable_sort(corder.begin(), corder.end(), [&](int x, int y) { return ccost[x] > ccost[y]; });
-    std::vector<hipStream_t> br(nb, nullptr);
-    std::vector<hipEvent_t> joined(nb, nullptr);
-    hipEvent_t fork = nullptr;
-    auto cleanup = [&]() {
-        for (auto &x : joined)
-            if (x) (void)hipEventDestroy(x);
-        if (fork) (void)hipEventDestroy(fork);
-        for (auto &x : br)
-            if (x) (void)hipStreamDestroy(x);
+    // device tables
+    auto up = [&](DevBuf &d, const void *h, size_t bytes) -> hipError_t {
+        hipError_t x = d.alloc(std::max<size_t>(bytes, 16));
+        if (x != hipSuccess || bytes == 0) return x;
+        return hipMemcpy(d.p, h, bytes, hipMemcpyHostToDevice);
     };
-    for (int i = 0; i < nb && e == hipSuccess; ++i) {
-        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&joined[i], hipEventDisableTiming);
-    }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        cleanup();
+    if ((e = up(plan.units, ua.data(), sizeof(CountArgs<T>) * ua.size())) != hipSuccess) return e;
+    if ((e = up(plan.tmpl, tmpl.data(), sizeof(WorkItem) * tmpl.size())) != hipSuccess) return e;
+    if ((e = plan.items.alloc(sizeof(WorkItem) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+    if ((e = plan.queue.alloc(sizeof(unsigned long long) * kClasses)) != hipSuccess) return e;
+    if (!costed && n_items > 0 &&
+        (e = hipMemcpy(plan.items.p, tmpl.data(), sizeof(WorkItem) * n_items, hipMemcpyHostToDevice)) != hipSuccess)
         return e;
+    if (costed) {
+        if ((e = up(plan.ssets, ssets.data(), sizeof(SchedSet) * ssets.size())) != hipSuccess) return e;
+        if ((e = up(plan.sgroups, sgroups.data(), sizeof(SchedGroup) * sgroups.size())) != hipSuccess) return e;
+        if ((e = up(plan.gid, gid.data(), sizeof(int32_t) * gid.size())) != hipSuccess) return e;
+        if ((e = up(plan.sunits, su.data(), sizeof(SchedUnit) * su.size())) != hipSuccess) return e;
+        if ((e = plan.ik0.alloc(sizeof(uint64_t) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+        if ((e = plan.ik1.alloc(sizeof(uint64_t) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+        if ((e = plan.iv0.alloc(sizeof(int32_t) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+        if ((e = plan.iv1.alloc(sizeof(int32_t) * std::max<int64_t>(1, n_items))) != hipSuccess) return e;
+        if ((e = plan.hist.alloc(sizeof(uint32_t) * radix_hist_words(std::max<int64_t>(M, n_items)))) != hipSuccess)
+            return e;
     }
-    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-        cleanup();
-        return e;
+
+    // 5. capture: scheduler, queue clear, persistent launches on parallel
+    // branches (costliest classes first, each onto the least loaded branch),
+    // join, reconciliation
+    std::vector<int> border = corder;
+    std::stable_sort(border.begin(), border.end(), [&](int x, int y) { return ccost[x] > ccost[y]; });
+    const int nb = std::max(1, std::min<int>(BatchCache::kBranches, (int)border.size()));
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    if (costed && M > 0) {
+        bool second = false;
+        e = sched_costs(sizeof(T) == 8 ? EPI_TS_I64 : EPI_TS_I32, sched, plan.ssets.as<SchedSet>(),
+                        plan.sgroups.as<SchedGroup>(), plan.gid.as<int32_t>(), M, mlp, plan.X.as<float>(),
+                        plan.y.as<float>(), st);
+        if (e == hipSuccess)
+            e = sched_keys(plan.ssets.as<SchedSet>(), plan.sgroups.as<SchedGroup>(), plan.gid.as<int32_t>(), M,
+                           plan.y.as<float>(), sched == EPI_SCHED_LEARNED, plan.k0.as<uint64_t>(),
+                           plan.v0.as<int32_t>(), st);
+        if (e == hipSuccess)
+            e = radix_sort(plan.k0.as<uint64_t>(), plan.v0.as<int32_t>(), plan.k1.as<uint64_t>(),
+                           plan.v1.as<int32_t>(), M, cshift.data(), (int)cshift.size(), plan.hist.as<uint32_t>(), st,
+                           &second);
+        if (e == hipSuccess && second != perm_second) e = hipErrorInvalidValue;
+        if (e == hipSuccess && n_items > 0) {
+            bool isec = false;
+            e = sched_item_keys(plan.tmpl.as<WorkItem>(), n_items, plan.sunits.as<SchedUnit>(), skey_base,
+                                plan.ik0.as<uint64_t>(), plan.iv0.as<int32_t>(), st);
+            if (e == hipSuccess)
+                e = radix_sort(plan.ik0.as<uint64_t>(), plan.iv0.as<int32_t>(), plan.ik1.as<uint64_t>(),
+                               plan.iv1.as<int32_t>(), n_items, ishift.data(), (int)ishift.size(),
+                               plan.hist.as<uint32_t>(), st, &isec);
+            if (e == hipSuccess)
+                e = sched_gather_items(plan.tmpl.as<WorkItem>(), isec ? plan.iv1.as<int32_t>() : plan.iv0.as<int32_t>(),
+                                       n_items, plan.items.as<WorkItem>(), st);
+        }
+    } else if (costed && M == 0) {
+        // nothing to order
+    }
+    for (auto &eg : empty_groups) {
+        if (e != hipSuccess) break;
+        CandSet &c = *sets[eg.first].c;
+        const Group &g = eg.second;
+        const int64_t G = g.end - g.begin;
+        k_zero_counts<T><<<(unsigned)((G + 255) / 256), 256, 0, st>>>(
+            c.compact ? nullptr : c.orig.as<int32_t>() + g.begin, G, c.counts.as<int32_t>() + (c.compact ? g.begin : 0),
+            !c.compact && c.tau.p ? c.tau.template as<T>() : nullptr);
+        e = hipGetLastError();
     }
     static_assert(kClasses <= 65536, "queue counters");
-    k_fill_u64<<<1, 256, 0, st>>>(reinterpret_cast<unsigned long long *>(d_queue.p), kClasses, 0ull);
-    e = hipEventRecord(fork, st);
-    for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], fork, 0);
+    if (e == hipSuccess) {
+        k_fill_u64<<<1, 256, 0, st>>>(plan.queue.as<unsigned long long>(), kClasses, 0ull);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(cache.fork, st);
+    for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(cache.br[i], cache.fork, 0);
     std::vector<double> load(nb, 0.0);
-    for (int cl : corder) {
+    for (int cl : border) {
         if (e != hipSuccess) break;
         const int bi = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[bi] += ccost[cl];
         const int N = clsN[cl];
-        const bool filt = filtN[cl];
+        const int64_t ncl = ioff[cl + 1] - ioff[cl];
+        if (ncl <= 0) continue;
         int per = 0;
         if (laneN[cl]) {
             const void *lfn = lane_persistent_fn<T>(N, pkN[cl]);
             const LaneLayout L = lane_layout(clsC[cl], Wn[cl], maxK[cl], maxT[cl]);
+            if (L.total > kLdsHard) {
+                e = hipErrorInvalidConfiguration;
+                break;
+            }
             if ((e = lane_lds_attr(lfn, L.total)) != hipSuccess) break;
             if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, lfn, Wn[cl], L.total)) != hipSuccess) break;
-            const int64_t grid =
-                std::max<int64_t>(1, std::min<int64_t>((int64_t)items[cl].size(), (int64_t)ncu * std::max(per, 1)));
-            e = lane_launch_persistent<T>(N, pkN[cl], (unsigned)grid, Wn[cl], L.total, br[bi],
-                                          d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[cl],
-                                          (int64_t)items[cl].size(), ioff[cl],
-                                          reinterpret_cast<unsigned long long *>(d_queue.p) + cl);
+            const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ncl, (int64_t)ncu * std::max(per, 1)));
+            e = lane_launch_persistent<T>(N, pkN[cl], (unsigned)grid, Wn[cl], L.total, cache.br[bi],
+                                          plan.units.as<CountArgs<T>>(), plan.items.as<WorkItem>() + ioff[cl], ncl,
+                                          ioff[cl], plan.queue.as<unsigned long long>() + cl);
             continue;
         }
-        PFn<T> fn = filt ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
+        PFn<T> fn = filtN[cl] ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
         const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
-        e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total);
-        if (e != hipSuccess) break;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(fn), Wn[cl], L.total);
-        if (e != hipSuccess) break;
-        const int64_t grid =
-            std::max<int64_t>(1, std::min<int64_t>((int64_t)items[cl].size(), (int64_t)ncu * std::max(per, 1)));
-        fn<<<(unsigned)grid, Wn[cl], L.total, br[bi]>>>(d_units.as<CountArgs<T>>(), d_items.as<WorkItem>() + ioff[cl],
-                                                        (int64_t)items[cl].size(), ioff[cl],
-                                                        reinterpret_cast<unsigned long long *>(d_queue.p) + cl);
+        if (L.total > kLdsHard) {
+            e = hipErrorInvalidConfiguration;
+            break;
+        }
+        if ((e = ensure_lds_attr<T>(reinterpret_cast<KFn<T>>(fn), L.total)) != hipSuccess) break;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(fn), Wn[cl],
+                                                              L.total)) != hipSuccess)
+            break;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ncl, (int64_t)ncu * std::max(per, 1)));
+        fn<<<(unsigned)grid, Wn[cl], L.total, cache.br[bi]>>>(plan.units.as<CountArgs<T>>(),
+                                                             plan.items.as<WorkItem>() + ioff[cl], ncl, ioff[cl],
+                                                             plan.queue.as<unsigned long long>() + cl);
         e = hipGetLastError();
     }
     // every branch joins back before the reconciliation (also after an
     // error, so that the capture ends cleanly)
     for (int i = 0; i < nb; ++i) {
-        hipError_t ej = hipEventRecord(joined[i], br[i]);
-        if (ej == hipSuccess) ej = hipStreamWaitEvent(st, joined[i], 0);
+        hipError_t ej = hipEventRecord(cache.joined[i], cache.br[i]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(st, cache.joined[i], 0);
         if (e == hipSuccess) e = ej;
     }
     for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
@@ -1564,28 +1661,115 @@ hipError_t batched_t(std::vector<BatchRef> &sets, int sched, const CountOptions 
         const int cl = cls_of(units[ui]);
         e = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), st);
     }
-    hipError_t ec = hipStreamEndCapture(st, &graph);
+    hipError_t ec = hipStreamEndCapture(st, &plan.graph);
     if (e == hipSuccess) e = ec;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the descriptors die here
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    cleanup();
-    for (auto &r : sets) r.c->n_items = n_items;
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan.exec, plan.graph, nullptr, nullptr, 0);
     return e;
 }
 
 }  // namespace
 
-hipError_t launch_count_batched(std::vector<BatchRef> &sets, int sched, const CountOptions &opt, Mlp &mlp,
-                                int32_t *d_flags, hipStream_t st) {
+hipError_t BatchCache::branches() {
+    if (fork) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kBranches && e == hipSuccess; ++i) {
+        if (!br[i]) e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+        if (e == hipSuccess && !joined[i]) e = hipEventCreateWithFlags(&joined[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    return e;
+}
+
+BatchPlan *BatchCache::find(const std::vector<int64_t> &key) {
+    for (size_t i = 0; i < plans.size(); ++i) {
+        if (plans[i]->key != key) continue;
+        std::unique_ptr<BatchPlan> p = std::move(plans[i]);
+        plans.erase(plans.begin() + (std::ptrdiff_t)i);
+        plans.push_back(std::move(p));
+        return plans.back().get();
+    }
+    return nullptr;
+}
+
+BatchPlan *BatchCache::find_id(uint64_t id) {
+    for (auto &p : plans)
+        if (p->id == id) return p.get();
+    return nullptr;
+}
+
+void BatchCache::evict_set(int32_t id) {
+    bool any = false;
+    for (auto &p : plans)
+        for (int32_t x : p->set_ids) any = any || x == id;
+    if (!any) return;
+    (void)hipDeviceSynchronize();
+    std::vector<std::unique_ptr<BatchPlan>> keep;
+    for (auto &p : plans) {
+        bool hit = false;
+        for (int32_t x : p->set_ids) hit = hit || x == id;
+        if (!hit) keep.push_back(std::move(p));
+    }
+    plans = std::move(keep);
+}
+
+void BatchCache::evict_all() {
+    if (plans.empty()) return;
+    (void)hipDeviceSynchronize();
+    plans.clear();
+}
+
+void BatchCache::clear() {
+    evict_all();
+    for (int i = 0; i < kBranches; ++i) {
+        if (joined[i]) (void)hipEventDestroy(joined[i]);
+        if (br[i]) (void)hipStreamDestroy(br[i]);
+        joined[i] = nullptr;
+        br[i] = nullptr;
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    fork = nullptr;
+}
+
+hipError_t launch_count_batched(std::vector<BatchRef> &sets, const std::vector<int32_t> &ids, int sched,
+                                const CountOptions &opt, Mlp &mlp, BatchCache &cache, int32_t *d_flags,
+                                hipStream_t st) {
     if (sets.empty()) return hipSuccess;
     const int kind = sets[0].s->ts_kind;
     for (auto &r : sets)
         if (r.s->ts_kind != kind) return hipErrorInvalidValue;
-    if (kind == EPI_TS_I64) return batched_t<int64_t>(sets, sched, opt, mlp, d_flags, st);
-    return batched_t<int32_t>(sets, sched, opt, mlp, d_flags, st);
+    const std::vector<int64_t> key = plan_key(sets, ids, sched, opt, mlp, d_flags);
+    BatchPlan *p = cache.find(key);
+    if (p) {
+        ++cache.replays;
+    } else {
+        if (cache.plans.size() >= BatchCache::kMaxPlans) {
+            (void)hipDeviceSynchronize();
+            cache.plans.erase(cache.plans.begin());
+        }
+        auto np = std::make_unique<BatchPlan>();
+        np->key = key;
+        np->set_ids = ids;
+        np->id = cache.next_id++;
+        hipError_t e = kind == EPI_TS_I64 ? plan_t<int64_t>(sets, sched, opt, mlp, d_flags, cache, *np, st)
+                                          : plan_t<int32_t>(sets, sched, opt, mlp, d_flags, cache, *np, st);
+        if (e != hipSuccess) {
+            (void)hipDeviceSynchronize();  // the plan's uploads end before its buffers are freed
+            return e;
+        }
+        ++cache.built;
+        cache.plans.push_back(std::move(np));
+        p = cache.plans.back().get();
+    }
+    hipError_t e = hipGraphLaunch(p->exec, st);
+    if (e != hipSuccess) return e;
+    ++p->launches;
+    for (auto &r : sets) {
+        r.c->n_items = p->n_items;
+        r.c->cycles_plan = 0;
+        r.c->last_plan = p->id;
+    }
+    sets[0].c->cycles_plan = opt.worklog ? p->id : 0;
+    return hipSuccess;
 }
 
 }  // namespace epi

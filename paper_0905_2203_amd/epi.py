@@ -45,7 +45,8 @@ EXPORTS = [
     "epi_validate_stream", "epi_validate_candidates",
     "epi_load_stream", "epi_load_stream_device", "epi_stream_info", "epi_read_type_index",
     "epi_release_stream", "epi_append_stream", "epi_submit_candidates", "epi_release_set",
-    "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device",
+    "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device", "epi_batched_stats",
+    "epi_read_schedule",
     "epi_mine", "epi_mine_levels", "epi_mine_level_info", "epi_mine_read", "epi_mine_read_at",
     "epi_mine_level_bytes", "epi_mine_release",
     "epi_mlp_init", "epi_mlp_params", "epi_mlp_get_params", "epi_mlp_set_params", "epi_mlp_forward",
@@ -65,6 +66,7 @@ EPI_OPT_ALLOW_REPEATS = 9
 EPI_OPT_MINE_LIST_ALPHAS = 10
 EPI_OPT_STREAM_ORDER = 11
 EPI_OPT_LANE_ENGINE = 12
+EPI_OPT_RING_CLASSES = 13
 
 
 class EpiError(RuntimeError):
@@ -112,6 +114,8 @@ def lib():
             "epi_set_option": ([P, INT, I64], I32),
             "epi_read_counts": ([P, I32, P, I64], I32),
             "epi_counts_device": ([P, I32, ctypes.POINTER(P)], I32),
+            "epi_batched_stats": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+            "epi_read_schedule": ([P, I32, P, P, I64], I32),
             "epi_mine": ([P, I32, I32, P, P, I32, I64, P, ctypes.POINTER(I32)], I32),
             "epi_mine_levels": ([P, I32, ctypes.POINTER(I32)], I32),
             "epi_mine_level_info": ([P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
@@ -293,6 +297,20 @@ class Context:
         p = P()
         self._check(lib().epi_counts_device(self.h, int(set_id), ctypes.byref(p)))
         return p.value or 0
+
+    def epi_batched_stats(self) -> dict:
+        """Plans built, replays of kept plans and plans kept by this context."""
+        b, r, k = I64(), I64(), I64()
+        self._check(lib().epi_batched_stats(self.h, ctypes.byref(b), ctypes.byref(r), ctypes.byref(k)))
+        return {"built": b.value, "replays": r.value, "kept": k.value}
+
+    def epi_read_schedule(self, set_id: int, m: int):
+        """(order, block): submission index and lane block of every lane slot
+        of the set's last batched count."""
+        order = np.zeros(int(m), np.int32)
+        block = np.zeros(int(m), np.int32)
+        self._check(lib().epi_read_schedule(self.h, int(set_id), _ptr(order), _ptr(block), int(m)))
+        return order, block
 
     # level-wise discovery ------------------------------------------------------
     def epi_mine(self, sid: int, menu, max_size: int, threshold: int, hip_stream=None) -> int:
