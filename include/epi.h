@@ -331,6 +331,23 @@ epi_status epi_read_worklog(epi_ctx *ctx, int32_t set_id, int32_t *work, int64_t
  * with cycles = null only *n_out receives the number of items. */
 epi_status epi_read_item_cycles(epi_ctx *ctx, int32_t set_id, int64_t *cycles, int64_t n_items, int64_t *n_out);
 
+/* epi_count in EPI_MODE_PLAIN for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same counts, written to the set's counts buffer, with
+ * `segments` time segments per launch group (0: automatic, as
+ * EPI_OPT_SEGMENTS = 0), and the per-(segment, episode) records of the
+ * segment-parallel count kept in the library's static device scratch of
+ * 64 MiB (held per device until the process ends).  Calls no hipMalloc,
+ * hipFree or host synchronisation; asynchronous on hip_stream (null: the
+ * context's stream); the work log is not recorded.  Every call on one GPU
+ * shares that scratch: calls that overlap on one GPU (other streams or other
+ * contexts) race; calls on one stream are ordered and safe.  Errors:
+ * EPI_ESIZE when a launch group's records exceed the scratch (fewer
+ * segments fit), EPI_EINVAL for sets with stream-order overlap or with
+ * episodes deeper than the rings (both need the tracking engine's working
+ * memory), EPI_ESTATE for an unknown set. */
+epi_status epi_count_noalloc(epi_ctx *ctx, int32_t set_id, int64_t segments, void *hip_stream);
+
 /* Batched plans of the context: *plans_built = plans captured and
  * instantiated so far, *replays = batched counts that launched a kept plan
  * again (no capture, no instantiation, no host scheduling), *plans_kept =

@@ -279,7 +279,8 @@ epi_status epi_create(int device, epi_ctx **out) {
         (e = ctx->c.flags.alloc(sizeof(int32_t) * kNumFlags)) != hipSuccess ||
         (e = hipMemset(ctx->c.flags.p, 0, sizeof(int32_t) * kNumFlags)) != hipSuccess ||
         (e = hipHostMalloc((void **)&ctx->c.stage, sizeof(int64_t) * kStageSlots, hipHostMallocDefault)) !=
-            hipSuccess) {
+            hipSuccess ||
+        (e = noalloc_init(device)) != hipSuccess) {
         g_create_err = hipGetErrorString(e);
         delete ctx;
         return EPI_EDEVICE;
@@ -1474,6 +1475,41 @@ epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sch
         chosen[0] = lanes;
         chosen[1] = per_cu;
     }
+    return EPI_OK;
+}
+
+epi_status epi_count_noalloc(epi_ctx *ctx, int32_t set_id, int64_t segments, void *hip_stream) {
+    if (!ctx) return EPI_EINVAL;
+    if (segments < 0) return fail(ctx, EPI_EINVAL, "segments must be >= 0");
+    CandSet *cs = find_set(ctx, set_id);
+    if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_id);
+    if (cs->stream_order) return fail(ctx, EPI_EINVAL, "set %d decides overlap in stream order", set_id);
+    if (cs->compact) return fail(ctx, EPI_EINVAL, "set %d cannot be counted here", set_id);
+    if (cs->deep)
+        return fail(ctx, EPI_EINVAL, "set %d holds episodes deeper than the rings (counted with working memory)",
+                    set_id);
+    Stream *s = find_stream(ctx, cs->stream_id);
+    unsigned char *scr = noalloc_scratch(ctx->c.device);
+    if (!scr) return fail(ctx, EPI_EDEVICE, "no scratch address for device %d", ctx->c.device);
+    CountOptions opt = ctx->c.opt;
+    opt.segments = segments;
+    opt.worklog = false;
+    for (const Group &g : cs->groups) {
+        const int64_t G = g.end - g.begin;
+        if (G <= 0 || s->n == 0) continue;
+        const int64_t P = plain_segments(*s, G, opt, nullptr);
+        const size_t need = plain_record_bytes(*s, P, G);
+        if (need > noalloc_scratch_bytes())
+            return fail(ctx, EPI_ESIZE, "%lld segments x %lld episodes need %zu B of records, the scratch holds %zu B",
+                        (long long)P, (long long)G, need, noalloc_scratch_bytes());
+    }
+    HIPTRY(ctx, hipSetDevice(ctx->c.device), "hipSetDevice");
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    HIPTRY(ctx, launch_count(*s, *cs, opt, ctx->c.flags.as<int32_t>(), st, scr, noalloc_scratch_bytes()),
+           "launching the count");
+    cs->logged = false;
+    cs->counted = true;
+    cs->counted_n = s->n;
     return EPI_OK;
 }
 

@@ -457,6 +457,12 @@ hipError_t validate_stream_device(const int32_t *d_types, const void *d_times, i
 // on the host; hipErrorOutOfMemory if a group's records do not fit).
 hipError_t launch_count(const Stream &s, CandSet &c, const CountOptions &opt, int32_t *d_flags, hipStream_t st,
                         unsigned char *ext_scratch = nullptr, size_t ext_bytes = 0);
+// Static device scratch of the allocation-free count (epi_noalloc.hip):
+// noalloc_init looks up its address on the current device (once per device),
+// noalloc_scratch returns it (null before init), noalloc_scratch_bytes its size.
+hipError_t noalloc_init(int device);
+unsigned char *noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 // Segments of a plain count of a group of G episodes on stream s (and the
 // tiles per segment, *S_out), and the bytes of its segment records.
 int64_t plain_segments(const Stream &s, int64_t G, const CountOptions &opt, int64_t *S_out);

@@ -46,7 +46,7 @@ EXPORTS = [
     "epi_load_stream", "epi_load_stream_device", "epi_stream_info", "epi_read_type_index",
     "epi_release_stream", "epi_append_stream", "epi_submit_candidates", "epi_release_set",
     "epi_count", "epi_set_option", "epi_sync", "epi_read_counts", "epi_counts_device", "epi_batched_stats",
-    "epi_read_schedule",
+    "epi_read_schedule", "epi_count_noalloc",
     "epi_mine", "epi_mine_levels", "epi_mine_level_info", "epi_mine_read", "epi_mine_read_at",
     "epi_mine_level_bytes", "epi_mine_release",
     "epi_mlp_init", "epi_mlp_params", "epi_mlp_get_params", "epi_mlp_set_params", "epi_mlp_forward",
@@ -116,6 +116,7 @@ def lib():
             "epi_counts_device": ([P, I32, ctypes.POINTER(P)], I32),
             "epi_batched_stats": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
             "epi_read_schedule": ([P, I32, P, P, I64], I32),
+            "epi_count_noalloc": ([P, I32, I64, P], I32),
             "epi_mine": ([P, I32, I32, P, P, I32, I64, P, ctypes.POINTER(I32)], I32),
             "epi_mine_levels": ([P, I32, ctypes.POINTER(I32)], I32),
             "epi_mine_level_info": ([P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P], I32),
@@ -297,6 +298,10 @@ class Context:
         p = P()
         self._check(lib().epi_counts_device(self.h, int(set_id), ctypes.byref(p)))
         return p.value or 0
+
+    def epi_count_noalloc(self, set_id: int, segments: int = 0, hip_stream=None):
+        st = None if hip_stream is None else P(int(hip_stream))
+        self._check(lib().epi_count_noalloc(self.h, int(set_id), int(segments), st))
 
     def epi_batched_stats(self) -> dict:
         """Plans built, replays of kept plans and plans kept by this context."""
