@@ -321,23 +321,38 @@ def large_bench(args):
     ctx.epi_sync()
 
     # the cost model: trained once on the work log of a disjoint candidate set
-    # (each episode's own work: no segments)
+    # (each episode's own work: no segments), or loaded from a file
     a = time.perf_counter()
-    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
-    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)
-    tid = ctx.epi_submit_candidates(sid, train)
-    ctx.epi_count([tid], mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
-    losses = ctx.epi_costmodel_train([tid], epochs=40, seed=7)
-    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
-    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
-    ctx.epi_release_set(tid)
+    if args.costmodel_in:
+        ctx.epi_costmodel_load(args.costmodel_in)
+        losses = [float("nan")]
+    else:
+        ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
+        ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)
+        tid = ctx.epi_submit_candidates(sid, train)
+        ctx.epi_count([tid], mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
+        losses = ctx.epi_costmodel_train([tid], epochs=40, seed=7)
+        ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
+        ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+        ctx.epi_release_set(tid)
+    if args.costmodel_out:
+        ctx.epi_costmodel_save(args.costmodel_out)
     train_s = time.perf_counter() - a
-    log(f"cost model trained in {train_s:.1f}s (loss {losses[0]:.3f} -> {losses[-1]:.3f})")
+    log(f"cost model ready in {train_s:.1f}s (loss {losses[0]:.3f} -> {losses[-1]:.3f})")
 
     legs = {"batched_learned": (epi.EPI_MODE_BATCHED, epi.EPI_SCHED_LEARNED),
             "plain": (epi.EPI_MODE_PLAIN, epi.EPI_SCHED_RR),
             "batched_rr": (epi.EPI_MODE_BATCHED, epi.EPI_SCHED_RR),
             "batched_heuristic": (epi.EPI_MODE_BATCHED, epi.EPI_SCHED_HEURISTIC)}
+    tuned = {}
+
+    def tune(sched, name):
+        if args.no_tune:
+            return
+        a = time.perf_counter()
+        tuned[name] = dict(zip(("tile", "ring_classes", "lanes", "target_lanes"), ctx.epi_autotune([cid], sched)))
+        tuned[name]["seconds"] = round(time.perf_counter() - a, 1)
+        log(f"  autotuned for {name}: {tuned[name]}")
 
     def run(mode, sched, steps, warmup, name):
         for w in range(warmup):
@@ -358,14 +373,26 @@ def large_bench(args):
         return float(np.mean(ms)), wall
 
     res, counts = {}, {}
-    # the headline leg: exactly K timed steps after W warm-up steps
+    reps = max(1, min(3, args.steps))
+    # the plain engine with its defaults, then the batched engine tuned for
+    # round robin, then tuned for the learned schedule (the headline leg:
+    # exactly K timed steps after W warm-up steps), then the heuristic
+    # schedule with the learned leg's setting
+    if not args.learned_only:
+        res["plain"], _ = run(*legs["plain"], reps, 1, "plain")
+        counts["plain"] = ctx.epi_read_counts(cid, m)
+        tune(epi.EPI_SCHED_RR, "batched_rr")
+        res["batched_rr"], _ = run(*legs["batched_rr"], reps, 1, "batched_rr")
+        counts["batched_rr"] = ctx.epi_read_counts(cid, m)
+    tune(epi.EPI_SCHED_LEARNED, "batched_learned")
+    st0 = ctx.epi_batched_stats()
     res["batched_learned"], wall_learned = run(*legs["batched_learned"], args.steps, args.warmup, "batched_learned")
     counts["batched_learned"] = ctx.epi_read_counts(cid, m)
-    stats = ctx.epi_batched_stats()
-    reps = max(1, min(3, args.steps))
-    for name in ("plain", "batched_rr", "batched_heuristic"):
-        res[name], _ = run(*legs[name], reps, 1, name)
-        counts[name] = ctx.epi_read_counts(cid, m)
+    st1 = ctx.epi_batched_stats()
+    stats = {"built": st1["built"] - st0["built"], "replays": st1["replays"] - st0["replays"]}
+    if not args.learned_only:
+        res["batched_heuristic"], _ = run(*legs["batched_heuristic"], reps, 1, "batched_heuristic")
+        counts["batched_heuristic"] = ctx.epi_read_counts(cid, m)
     equal = all(np.array_equal(counts[k], counts["batched_learned"]) for k in counts)
 
     # parity: every count against the oracle-written expected counts of this
@@ -436,11 +463,13 @@ def large_bench(args):
             "mode": "batched + learned schedule",
         },
         "modes": {k: {"ms_per_count": v, "cand_ev_per_s": m * n / (v / 1e3)} for k, v in res.items()},
-        "learned_vs_plain": res["plain"] / res["batched_learned"],
-        "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
-        "learned_vs_heuristic": res["batched_heuristic"] / res["batched_learned"],
+        "learned_vs_plain": res["plain"] / res["batched_learned"] if "plain" in res else None,
+        "learned_vs_rr": res["batched_rr"] / res["batched_learned"] if "batched_rr" in res else None,
+        "learned_vs_heuristic": res["batched_heuristic"] / res["batched_learned"] if "batched_heuristic" in res else None,
         "wall_ms_per_step": 1e3 * wall_learned / args.steps,
+        # the learned leg's warm-up and timed counts: plans captured, replays
         "graph": {"plans_built": stats["built"], "replays": stats["replays"]},
+        "autotuned": tuned,
         "cost_model": {"train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                        "train_candidates": int(train["N"].size)},
         "roofline": {
@@ -473,6 +502,11 @@ def main():
                          "candidates with --mining)")
     ap.add_argument("--scale", type=float, default=1.0, help="size scale of the Large workload")
     ap.add_argument("--mining", action="store_true", help="level-wise discovery of the mining preset")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="Large line: time only the batched + learned leg (profiling runs)")
+    ap.add_argument("--no-tune", action="store_true", help="Large line: engine defaults, no autotuning")
+    ap.add_argument("--costmodel-in", default="", help="Large line: load the cost model from this file")
+    ap.add_argument("--costmodel-out", default="", help="Large line: save the trained cost model to this file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (scale reference for HBM byte counters)")
     ap.add_argument("--ablation", default="",
@@ -513,7 +547,7 @@ def main():
         mining_bench(args)
         return
     if args.cpu_sample <= 0:
-        args.cpu_sample = 384
+        args.cpu_sample = 6000
     large_bench(args)
 
 

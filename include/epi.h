@@ -236,8 +236,10 @@ epi_status epi_append_stream(epi_ctx *ctx, int32_t stream_id, const int32_t *typ
  *                         occurrences recorded, predecessor queries,
  *                         completions, deepest interval ring) and, in batched
  *                         mode, a wall-clock start/end per work item
- *   EPI_OPT_TARGET_ITEMS  batched mode: number of work items the scheduler
- *                         aims at (0 = 8 per compute unit)
+ *   EPI_OPT_TARGET_ITEMS  accepted for compatibility; the batched scheduler
+ *                         cuts every lane block of a launch group into the
+ *                         same segments (EPI_OPT_TARGET_LANES) and orders
+ *                         the items on the device, so it has no effect
  *   EPI_OPT_MINE_LIST_BYTES  level-wise discovery, extension engine: device
  *                         bytes that the end-event lists of every candidate
  *                         of a level may take (default 8 GiB); a level with
@@ -301,16 +303,22 @@ enum { EPI_OPT_SEGMENTS = 1, EPI_OPT_LANES = 2, EPI_OPT_TARGET_LANES = 3, EPI_OP
        EPI_OPT_LANE_ENGINE = 12, EPI_OPT_RING_CLASSES = 13 };
 epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
-/* Autotune the batched engine for these sets and schedule: time every
- * setting of lanes per workgroup {64, 128, 256} x work items per compute
- * unit {4, 8, 16, 32} (each trial is a full batched count; the counts do
- * not depend on the setting), keep the fastest and apply it to the context
- * (EPI_OPT_LANES, EPI_OPT_TARGET_ITEMS).  With cache_path (may be null) the
+/* Autotune the batched engine for these sets and schedule by coordinate
+ * descent from the defaults, one knob at a time: the streams' tile size
+ * (largest events per tile {2048, 1024, 512}; the streams are re-tiled), the
+ * launch groups (EPI_OPT_RING_CLASSES {0, 1, 2}), lanes per workgroup
+ * (EPI_OPT_LANES {automatic, 128, 64}) and the segment target
+ * (EPI_OPT_TARGET_LANES {131072, 262144, 524288}).  Each trial builds the
+ * batched plan, then times one replay with hipEvents; the counts do not
+ * depend on the setting.  The fastest is kept: the streams stay re-tiled and
+ * the options are set on the context.  With cache_path (may be null) the
  * choice is appended to that text file under a key of the workload's shape
  * (timestamp kind, schedule, K, log2 sizes of events, candidates and
- * candidates per episode size); a later call with the same key reads it
- * instead of timing (unreadable or malformed entries are ignored).
- * chosen[2] (may be null) receives lanes and work items per compute unit. */
+ * candidates per episode size); a later call with the same key applies it
+ * without timing (unreadable or malformed entries are ignored).  chosen[4]
+ * (may be null) receives tile size, ring classes, lanes (0 = automatic) and
+ * segment target.  Sets from level-wise discovery or with stream-order
+ * overlap: EPI_EINVAL. */
 epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched, const char *cache_path,
                         int64_t *chosen);
 

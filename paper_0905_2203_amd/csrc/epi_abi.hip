@@ -1399,20 +1399,34 @@ std::string tune_key(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched)
     return key;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int64_t *lanes, int64_t *items) {
+// One tuned setting of the batched engine.
+struct TuneSetting {
+    int64_t tile = kTile;        // largest events per tile of the sets' streams
+    int64_t rings = 0;           // EPI_OPT_RING_CLASSES
+    int64_t lanes = 0;           // EPI_OPT_LANES (0: automatic)
+    int64_t target = 262144;     // EPI_OPT_TARGET_LANES
+};
+
+bool tune_valid(const TuneSetting &t) {
+    return (t.tile == 2048 || t.tile == 1024 || t.tile == 512 || t.tile == 256) && t.rings >= 0 && t.rings <= 2 &&
+           (t.lanes == 0 || t.lanes == 64 || t.lanes == 128 || t.lanes == 256) && t.target >= 1024 &&
+           t.target <= (int64_t(1) << 26);
+}
+
+bool cache_lookup(const char *path, const std::string &key, TuneSetting *out) {
     if (!path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
     char line[1024], kb[512];
-    long long a, b;
+    long long a, b, c, d;
     bool found = false;
-    // one entry per line: key lanes items; other lines are ignored
+    // one entry per line: key tile rings lanes target; other lines are ignored
     while (fgets(line, sizeof line, f)) {
         char extra;
-        if (sscanf(line, "%511s %lld %lld %c", kb, &a, &b, &extra) != 3) continue;
-        if (key == kb && (a == 64 || a == 128 || a == 256) && b >= 1 && b <= 4096) {
-            *lanes = a;
-            *items = b;
+        if (sscanf(line, "%511s %lld %lld %lld %lld %c", kb, &a, &b, &c, &d, &extra) != 5) continue;
+        const TuneSetting t{a, b, c, d};
+        if (key == kb && tune_valid(t)) {
+            *out = t;
             found = true;  // the last valid entry wins
         }
     }
@@ -1420,60 +1434,119 @@ bool cache_lookup(const char *path, const std::string &key, int64_t *lanes, int6
     return found;
 }
 
+// Re-tile every stream of the sets to tile cap `cap` (plans over the old
+// tiles are dropped first).
+epi_status retile(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int64_t cap) {
+    std::vector<Stream *> ss;
+    for (int32_t i = 0; i < k; ++i) {
+        Stream *s = find_stream(ctx, find_set(ctx, set_ids[i])->stream_id);
+        if (std::find(ss.begin(), ss.end(), s) == ss.end()) ss.push_back(s);
+    }
+    bool any = false;
+    for (Stream *s : ss) any = any || s->tile_cap != cap;
+    if (!any) return EPI_OK;
+    for (auto &kv : ctx->c.mines)
+        for (Stream *s : ss)
+            if (find_stream(ctx, kv.second->stream_id) == s)
+                return fail(ctx, EPI_ESTATE, "a level-wise discovery run (%d) uses a stream to be re-tiled", kv.first);
+    HIPTRY(ctx, hipDeviceSynchronize(), "sync");
+    ctx->c.batch.evict_all();
+    for (Stream *s : ss) {
+        if (s->tile_cap == cap) continue;
+        s->tile_cap = (int)cap;
+        HIPTRY(ctx, build_type_index(*s, ctx->c.stream), "re-tiling a stream");
+    }
+    HIPTRY(ctx, hipStreamSynchronize(ctx->c.stream), "sync");
+    return EPI_OK;
+}
+
+void apply_setting(epi_ctx *ctx, const TuneSetting &t) {
+    ctx->c.opt.ring_classes = (int)t.rings;
+    ctx->c.opt.lanes = (int)t.lanes;
+    ctx->c.opt.target_lanes = t.target;
+}
+
 }  // namespace
 
 epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched, const char *cache_path,
                         int64_t *chosen) {
     if (!ctx || k < 1 || !set_ids) return fail(ctx, EPI_EINVAL, "bad arguments");
-    for (int32_t i = 0; i < k; ++i)
-        if (!find_set(ctx, set_ids[i])) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+    for (int32_t i = 0; i < k; ++i) {
+        CandSet *cs = find_set(ctx, set_ids[i]);
+        if (!cs) return fail(ctx, EPI_ESTATE, "unknown set id %d", set_ids[i]);
+        if (cs->compact || cs->stream_order)
+            return fail(ctx, EPI_EINVAL, "set %d cannot be counted in batched mode", set_ids[i]);
+    }
     const std::string key = tune_key(ctx, set_ids, k, sched);
-    int64_t lanes = 0, per_cu = 8;
-    int ncu = 0;
-    HIPTRY(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->c.device), "attribute");
-    if (!cache_lookup(cache_path, key, &lanes, &per_cu)) {
+    TuneSetting best;
+    best.target = ctx->c.opt.target_lanes;
+    if (!cache_lookup(cache_path, key, &best)) {
+        // coordinate descent from the defaults: tile cap, then launch-group
+        // merging, then lanes per workgroup, then the segment target; each
+        // trial is a batched count whose plan is built first and then timed
+        // as a replay (hipEvents on the context's stream)
         const CountOptions saved = ctx->c.opt;
-        double best = 1e300;
         hipEvent_t a, b;
         HIPTRY(ctx, hipEventCreate(&a), "event");
         HIPTRY(ctx, hipEventCreate(&b), "event");
-        for (int64_t W : {64, 128, 256}) {
-            for (int64_t pc : {4, 8, 16, 32}) {
-                ctx->c.opt.lanes = (int)W;
-                ctx->c.opt.target_items = pc * ncu;
-                (void)hipEventRecord(a, ctx->c.stream);
-                epi_status v = epi_count(ctx, set_ids, k, EPI_MODE_BATCHED, sched, nullptr);
-                (void)hipEventRecord(b, ctx->c.stream);
-                if (v != EPI_OK) {
-                    ctx->c.opt = saved;
-                    return v;
-                }
-                HIPTRY(ctx, hipEventSynchronize(b), "sync");
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, a, b);
-                if (ms < best) {
-                    best = ms;
-                    lanes = W;
-                    per_cu = pc;
+        auto trial = [&](const TuneSetting &t, float *ms) -> epi_status {
+            *ms = INFINITY;
+            epi_status v = retile(ctx, set_ids, k, t.tile);
+            if (v != EPI_OK) return v;
+            apply_setting(ctx, t);
+            if (epi_count(ctx, set_ids, k, EPI_MODE_BATCHED, sched, nullptr) != EPI_OK || epi_sync(ctx) != EPI_OK) {
+                (void)hipGetLastError();
+                return EPI_OK;  // a setting that cannot run loses
+            }
+            (void)hipEventRecord(a, ctx->c.stream);
+            v = epi_count(ctx, set_ids, k, EPI_MODE_BATCHED, sched, nullptr);
+            (void)hipEventRecord(b, ctx->c.stream);
+            if (v != EPI_OK) {
+                (void)hipGetLastError();
+                return EPI_OK;
+            }
+            HIPTRY(ctx, hipEventSynchronize(b), "sync");
+            (void)hipEventElapsedTime(ms, a, b);
+            return epi_sync(ctx);
+        };
+        float best_ms = INFINITY;
+        epi_status v = trial(best, &best_ms);
+        const int64_t menus[4][3] = {{2048, 1024, 512}, {0, 1, 2}, {0, 128, 64}, {131072, 262144, 524288}};
+        for (int d = 0; v == EPI_OK && d < 4; ++d) {
+            for (int64_t x : menus[d]) {
+                TuneSetting t = best;
+                int64_t *field = d == 0 ? &t.tile : d == 1 ? &t.rings : d == 2 ? &t.lanes : &t.target;
+                if (*field == x) continue;
+                *field = x;
+                float ms = INFINITY;
+                if ((v = trial(t, &ms)) != EPI_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
                 }
             }
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
         ctx->c.opt = saved;
+        if (v != EPI_OK) return v;
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s %lld %lld\n", key.c_str(), (long long)lanes, (long long)per_cu);
+                fprintf(f, "%s %lld %lld %lld %lld\n", key.c_str(), (long long)best.tile, (long long)best.rings,
+                        (long long)best.lanes, (long long)best.target);
                 fclose(f);
             }
         }
     }
-    ctx->c.opt.lanes = (int)lanes;
-    ctx->c.opt.target_items = per_cu * ncu;
+    epi_status v = retile(ctx, set_ids, k, best.tile);
+    if (v != EPI_OK) return v;
+    apply_setting(ctx, best);
     if (chosen) {
-        chosen[0] = lanes;
-        chosen[1] = per_cu;
+        chosen[0] = best.tile;
+        chosen[1] = best.rings;
+        chosen[2] = best.lanes;
+        chosen[3] = best.target;
     }
     return EPI_OK;
 }

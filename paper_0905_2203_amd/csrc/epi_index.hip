@@ -241,7 +241,8 @@ int64_t longest_tile(const std::vector<int64_t> &g, int64_t n, int T) {
 
 // Events per tile of a stream (Stream::T).
 hipError_t pick_tile(Stream &s, hipStream_t st) {
-    s.T = kTile;
+    const int cap = std::max(kMinTile, std::min(kTile, s.tile_cap));
+    s.T = cap;
     if (s.n <= kMinTile) return hipSuccess;
     const int64_t ng = (s.n + kMinTile - 1) / kMinTile + 1;
     DevBuf d;
@@ -264,7 +265,7 @@ hipError_t pick_tile(Stream &s, hipStream_t st) {
     }
     // the last sample is the last time (index n - 1)
     for (int64_t bound : {int64_t(1) << 28, int64_t(1) << 30}) {
-        for (int T = kTile; T >= kMinTile; T /= 2) {
+        for (int T = cap; T >= kMinTile; T /= 2) {
             if (longest_tile(g, s.n, T) < bound) {
                 s.T = T;
                 return hipSuccess;

@@ -170,6 +170,7 @@ struct Stream {
     // units (relative times of a tile then leave 3 bits for a node index in
     // a 31-bit key), else the largest spanning less than 2^30, else 2048.
     int T = kTile;      // events per tile
+    int tile_cap = kTile;  // largest T the stream may pick (the autotuner lowers it)
     int64_t B = 0;      // number of tiles
     DevBuf tiled_ts;    // T[B*T] (the last tile is padded)
     DevBuf tile_loff;   // uint16[B*(K+1)]

@@ -462,9 +462,9 @@ class Context:
         self._check(lib().epi_costmodel_load(self.h, str(path).encode()))
 
     def epi_autotune(self, set_ids, sched: int = EPI_SCHED_RR, cache_path=None):
-        """Returns (lanes, work items per compute unit)."""
+        """Returns (tile size, ring classes, lanes, segment target)."""
         ids = np.ascontiguousarray(np.atleast_1d(np.asarray(set_ids, np.int32)))
-        out = np.zeros(2, np.int64)
+        out = np.zeros(4, np.int64)
         cp = None if cache_path is None else str(cache_path).encode()
         self._check(lib().epi_autotune(self.h, _ptr(ids), ids.size, int(sched), cp, _ptr(out)))
-        return int(out[0]), int(out[1])
+        return tuple(int(x) for x in out)

@@ -219,20 +219,26 @@ def test_autotune_and_cache(ctx, tmp_path):
     sid = ctx.epi_load_stream(s["types"], s["times"], s["K"])
     cid = ctx.epi_submit_candidates(sid, c)
     cache = tmp_path / "tune.txt"
-    cache.write_text("garbage line\nts1_x 77 -3\n")  # malformed entries are ignored
+    cache.write_text("garbage line\nts1_x 77 -3\nts1_x 4096 0 0 262144\n")  # malformed entries are ignored
     try:
-        lanes, per_cu = ctx.epi_autotune([cid], epi.EPI_SCHED_RR, cache)
-        say(f"autotune: lanes={lanes} items/CU={per_cu}")
-        assert lanes in (64, 128, 256) and per_cu in (4, 8, 16, 32)
-        assert np.array_equal(ctx.epi_read_counts(cid, c["N"].size), want)
-        # the cache answers the second call
-        assert ctx.epi_autotune([cid], epi.EPI_SCHED_RR, cache) == (lanes, per_cu)
-        assert len(cache.read_text().splitlines()) == 3
-        ctx.epi_count([cid], mode=epi.EPI_MODE_BATCHED)
-        assert np.array_equal(ctx.epi_read_counts(cid, c["N"].size), want)
+        for sched in (epi.EPI_SCHED_RR, epi.EPI_SCHED_HEURISTIC):
+            chosen = ctx.epi_autotune([cid], sched, cache)
+            say(f"autotune sched={sched}: tile, ring classes, lanes, target = {chosen}")
+            tile, rings, lanes, target = chosen
+            assert tile in (2048, 1024, 512) and rings in (0, 1, 2) and lanes in (0, 64, 128)
+            assert target in (131072, 262144, 524288)
+            assert np.array_equal(ctx.epi_read_counts(cid, c["N"].size), want)
+            # the cache answers the second call
+            assert ctx.epi_autotune([cid], sched, cache) == chosen
+            ctx.epi_count([cid], mode=epi.EPI_MODE_BATCHED, sched=sched)
+            assert np.array_equal(ctx.epi_read_counts(cid, c["N"].size), want)
+            ctx.epi_count([cid], mode=epi.EPI_MODE_PLAIN)
+            assert np.array_equal(ctx.epi_read_counts(cid, c["N"].size), want)
+        assert len(cache.read_text().splitlines()) == 5
     finally:
         ctx.epi_set_option(epi.EPI_OPT_LANES, 0)
-        ctx.epi_set_option(epi.EPI_OPT_TARGET_ITEMS, 0)
+        ctx.epi_set_option(epi.EPI_OPT_RING_CLASSES, 0)
+        ctx.epi_set_option(epi.EPI_OPT_TARGET_LANES, 262144)
         ctx.epi_release_set(cid)
         ctx.epi_release_stream(sid)
 
