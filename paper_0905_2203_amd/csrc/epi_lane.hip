@@ -11,21 +11,26 @@
 // at or after the latest event) at once.  What differs is where the state
 // lives and what the step costs:
 //
-//   * each node has its own ring of exactly q_j entries (not the episode's
-//     deepest), laid out back to back per lane in LDS (lane-interleaved, so a
-//     wave-wide access to one entry index touches consecutive words); the
-//     ring's head and fill (4 bits each), capacity (4 bits) and base entry
-//     (8 bits) are bit fields of a few registers, selected by the node index
-//     with one shift;
+//   * node 0's admission test (a start only strictly after the last
+//     completion e) is a ring too: ring 0 holds the one interval (e, +inf],
+//     ring r >= 1 holds node r-1's records, i.e. node r's acceptance
+//     intervals; so every event, whatever its node j, queries ring j and, if
+//     covered, records into ring j+1 (or completes, at j = N-1): one path for
+//     every node, and a completion rewrites ring 0 and empties the others;
+//   * ring r >= 1 has exactly q_{r-1} entries (not the episode's deepest),
+//     the rings of a lane back to back and lane-interleaved in LDS (a
+//     wave-wide access to one entry index touches consecutive words); each
+//     ring's head and fill (4 bits each) are a byte of one 64-bit register,
+//     its capacity (4 bits) and base entry (8 bits) fields of two more,
+//     selected by the ring index with one shift;
 //   * dead intervals (end before the current time) are dropped lazily: a
 //     query skips them from the head; a record drops the head only when the
-//     ring is full, and then the head is dead (at most q_j - 1 intervals other
+//     ring is full, and then the head is dead (at most q - 1 intervals other
 //     than the new one can be live);
-//   * a completion empties every ring by clearing the fill fields (two
-//     register writes);
-//   * the lane's next event is the minimum over its N per-node heads; when
-//     relative times fit 28 bits, a head is the 31-bit key time * 8 + node and
-//     the minimum is N - 1 integer minimum instructions (PK).
+//   * each node's tile cursor and end are one packed register, its head the
+//     next event; the lane's next event is the minimum over the N heads; when
+//     relative times fit 28 bits, a head is the 31-bit key time * 8 + node
+//     and the minimum is N - 1 integer minimum instructions (PK).
 //
 // Times are int32 offsets from the first time of the tile being walked
 // (tiles are short enough: lane_rel_ok); at every tile the live intervals and
@@ -45,25 +50,6 @@ namespace epi {
 
 namespace {
 
-// 8-bit field k (k < 8) of the register pair (r0: fields 0-3, r1: 4-7).
-template <int NS>
-__device__ __forceinline__ uint32_t f8(uint32_t r0, uint32_t r1, int k) {
-    const uint32_t sh = (uint32_t)(k & 3) << 3;
-    if constexpr (NS <= 4) return (r0 >> sh) & 0xffu;
-    return ((k < 4 ? r0 : r1) >> sh) & 0xffu;
-}
-
-template <int NS>
-__device__ __forceinline__ void set8(uint32_t &r0, uint32_t &r1, int k, uint32_t v) {
-    const uint32_t sh = (uint32_t)(k & 3) << 3, m = 0xffu << sh;
-    if constexpr (NS <= 4) {
-        r0 = (r0 & ~m) | (v << sh);
-    } else {
-        if (k < 4) r0 = (r0 & ~m) | (v << sh);
-        else r1 = (r1 & ~m) | (v << sh);
-    }
-}
-
 template <typename T, int N, bool PK>
 __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, int p, int64_t item,
                                           unsigned char *smem) {
@@ -72,7 +58,6 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
     constexpr T kEnd = TsLimits<T>::hi();
     constexpr R rEnd = INT32_MAX;
     constexpr int L = N > 1 ? N - 1 : 1;  // interval slots (array size)
-    constexpr int NS = N > 1 ? N - 1 : 1;
     const int W = blockDim.x, lane = threadIdx.x;
     const int64_t s = blk * W + lane;
     const bool active = s < a.G;
@@ -86,13 +71,18 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
     int2 *rl = reinterpret_cast<int2 *>(smem + a.off_qse) + lane;
     const int wsh = 31 - __clz(W);
 
-    // the episode: types, interval bounds, ring capacities and bases
+    // the episode: types, interval bounds, ring capacities and bases.  Ring 0
+    // is node 0's: the one interval (e, +inf] of the starts the machine admits
+    // (e: the last completion); ring r >= 1 holds node r-1's records, i.e. the
+    // acceptance intervals of node r.  A query at node j reads ring j, a record
+    // at node j < N-1 writes ring j+1: one path for every node.
     int32_t ty[N];
     R loR[L], hiR[L];
     T H = 0;
-    uint32_t qpk = 0, bp0 = 0, bp1 = 0;
+    uint32_t capk = 1;   // 4 bits per ring: capacity
+    uint64_t basek = 0;  // 8 bits per ring: first entry
     {
-        uint32_t base = 0;
+        uint32_t base = 1;
 #pragma unroll
         for (int k = 0; k < N; ++k) ty[k] = a.t16 ? (int32_t)a.t16[(int64_t)k * a.m + slot] : a.ctypes[(int64_t)k * a.m + slot];
 #pragma unroll
@@ -114,12 +104,13 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 atomicAdd(&a.flags[kFlagQueueOverflow], 1);
                 q = kLaneMaxQ;
             }
-            qpk |= q << (4 * k);
-            set8<NS>(bp0, bp1, k, base);
+            capk |= q << (4 * (k + 1));
+            basek |= (uint64_t)base << (8 * (k + 1));
             base += q;
         }
     }
-    uint32_t hn0 = 0, hn1 = 0;  // per ring: head | fill << 4
+    // per ring: head (4 bits) | fill << 4, 8 bits each
+    uint64_t hf = uint64_t(1) << 4;  // ring 0 holds its interval
 
     const int64_t b0 = (int64_t)p * a.S;
     const int64_t b1 = b0 + a.S < a.B ? b0 + a.S : a.B;
@@ -158,10 +149,11 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
 
     // origin of the relative times: the first time of the tile walked
     T t0b = a.tile_t0[bs];
-    R e;  // last completion, relative
     {
-        const bool before = e0 < t0b && (uint64_t)t0b - (uint64_t)e0 > 2u;
-        e = before ? R(-2) : (R)(int64_t)((uint64_t)e0 - (uint64_t)t0b);
+        // ring 0's interval (e, +inf]; any e before the origin reads as -1
+        const bool before = e0 < t0b && (uint64_t)t0b - (uint64_t)e0 > 1u;
+        const R e = before ? R(-1) : (R)(int64_t)((uint64_t)e0 - (uint64_t)t0b);
+        if (active) rl[0] = make_int2(e, rEnd);
     }
     int32_t cnt = 0;
     T last = kMin;
@@ -171,19 +163,21 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
         const T nb = a.tile_t0[b];
         const R d = (R)(nb - t0b);  // the previous tile's span (0 for the first)
         if (d != 0 && active) {
+            // move every live interval by the span: starts before the new
+            // origin read as -1, ends as -2 (ring 0's +inf end stays)
 #pragma unroll
-            for (int k = 0; k + 1 < N; ++k) {
-                const uint32_t hn = f8<NS>(hn0, hn1, k), Q = (qpk >> (4 * k)) & 15u, base = f8<NS>(bp0, bp1, k);
-                uint32_t hd = hn & 15u;
-                for (uint32_t i = 0; i < (hn >> 4); ++i) {
+            for (int r = 0; r < N; ++r) {
+                const uint32_t m = (uint32_t)(hf >> (8 * r)) & 0xffu;
+                const uint32_t Q = (capk >> (4 * r)) & 15u, base = (uint32_t)(basek >> (8 * r)) & 0xffu;
+                uint32_t hd = m & 15u;
+                for (uint32_t i = 0; i < (m >> 4); ++i) {
                     int2 &v = rl[(int)(base + hd) << wsh];
                     const R vs = v.x - d, ve = v.y - d;
                     v.x = vs < R(-1) ? R(-1) : vs;
-                    v.y = ve < R(-2) ? R(-2) : ve;
+                    v.y = v.y == rEnd ? rEnd : (ve < R(-2) ? R(-2) : ve);
                     hd = hd + 1 == Q ? 0u : hd + 1;
                 }
             }
-            e = e - d < R(-2) ? R(-2) : (R)(e - d);
         }
         t0b = nb;
         {
@@ -199,16 +193,14 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
         for (int i = lane; i <= a.K; i += W) obuf[i] = a.loff[b * (a.K + 1) + i];
         __syncthreads();
         if (!active) continue;
-        int cur[N], stp[N];
+        // per node: tile cursor | end << 16, and the head (next event)
+        uint32_t cs[N];
         R head[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            cur[k] = obuf[ty[k]];
-            stp[k] = obuf[ty[k] + 1];
-        }
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            R v = cur[k] < stp[k] ? tbuf[cur[k]] : rEnd;
+            const uint32_t c = obuf[ty[k]], st = obuf[ty[k] + 1];
+            cs[k] = c | st << 16;
+            R v = c < st ? tbuf[c] : rEnd;
             v = v < EpR ? v : rEnd;
             head[k] = PK ? (v == rEnd ? rEnd : (R)((v << 3) | k)) : v;
         }
@@ -236,107 +228,93 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 if (t == rEnd) break;
             }
             ++w_visits;
-            bool done = false;
-            if constexpr (N == 1) {
-                if (t > e) {
-                    e = t;
-                    done = true;
+            // query ring j: skip dead intervals from the head; t is covered iff
+            // the first live one starts before it (ring 0: iff t > e)
+            w_queries += j > 0 ? 1u : 0u;
+            bool ok;
+            {
+                const uint32_t sh = 8u * (uint32_t)j;
+                const uint32_t m = (uint32_t)(hf >> sh) & 0xffu;
+                const uint32_t Q = (capk >> (4 * j)) & 15u, base = (uint32_t)(basek >> sh) & 0xffu;
+                uint32_t hd = m & 15u, n = m >> 4;
+                int2 f = make_int2(0, 0);
+                while (n > 0) {
+                    f = rl[(int)(base + hd) << wsh];
+                    if (f.y >= t) break;
+                    hd = hd + 1 == Q ? 0u : hd + 1;
+                    --n;
                 }
-            } else {
-                bool ok;
-                if (j == 0) {
-                    ok = t > e;
-                } else {
-                    // query the ring of node j - 1: drop dead intervals from the head,
-                    // then t is covered iff the first live one starts before it
-                    ++w_queries;
-                    const int q = j - 1;
-                    const uint32_t hn = f8<NS>(hn0, hn1, q), Q = (qpk >> (4 * q)) & 15u, base = f8<NS>(bp0, bp1, q);
-                    uint32_t hd = hn & 15u, n = hn >> 4;
-                    int2 f = make_int2(0, 0);
-                    while (n > 0) {
-                        f = rl[(int)(base + hd) << wsh];
-                        if (f.y >= t) break;
-                        hd = hd + 1 == Q ? 0u : hd + 1;
-                        --n;
-                    }
-                    ok = n > 0 && f.x < t;
-                    const uint32_t nh = hd | (n << 4);
-                    if (nh != hn) set8<NS>(hn0, hn1, q, nh);
-                }
-                if (ok) {
-                    if (j == N - 1) {
-                        e = t;
-                        done = true;
-                        hn0 = 0;
-                        hn1 = 0;
-                    } else {
-                        // record at node j: merge into the newest interval when they
-                        // touch, else append (dropping the head, dead, when full)
-                        ++w_records;
-                        R lj = loR[0], hj = hiR[0];
-#pragma unroll
-                        for (int k = 1; k + 1 < N; ++k) {
-                            if (k == j) {
-                                lj = loR[k];
-                                hj = hiR[k];
-                            }
-                        }
-                        const R ns = t + lj, ne = t + hj;
-                        const uint32_t hn = f8<NS>(hn0, hn1, j), Q = (qpk >> (4 * j)) & 15u,
-                                       base = f8<NS>(bp0, bp1, j);
-                        uint32_t hd = hn & 15u, n = hn >> 4;
-                        bool merged = Q == 0;  // (no ring: never, j < N - 1)
-                        if (n > 0 && !merged) {
-                            uint32_t bk = hd + n - 1;
-                            if (bk >= Q) bk -= Q;
-                            int2 &be = rl[(int)(base + bk) << wsh];
-                            if (ns <= be.y) {
-                                be.y = ne;
-                                merged = true;
-                            }
-                        }
-                        if (!merged) {
-                            if (n == Q) {
-                                hd = hd + 1 == Q ? 0u : hd + 1;
-                                --n;
-                            }
-                            uint32_t tl = hd + n;
-                            if (tl >= Q) tl -= Q;
-                            rl[(int)(base + tl) << wsh] = make_int2(ns, ne);
-                            ++n;
-                            w_maxq = n > w_maxq ? n : w_maxq;
-                            set8<NS>(hn0, hn1, j, hd | (n << 4));
-                        }
-                    }
-                }
+                ok = n > 0 && f.x < t;
+                const uint32_t nm = hd | (n << 4);
+                if (nm != m) hf = (hf & ~(uint64_t(0xff) << sh)) | ((uint64_t)nm << sh);
             }
-            if (done) {
-                ++w_done;
-                if (t >= BpR) {
-                    const T ta = (T)t + t0b;  // absolute
-                    if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = ta;
-                    ++cnt;
-                    last = ta;
+            if (ok) {
+                if (j == N - 1) {
+                    // completion: ring 0 becomes (t, +inf], every other ring empties
+                    rl[0] = make_int2(t, rEnd);
+                    hf = uint64_t(1) << 4;
+                    ++w_done;
+                    if (t >= BpR) {
+                        const T ta = (T)t + t0b;  // absolute
+                        if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = ta;
+                        ++cnt;
+                        last = ta;
+                    }
+                } else {
+                    // record at node j into ring j+1: merge into its newest
+                    // interval when they touch, else append (dropping the
+                    // head, dead, when full)
+                    ++w_records;
+                    R lj = loR[0], hj = hiR[0];
+#pragma unroll
+                    for (int k = 1; k + 1 < N; ++k) {
+                        if (k == j) {
+                            lj = loR[k];
+                            hj = hiR[k];
+                        }
+                    }
+                    const R ns = t + lj, ne = t + hj;
+                    const uint32_t r = (uint32_t)j + 1u, sh = 8u * r;
+                    const uint32_t m = (uint32_t)(hf >> sh) & 0xffu;
+                    const uint32_t Q = (capk >> (4 * r)) & 15u, base = (uint32_t)(basek >> sh) & 0xffu;
+                    uint32_t hd = m & 15u, n = m >> 4;
+                    bool merged = false;
+                    if (n > 0) {
+                        uint32_t bk = hd + n - 1;
+                        if (bk >= Q) bk -= Q;
+                        int2 &be = rl[(int)(base + bk) << wsh];
+                        if (ns <= be.y) {
+                            be.y = ne;
+                            merged = true;
+                        }
+                    }
+                    if (!merged) {
+                        if (n == Q) {
+                            hd = hd + 1 == Q ? 0u : hd + 1;
+                            --n;
+                        }
+                        uint32_t tl = hd + n;
+                        if (tl >= Q) tl -= Q;
+                        rl[(int)(base + tl) << wsh] = make_int2(ns, ne);
+                        ++n;
+                        w_maxq = n > w_maxq ? n : w_maxq;
+                        hf = (hf & ~(uint64_t(0xff) << sh)) | ((uint64_t)(hd | (n << 4)) << sh);
+                    }
                 }
             }
             // advance node j
-            int c = cur[0], st = stp[0];
+            uint32_t c = cs[0];
 #pragma unroll
-            for (int k = 1; k < N; ++k) {
-                if (k == j) {
-                    c = cur[k];
-                    st = stp[k];
-                }
-            }
-            ++c;
-            R v = c < st ? tbuf[c] : rEnd;
+            for (int k = 1; k < N; ++k) c = k == j ? cs[k] : c;
+            c += 1u;
+            const uint32_t cl = c & 0xffffu;
+            R v = cl < (c >> 16) ? tbuf[cl] : rEnd;
             v = v < EpR ? v : rEnd;
             const R nk = PK ? (v == rEnd ? rEnd : (R)((v << 3) | j)) : v;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 if (k == j) {
-                    cur[k] = c;
+                    cs[k] = c;
                     head[k] = nk;
                 }
             }
@@ -428,7 +406,7 @@ LaneLayout lane_layout(int C, int W, int K, int tile) {
     LaneLayout L;
     size_t o = 0;
     L.off_ring = (uint32_t)o;
-    o += al16((size_t)(C > 0 ? C : 1) * W * sizeof(int2));
+    o += al16((size_t)((C > 0 ? C : 1) + 1) * W * sizeof(int2));  // + ring 0 (node 0's starts)
     L.off_tbuf = (uint32_t)o;
     o += al16((size_t)tile * sizeof(int32_t));
     L.off_obuf = (uint32_t)o;
