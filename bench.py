@@ -350,7 +350,8 @@ def large_bench(args):
         if args.no_tune:
             return
         a = time.perf_counter()
-        tuned[name] = dict(zip(("tile", "ring_classes", "lanes", "target_lanes"), ctx.epi_autotune([cid], sched)))
+        tuned[name] = dict(zip(("tile", "ring_classes", "lanes", "target_lanes"),
+                               ctx.epi_autotune([cid], sched, args.tune_cache or None)))
         tuned[name]["seconds"] = round(time.perf_counter() - a, 1)
         log(f"  autotuned for {name}: {tuned[name]}")
 
@@ -505,6 +506,7 @@ def main():
     ap.add_argument("--learned-only", action="store_true",
                     help="Large line: time only the batched + learned leg (profiling runs)")
     ap.add_argument("--no-tune", action="store_true", help="Large line: engine defaults, no autotuning")
+    ap.add_argument("--tune-cache", default="", help="Large line: autotuner cache file (read, else written)")
     ap.add_argument("--costmodel-in", default="", help="Large line: load the cost model from this file")
     ap.add_argument("--costmodel-out", default="", help="Large line: save the trained cost model to this file")
     ap.add_argument("--calibrate-copy", action="store_true",
