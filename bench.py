@@ -92,10 +92,12 @@ def _timed(ctx, fn, reps):
     return float(np.median(out))
 
 
-def ablation(k, scale, reps, lane_engine=1, ring_classes=0):
+def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False):
     """Plain engine vs the batched persistent engine under round-robin, the
     event-count heuristic and the learned cost model, on workload preset k.
-    Every mode's counts are checked equal; one JSON line per preset."""
+    Every mode's counts are checked equal; one JSON line per preset.  With
+    tune, the batched legs run autotuned (round robin tuned for itself, the
+    heuristic and measured schedules with the learned schedule's setting)."""
     import spikegen as sg
     from paper_0905_2203_amd import epi
 
@@ -129,12 +131,16 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0):
     def counts():
         return [ctx.epi_read_counts(cid, c["N"].size) for cid, (_, c) in zip(cids, sets)]
 
+    tuned = {}
     res["plain"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_PLAIN), reps)
     ref = counts()
-    for name, sched in (("batched_rr", epi.EPI_SCHED_RR), ("batched_heuristic", epi.EPI_SCHED_HEURISTIC)):
-        res[name] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=sched), reps)
-        assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), name
-        log(f"  {name}: {res[name]:.3f}s")
+    if tune:
+        tuned["batched_rr"] = ctx.epi_autotune(cids, epi.EPI_SCHED_RR)
+        log(f"  tuned for round robin: {tuned['batched_rr']}")
+    res["batched_rr"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR),
+                               reps)
+    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "batched_rr"
+    log(f"  batched_rr: {res['batched_rr']:.3f}s")
     # learned: work log of disjoint training candidates on the same streams
     ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
     ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)  # log each episode's own work
@@ -145,9 +151,15 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0):
     train_s = time.perf_counter() - a
     ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
     ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+    if tune:
+        tuned["batched_learned"] = ctx.epi_autotune(cids, epi.EPI_SCHED_LEARNED)
+        log(f"  tuned for the learned schedule: {tuned['batched_learned']}")
     res["batched_learned"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
                                                                sched=epi.EPI_SCHED_LEARNED), reps)
     assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "learned"
+    res["batched_heuristic"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                                 sched=epi.EPI_SCHED_HEURISTIC), reps)
+    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "heuristic"
     log(f"  plain {res['plain']:.3f}s learned {res['batched_learned']:.3f}s (training {train_s:.1f}s)")
     # measured: the schedule by each episode's own logged work (an exact cost model)
     ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
@@ -198,7 +210,7 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0):
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s", "lane_engine": lane_engine,
-        "ring_classes": ring_classes,
+        "ring_classes": ring_classes, "tuned": tuned,
         "value": {m: units / t for m, t in res.items()},
         "seconds": res,
         "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
@@ -514,6 +526,7 @@ def main():
     ap.add_argument("--ablation", default="",
                     help="comma list of workload presets (1, 3, 4, 5): plain vs batched schedules, one JSON line each")
     ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
+    ap.add_argument("--abl-tune", action="store_true", help="ablation: autotune the batched legs")
     ap.add_argument("--lane-engine", type=int, default=1,
                     help="ablation: 1 = register-indexed lane machines where they apply, 0 = LDS-ring machines")
     ap.add_argument("--ring-classes", type=int, default=-1,
@@ -527,7 +540,8 @@ def main():
         return
     if args.ablation:
         for k in [int(x) for x in args.ablation.split(",") if x]:
-            ablation(k, args.abl_scale, max(1, args.steps), args.lane_engine, max(0, args.ring_classes))
+            ablation(k, args.abl_scale, max(1, args.steps), args.lane_engine, max(0, args.ring_classes),
+                     args.abl_tune)
         return
     if args.calibrate_copy:
         import torch

@@ -1512,19 +1512,27 @@ epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sch
         float best_ms = INFINITY;
         epi_status v = trial(best, &best_ms);
         const int64_t menus[4][3] = {{2048, 1024, 512}, {0, 1, 2}, {0, 128, 64}, {131072, 262144, 524288}};
-        for (int d = 0; v == EPI_OK && d < 4; ++d) {
-            for (int64_t x : menus[d]) {
-                TuneSetting t = best;
-                int64_t *field = d == 0 ? &t.tile : d == 1 ? &t.rings : d == 2 ? &t.lanes : &t.target;
-                if (*field == x) continue;
-                *field = x;
-                float ms = INFINITY;
-                if ((v = trial(t, &ms)) != EPI_OK) break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
+        // a second pass when the first moved (the knobs interact: wider
+        // groups change which lane width keeps the most waves resident)
+        for (int pass = 0; v == EPI_OK && pass < 2; ++pass) {
+            const TuneSetting start = best;
+            for (int d = 0; v == EPI_OK && d < 4; ++d) {
+                for (int64_t x : menus[d]) {
+                    TuneSetting t = best;
+                    int64_t *field = d == 0 ? &t.tile : d == 1 ? &t.rings : d == 2 ? &t.lanes : &t.target;
+                    if (*field == x) continue;
+                    *field = x;
+                    float ms = INFINITY;
+                    if ((v = trial(t, &ms)) != EPI_OK) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = t;
+                    }
                 }
             }
+            if (best.tile == start.tile && best.rings == start.rings && best.lanes == start.lanes &&
+                best.target == start.target)
+                break;
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
