@@ -363,3 +363,50 @@ def test_learned_schedule_gain(ctx, rings):
         ctx.epi_release_set(tid)
         ctx.epi_release_set(cid)
         ctx.epi_release_stream(sid)
+
+
+def test_heuristic_schedule_is_a_stable_cost_sort(ctx):
+    """The device scheduler's order, pinned exactly: with the heuristic cost
+    (the summed event counts of an episode's types, an integer the host can
+    compute) every launch group's lanes hold its episodes sorted by descending
+    cost, equal costs in submission order (the radix sort is stable), and the
+    groups stay where round robin puts them.  Two sets on two streams, so the
+    global slot order spans sets."""
+    recs = _recordings(n_rec=2)
+    sids, cids = [], []
+    for s, c in recs:
+        sids.append(ctx.epi_load_stream(s["types"], s["times"], s["K"]))
+        cids.append(ctx.epi_submit_candidates(sids[-1], c))
+    try:
+        ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
+        rr = [ctx.epi_read_schedule(cid, c["N"].size) for cid, (_, c) in zip(cids, recs)]
+        ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_HEURISTIC)
+        for (s, c), cid, (rr_order, rr_block) in zip(recs, cids, rr):
+            m = c["N"].size
+            assert np.array_equal(ctx.epi_read_counts(cid, m), oracle.count(s, c))
+            order, block = ctx.epi_read_schedule(cid, m)
+            assert np.array_equal(block, rr_block)  # same lane blocks
+            cnt = np.bincount(s["types"], minlength=s["K"])
+            cost = np.array([cnt[c["types"][i, :c["N"][i]]].sum() for i in range(m)])
+            # launch groups (the submission groups): episode size x class of
+            # ring entries (the sum over intervals of 1 + hi // (hi - lo + 1),
+            # rounded up to 1..8, 10, 12, 14, 16, 20, ..., 112); in the
+            # round-robin lane order each group is a run, in submission order
+            live = np.arange(7)[None, :] < (c["N"].astype(np.int64) - 1)[:, None]
+            ring = np.where(live, 1 + c["hi"] // np.maximum(c["hi"] - c["lo"] + 1, 1), 0).sum(axis=1)
+            caps = np.array([1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 112])
+            key = c["N"].astype(np.int64) * 64 + np.searchsorted(caps, np.maximum(ring, 1))
+            k_rr = key[rr_order]
+            assert np.all(np.diff(k_rr) >= 0)
+            grp = np.concatenate([[0], np.cumsum(k_rr[1:] != k_rr[:-1])])
+            for g in np.unique(grp):
+                sl = np.flatnonzero(grp == g)
+                members = rr_order[sl]  # submission order
+                want = members[np.argsort(-cost[members], kind="stable")]
+                assert np.array_equal(order[sl], want), f"group {g}"
+        say(f"heuristic lane order equals a stable descending sort of the summed type counts in every group")
+    finally:
+        for cid in cids:
+            ctx.epi_release_set(cid)
+        for sid in sids:
+            ctx.epi_release_stream(sid)
