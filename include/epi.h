@@ -308,7 +308,7 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
  * (largest events per tile {2048, 1024, 512}; the streams are re-tiled), the
  * launch groups (EPI_OPT_RING_CLASSES {0, 1, 2}), lanes per workgroup
  * (EPI_OPT_LANES {automatic, 128, 64}) and the segment target
- * (EPI_OPT_TARGET_LANES {131072, 262144, 524288}), and once more over the
+ * (EPI_OPT_TARGET_LANES {131072, 524288, 1048576}), and once more over the
  * four when the first pass moved.  Each trial builds the
  * batched plan, then times one replay with hipEvents; the counts do not
  * depend on the setting.  The fastest is kept: the streams stay re-tiled and

@@ -1511,7 +1511,7 @@ epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sch
         };
         float best_ms = INFINITY;
         epi_status v = trial(best, &best_ms);
-        const int64_t menus[4][3] = {{2048, 1024, 512}, {0, 1, 2}, {0, 128, 64}, {131072, 262144, 524288}};
+        const int64_t menus[4][3] = {{2048, 1024, 512}, {0, 1, 2}, {0, 128, 64}, {131072, 524288, 1048576}};
         // a second pass when the first moved (the knobs interact: wider
         // groups change which lane width keeps the most waves resident)
         for (int pass = 0; v == EPI_OK && pass < 2; ++pass) {
