@@ -225,6 +225,7 @@ hipError_t upload_candidates(CandSet &cs, int64_t m, const uint8_t *N, const int
             hipSuccess)
             return e;
     }
+    cs.h_order = order;
     // host staging vectors die here: wait for the copies
     return hipStreamSynchronize(st);
 }

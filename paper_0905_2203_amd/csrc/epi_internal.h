@@ -250,6 +250,7 @@ struct CandSet {
     // host copy of the candidates (submission order; not for the compact
     // layout): sizes [m], types [m][8], lo and hi [m][7]
     std::vector<uint8_t> h_N;
+    std::vector<int32_t> h_order;  // grouped slot -> submission index (the host copy of orig)
     std::vector<int32_t> h_types;
     std::vector<int64_t> h_lo, h_hi;
     DevBuf track_work, track_desc;  // working set of the tracking engine, kept for the next count

@@ -1503,20 +1503,36 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
     }
     std::vector<WorkItem> tmpl;
     std::vector<int64_t> ioff(kClasses + 1, 0);
-    std::vector<double> ccost(kClasses, 0.0);  // items per class (the branch balance)
+    // the branch balance: each class's work as the summed event counts of
+    // its episodes' types (the events its lanes visit), from host copies
+    std::vector<double> ccost(kClasses, 0.0);
+    for (size_t ui = 0; ui < units.size(); ++ui) {
+        const UnitH &u = units[ui];
+        const Stream &s = *sets[u.set].s;
+        const CandSet &c = *sets[u.set].c;
+        double w = 0;
+        if (!c.compact && (int64_t)c.h_N.size() == c.m && (int64_t)s.h_off.size() == (int64_t)s.K + 1) {
+            // slots -> submission indices are the set's grouping order; the
+            // unit's slots hold the candidates of one launch group, whose
+            // work the host knows per candidate
+            for (int64_t i = 0; i < u.G; ++i) {
+                const int64_t o = c.h_order.empty() ? u.begin + i : c.h_order[u.begin + i];
+                const int32_t *ty = c.h_types.data() + o * kMaxN;
+                for (int j = 0; j < c.h_N[o]; ++j) w += (double)(s.h_off[ty[j] + 1] - s.h_off[ty[j]]);
+            }
+        } else {
+            w = (double)u.G * (double)u.N * (double)s.n / std::max(1.0, (double)s.K);
+        }
+        ccost[cls_of(u)] += w;
+    }
     for (int cl = 0; cl < kClasses; ++cl) {
         ioff[cl] = (int64_t)tmpl.size();
         for (size_t ui = 0; ui < units.size(); ++ui) {
             const UnitH &u = units[ui];
             if (cls_of(u) != cl) continue;
             const int64_t nb = (u.G + Wn[cl] - 1) / Wn[cl];
-            for (int64_t b = 0; b < nb; ++b) {
-                const auto &s = *sets[u.set].s;
-                // a lane block's items cost about its lanes' visits: weight the
-                // branch balance by the stream's events per segment
-                ccost[cl] += (double)std::min<int64_t>(Wn[cl], u.G - b * Wn[cl]) * (double)s.n / 64.0;
+            for (int64_t b = 0; b < nb; ++b)
                 for (int64_t p = 0; p < u.P; ++p) tmpl.push_back(WorkItem{(int32_t)ui, (int32_t)p, b});
-            }
         }
     }
     ioff[kClasses] = (int64_t)tmpl.size();
@@ -1608,6 +1624,18 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
     }
     if (e == hipSuccess) e = hipEventRecord(cache.fork, st);
     for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(cache.br[i], cache.fork, 0);
+    // the segmented units of a class are reconciled on the class's branch as
+    // soon as its persistent kernel ends (their records are all written by
+    // it), overlapping the other branches' kernels
+    auto reconcile_class = [&](int cl, hipStream_t bst) -> hipError_t {
+        for (size_t ui = 0; ui < units.size(); ++ui) {
+            if (units[ui].P <= 1 || cls_of(units[ui]) != cl) continue;
+            const int N = units[ui].N;
+            const hipError_t x = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), bst);
+            if (x != hipSuccess) return x;
+        }
+        return hipSuccess;
+    };
     std::vector<double> load(nb, 0.0);
     for (int cl : border) {
         if (e != hipSuccess) break;
@@ -1630,6 +1658,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
             e = lane_launch_persistent<T>(N, pkN[cl], (unsigned)grid, Wn[cl], L.total, cache.br[bi],
                                           plan.units.as<CountArgs<T>>(), plan.items.as<WorkItem>() + ioff[cl], ncl,
                                           ioff[cl], plan.queue.as<unsigned long long>() + cl);
+            if (e == hipSuccess) e = reconcile_class(cl, cache.br[bi]);
             continue;
         }
         PFn<T> fn = filtN[cl] ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
@@ -1647,19 +1676,14 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
                                                              plan.items.as<WorkItem>() + ioff[cl], ncl, ioff[cl],
                                                              plan.queue.as<unsigned long long>() + cl);
         e = hipGetLastError();
+        if (e == hipSuccess) e = reconcile_class(cl, cache.br[bi]);
     }
-    // every branch joins back before the reconciliation (also after an
-    // error, so that the capture ends cleanly)
+    // every branch joins back (also after an error, so that the capture ends
+    // cleanly)
     for (int i = 0; i < nb; ++i) {
         hipError_t ej = hipEventRecord(cache.joined[i], cache.br[i]);
         if (ej == hipSuccess) ej = hipStreamWaitEvent(st, cache.joined[i], 0);
         if (e == hipSuccess) e = ej;
-    }
-    for (size_t ui = 0; ui < units.size() && e == hipSuccess; ++ui) {
-        if (units[ui].P <= 1) continue;
-        const int N = units[ui].N;
-        const int cl = cls_of(units[ui]);
-        e = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), st);
     }
     hipError_t ec = hipStreamEndCapture(st, &plan.graph);
     if (e == hipSuccess) e = ec;
