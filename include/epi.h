@@ -305,7 +305,8 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
 
 /* Autotune the batched engine for these sets and schedule by coordinate
  * descent from the defaults, one knob at a time: the streams' tile size
- * (largest events per tile {2048, 1024, 512}; the streams are re-tiled), the
+ * (largest events per tile: the default 2048, then {4096, 1024, 512}; the
+ * streams are re-tiled), the
  * launch groups (EPI_OPT_RING_CLASSES {0, 1, 2}), lanes per workgroup
  * (EPI_OPT_LANES {automatic, 128, 64}) and the segment target
  * (EPI_OPT_TARGET_LANES {131072, 524288, 1048576}), and once more over the

@@ -1402,14 +1402,15 @@ std::string tune_key(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sched)
 
 // One tuned setting of the batched engine.
 struct TuneSetting {
-    int64_t tile = kTile;        // largest events per tile of the sets' streams
+    int64_t tile = kDefaultTile; // largest events per tile of the sets' streams
     int64_t rings = 0;           // EPI_OPT_RING_CLASSES
     int64_t lanes = 0;           // EPI_OPT_LANES (0: automatic)
     int64_t target = 262144;     // EPI_OPT_TARGET_LANES
 };
 
 bool tune_valid(const TuneSetting &t) {
-    return (t.tile == 2048 || t.tile == 1024 || t.tile == 512 || t.tile == 256) && t.rings >= 0 && t.rings <= 2 &&
+    return (t.tile == 4096 || t.tile == 2048 || t.tile == 1024 || t.tile == 512 || t.tile == 256) && t.rings >= 0 &&
+           t.rings <= 2 &&
            (t.lanes == 0 || t.lanes == 64 || t.lanes == 128 || t.lanes == 256) && t.target >= 1024 &&
            t.target <= (int64_t(1) << 26);
 }
@@ -1512,7 +1513,7 @@ epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sch
         };
         float best_ms = INFINITY;
         epi_status v = trial(best, &best_ms);
-        const int64_t menus[4][3] = {{2048, 1024, 512}, {0, 1, 2}, {0, 128, 64}, {131072, 524288, 1048576}};
+        const int64_t menus[4][3] = {{4096, 1024, 512}, {0, 1, 2}, {0, 128, 64}, {131072, 524288, 1048576}};
         // a second pass when the first moved (the knobs interact: wider
         // groups change which lane width keeps the most waves resident)
         for (int pass = 0; v == EPI_OK && pass < 2; ++pass) {

@@ -107,15 +107,18 @@ hipError_t measured_costs(const CandSet &c, hipStream_t st);
 // ---- register-indexed lane machines (epi_lane.hip) --------------------------
 // A group of episodes can be counted by them when the stream's tiles are
 // short enough for int32 relative times (lane_rel_ok) and every interval's
-// ring bound is at most kLaneMaxQ.  pk: relative times fit 28 bits, so
-// (time, node) pack into one 31-bit key.
+// ring bound is at most kLaneMaxQ.  pk: relative times stay below 2^29 - 1,
+// so (time, node) pack into one 32-bit unsigned key below its all-ones end
+// marker.
 constexpr int kLaneMaxQ = 15;
 
 inline bool lane_rel_ok(int64_t max_tile_span, int64_t hspan) {
     return max_tile_span >= 0 && hspan >= 0 && hspan < (int64_t(1) << 29) && max_tile_span < (int64_t(1) << 30) &&
            max_tile_span + 2 * hspan < (int64_t(1) << 31) - 64;
 }
-inline bool lane_pk_ok(int64_t max_tile_span) { return max_tile_span >= 0 && max_tile_span < (int64_t(1) << 28); }
+inline bool lane_pk_ok(int64_t max_tile_span) {
+    return max_tile_span >= 0 && max_tile_span < (int64_t(1) << 29) - 1;
+}
 
 // Ring entries of an episode: sum over its intervals of the ring bound.
 inline int lane_ring_entries(int N, const int64_t *lo, const int64_t *hi) {

@@ -264,7 +264,7 @@ hipError_t pick_tile(Stream &s, hipStream_t st) {
         for (int64_t i = 0; i < ng; ++i) g[i] = g32[i];
     }
     // the last sample is the last time (index n - 1)
-    for (int64_t bound : {int64_t(1) << 28, int64_t(1) << 30}) {
+    for (int64_t bound : {(int64_t(1) << 29) - 1, int64_t(1) << 30}) {
         for (int T = cap; T >= kMinTile; T /= 2) {
             if (longest_tile(g, s.n, T) < bound) {
                 s.T = T;

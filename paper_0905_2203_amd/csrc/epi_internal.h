@@ -17,7 +17,8 @@ namespace epi {
 constexpr int kMaxN = EPI_MAX_N;
 constexpr int kMaxK = 4096;        // LDS histogram bound of the index build
 constexpr int kMaxQueue = 16;      // deepest merged-interval ring (LDS) per node
-constexpr int kTile = 2048;        // largest number of events per stream tile (the stream picks its own, Stream::T)
+constexpr int kTile = 4096;        // largest number of events per stream tile (the stream picks its own, Stream::T)
+constexpr int kDefaultTile = 2048; // largest a stream picks unless the autotuner raises or lowers it
 constexpr int kMinTile = 256;      // smallest tile a stream may pick
 constexpr int kMlpHidden = 64;     // hidden units of the cost model
 constexpr int kFeatures = 24;      // cost-model features per candidate
@@ -166,11 +167,12 @@ struct Stream {
     // Tile-major copy of the index: tile b holds stream positions
     // [b*T, (b+1)*T); inside a tile the events are grouped by type (each
     // group in time order) starting at tile_loff[b*(K+1) + type].  T is the
-    // largest of 2048, 1024, 512, 256 whose tiles span less than 2^28 time
-    // units (relative times of a tile then leave 3 bits for a node index in
-    // a 31-bit key), else the largest spanning less than 2^30, else 2048.
-    int T = kTile;      // events per tile
-    int tile_cap = kTile;  // largest T the stream may pick (the autotuner lowers it)
+    // largest power of two from tile_cap down to 256 whose tiles span less
+    // than 2^29 - 1 time units (relative times of a tile then leave 3 bits
+    // for a node index in a 32-bit unsigned key), else the largest spanning
+    // less than 2^30, else tile_cap.
+    int T = kDefaultTile;  // events per tile
+    int tile_cap = kDefaultTile;  // largest T the stream may pick (the autotuner sets it)
     int64_t B = 0;      // number of tiles
     DevBuf tiled_ts;    // T[B*T] (the last tile is padded)
     DevBuf tile_loff;   // uint16[B*(K+1)]

@@ -29,8 +29,9 @@
 //     than the new one can be live);
 //   * each node's tile cursor and end are one packed register, its head the
 //     next event; the lane's next event is the minimum over the N heads; when
-//     relative times fit 28 bits, a head is the 31-bit key time * 8 + node
-//     and the minimum is N - 1 integer minimum instructions (PK).
+//     relative times stay below 2^29 - 1, a head is the 32-bit unsigned key
+//     time * 8 + node and the minimum is N - 1 integer minimum instructions
+//     (PK).
 //
 // Times are int32 offsets from the first time of the tile being walked
 // (tiles are short enough: lane_rel_ok); at every tile the live intervals and
@@ -54,6 +55,10 @@ template <typename T, int N, bool PK>
 __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, int p, int64_t item,
                                           unsigned char *smem) {
     using R = int32_t;
+    // heads: PK, the unsigned key time * 8 + node (times below 2^29 - 1),
+    // all ones when the node has no event left; else the relative time
+    using HK = std::conditional_t<PK, uint32_t, int32_t>;
+    constexpr HK kNoHead = PK ? HK(0xffffffffu) : HK(INT32_MAX);
     constexpr T kMin = TsLimits<T>::lo();
     constexpr T kEnd = TsLimits<T>::hi();
     constexpr R rEnd = INT32_MAX;
@@ -195,26 +200,26 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
         if (!active) continue;
         // per node: tile cursor | end << 16, and the head (next event)
         uint32_t cs[N];
-        R head[N];
+        HK head[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const uint32_t c = obuf[ty[k]], st = obuf[ty[k] + 1];
             cs[k] = c | st << 16;
             R v = c < st ? tbuf[c] : rEnd;
             v = v < EpR ? v : rEnd;
-            head[k] = PK ? (v == rEnd ? rEnd : (R)((v << 3) | k)) : v;
+            head[k] = PK ? (v == rEnd ? kNoHead : (HK)(((uint32_t)v << 3) | (uint32_t)k)) : (HK)v;
         }
         while (true) {
             // next event of the lane's types (lowest node first among equal times)
             R t;
             int j;
             if constexpr (PK) {
-                R key = head[0];
+                HK key = head[0];
 #pragma unroll
                 for (int k = 1; k < N; ++k) key = head[k] < key ? head[k] : key;
-                if (key == rEnd) break;
-                j = key & 7;
-                t = key >> 3;
+                if (key == kNoHead) break;
+                j = (int)(key & 7u);
+                t = (R)(key >> 3);
             } else {
                 t = head[0];
                 j = 0;
@@ -310,7 +315,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
             const uint32_t cl = c & 0xffffu;
             R v = cl < (c >> 16) ? tbuf[cl] : rEnd;
             v = v < EpR ? v : rEnd;
-            const R nk = PK ? (v == rEnd ? rEnd : (R)((v << 3) | j)) : v;
+            const HK nk = PK ? (v == rEnd ? kNoHead : (HK)(((uint32_t)v << 3) | (uint32_t)j)) : (HK)v;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 if (k == j) {

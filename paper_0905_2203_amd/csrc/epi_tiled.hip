@@ -787,7 +787,7 @@ struct Layout {
 // rel: the machines and the staged tile hold int32 relative times; tile:
 // events per tile of the stream(s).
 template <typename T>
-Layout<T> layout(int N, int Q, int W, int K, bool tiles, bool rel = false, int tile = kTile) {
+Layout<T> layout(int N, int Q, int W, int K, bool tiles, bool rel, int tile) {
     Layout<T> L;
     const size_t lv = N > 1 ? N - 1 : 0;
     const size_t ts = rel ? sizeof(int32_t) : sizeof(T);  // machine time
@@ -823,12 +823,12 @@ constexpr uint32_t kLdsHard = 160 * 1024;
 // Widest workgroup (at most max_lanes) whose LDS fits comfortably; else the
 // widest that fits at all.
 template <typename T>
-int pick_lanes(int N, int Q, int K, int max_lanes, bool rel = false) {
+int pick_lanes(int N, int Q, int K, int max_lanes, bool rel, int tile) {
     int fit = 64;
     bool any = false;
     for (int W : {256, 128, 64}) {
         if (max_lanes > 0 && W > max_lanes) continue;
-        const Layout<T> L = layout<T>(N, Q, W, K, true, rel);
+        const Layout<T> L = layout<T>(N, Q, W, K, true, rel, tile);
         if (L.total <= kLdsSoft) return W;
         if (!any && L.total <= kLdsHard) {
             fit = W;
@@ -843,11 +843,11 @@ int pick_lanes(int N, int Q, int K, int max_lanes, bool rel = false) {
 // runtime counts them (LDS and registers); ties go to the wider one, whose
 // waves share one staged tile.  Falls back to pick_lanes.
 template <typename T>
-int pick_lanes_fn(const void *fn, int N, int Q, int K, int max_lanes, bool rel) {
+int pick_lanes_fn(const void *fn, int N, int Q, int K, int max_lanes, bool rel, int tile) {
     int best = 0, bestW = 0;
     for (int W : {256, 128, 64}) {
         if (max_lanes > 0 && W > max_lanes) continue;
-        const Layout<T> L = layout<T>(N, Q, W, K, true, rel);
+        const Layout<T> L = layout<T>(N, Q, W, K, true, rel, tile);
         if (L.total > kLdsHard) continue;
         if (L.total > kLdsSoft &&
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total) != hipSuccess) {
@@ -865,7 +865,7 @@ int pick_lanes_fn(const void *fn, int N, int Q, int K, int max_lanes, bool rel) 
             bestW = W;
         }
     }
-    return best > 0 ? bestW : pick_lanes<T>(N, Q, K, max_lanes, rel);
+    return best > 0 ? bestW : pick_lanes<T>(N, Q, K, max_lanes, rel, tile);
 }
 
 template <typename T>
@@ -983,8 +983,8 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         if (!fn && !lfn) return hipErrorInvalidValue;
         const int C = std::max(1, g.C);
         const int W = lane ? lane_pick_width(lfn, C, s.K, s.T, opt.lanes)
-                           : pick_lanes_fn<T>(reinterpret_cast<const void *>(fn), g.N, g.Q, s.K, opt.lanes, rel);
-        const Layout<T> L = layout<T>(g.N, g.Q, W, s.K, true, rel);
+                           : pick_lanes_fn<T>(reinterpret_cast<const void *>(fn), g.N, g.Q, s.K, opt.lanes, rel, s.T);
+        const Layout<T> L = layout<T>(g.N, g.Q, W, s.K, true, rel, s.T);
         const LaneLayout LL = lane_layout(C, W, s.K, s.T);
         const uint32_t lds = lane ? LL.total : L.total;
         if (lds > kLdsHard) return hipErrorInvalidConfiguration;
@@ -1060,7 +1060,7 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
             fn<<<grid, W, lds, st>>>(a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        if (P > 1 && (e = launch_reconcile<T>(a, g.N, layout<T>(g.N, g.Q, kRecLanes, s.K, false), st)) != hipSuccess)
+        if (P > 1 && (e = launch_reconcile<T>(a, g.N, layout<T>(g.N, g.Q, kRecLanes, s.K, false, false, 0), st)) != hipSuccess)
             return e;
     }
     return hipSuccess;
@@ -1077,7 +1077,7 @@ hipError_t count_append_t(const Stream &s, CandSet &c, int64_t B, int32_t *d_fla
         if (G <= 0) continue;
         AFn<T> fn = pick_append<T>(g.N);
         if (!fn) return hipErrorInvalidValue;
-        const Layout<T> L = layout<T>(g.N, g.Q, kRecLanes, s.K, false);
+        const Layout<T> L = layout<T>(g.N, g.Q, kRecLanes, s.K, false, false, 0);
         CountArgs<T> a{};
         a.ts_by_type = s.ts_by_type.as<T>();
         a.type_off = s.type_off.as<int32_t>();
@@ -1409,7 +1409,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
                                      : pick_persistent_f<T, false>(clsN[cl], relN[cl]);
         if (!pfn) return hipErrorInvalidValue;
         Wn[cl] = pick_lanes_fn<T>(reinterpret_cast<const void *>(pfn), clsN[cl], clsQ[cl], maxK[cl], opt.lanes,
-                                  relN[cl]);
+                                  relN[cl], maxT[cl]);
     }
 
     // 3. the candidate sort's passes (decided now: the permutation's buffer
@@ -1491,7 +1491,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
             a.off_obuf = L.off_obuf;
             a.off_misc = L.off_misc;
         } else {
-            const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
+            const Layout<T> L = layout<T>(clsN[cl], clsQ[cl], Wn[cl], maxK[cl], true, relN[cl], maxT[cl]);
             a.off_qse = L.off_qse;
             a.off_tbuf = L.off_tbuf;
             a.off_qh = L.off_qh;
@@ -1631,7 +1631,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
         for (size_t ui = 0; ui < units.size(); ++ui) {
             if (units[ui].P <= 1 || cls_of(units[ui]) != cl) continue;
             const int N = units[ui].N;
-            const hipError_t x = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false), bst);
+            const hipError_t x = launch_reconcile<T>(ua[ui], N, layout<T>(N, clsQ[cl], kRecLanes, maxK[cl], false, false, 0), bst);
             if (x != hipSuccess) return x;
         }
         return hipSuccess;
@@ -1662,7 +1662,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
             continue;
         }
         PFn<T> fn = filtN[cl] ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
-        const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true, relN[cl]);
+        const Layout<T> L = layout<T>(N, clsQ[cl], Wn[cl], maxK[cl], true, relN[cl], maxT[cl]);
         if (L.total > kLdsHard) {
             e = hipErrorInvalidConfiguration;
             break;
