@@ -311,7 +311,8 @@ epi_status epi_set_option(epi_ctx *ctx, int option, int64_t value);
  * (EPI_OPT_LANES {automatic, 128, 64}) and the segment target
  * (EPI_OPT_TARGET_LANES {131072, 524288, 1048576}), and once more over the
  * four when the first pass moved.  Each trial builds the
- * batched plan, then times one replay with hipEvents; the counts do not
+ * batched plan, then times two replays with hipEvents (the faster counts);
+ * the counts do not
  * depend on the setting.  The fastest is kept: the streams stay re-tiled and
  * the options are set on the context.  With cache_path (may be null) the
  * choice is appended to that text file under a key of the workload's shape
