@@ -177,6 +177,17 @@ __device__ __forceinline__ int64_t n_extensions(const WalkArgs<T> &a, int64_t jo
     return a.out_off[alpha + 1] - a.out_off[alpha];
 }
 
+// A batch event in LDS: its time, its start per menu interval (minimum of
+// the type: no occurrence ends there) and, counting, the next leader event of
+// the same owner.  One record per event, so that a greedy step reads it with
+// one address.
+template <typename T, int MP>
+struct alignas(16) EvRec {
+    T t;
+    T s[MP];
+    int32_t n;
+};
+
 // One job: alpha (or a piece of its chain list) and all of its extensions
 // (or, writing, its frequent ones).  MP greedy states per lane, one per menu
 // interval: MP = M for menus of up to 4 intervals, else 8 with the unused
@@ -191,12 +202,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     __shared__ unsigned long long want[kWave];      // batch lanes holding each owner's events
     __shared__ int32_t gtype[kWave];
     __shared__ int64_t gkey[MP][kWave];
-    // the batch's events (slot 64: a null event that no greedy keeps)
-    __shared__ T ev_t[kWave + 1];
-    __shared__ T ev_s[MP][kWave + 1];
-    // counting: the next leader event of the same owner (64: none), and each
-    // owner's end events per interval
-    __shared__ int32_t ev_n[kWave + 1];
+    // the batch's events (slot 64: a null event that no greedy keeps; its
+    // next leader, 64, is none)
+    __shared__ EvRec<T, MP> evr[kWave + 1];
+    // counting: each owner's end events per interval
     __shared__ int32_t cnv[MODE == kCount ? MP : 1][kWave];
     // writing: each owner's first slot and entries so far, per interval
     __shared__ int64_t okey[WRITE ? MP : 1][kWave];
@@ -219,6 +228,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         clen = a.clen[alpha];
     }
     const_ptr<ChainEntry<T>> xc = (const_ptr<ChainEntry<T>>)(a.chain + c0);
+    const ChainEntry<T> *xg = a.chain + c0;  // the same entries, read per lane
     // this job's piece of the chain list
     const int32_t e0 = (int32_t)((int64_t)clen * seg / a.nseg);
     const int32_t e1 = (int32_t)((int64_t)clen * (seg + 1) / a.nseg);
@@ -233,10 +243,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
     for (int k = lane; k < a.K; k += kWave) slot_of[k] = kNoSlot;
     want[lane] = 0;
     if (lane == 0) {
-        ev_t[kWave] = kMin;
-        ev_n[kWave] = kWave;
+        evr[kWave].t = kMin;
+        evr[kWave].n = kWave;
 #pragma unroll
-        for (int m = 0; m < MP; ++m) ev_s[m][kWave] = kMin;
+        for (int m = 0; m < MP; ++m) evr[kWave].s[m] = kMin;
     }
     unsigned long long walked = 0;
     // rounds of up to 64 distinct extension types (one lane each)
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
         for (int m = 0; m < MP; ++m) {
             key[m] = has ? gkey[m][lane] : -1;
             own[m] = key[m] >= 0;
-            pe[m] = kMin;
+            pe[m] = own[m] ? kMin : kMax;  // an interval the lane does not count keeps nothing
             cnt[m] = 0;
             nv[m] = 0;
         }
@@ -381,9 +391,9 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     vm |= v << m;
                 }
                 // the event in LDS, for its owner and its same-type neighbours
-                ev_t[lane] = t;
+                evr[lane].t = t;
 #pragma unroll
-                for (int m = 0; m < MP; ++m) ev_s[m][lane] = sv[m];
+                for (int m = 0; m < MP; ++m) evr[lane].s[m] = sv[m];
                 // delivered to the owner of its type when that owner counts
                 // one of those intervals
                 const uint32_t sl = vm ? (uint32_t)slot_of[ty] : 0u;
@@ -419,12 +429,12 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                         const int pl = 63 - __builtin_clzll(bm);
 #pragma unroll
                         for (int m = 0; m < MP; ++m)
-                            lead |= (uint32_t)((sv[m] != kMin) & (sv[m] != ev_s[m][pl])) << m;
+                            lead |= (uint32_t)((sv[m] != kMin) & (sv[m] != evr[pl].s[m])) << m;
                     }
                     lb = __ballot(dl & ((lead & (sl >> 8)) != 0));
                     // the owner's leaders as a list in time order
                     const uint64_t nx = wo & lb & ~((2ull << lane) - 1ull);
-                    ev_n[lane] = nx ? __builtin_ctzll(nx) : kWave;
+                    evr[lane].n = nx ? __builtin_ctzll(nx) : kWave;
                 }
                 if (WRITE && dl) {
                     // each event writes itself, after the owner's entries so
@@ -455,15 +465,15 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     const uint64_t wl = wm & lb;
                     int k = wl ? __builtin_ctzll(wl) : kWave;
                     if (__ballot(k < kWave)) do {  // uniform
-                        const T yt = ev_t[k];
+                        const EvRec<T, MP> y = evr[k];
 #pragma unroll
                         for (int m = 0; m < MP; ++m) {
-                            const T ys = ev_s[m][k];
-                            const bool g = own[m] & (ys > pe[m]);
-                            cnt[m] += g;
-                            pe[m] = g ? yt : pe[m];
+                            const bool g = y.s[m] > pe[m];
+                            unsigned co;  // (an add with carry-in: no select of 0 or 1)
+                            cnt[m] = (int32_t)__builtin_addc((unsigned)cnt[m], 0u, (unsigned)g, &co);
+                            pe[m] = g ? y.t : pe[m];
                         }
-                        k = ev_n[k];
+                        k = y.n;
                     } while (__ballot(k < kWave));
                 }
             }
