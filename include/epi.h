@@ -157,7 +157,12 @@ epi_status epi_release_set(epi_ctx *ctx, int32_t set_id);
  *                     kernel per launch class (episode size, ring class,
  *                     machine time type) pulls (set, lane block, segment)
  *                     work items from a device queue, then the segmented
- *                     ones are reconciled (returns when done).
+ *                     ones are reconciled.  The graph is kept per (sets,
+ *                     schedule, options, cost model) and replayed by later
+ *                     calls, which are asynchronous; a call that plans a
+ *                     new graph synchronises the stream while it plans, and
+ *                     episodes with a ring bound above 15 (counted by the
+ *                     tracking engine) make the call return when done.
  *   EPI_MODE_INCREMENTAL  after epi_append_stream: only the appended
  *                     events are counted (see epi_append_stream).
  *   EPI_MODE_TRACKING parallel over events instead of episodes, for a few
