@@ -1,9 +1,10 @@
 """The register-indexed lane machines (EPI_OPT_LANE_ENGINE = 1, the default)
 against the CPU oracle and against the LDS-ring machines, on streams that
 take each key form: int32 microsecond streams and int64 nanosecond streams
-whose tiles fit 28-bit relative times (packed (time, node) keys), bursty
-nanosecond streams that need smaller tiles or fit only 30 bits (separate
-keys); every episode size 1..8, per-node ring depths from 1 to the limit,
+whose tiles fit relative times below 2^29 - 1 (packed (time, node) keys,
+unsigned: one stream's tiles span between 2^28 and 2^29 ns, where a signed
+key would wrap), bursty nanosecond streams that need smaller tiles or fit
+only 30 bits (separate keys); every episode size 1..8, per-node ring depths from 1 to the limit,
 forced segment counts, plain and batched modes.  Episodes with an interval
 deeper than the rings (bound > 15) are counted by the per-event tracking
 engine in every mode; they are legal (Sec. II-C admits any 0 <= lo < hi)
@@ -37,6 +38,15 @@ def _streams():
                                               cascades=[6], cascade_trigger_hz=[8.0])
     yield "int64_ns_bursty", sg.bursty_stream(rng, K=10, dur_s=120.0, shape=2.0, scale_hz=3.0)
     yield "int64_ns_sparse", sg.poisson_stream(rng, K=8, rate_hz=2.0, dur_s=900.0, ts_kind=1, unit_per_ms=1_000_000)
+    yield "int64_ns_29bit", sg.poisson_stream(rng, K=8, rate_hz=80.0, dur_s=20.0, ts_kind=1, unit_per_ms=1_000_000)
+
+
+def _longest_tile(times, T):
+    """Longest time span of the T-event tiles of a stream (the library's tile
+    choice takes the largest power-of-two tile whose spans fit the keys)."""
+    n = times.size
+    last = np.minimum(np.arange(T - 1, n + T - 1, T), n - 1)
+    return int((times[last] - times[::T]).max())
 
 
 def _episodes(rng, K, unit, m):
@@ -73,11 +83,17 @@ def _count(ctx, cid, m, mode=epi.EPI_MODE_PLAIN, sched=epi.EPI_SCHED_RR):
     return ctx.epi_read_counts(cid, m)
 
 
-@pytest.mark.parametrize("name", ["int32_us", "int64_ns_dense", "int64_ns_bursty", "int64_ns_sparse"])
+@pytest.mark.parametrize("name", ["int32_us", "int64_ns_dense", "int64_ns_bursty", "int64_ns_sparse", "int64_ns_29bit"])
 def test_lane_machines_equal_oracle(ctx, name):
     s = dict(_streams())[name]
     unit = s["unit_per_ms"]
-    seed = {"int32_us": 11, "int64_ns_dense": 12, "int64_ns_bursty": 13, "int64_ns_sparse": 14}[name]
+    if name == "int64_ns_29bit":
+        # the premise: 512-event tiles are too long for the packed keys, 256-event
+        # tiles fit them with relative times of 2^28 ns or more
+        assert _longest_tile(s["times"], 512) >= (1 << 29) - 1
+        assert (1 << 28) <= _longest_tile(s["times"], 256) < (1 << 29) - 1
+    seed = {"int32_us": 11, "int64_ns_dense": 12, "int64_ns_bursty": 13, "int64_ns_sparse": 14,
+            "int64_ns_29bit": 15}[name]
     rng = np.random.Generator(np.random.PCG64(seed))
     c = sg.concat_candidates(_episodes(rng, s["K"], unit, 600), _deep(rng, s["K"], unit))
     m = c["N"].size
