@@ -92,12 +92,18 @@ def _timed(ctx, fn, reps):
     return float(np.median(out))
 
 
-def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False):
+ABL_LEGS = ("plain", "batched_rr", "batched_learned", "batched_heuristic", "batched_measured")
+RECORDINGS_PROFILE = "k_lane_persistent_recordings.md"
+
+
+def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False, legs=ABL_LEGS, tune_cache=None):
     """Plain engine vs the batched persistent engine under round-robin, the
     event-count heuristic and the learned cost model, on workload preset k.
     Every mode's counts are checked equal; one JSON line per preset.  With
     tune, the batched legs run autotuned (round robin tuned for itself, the
-    heuristic and measured schedules with the learned schedule's setting)."""
+    heuristic and measured schedules with the learned schedule's setting;
+    tune_cache: the autotuner's cache file, read, else written).  legs: the
+    legs to time (profiling runs time one)."""
     import spikegen as sg
     from paper_0905_2203_amd import epi
 
@@ -132,15 +138,26 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False):
         return [ctx.epi_read_counts(cid, c["N"].size) for cid, (_, c) in zip(cids, sets)]
 
     tuned = {}
-    res["plain"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_PLAIN), reps)
-    ref = counts()
-    if tune:
-        tuned["batched_rr"] = ctx.epi_autotune(cids, epi.EPI_SCHED_RR)
-        log(f"  tuned for round robin: {tuned['batched_rr']}")
-    res["batched_rr"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR),
-                               reps)
-    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "batched_rr"
-    log(f"  batched_rr: {res['batched_rr']:.3f}s")
+    ref = None
+
+    def check(leg):
+        nonlocal ref
+        got = counts()
+        if ref is None:
+            ref = got
+        assert all(np.array_equal(a, b) for a, b in zip(got, ref)), leg
+
+    if "plain" in legs:
+        res["plain"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_PLAIN), reps)
+        check("plain")
+    if "batched_rr" in legs:
+        if tune:
+            tuned["batched_rr"] = ctx.epi_autotune(cids, epi.EPI_SCHED_RR, tune_cache)
+            log(f"  tuned for round robin: {tuned['batched_rr']}")
+        res["batched_rr"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                              sched=epi.EPI_SCHED_RR), reps)
+        check("batched_rr")
+        log(f"  batched_rr: {res['batched_rr']:.3f}s")
     # learned: work log of disjoint training candidates on the same streams
     ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
     ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)  # log each episode's own work
@@ -152,25 +169,28 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False):
     ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
     ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
     if tune:
-        tuned["batched_learned"] = ctx.epi_autotune(cids, epi.EPI_SCHED_LEARNED)
+        tuned["batched_learned"] = ctx.epi_autotune(cids, epi.EPI_SCHED_LEARNED, tune_cache)
         log(f"  tuned for the learned schedule: {tuned['batched_learned']}")
-    res["batched_learned"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
-                                                               sched=epi.EPI_SCHED_LEARNED), reps)
-    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "learned"
-    res["batched_heuristic"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
-                                                                 sched=epi.EPI_SCHED_HEURISTIC), reps)
-    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "heuristic"
-    log(f"  plain {res['plain']:.3f}s learned {res['batched_learned']:.3f}s (training {train_s:.1f}s)")
-    # measured: the schedule by each episode's own logged work (an exact cost model)
-    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
-    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)
-    ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
-    ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
-    ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
-    res["batched_measured"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
-                                                                sched=epi.EPI_SCHED_MEASURED), reps)
-    assert all(np.array_equal(a, b) for a, b in zip(counts(), ref)), "measured"
-    log(f"  measured-cost schedule {res['batched_measured']:.3f}s")
+    if "batched_learned" in legs:
+        res["batched_learned"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                                   sched=epi.EPI_SCHED_LEARNED), reps)
+        check("batched_learned")
+        log(f"  learned {res['batched_learned']:.3f}s (training {train_s:.1f}s)")
+    if "batched_heuristic" in legs:
+        res["batched_heuristic"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                                     sched=epi.EPI_SCHED_HEURISTIC), reps)
+        check("batched_heuristic")
+    if "batched_measured" in legs:
+        # measured: the schedule by each episode's own logged work (an exact cost model)
+        ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 1)
+        ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 1)
+        ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED, sched=epi.EPI_SCHED_RR)
+        ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
+        ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
+        res["batched_measured"] = _timed(ctx, lambda: ctx.epi_count(cids, mode=epi.EPI_MODE_BATCHED,
+                                                                    sched=epi.EPI_SCHED_MEASURED), reps)
+        check("batched_measured")
+        log(f"  measured-cost schedule {res['batched_measured']:.3f}s")
     # parity: a seeded sample of every set's counts against the oracle, which
     # is timed on it (all host cores)
     parity = "not checked"
@@ -207,16 +227,32 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False):
         ty_ = c_["types"].astype(np.int64)
         per = np.where(np.arange(8)[None, :] < N_[:, None], tc[np.clip(ty_, 0, None)], 0).sum(axis=1)
         alg += int(per.sum()) * tsb + int(N_.size) * ((128 if tsb == 8 else 72) + 4)
+    def ratio(a, b):
+        return res[a] / res[b] if a in res and b in res else None
+
+    roofline = None
+    if "batched_learned" in res:
+        # the learned count against 8 TB/s; traffic from the committed profile
+        # of this preset's learned count while the engine sources match it
+        ach = alg / res["batched_learned"] / 1e9
+        traffic = None
+        if k == 3 and abs(scale - 1.0) < 1e-9:
+            traffic = profiled("batched_learned_graph", "traffic_bytes_per_launch", "bytes", RECORDINGS_PROFILE,
+                               LARGE_SOURCES)
+        roofline = {"bound": "hbm", "kernel": "batched count graph, learned schedule", "achieved": ach,
+                    "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
+                    "traffic": None if traffic is None else int(traffic)}
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s", "lane_engine": lane_engine,
         "ring_classes": ring_classes, "tuned": tuned,
         "value": {m: units / t for m, t in res.items()},
         "seconds": res,
-        "learned_vs_rr": res["batched_rr"] / res["batched_learned"],
-        "learned_vs_heuristic": res["batched_heuristic"] / res["batched_learned"],
-        "learned_vs_plain": res["plain"] / res["batched_learned"],
-        "measured_vs_learned": res["batched_learned"] / res["batched_measured"],
+        "learned_vs_rr": ratio("batched_rr", "batched_learned"),
+        "learned_vs_heuristic": ratio("batched_heuristic", "batched_learned"),
+        "learned_vs_plain": ratio("plain", "batched_learned"),
+        "measured_vs_learned": ratio("batched_learned", "batched_measured"),
+        "roofline": roofline,
         "cost_model": {"train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                        "train_candidates": int(sum(c["N"].size for _, c in train_sets))},
         "counts_equal_across_modes": True,
@@ -511,14 +547,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="candidates timed on the CPU (default: 384 of the Large workload; 200k level-3 "
+                    help="candidates timed on the CPU (default: 6000 of the Large workload; 200k level-3 "
                          "candidates with --mining)")
     ap.add_argument("--scale", type=float, default=1.0, help="size scale of the Large workload")
     ap.add_argument("--mining", action="store_true", help="level-wise discovery of the mining preset")
     ap.add_argument("--learned-only", action="store_true",
                     help="Large line: time only the batched + learned leg (profiling runs)")
     ap.add_argument("--no-tune", action="store_true", help="Large line: engine defaults, no autotuning")
-    ap.add_argument("--tune-cache", default="", help="Large line: autotuner cache file (read, else written)")
+    ap.add_argument("--tune-cache", default="",
+                    help="Large line and --abl-tune: autotuner cache file (read, else written)")
     ap.add_argument("--costmodel-in", default="", help="Large line: load the cost model from this file")
     ap.add_argument("--costmodel-out", default="", help="Large line: save the trained cost model to this file")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -527,6 +564,7 @@ def main():
                     help="comma list of workload presets (1, 3, 4, 5): plain vs batched schedules, one JSON line each")
     ap.add_argument("--abl-scale", type=float, default=1.0, help="size scale of the ablation workloads")
     ap.add_argument("--abl-tune", action="store_true", help="ablation: autotune the batched legs")
+    ap.add_argument("--abl-legs", default=",".join(ABL_LEGS), help="ablation: comma list of the legs to time")
     ap.add_argument("--lane-engine", type=int, default=1,
                     help="ablation: 1 = register-indexed lane machines where they apply, 0 = LDS-ring machines")
     ap.add_argument("--ring-classes", type=int, default=-1,
@@ -541,7 +579,7 @@ def main():
     if args.ablation:
         for k in [int(x) for x in args.ablation.split(",") if x]:
             ablation(k, args.abl_scale, max(1, args.steps), args.lane_engine, max(0, args.ring_classes),
-                     args.abl_tune)
+                     args.abl_tune, tuple(x for x in args.abl_legs.split(",") if x), args.tune_cache or None)
         return
     if args.calibrate_copy:
         import torch
