@@ -168,7 +168,7 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False, legs=ABL
     train_s = time.perf_counter() - a
     ctx.epi_set_option(epi.EPI_OPT_WORKLOG, 0)
     ctx.epi_set_option(epi.EPI_OPT_SEGMENTS, 0)
-    if tune:
+    if tune and any(x in legs for x in ("batched_learned", "batched_heuristic", "batched_measured")):
         tuned["batched_learned"] = ctx.epi_autotune(cids, epi.EPI_SCHED_LEARNED, tune_cache)
         log(f"  tuned for the learned schedule: {tuned['batched_learned']}")
     if "batched_learned" in legs:
@@ -235,13 +235,17 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False, legs=ABL
         # the learned count against 8 TB/s; traffic from the committed profile
         # of this preset's learned count while the engine sources match it
         ach = alg / res["batched_learned"] / 1e9
-        traffic = None
-        if k == 3 and abs(scale - 1.0) < 1e-9:
+        traffic = tset = None
+        if k == 3 and abs(scale - 1.0) < 1e-9 and tune:
             traffic = profiled("batched_learned_graph", "traffic_bytes_per_launch", "bytes", RECORDINGS_PROFILE,
                                LARGE_SOURCES)
+            tset = profiled("batched_learned_graph", "traffic_bytes_per_launch", "setting", RECORDINGS_PROFILE,
+                            LARGE_SOURCES)
         roofline = {"bound": "hbm", "kernel": "batched count graph, learned schedule", "achieved": ach,
                     "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
-                    "traffic": None if traffic is None else int(traffic)}
+                    "traffic": None if traffic is None else int(traffic),
+                    # the (tile, launch groups, lanes, segment target) the counters were taken at
+                    "traffic_setting": tset}
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
         "ablation_preset": k, "scale": scale, "unit": "cand*ev/s", "lane_engine": lane_engine,
@@ -487,6 +491,8 @@ def large_bench(args):
     achieved = alg / t_step / 1e9
     kname = "batched count graph (k_lane_persistent per launch class on parallel branches, scheduler, reconcile)"
     traffic = profiled("batched_learned_graph", "traffic_bytes_per_launch", "bytes", LARGE_PROFILE, LARGE_SOURCES)
+    traffic_setting = profiled("batched_learned_graph", "traffic_bytes_per_launch", "setting", LARGE_PROFILE,
+                               LARGE_SOURCES)
     ctx.epi_release_set(cid)
     ctx.epi_release_stream(sid)
     ctx.close()
@@ -529,6 +535,9 @@ def large_bench(args):
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
+            # the (tile, launch groups, lanes, segment target) the counters were
+            # taken at; the run's own setting is under "autotuned"
+            "traffic_setting": traffic_setting,
             "algorithmic_bytes": alg,
             "per_unit": "per candidate: sum over its nodes of the node type's events x 8 B + 128 B descriptor "
                         "+ 4 B count; one launch = one count of all candidates",
