@@ -1624,9 +1624,12 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
     }
     if (e == hipSuccess) e = hipEventRecord(cache.fork, st);
     for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(cache.br[i], cache.fork, 0);
-    // the segmented units of a class are reconciled on the class's branch as
-    // soon as its persistent kernel ends (their records are all written by
-    // it), overlapping the other branches' kernels
+    // the segmented units of a class are reconciled on the class's branch
+    // (their records are all written by its kernel), after the branch's last
+    // persistent kernel: a reconciliation queued between two classes waits
+    // for CUs that the other branches' persistent kernels hold and keeps its
+    // branch's next class waiting too; at the branch's end it overlaps the
+    // other branches' last kernels instead
     auto reconcile_class = [&](int cl, hipStream_t bst) -> hipError_t {
         for (size_t ui = 0; ui < units.size(); ++ui) {
             if (units[ui].P <= 1 || cls_of(units[ui]) != cl) continue;
@@ -1637,6 +1640,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
         return hipSuccess;
     };
     std::vector<double> load(nb, 0.0);
+    std::vector<std::vector<int>> brcls(nb);
     for (int cl : border) {
         if (e != hipSuccess) break;
         const int bi = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -1658,7 +1662,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
             e = lane_launch_persistent<T>(N, pkN[cl], (unsigned)grid, Wn[cl], L.total, cache.br[bi],
                                           plan.units.as<CountArgs<T>>(), plan.items.as<WorkItem>() + ioff[cl], ncl,
                                           ioff[cl], plan.queue.as<unsigned long long>() + cl);
-            if (e == hipSuccess) e = reconcile_class(cl, cache.br[bi]);
+            brcls[bi].push_back(cl);
             continue;
         }
         PFn<T> fn = filtN[cl] ? pick_persistent_f<T, true>(N, relN[cl]) : pick_persistent_f<T, false>(N, relN[cl]);
@@ -1676,8 +1680,11 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
                                                              plan.items.as<WorkItem>() + ioff[cl], ncl, ioff[cl],
                                                              plan.queue.as<unsigned long long>() + cl);
         e = hipGetLastError();
-        if (e == hipSuccess) e = reconcile_class(cl, cache.br[bi]);
+        brcls[bi].push_back(cl);
     }
+    for (int bi = 0; bi < nb && e == hipSuccess; ++bi)
+        for (int cl : brcls[bi])
+            if (e == hipSuccess) e = reconcile_class(cl, cache.br[bi]);
     // every branch joins back (also after an error, so that the capture ends
     // cleanly)
     for (int i = 0; i < nb; ++i) {
