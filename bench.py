@@ -78,6 +78,39 @@ def profiled_traffic(kernel_name):
     return None if v is None else int(v)
 
 
+def host_cpu():
+    """The host CPU's model name (the CPU baseline runs on it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_gbps(stream=None):
+    """Practical HBM bandwidth: a 1 GiB device-to-device copy (read + write
+    bytes over its time), best of 5 after a warm-up, timed with HIP events."""
+    import torch
+
+    a = torch.empty(1 << 28, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    best = None
+    with torch.cuda.stream(stream or torch.cuda.current_stream()):
+        for i in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            if i > 0:
+                best = ms if best is None else min(best, ms)
+    del a, b
+    return 2 * (1 << 30) / (best / 1e3) / 1e9
+
+
 def _timed(ctx, fn, reps):
     import torch
 
@@ -482,7 +515,7 @@ def large_bench(args):
                 parity = f"{'ok' if bad == 0 and equal else 'MISMATCH'}: {idx.size} sampled counts vs the oracle, {bad} differ"
             cpu = dict(value=idx.size * n / el, unit="cand*ev/s", cores=cores, kind="oracle",
                        sample=f"{idx.size} of the {m} candidates (evenly spaced), all {n} events, "
-                              f"decomposition oracle in {el:.1f}s")
+                              f"decomposition oracle in {el:.1f}s", host=host_cpu())
         except Exception as exc:
             log(f"oracle leg failed: {exc!r}")
 
@@ -496,6 +529,10 @@ def large_bench(args):
     ctx.epi_release_set(cid)
     ctx.epi_release_stream(sid)
     ctx.close()
+    del d_types, d_times
+    # the practical HBM peak on this GPU, beside the published 8 TB/s
+    copy_bw = copy_gbps(stream)
+    log(f"  1 GiB device copy: {copy_bw:.0f} GB/s (read + write)")
     value = m * n / t_step
     line = {
         "metric": "candidate-episode x events counted/sec (exact), plain vs batched+learned-sched",
@@ -538,6 +575,8 @@ def large_bench(args):
             # the (tile, launch groups, lanes, segment target) the counters were
             # taken at; the run's own setting is under "autotuned"
             "traffic_setting": traffic_setting,
+            # a 1 GiB device copy on the same GPU: the practical HBM peak
+            "copy_GBps": copy_bw,
             "algorithmic_bytes": alg,
             "per_unit": "per candidate: sum over its nodes of the node type's events x 8 B + 128 B descriptor "
                         "+ 4 B count; one launch = one count of all candidates",
@@ -556,7 +595,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="candidates timed on the CPU (default: 6000 of the Large workload; 200k level-3 "
+                    help="candidates timed on the CPU (default: 8000 of the Large workload; 1.5M level-3 "
                          "candidates with --mining)")
     ap.add_argument("--scale", type=float, default=1.0, help="size scale of the Large workload")
     ap.add_argument("--mining", action="store_true", help="level-wise discovery of the mining preset")
@@ -606,11 +645,11 @@ def main():
         sys.exit(2)
     if args.mining:
         if args.cpu_sample <= 0:
-            args.cpu_sample = 200_000
+            args.cpu_sample = 1_500_000  # about 10 s of the oracle on 16 host threads
         mining_bench(args)
         return
     if args.cpu_sample <= 0:
-        args.cpu_sample = 6000
+        args.cpu_sample = 8000  # about 11 s of the oracle on 16 host threads
     large_bench(args)
 
 
