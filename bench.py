@@ -760,7 +760,7 @@ def mining_bench(args):
             oracle.count(s, sc, nthreads=cores)
             el = time.perf_counter() - a
             cpu = dict(value=len(sample) * n / el, unit="cand*ev/s", cores=cores, kind="oracle",
-                       sample=f"{len(sample)} of the {len(c3)} level-3 candidates (every {step_}th), "
+                       sample=f"{len(sample)} of the {len(c3)} level-3 candidates (1 in {step_}), "
                               f"counted by the decomposition oracle in {el:.1f}s")
     except Exception as exc:  # the benchmark line is still printed
         log(f"oracle leg failed: {exc!r}")
