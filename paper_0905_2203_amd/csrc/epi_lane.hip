@@ -232,10 +232,8 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 }
                 if (t == rEnd) break;
             }
-            ++w_visits;
             // query ring j: skip dead intervals from the head; t is covered iff
             // the first live one starts before it (ring 0: iff t > e)
-            w_queries += j > 0 ? 1u : 0u;
             bool ok;
             {
                 const uint32_t sh = 8u * (uint32_t)j;
@@ -322,6 +320,16 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                     cs[k] = c;
                     head[k] = nk;
                 }
+            }
+        }
+        if (a.work) {
+            // visits of this tile: each node's events its cursor moved past
+            // (a query at every node but node 0)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const uint32_t v = (cs[k] & 0xffffu) - (uint32_t)obuf[ty[k]];
+                w_visits += v;
+                if (k > 0) w_queries += v;
             }
         }
     }
