@@ -1488,9 +1488,10 @@ epi_status epi_autotune(epi_ctx *ctx, const int32_t *set_ids, int32_t k, int sch
         // trial is a batched count whose plan is built first and then timed
         // as a replay (hipEvents on the context's stream)
         const CountOptions saved = ctx->c.opt;
-        hipEvent_t a, b;
-        HIPTRY(ctx, hipEventCreate(&a), "event");
-        HIPTRY(ctx, hipEventCreate(&b), "event");
+        hipEvent_t a = nullptr, b = nullptr;
+        hipError_t he = hipEventCreate(&a);
+        if (he == hipSuccess && (he = hipEventCreate(&b)) != hipSuccess) (void)hipEventDestroy(a);
+        if (he != hipSuccess) return hipfail(ctx, he, "event");
         auto trial = [&](const TuneSetting &t, float *ms) -> epi_status {
             *ms = INFINITY;
             epi_status v = retile(ctx, set_ids, k, t.tile);
