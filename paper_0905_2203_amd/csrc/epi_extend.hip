@@ -133,6 +133,23 @@ __device__ __forceinline__ T read_lane(T v, int l) {
     }
 }
 
+// An entry's (t, s) as one scalar load of both words.
+template <typename T>
+__device__ __forceinline__ void load_ts(const_ptr<ChainEntry<T>> e, T &t, T &s) {
+    // (the entries are 4-byte aligned: the types say so)
+    if constexpr (sizeof(T) == 4) {
+        typedef uint64_t u64a4 __attribute__((aligned(4)));
+        const uint64_t v = *(const_ptr<u64a4>)e;
+        t = (T)(uint32_t)v;
+        s = (T)(uint32_t)(v >> 32);
+    } else {
+        typedef unsigned u4 __attribute__((ext_vector_type(4), aligned(8)));
+        const u4 v = *(const_ptr<u4>)e;
+        t = (T)(((uint64_t)v.y << 32) | v.x);
+        s = (T)(((uint64_t)v.w << 32) | v.z);
+    }
+}
+
 // Walk kinds: count (greedy counts and end-event counts per candidate),
 // write (chain lists of the frequent episodes), size (end events per
 // candidate and piece), list (end events of every candidate, per piece), and
@@ -370,8 +387,9 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     cxs[m] = kMin;
                 }
                 for (int32_t q = ilo; q < clen; ++q) {  // uniform
-                    const T qt = xc[q].t;
-                    const T qs = xc[q].s;
+                    // (t, s) in one load: one wait per entry
+                    T qt, qs;
+                    load_ts(xc + q, qt, qs);
                     if (qt >= tl) break;
 #pragma unroll
                     for (int m = 0; m < MP; ++m) {
