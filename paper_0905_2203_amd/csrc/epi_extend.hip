@@ -359,11 +359,10 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
             const int32_t total = __builtin_amdgcn_readlane(S, 63);
             carry = max(carry, __builtin_amdgcn_readlane(e, 63 - __builtin_clzll(__ballot(ci))));
             walked += (unsigned long long)total;
-            for (int32_t b = 0; b < total; b += kWave) {  // uniform
-                // stream position of this lane: the runs meeting [b, b + 64)
-                // are visited in order
+            // stream position of this lane in the batch at b: the runs
+            // meeting [b, b + 64) are visited in order
+            auto position = [&](int32_t b) -> int32_t {
                 const int32_t o = b + lane;
-                const bool ev = o < total;
                 uint64_t runs = __ballot(len > 0 && X < b + kWave && S > b);
                 int32_t P = 0;
                 while (runs) {
@@ -373,8 +372,34 @@ __global__ __launch_bounds__(kWave) void k_ext_walk(WalkArgs<T> a) {
                     const int32_t bj = __builtin_amdgcn_readlane(beg, j);
                     if (o >= Xj) P = bj + (o - Xj);
                 }
-                const int32_t ty = ev ? (int32_t)a.ty16[P] : 0;
-                const T t = ev ? a.times[P] : kMax;
+                return P;
+            };
+            // the next batch's events are loaded before this batch is
+            // processed (its loads then wait behind this batch's work)
+            int32_t Pn = 0, tyn = 0;
+            T tn = kMax;
+            if (total > 0) {
+                Pn = position(0);
+                if (lane < total) {
+                    tyn = (int32_t)a.ty16[Pn];
+                    tn = a.times[Pn];
+                }
+            }
+            for (int32_t b = 0; b < total; b += kWave) {  // uniform
+                const int32_t o = b + lane;
+                const bool ev = o < total;
+                const int32_t P = Pn;
+                const int32_t ty = tyn;
+                const T t = tn;
+                if (b + kWave < total) {  // uniform
+                    Pn = position(b + kWave);
+                    tyn = 0;
+                    tn = kMax;
+                    if (o + kWave < total) {
+                        tyn = (int32_t)a.ty16[Pn];
+                        tn = a.times[Pn];
+                    }
+                }
                 const int nb = min(total - b, kWave);
                 const T tf = read_lane(t, 0), tl = read_lane(t, nb - 1);
                 // s_m(y): start of the latest end event x with
