@@ -232,6 +232,11 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 }
                 if (t == rEnd) break;
             }
+            // node j's cursor (selected here, where the node tests dominate the
+            // record's interval select, which then reuses them)
+            uint32_t c = cs[0];
+#pragma unroll
+            for (int k = 1; k < N; ++k) c = k == j ? cs[k] : c;
             // query ring j: skip dead intervals from the head; t is covered iff
             // the first live one starts before it (ring 0: iff t > e)
             bool ok;
@@ -306,9 +311,6 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 }
             }
             // advance node j
-            uint32_t c = cs[0];
-#pragma unroll
-            for (int k = 1; k < N; ++k) c = k == j ? cs[k] : c;
             c += 1u;
             const uint32_t cl = c & 0xffffu;
             R v = cl < (c >> 16) ? tbuf[cl] : rEnd;
