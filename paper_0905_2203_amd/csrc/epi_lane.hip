@@ -211,14 +211,19 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
         }
         while (true) {
             // next event of the lane's types (lowest node first among equal times)
+            // A lane whose events are all visited stays in the loop until
+            // the wave leaves together: it visits nothing (live = false: its
+            // query fails and its cursor stays), so no value of it is
+            // carried round the loop.
             R t;
             int j;
+            bool live;
             if constexpr (PK) {
                 HK key = head[0];
 #pragma unroll
                 for (int k = 1; k < N; ++k) key = head[k] < key ? head[k] : key;
-                if (key == kNoHead) break;
-                j = (int)(key & 7u);
+                live = key != kNoHead;
+                j = live ? (int)(key & 7u) : 0;
                 t = (R)(key >> 3);
             } else {
                 t = head[0];
@@ -230,8 +235,9 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                         j = k;
                     }
                 }
-                if (t == rEnd) break;
+                live = t != rEnd;
             }
+            if (__ballot(live) == 0) break;  // uniform
             // node j's cursor (selected here, where the node tests dominate the
             // record's interval select, which then reuses them)
             uint32_t c = cs[0];
@@ -252,7 +258,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                     hd = hd + 1 == Q ? 0u : hd + 1;
                     --n;
                 }
-                ok = n > 0 && f.x < t;
+                ok = live && n > 0 && f.x < t;
                 const uint32_t nm = hd | (n << 4);
                 if (nm != m) hf = (hf & ~(uint64_t(0xff) << sh)) | ((uint64_t)nm << sh);
             }
@@ -311,7 +317,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 }
             }
             // advance node j
-            c += 1u;
+            c += live ? 1u : 0u;
             const uint32_t cl = c & 0xffffu;
             R v = cl < (c >> 16) ? tbuf[cl] : rEnd;
             v = v < EpR ? v : rEnd;
