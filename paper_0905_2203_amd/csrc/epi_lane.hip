@@ -260,7 +260,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 }
                 ok = live && n > 0 && f.x < t;
                 const uint32_t nm = hd | (n << 4);
-                if (nm != m) hf = (hf & ~(uint64_t(0xff) << sh)) | ((uint64_t)nm << sh);
+                hf ^= (uint64_t)(nm ^ m) << sh;  // ring j's byte m becomes nm
             }
             if (ok) {
                 if (j == N - 1) {
@@ -312,7 +312,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                         rl[(int)(base + tl) << wsh] = make_int2(ns, ne);
                         ++n;
                         w_maxq = n > w_maxq ? n : w_maxq;
-                        hf = (hf & ~(uint64_t(0xff) << sh)) | ((uint64_t)(hd | (n << 4)) << sh);
+                        hf ^= (uint64_t)((hd | (n << 4)) ^ m) << sh;  // ring r's byte m becomes the new one
                     }
                 }
             }
