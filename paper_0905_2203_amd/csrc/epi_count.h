@@ -132,15 +132,16 @@ struct LaneLayout {
 };
 LaneLayout lane_layout(int C, int W, int K, int tile);
 
-// Kernel symbols (for attributes and occupancy) and launches.
+// Kernel symbols (for attributes and occupancy) and launches; wl: the work
+// log is kept (a.work set).
 template <typename T>
-const void *lane_tiled_fn(int N, bool pk);
+const void *lane_tiled_fn(int N, bool pk, bool wl);
 template <typename T>
-const void *lane_persistent_fn(int N, bool pk);
+const void *lane_persistent_fn(int N, bool pk, bool wl);
 template <typename T>
 hipError_t lane_launch_tiled(const CountArgs<T> &a, int N, bool pk, dim3 grid, int W, uint32_t lds, hipStream_t st);
 template <typename T>
-hipError_t lane_launch_persistent(int N, bool pk, unsigned grid, int W, uint32_t lds, hipStream_t st,
+hipError_t lane_launch_persistent(int N, bool pk, bool wl, unsigned grid, int W, uint32_t lds, hipStream_t st,
                                   const CountArgs<T> *units, const WorkItem *items, int64_t n_items, int64_t item_base,
                                   unsigned long long *queue);
 

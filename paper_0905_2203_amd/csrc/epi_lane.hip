@@ -51,7 +51,9 @@ namespace epi {
 
 namespace {
 
-template <typename T, int N, bool PK>
+// WL: the work log is kept (its counters cost nothing in the visit loop
+// without it).
+template <typename T, int N, bool PK, bool WL>
 __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, int p, int64_t item,
                                           unsigned char *smem) {
     using R = int32_t;
@@ -267,7 +269,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                     // completion: ring 0 becomes (t, +inf], every other ring empties
                     rl[0] = make_int2(t, rEnd);
                     hf = uint64_t(1) << 4;
-                    ++w_done;
+                    if constexpr (WL) ++w_done;
                     if (t >= BpR) {
                         const T ta = (T)t + t0b;  // absolute
                         if (a.P > 1 && cnt < kRecFirst) a.rec_first[((int64_t)p * kRecFirst + cnt) * a.G + s] = ta;
@@ -278,7 +280,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                     // record at node j into ring j+1: merge into its newest
                     // interval when they touch, else append (dropping the
                     // head, dead, when full)
-                    ++w_records;
+                    if constexpr (WL) ++w_records;
                     R lj = loR[0], hj = hiR[0];
 #pragma unroll
                     for (int k = 1; k + 1 < N; ++k) {
@@ -311,7 +313,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                         if (tl >= Q) tl -= Q;
                         rl[(int)(base + tl) << wsh] = make_int2(ns, ne);
                         ++n;
-                        w_maxq = n > w_maxq ? n : w_maxq;
+                        if constexpr (WL) w_maxq = n > w_maxq ? n : w_maxq;
                         hf ^= (uint64_t)((hd | (n << 4)) ^ m) << sh;  // ring r's byte m becomes the new one
                     }
                 }
@@ -330,7 +332,7 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
                 }
             }
         }
-        if (a.work) {
+        if constexpr (WL) {
             // visits of this tile: each node's events its cursor moved past
             // (a query at every node but node 0)
 #pragma unroll
@@ -361,15 +363,15 @@ __device__ __forceinline__ void lane_item(const CountArgs<T> &a, int64_t blk, in
     }
 }
 
-template <typename T, int N, bool PK>
+template <typename T, int N, bool PK, bool WL>
 __global__ __launch_bounds__(256) void k_lane_tiled(CountArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    lane_item<T, N, PK>(a, blockIdx.x, blockIdx.y, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, smem);
+    lane_item<T, N, PK, WL>(a, blockIdx.x, blockIdx.y, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, smem);
 }
 
 // Persistent form: every workgroup takes work items (unit, lane block,
 // segment) from a device queue until it is empty.
-template <typename T, int N, bool PK>
+template <typename T, int N, bool PK, bool WL>
 __global__ __launch_bounds__(256) void k_lane_persistent(const CountArgs<T> *__restrict__ units,
                                                          const WorkItem *__restrict__ items, int64_t n_items,
                                                          int64_t item_base, unsigned long long *__restrict__ queue) {
@@ -385,36 +387,36 @@ __global__ __launch_bounds__(256) void k_lane_persistent(const CountArgs<T> *__r
         if ((uint64_t)it >= (uint64_t)n_items) break;
         const WorkItem w = items[it];
         const CountArgs<T> a = units[w.unit];
-        lane_item<T, N, PK>(a, w.blk, w.p, item_base + it, smem);
+        lane_item<T, N, PK, WL>(a, w.blk, w.p, item_base + it, smem);
     }
 }
 
-template <typename T, bool PK>
+template <typename T, bool PK, bool WL>
 const void *tiled_sym(int N) {
     switch (N) {
-        case 1: return reinterpret_cast<const void *>(k_lane_tiled<T, 1, PK>);
-        case 2: return reinterpret_cast<const void *>(k_lane_tiled<T, 2, PK>);
-        case 3: return reinterpret_cast<const void *>(k_lane_tiled<T, 3, PK>);
-        case 4: return reinterpret_cast<const void *>(k_lane_tiled<T, 4, PK>);
-        case 5: return reinterpret_cast<const void *>(k_lane_tiled<T, 5, PK>);
-        case 6: return reinterpret_cast<const void *>(k_lane_tiled<T, 6, PK>);
-        case 7: return reinterpret_cast<const void *>(k_lane_tiled<T, 7, PK>);
-        case 8: return reinterpret_cast<const void *>(k_lane_tiled<T, 8, PK>);
+        case 1: return reinterpret_cast<const void *>(k_lane_tiled<T, 1, PK, WL>);
+        case 2: return reinterpret_cast<const void *>(k_lane_tiled<T, 2, PK, WL>);
+        case 3: return reinterpret_cast<const void *>(k_lane_tiled<T, 3, PK, WL>);
+        case 4: return reinterpret_cast<const void *>(k_lane_tiled<T, 4, PK, WL>);
+        case 5: return reinterpret_cast<const void *>(k_lane_tiled<T, 5, PK, WL>);
+        case 6: return reinterpret_cast<const void *>(k_lane_tiled<T, 6, PK, WL>);
+        case 7: return reinterpret_cast<const void *>(k_lane_tiled<T, 7, PK, WL>);
+        case 8: return reinterpret_cast<const void *>(k_lane_tiled<T, 8, PK, WL>);
         default: return nullptr;
     }
 }
 
-template <typename T, bool PK>
+template <typename T, bool PK, bool WL>
 const void *persistent_sym(int N) {
     switch (N) {
-        case 1: return reinterpret_cast<const void *>(k_lane_persistent<T, 1, PK>);
-        case 2: return reinterpret_cast<const void *>(k_lane_persistent<T, 2, PK>);
-        case 3: return reinterpret_cast<const void *>(k_lane_persistent<T, 3, PK>);
-        case 4: return reinterpret_cast<const void *>(k_lane_persistent<T, 4, PK>);
-        case 5: return reinterpret_cast<const void *>(k_lane_persistent<T, 5, PK>);
-        case 6: return reinterpret_cast<const void *>(k_lane_persistent<T, 6, PK>);
-        case 7: return reinterpret_cast<const void *>(k_lane_persistent<T, 7, PK>);
-        case 8: return reinterpret_cast<const void *>(k_lane_persistent<T, 8, PK>);
+        case 1: return reinterpret_cast<const void *>(k_lane_persistent<T, 1, PK, WL>);
+        case 2: return reinterpret_cast<const void *>(k_lane_persistent<T, 2, PK, WL>);
+        case 3: return reinterpret_cast<const void *>(k_lane_persistent<T, 3, PK, WL>);
+        case 4: return reinterpret_cast<const void *>(k_lane_persistent<T, 4, PK, WL>);
+        case 5: return reinterpret_cast<const void *>(k_lane_persistent<T, 5, PK, WL>);
+        case 6: return reinterpret_cast<const void *>(k_lane_persistent<T, 6, PK, WL>);
+        case 7: return reinterpret_cast<const void *>(k_lane_persistent<T, 7, PK, WL>);
+        case 8: return reinterpret_cast<const void *>(k_lane_persistent<T, 8, PK, WL>);
         default: return nullptr;
     }
 }
@@ -439,18 +441,20 @@ LaneLayout lane_layout(int C, int W, int K, int tile) {
 }
 
 template <typename T>
-const void *lane_tiled_fn(int N, bool pk) {
-    return pk ? tiled_sym<T, true>(N) : tiled_sym<T, false>(N);
+const void *lane_tiled_fn(int N, bool pk, bool wl) {
+    if (wl) return pk ? tiled_sym<T, true, true>(N) : tiled_sym<T, false, true>(N);
+    return pk ? tiled_sym<T, true, false>(N) : tiled_sym<T, false, false>(N);
 }
 
 template <typename T>
-const void *lane_persistent_fn(int N, bool pk) {
-    return pk ? persistent_sym<T, true>(N) : persistent_sym<T, false>(N);
+const void *lane_persistent_fn(int N, bool pk, bool wl) {
+    if (wl) return pk ? persistent_sym<T, true, true>(N) : persistent_sym<T, false, true>(N);
+    return pk ? persistent_sym<T, true, false>(N) : persistent_sym<T, false, false>(N);
 }
 
 template <typename T>
 hipError_t lane_launch_tiled(const CountArgs<T> &a, int N, bool pk, dim3 grid, int W, uint32_t lds, hipStream_t st) {
-    const void *fn = lane_tiled_fn<T>(N, pk);
+    const void *fn = lane_tiled_fn<T>(N, pk, a.work != nullptr);
     if (!fn) return hipErrorInvalidValue;
     CountArgs<T> arg = a;
     void *args[] = {&arg};
@@ -458,25 +462,25 @@ hipError_t lane_launch_tiled(const CountArgs<T> &a, int N, bool pk, dim3 grid, i
 }
 
 template <typename T>
-hipError_t lane_launch_persistent(int N, bool pk, unsigned grid, int W, uint32_t lds, hipStream_t st,
+hipError_t lane_launch_persistent(int N, bool pk, bool wl, unsigned grid, int W, uint32_t lds, hipStream_t st,
                                   const CountArgs<T> *units, const WorkItem *items, int64_t n_items, int64_t item_base,
                                   unsigned long long *queue) {
-    const void *fn = lane_persistent_fn<T>(N, pk);
+    const void *fn = lane_persistent_fn<T>(N, pk, wl);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {&units, &items, &n_items, &item_base, &queue};
     return hipLaunchKernel(fn, dim3(grid), dim3((unsigned)W), args, lds, st);
 }
 
-template const void *lane_tiled_fn<int32_t>(int, bool);
-template const void *lane_tiled_fn<int64_t>(int, bool);
-template const void *lane_persistent_fn<int32_t>(int, bool);
-template const void *lane_persistent_fn<int64_t>(int, bool);
+template const void *lane_tiled_fn<int32_t>(int, bool, bool);
+template const void *lane_tiled_fn<int64_t>(int, bool, bool);
+template const void *lane_persistent_fn<int32_t>(int, bool, bool);
+template const void *lane_persistent_fn<int64_t>(int, bool, bool);
 template hipError_t lane_launch_tiled<int32_t>(const CountArgs<int32_t> &, int, bool, dim3, int, uint32_t, hipStream_t);
 template hipError_t lane_launch_tiled<int64_t>(const CountArgs<int64_t> &, int, bool, dim3, int, uint32_t, hipStream_t);
-template hipError_t lane_launch_persistent<int32_t>(int, bool, unsigned, int, uint32_t, hipStream_t,
+template hipError_t lane_launch_persistent<int32_t>(int, bool, bool, unsigned, int, uint32_t, hipStream_t,
                                                     const CountArgs<int32_t> *, const WorkItem *, int64_t, int64_t,
                                                     unsigned long long *);
-template hipError_t lane_launch_persistent<int64_t>(int, bool, unsigned, int, uint32_t, hipStream_t,
+template hipError_t lane_launch_persistent<int64_t>(int, bool, bool, unsigned, int, uint32_t, hipStream_t,
                                                     const CountArgs<int64_t> *, const WorkItem *, int64_t, int64_t,
                                                     unsigned long long *);
 

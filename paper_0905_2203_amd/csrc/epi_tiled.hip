@@ -979,7 +979,8 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         const bool rel = !lane && rel_ok<T>(s, g.hspan);
         const bool filtered = c.compact && c.pred_bits && c.succ_bits;
         KFn<T> fn = lane ? nullptr : pick_count<T>(g.N, filtered, rel);
-        const void *lfn = lane ? lane_tiled_fn<T>(g.N, pk) : nullptr;
+        const bool wl = opt.worklog && c.work.p;  // (a.work below)
+        const void *lfn = lane ? lane_tiled_fn<T>(g.N, pk, wl) : nullptr;
         if (!fn && !lfn) return hipErrorInvalidValue;
         const int C = std::max(1, g.C);
         const int W = lane ? lane_pick_width(lfn, C, s.K, s.T, opt.lanes)
@@ -1017,7 +1018,7 @@ hipError_t count_t(const Stream &s, CandSet &c, const CountOptions &opt, int32_t
         a.tau = !c.compact && c.tau.p ? c.tau.as<T>() : nullptr;
         a.flags = d_flags;
         a.perm = nullptr;
-        a.work = opt.worklog && c.work.p ? c.work.as<int32_t>() : nullptr;
+        a.work = wl ? c.work.as<int32_t>() : nullptr;
         a.cycles = nullptr;
         if (lane) {
             a.off_qse = LL.off_ring;
@@ -1402,7 +1403,8 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
         crank[cl] = (int)corder.size();
         corder.push_back(cl);
         if (laneN[cl]) {
-            Wn[cl] = lane_pick_width(lane_persistent_fn<T>(clsN[cl], pkN[cl]), clsC[cl], maxK[cl], maxT[cl], opt.lanes);
+            Wn[cl] = lane_pick_width(lane_persistent_fn<T>(clsN[cl], pkN[cl], opt.worklog), clsC[cl], maxK[cl], maxT[cl],
+                                     opt.lanes);
             continue;
         }
         const PFn<T> pfn = filtN[cl] ? pick_persistent_f<T, true>(clsN[cl], relN[cl])
@@ -1650,7 +1652,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
         if (ncl <= 0) continue;
         int per = 0;
         if (laneN[cl]) {
-            const void *lfn = lane_persistent_fn<T>(N, pkN[cl]);
+            const void *lfn = lane_persistent_fn<T>(N, pkN[cl], opt.worklog);
             const LaneLayout L = lane_layout(clsC[cl], Wn[cl], maxK[cl], maxT[cl]);
             if (L.total > kLdsHard) {
                 e = hipErrorInvalidConfiguration;
@@ -1659,7 +1661,7 @@ hipError_t plan_t(std::vector<BatchRef> &sets, int sched, const CountOptions &op
             if ((e = lane_lds_attr(lfn, L.total)) != hipSuccess) break;
             if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, lfn, Wn[cl], L.total)) != hipSuccess) break;
             const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ncl, (int64_t)ncu * std::max(per, 1)));
-            e = lane_launch_persistent<T>(N, pkN[cl], (unsigned)grid, Wn[cl], L.total, cache.br[bi],
+            e = lane_launch_persistent<T>(N, pkN[cl], opt.worklog, (unsigned)grid, Wn[cl], L.total, cache.br[bi],
                                           plan.units.as<CountArgs<T>>(), plan.items.as<WorkItem>() + ioff[cl], ncl,
                                           ioff[cl], plan.queue.as<unsigned long long>() + cl);
             brcls[bi].push_back(cl);
