@@ -252,14 +252,7 @@ def ablation(k, scale, reps, lane_engine=1, ring_classes=0, tune=False, legs=ABL
         log(f"oracle leg failed: {exc!r}")
     # algorithmic bytes of the state-machine engines: each candidate reads the
     # times of its own types' events, its descriptor, and writes its count
-    alg = 0
-    for s_, c_ in sets:
-        tc = np.bincount(s_["types"], minlength=s_["K"]).astype(np.int64)
-        tsb = 8 if s_["ts_kind"] == 1 else 4
-        N_ = c_["N"].astype(np.int64)
-        ty_ = c_["types"].astype(np.int64)
-        per = np.where(np.arange(8)[None, :] < N_[:, None], tc[np.clip(ty_, 0, None)], 0).sum(axis=1)
-        alg += int(per.sum()) * tsb + int(N_.size) * ((128 if tsb == 8 else 72) + 4)
+    alg = sum(alg_bytes(s_, c_) for s_, c_ in sets)
     def ratio(a, b):
         return res[a] / res[b] if a in res and b in res else None
 
